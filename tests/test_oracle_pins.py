@@ -1,0 +1,511 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks one oracle function against something other than itself:
+a closed form, a library routine, an invariant, brute force, or central
+finite differences.  None of these tests needs a GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+from scipy.special import sph_harm_y
+
+from paper_2603_09277_amd import scenes
+
+PI = math.pi
+
+
+def make_scene(means, scales, quats, opac, sh, deg):
+    return scenes.Scene(np.asarray(means, np.float32).reshape(-1, 3), np.asarray(scales, np.float32).reshape(-1, 3),
+                        np.asarray(quats, np.float32).reshape(-1, 4), np.asarray(opac, np.float32).reshape(-1),
+                        np.asarray(sh, np.float32).reshape(len(np.asarray(opac).reshape(-1)), -1, 3), deg)
+
+
+def ident_cam(W=64, H=64, f=50.0):
+    return scenes.Camera(W, H, f, f, W / 2.0, H / 2.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32), 0.2)
+
+
+def small_random_scene(seed, n=64, deg=1, W=40, H=32):
+    rng = np.random.default_rng(seed)
+    means = np.stack([rng.uniform(-0.8, 0.8, n), rng.uniform(-0.6, 0.6, n), rng.uniform(3.0, 5.0, n)], 1)
+    scales = np.exp(rng.normal(-2.3, 0.4, (n, 3)))
+    quats = rng.standard_normal((n, 4))
+    opac = 1 / (1 + np.exp(-rng.normal(0.0, 1.0, n)))
+    K = (deg + 1) ** 2
+    sh = rng.normal(0.0, 0.3, (n, K, 3))
+    sh[:, 0, :] = rng.uniform(-1.0, 1.0, (n, 3))
+    # a camera slightly rotated and shifted, so the world->camera transpose is exercised
+    R = Rotation.from_euler("xyz", [0.05, -0.08, 0.03]).as_matrix()
+    cam = scenes.Camera(W, H, 36.0, 38.0, W / 2.0 + 0.7, H / 2.0 - 0.4, R.astype(np.float32),
+                        np.array([0.1, -0.05, 0.2], np.float32), 0.2)
+    return make_scene(means, scales, quats, opac, sh, deg), cam
+
+
+def scipy_real_sh(deg, d):
+    """Real SH without the Condon-Shortley phase, from scipy's complex SH
+    (which carries the phase (-1)^m)."""
+    x, y, z = d
+    theta = math.acos(max(-1.0, min(1.0, z)))
+    phi = math.atan2(y, x)
+    out = []
+    for l in range(deg + 1):
+        for m in range(-l, l + 1):
+            am = abs(m)
+            Yc = complex(sph_harm_y(l, am, theta, phi))
+            if m == 0:
+                out.append(Yc.real)
+            elif m > 0:
+                out.append(math.sqrt(2) * (-1) ** am * Yc.real)
+            else:
+                out.append(math.sqrt(2) * (-1) ** am * Yc.imag)
+    return np.array(out)
+
+
+# --------------------------------------------------------------------------- #
+# P2 spherical harmonics
+# --------------------------------------------------------------------------- #
+
+def test_sh_matches_scipy_and_addition_theorem(orc):
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        Y, _ = orc.sh_basis(3, d)
+        np.testing.assert_allclose(Y, scipy_real_sh(3, d), rtol=0, atol=1e-13)
+        for l in range(4):
+            s = np.sum(Y[l * l:(l + 1) * (l + 1)] ** 2)
+            assert abs(s - (2 * l + 1) / (4 * PI)) < 1e-13
+
+
+def test_sh_orthonormal_by_quadrature(orc):
+    # Gauss-Legendre in cos(theta) x uniform phi integrates degree <= 6 exactly
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    nphi = 16
+    G = np.zeros((16, 16))
+    for ct, w in zip(xg, wg):
+        st = math.sqrt(1 - ct * ct)
+        for j in range(nphi):
+            ph = 2 * PI * j / nphi
+            Y, _ = orc.sh_basis(3, (st * math.cos(ph), st * math.sin(ph), ct))
+            G += np.outer(Y, Y) * w * (2 * PI / nphi)
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_derivative_fd(orc):
+    rng = np.random.default_rng(1)
+    h = 1e-6
+    for _ in range(10):
+        p = rng.standard_normal(3)
+        _, dY = orc.sh_basis(3, p)
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            fd = (orc.sh_basis(3, p + e)[0] - orc.sh_basis(3, p - e)[0]) / (2 * h)
+            np.testing.assert_allclose(dY[:, a], fd, rtol=1e-6, atol=1e-7)
+
+
+# --------------------------------------------------------------------------- #
+# P1 projection
+# --------------------------------------------------------------------------- #
+
+def test_projection_isotropic_on_axis(orc):
+    cam = ident_cam()
+    rng = np.random.default_rng(2)
+    s, z = 0.08, 5.0
+    results = []
+    for q in [rng.standard_normal(4) for _ in range(5)] + [[1, 0, 0, 0], [-1, 0, 0, 0]]:
+        sc = make_scene([0, 0, z], [s, s, s], q, [0.5], [0.0, 0.0, 0.0], 0)
+        pr = orc.project(sc, cam)
+        v = (float(np.float32(s)) * 50.0 / z) ** 2 + 0.3
+        np.testing.assert_allclose(pr["cov2d"][0], [v, 0.0, v], rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(pr["conic"][0], [1 / v, 0.0, 1 / v], rtol=1e-12, atol=1e-15)
+        assert pr["mean2d"][0].tolist() == [32.0, 32.0]
+        assert pr["depth"][0] == pytest.approx(z, rel=1e-15)
+        assert pr["radius"][0] == math.ceil(3 * math.sqrt(v))
+        results.append(pr["cov2d"][0].copy())
+    # rotation invariance for isotropic scale, and q == -q
+    for r in results[1:]:
+        np.testing.assert_allclose(r, results[0], rtol=1e-12, atol=1e-14)
+
+
+def pinhole(cam, p):
+    return np.array([cam.fx * p[0] / p[2] + cam.cx, cam.fy * p[1] / p[2] + cam.cy])
+
+
+def fd_jacobian(cam, p, h=1e-5):
+    J = np.zeros((2, 3))
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        J[:, a] = (pinhole(cam, p + e) - pinhole(cam, p - e)) / (2 * h)
+    return J
+
+
+def test_projection_matches_local_affine_approximation(orc):
+    """EWA (Eq. 2) linearises the pinhole map at the mean: Sigma' = J Rc Sigma Rc^T J^T + 0.3 I,
+    with J the derivative of the pinhole map (here by finite differences) and Sigma built from
+    scipy's quaternion rotation.  Off-screen means use the derivative at the mean moved onto the
+    1.3x field-of-view boundary at the same depth."""
+    sc, cam = small_random_scene(3, n=64, deg=0)
+    # push a few means far to the side so the Jacobian clamp engages
+    sc.means[:4, 0] = np.array([9.0, -9.0, 7.5, -8.0], np.float32)
+    sc.means[4:6, 1] = np.array([7.0, -7.0], np.float32)
+    pr = orc.project(sc, cam)
+    Rc = cam.R.astype(np.float64)
+    limx, limy = 1.3 * cam.width / 2 / cam.fx, 1.3 * cam.height / 2 / cam.fy
+    for i in range(sc.n):
+        q = sc.quats[i].astype(np.float64)
+        Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        S = np.diag(sc.scales[i].astype(np.float64) ** 2)
+        Sig = Rq @ S @ Rq.T
+        t = Rc @ sc.means[i].astype(np.float64) + cam.t.astype(np.float64)
+        u, v = t[0] / t[2], t[1] / t[2]
+        tcl = np.array([np.clip(u, -limx, limx) * t[2], np.clip(v, -limy, limy) * t[2], t[2]])
+        J = fd_jacobian(cam, tcl)
+        cov = J @ Rc @ Sig @ Rc.T @ J.T + 0.3 * np.eye(2)
+        np.testing.assert_allclose(pr["cov2d"][i], [cov[0, 0], cov[0, 1], cov[1, 1]], rtol=2e-7)
+        inv = np.linalg.inv(cov)
+        np.testing.assert_allclose(pr["conic"][i], [inv[0, 0], inv[0, 1], inv[1, 1]], rtol=2e-7)
+        np.testing.assert_allclose(pr["mean2d"][i], pinhole(cam, t), rtol=1e-13)
+        assert pr["depth"][i] == pytest.approx(t[2], rel=1e-13)
+        lam = np.linalg.eigvalsh(cov).max()
+        r = 3 * math.sqrt(lam)
+        if abs(r - round(r)) > 1e-6:
+            assert pr["radius"][i] == math.ceil(r)
+        clampx = abs(u) > limx
+        assert bool(pr["mask"][i] & 8) == clampx
+
+
+def test_projection_monte_carlo(orc):
+    """A small Gaussian's projected samples have covariance Sigma' - 0.3 I (to first order)."""
+    cam = ident_cam(W=128, H=128, f=100.0)
+    q = np.array([0.9, 0.2, -0.3, 0.1])
+    sc = make_scene([0.3, -0.2, 6.0], [0.02, 0.05, 0.01], q, [0.5], [0, 0, 0], 0)
+    pr = orc.project(sc, cam)
+    Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    Sig = Rq @ np.diag(sc.scales[0].astype(np.float64) ** 2) @ Rq.T
+    rng = np.random.default_rng(4)
+    pts = rng.multivariate_normal(sc.means[0].astype(np.float64), Sig, size=400_000)
+    uv = np.stack([100 * pts[:, 0] / pts[:, 2] + 64, 100 * pts[:, 1] / pts[:, 2] + 64], 1)
+    C = np.cov(uv.T)
+    got = np.array([[pr["cov2d"][0][0] - 0.3, pr["cov2d"][0][1]], [pr["cov2d"][0][1], pr["cov2d"][0][2] - 0.3]])
+    np.testing.assert_allclose(got, C, rtol=2e-2, atol=2e-2 * np.abs(C).max())
+
+
+def test_projection_colour_and_culling(orc):
+    sc, cam = small_random_scene(5, n=32, deg=3)
+    sc.means[0] = np.array([0.0, 0.0, -0.1], np.float32)   # in front of the near plane
+    sc.means[1, 0] = np.nan                                  # non-finite input
+    pr = orc.project(sc, cam)
+    assert pr["radius"][0] == 0 and pr["radius"][1] == 0
+    Rc = cam.R.astype(np.float64)
+    campos = -Rc.T @ cam.t.astype(np.float64)
+    for i in range(2, sc.n):
+        d = sc.means[i].astype(np.float64) - campos
+        d /= np.linalg.norm(d)
+        Y = scipy_real_sh(3, d)
+        col = Y @ sc.sh[i].astype(np.float64) + 0.5
+        np.testing.assert_allclose(pr["rgb"][i], np.maximum(col, 0.0), atol=1e-13)
+        assert (pr["mask"][i] & 7) == sum(1 << c for c in range(3) if col[c] < 0)
+
+
+# --------------------------------------------------------------------------- #
+# P3 / P4 / P5 blending
+# --------------------------------------------------------------------------- #
+
+def tiles_overlapping(mx, my, r, W, H, tw, th):
+    """Interval-overlap statement of the tile rule: tile [tx*tw, (tx+1)*tw) x [..] meets
+    [mx - r, mx + r] x [my - r, my + r]."""
+    gx, gy = (W + tw - 1) // tw, (H + th - 1) // th
+    out = set()
+    if r <= 0:
+        return out
+    lo_x, hi_x, lo_y, hi_y = mx - r, mx + r, my - r, my + r
+    for ty in range(gy):
+        for tx in range(gx):
+            if tx * tw <= hi_x and (tx + 1) * tw > lo_x and ty * th <= hi_y and (ty + 1) * th > lo_y:
+                out.add(ty * gx + tx)
+    return out
+
+
+def test_single_gaussian_image(orc):
+    cam = ident_cam(W=48, H=40, f=60.0)
+    s, z, op = 0.12, 4.0, 0.8
+    sh = np.array([0.7, -0.4, 1.2]).reshape(1, 1, 3)
+    # on the optical axis the projected covariance is isotropic: v = (s f / z)^2 + 0.3
+    sc = make_scene([0.0, 0.0, z], [s, s, s], [1, 0, 0, 0], [op], sh, 0)
+    f = orc.forward_view(sc, cam, tile=(8, 8))
+    pr = f["proj"]
+    v = (float(np.float32(s)) * 60.0 / z) ** 2 + 0.3
+    mx, my = pr["mean2d"][0]
+    col = sc.sh[0, 0].astype(np.float64) * (0.5 / math.sqrt(PI)) + 0.5
+    assert (mx, my) == (24.0, 20.0)
+    tiles = tiles_overlapping(mx, my, pr["radius"][0], 48, 40, 8, 8)
+    for py in range(40):
+        for px in range(48):
+            a = min(0.99, float(np.float32(op)) * math.exp(-((px + 0.5 - mx) ** 2 + (py + 0.5 - my) ** 2) / (2 * v)))
+            inside = ((py // 8) * 6 + px // 8) in tiles
+            if inside and a >= 1 / 255:
+                np.testing.assert_allclose(f["rgb"][py, px], a * col, rtol=1e-12, atol=1e-15)
+                assert f["T"][py, px] == pytest.approx(1 - a, rel=1e-12)
+                hb = -a * math.log(a) - (1 - a) * math.log(1 - a)
+                assert f["H"][py, px] == pytest.approx(hb, rel=1e-11)
+            else:
+                assert np.all(f["rgb"][py, px] == 0) and f["T"][py, px] == 1.0 and f["H"][py, px] == 0.0
+
+
+def test_two_gaussians_over_operator(orc):
+    """Two Gaussians on the optical axis: C = a1 c1 + (1 - a1) a2 c2, nearer first."""
+    cam = ident_cam(W=16, H=16, f=40.0)
+    sh = np.array([[0.9, 0.1, -0.5], [-0.6, 0.8, 0.3]]).reshape(2, 1, 3)
+    # index 0 is the FAR one: the list must be ordered by depth, not index
+    sc = make_scene([[0, 0, 6.0], [0, 0, 3.0]], [[0.2] * 3, [0.1] * 3], [[1, 0, 0, 0]] * 2, [0.7, 0.6], sh, 0)
+    f = orc.forward_view(sc, cam, tile=(16, 16))
+    pr = f["proj"]
+    p = np.array([8.5, 7.5])
+    c = sc.sh[:, 0].astype(np.float64) * (0.5 / math.sqrt(PI)) + 0.5
+    a = []
+    for g in range(2):
+        v = pr["cov2d"][g][0]
+        a.append(min(0.99, float(np.float32([0.7, 0.6][g])) * math.exp(-np.sum((p - pr["mean2d"][g]) ** 2) / (2 * v))))
+    exp_c = a[1] * c[1] + (1 - a[1]) * a[0] * c[0]
+    np.testing.assert_allclose(f["rgb"][7, 8], exp_c, rtol=1e-12)
+    w = [a[1], (1 - a[1]) * a[0], (1 - a[1]) * (1 - a[0])]
+    assert f["H"][7, 8] == pytest.approx(-sum(x * math.log(x) for x in w), rel=1e-12)
+    assert list(f["values"]) == [1, 0]
+
+
+def test_weights_sum_to_one(orc):
+    """Eq. 9: with every colour 1 the image is sum_i w_i = 1 - T_final; 0 <= H <= ln(N + 1)."""
+    sc, cams, _ = scenes.workload("tiny")
+    cam = cams[0]
+    pr = orc.project(sc, cam)
+    vals, rng_ = orc.bin_lists(pr["mean2d"], pr["radius"], pr["depth32"], 128, 128, 16, 16)
+    out = orc.render(128, 128, 16, 16, pr["mean2d"], pr["conic"], pr["opacity"], np.ones_like(pr["rgb"]), rng_, vals)
+    for ch in range(3):
+        np.testing.assert_allclose(out["rgb"][..., ch] + out["T"], 1.0, atol=1e-12)
+    assert out["T"].min() >= 1e-4
+    assert np.all(out["H"] >= -1e-15)
+    assert np.all(out["H"] <= np.log(out["ncontrib"] + 1.0) + 1e-12)
+
+
+# --------------------------------------------------------------------------- #
+# P6 / P7 entropy and Algorithm 1
+# --------------------------------------------------------------------------- #
+
+def test_entropy_single_and_equal_alphas(orc):
+    for a in [0.01, 0.3, 0.5, 0.97]:
+        assert orc.entropy_of_alphas([a]) == pytest.approx(-a * math.log(a) - (1 - a) * math.log(1 - a), rel=1e-14)
+        for m in ("chain", "alg1", "cancelled"):
+            assert orc.dH_dalpha([a], m)[0] == pytest.approx(math.log((1 - a) / a), rel=1e-12, abs=1e-14)
+    # N equal alphas a: w_i = a q^{i-1}, T = q^N; closed-form geometric sums
+    for a, N in [(0.1, 7), (0.35, 20), (0.02, 50)]:
+        q = 1 - a
+        sum_jqj = q * (1 - N * q ** (N - 1) + (N - 1) * q ** N) / (1 - q) ** 2   # sum_{j<N} j q^j
+        Hc = -(math.log(a) * (1 - q ** N) + a * math.log(q) * sum_jqj) - q ** N * N * math.log(q)
+        assert orc.entropy_of_alphas([a] * N) == pytest.approx(Hc, rel=1e-12)
+
+
+def test_alg1_matches_chain_rule_cancelled_and_fd(orc):
+    rng = np.random.default_rng(6)
+    for n in [1, 2, 5, 40, 200]:
+        a = rng.uniform(1 / 255, 0.99, n) ** 2
+        a = np.clip(a, 1 / 255, 0.99)
+        g_chain = orc.dH_dalpha(a, "chain")
+        g_alg1 = orc.dH_dalpha(a, "alg1")
+        g_can = orc.dH_dalpha(a, "cancelled")
+        np.testing.assert_allclose(g_alg1, g_chain, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(g_can, g_chain, rtol=1e-9, atol=1e-12)
+        h = 1e-7
+        for i in rng.choice(n, min(n, 6), replace=False):
+            ap, am = a.copy(), a.copy()
+            ap[i] += h
+            am[i] -= h
+            fd = (orc.entropy_of_alphas(ap) - orc.entropy_of_alphas(am)) / (2 * h)
+            assert g_alg1[i] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+# --------------------------------------------------------------------------- #
+# P8 binning, sort, ranges
+# --------------------------------------------------------------------------- #
+
+def test_binning_matches_brute_force(orc):
+    sc, cams, _ = scenes.workload("tiny")
+    cam = cams[0]
+    pr = orc.project(sc, cam)
+    for tw, th in [(16, 16), (8, 8), (32, 8)]:
+        total, tt, _ = orc.count_pairs(pr["mean2d"], pr["radius"], 128, 128, tw, th)
+        exp_pairs = []
+        for i in range(sc.n):
+            ts = tiles_overlapping(pr["mean2d"][i][0], pr["mean2d"][i][1], pr["radius"][i], 128, 128, tw, th)
+            assert tt[i] == len(ts)
+            exp_pairs += [(t, pr["depth32"][i].view(np.uint32), i) for t in ts]
+        assert total == len(exp_pairs)
+        vals, ranges = orc.bin_lists(pr["mean2d"], pr["radius"], pr["depth32"], 128, 128, tw, th)
+        arr = np.array(exp_pairs, dtype=np.int64)
+        order = np.lexsort((arr[:, 2], arr[:, 1], arr[:, 0]))
+        np.testing.assert_array_equal(vals, arr[order, 2])
+        tiles_sorted = arr[order, 0]
+        for t in range(ranges.shape[0]):
+            idx = np.nonzero(tiles_sorted == t)[0]
+            if len(idx):
+                assert ranges[t].tolist() == [idx[0], idx[-1] + 1]
+            else:
+                assert ranges[t, 1] - ranges[t, 0] == 0
+
+
+def test_equal_depth_ties_break_by_index(orc):
+    cam = ident_cam(W=32, H=32, f=40.0)
+    n = 5
+    sc = make_scene(np.tile([0.0, 0.0, 4.0], (n, 1)), np.full((n, 3), 0.1), np.tile([1, 0, 0, 0], (n, 1)),
+                    np.full(n, 0.5), np.zeros((n, 1, 3)), 0)
+    pr = orc.project(sc, cam)
+    vals, ranges = orc.bin_lists(pr["mean2d"], pr["radius"], pr["depth32"], 32, 32, 16, 16)
+    for t in range(4):
+        assert list(vals[ranges[t, 0]:ranges[t, 1]]) == list(range(n))
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_tiled_render_equals_untiled_brute_force(orc, tile):
+    sc, cams, _ = scenes.workload("tiny")
+    cam = cams[0]
+    pr = orc.project(sc, cam)
+    tw, th = tile
+    vals, ranges = orc.bin_lists(pr["mean2d"], pr["radius"], pr["depth32"], 128, 128, tw, th)
+    a = orc.render(128, 128, tw, th, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"], ranges, vals)
+    b = orc.render_bruteforce(128, 128, tw, th, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"],
+                              pr["radius"], pr["depth32"])
+    for k in ("rgb", "H", "T", "ncontrib", "flags"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+# --------------------------------------------------------------------------- #
+# P9 backward: central finite differences with kink detection
+# --------------------------------------------------------------------------- #
+
+def _loss_sig(orc, scene, cam, target, gamma, tile):
+    f = orc.forward_view(scene, cam, tile)
+    L = float(np.abs(f["rgb"] - target).mean()) + gamma * f["L_E"]
+    pr = f["proj"]
+    sig = (f["sig"], pr["mask"].tobytes(), pr["radius"].tobytes(), f["values"].tobytes(),
+           np.sign(f["rgb"] - target).astype(np.int8).tobytes())
+    return L, sig
+
+
+def _fd_check(orc, scene, cam, target, gamma, tile, grads, params, rng, n_gauss, rtol, atol_frac):
+    checked = 0
+    redrawn = 0
+    for g in rng.choice(scene.n, n_gauss, replace=False):
+        for name in params:
+            arr = getattr(scene, name)
+            flat = arr.reshape(scene.n, -1)
+            for j in range(flat.shape[1]):
+                x0 = flat[g, j]
+                eps = 1e-4 * max(1.0, abs(float(x0))) if name != "scales" else 1e-4 * float(x0)
+                xp, xm = np.float32(x0 + eps), np.float32(x0 - eps)
+                flat[g, j] = xp
+                Lp, sp = _loss_sig(orc, scene, cam, target, gamma, tile)
+                flat[g, j] = xm
+                Lm, sm = _loss_sig(orc, scene, cam, target, gamma, tile)
+                flat[g, j] = x0
+                if sp != sm:
+                    redrawn += 1
+                    continue
+                fd = (Lp - Lm) / (float(xp) - float(xm))
+                an = grads[name].reshape(scene.n, -1)[g, j]
+                scale = np.abs(grads[name]).max()
+                assert abs(an - fd) <= rtol * abs(fd) + atol_frac * scale + 1e-12, (name, g, j, an, fd)
+                checked += 1
+    return checked, redrawn
+
+
+def test_full_backward_matches_central_fd(orc):
+    scene, cam = small_random_scene(7, n=64, deg=1)
+    scene.scales *= 2.0
+    rng = np.random.default_rng(8)
+    target = rng.uniform(0, 1, (cam.height, cam.width, 3))
+    gamma = 0.5      # large, so the entropy term is well exercised
+    tile = (8, 8)
+    L, grads, _ = orc.loss_and_grads(scene, [cam], [target], gamma, tile)
+    checked, redrawn = _fd_check(orc, scene, cam, target, gamma, tile, grads,
+                                 ["means", "scales", "quats", "opacities", "sh"], rng, 24, 1e-4, 1e-6)
+    assert checked > 300 and redrawn < checked // 4
+
+
+def test_entropy_only_backward_matches_fd(orc):
+    """gamma-only loss (no L1): isolates Eq. 13-15 through the whole chain."""
+    scene, cam = small_random_scene(9, n=48, deg=0)
+    scene.scales *= 2.5
+    rng = np.random.default_rng(10)
+    tile = (16, 16)
+    f = orc.forward_view(scene, cam, tile)
+    M = cam.width * cam.height
+    pr = f["proj"]
+    g2 = orc.backward_render(cam.width, cam.height, 16, 16, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"],
+                             f["ranges"], f["values"], np.zeros((cam.height, cam.width, 3)),
+                             np.full((cam.height, cam.width), 1.0 / M))
+    grads = orc.backward_project(scene, cam, g2)
+
+    def loss_sig(sc):
+        ff = orc.forward_view(sc, cam, tile)
+        return ff["L_E"], (ff["sig"], ff["proj"]["mask"].tobytes(), ff["values"].tobytes())
+
+    checked = 0
+    for g in rng.choice(scene.n, 16, replace=False):
+        for name in ["means", "scales", "quats", "opacities"]:
+            flat = getattr(scene, name).reshape(scene.n, -1)
+            for j in range(flat.shape[1]):
+                x0 = flat[g, j]
+                eps = 1e-4 * (abs(float(x0)) if name == "scales" else max(1.0, abs(float(x0))))
+                xp, xm = np.float32(x0 + eps), np.float32(x0 - eps)
+                flat[g, j] = xp
+                Lp, sp = loss_sig(scene)
+                flat[g, j] = xm
+                Lm, sm = loss_sig(scene)
+                flat[g, j] = x0
+                if sp != sm:
+                    continue
+                fd = (Lp - Lm) / (float(xp) - float(xm))
+                an = grads[name].reshape(scene.n, -1)[g, j]
+                assert abs(an - fd) <= 1e-4 * abs(fd) + 1e-6 * np.abs(grads[name]).max() + 1e-13, (name, g, j, an, fd)
+                checked += 1
+    assert checked > 100
+
+
+def test_render_backward_matches_fd_on_records(orc):
+    """Blend backward alone: perturb the 2D records (mean, conic, opacity, colour) with fixed lists."""
+    scene, cam = small_random_scene(11, n=40, deg=0)
+    scene.scales *= 2.0
+    pr = orc.project(scene, cam)
+    W, H, tw, th = cam.width, cam.height, 8, 8
+    vals, ranges = orc.bin_lists(pr["mean2d"], pr["radius"], pr["depth32"], W, H, tw, th)
+    rng = np.random.default_rng(12)
+    gC = rng.standard_normal((H, W, 3))
+    gH = rng.standard_normal((H, W))
+
+    def f(rec):
+        o = orc.render(W, H, tw, th, rec["mean2d"], rec["conic"], rec["opacity"], rec["rgb"], ranges, vals)
+        return float((o["rgb"] * gC).sum() + (o["H"] * gH).sum()), o["sig"]
+
+    rec = {k: pr[k].copy() for k in ("mean2d", "conic", "opacity", "rgb")}
+    g = orc.backward_render(W, H, tw, th, rec["mean2d"], rec["conic"], rec["opacity"], rec["rgb"], ranges, vals, gC, gH)
+    h = 1e-6
+    checked = 0
+    for gi in rng.choice(scene.n, 20, replace=False):
+        for key in ("mean2d", "conic", "opacity", "rgb"):
+            arr = rec[key].reshape(scene.n, -1)
+            for j in range(arr.shape[1]):
+                x0 = arr[gi, j]
+                arr[gi, j] = x0 + h
+                Lp, sp = f(rec)
+                arr[gi, j] = x0 - h
+                Lm, sm = f(rec)
+                arr[gi, j] = x0
+                if sp != sm:
+                    continue
+                fd = (Lp - Lm) / (2 * h)
+                an = g[key].reshape(scene.n, -1)[gi, j]
+                assert abs(an - fd) <= 1e-5 * abs(fd) + 1e-6 * np.abs(g[key]).max() + 1e-9, (key, gi, j, an, fd)
+                checked += 1
+    assert checked > 100

@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Forward+backward rasterize iterations/s and Gaussian-tile pairs/s on one MI355X.
+
+One step = one pass of the whole hot path over one batch of views: EWA
+projection and SH colour, depth sort, tile binning (prefix sum + pair
+emission), tile sort, per-tile ranges, front-to-back blend with the entropy
+term, per-view mean entropy, L1 loss and its gradient, back-to-front blend
+backward with Alg. 1, projection backward.  Every stage runs in the HIP
+library (libgsr.so); inputs are resident in HBM before the timed region.
+
+Default workload: 200,000 Gaussians, one 1296x840 camera, SH degree 3, FP32,
+16x16 tiles, loss L1 + 0.015 L_E.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd rasterize iters/s and Gaussian-tile pairs/s at 1 MI355X; batched vs plain"
+GAMMA = 0.015
+HBM_PEAK_GBS = 8000.0
+# VALU issue rate without packed FP32: 256 CUs x 64 lanes x 2.4 GHz (one FP32 op per lane per clock)
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# Algorithmic work per unit (see the design notes for the derivation)
+OPS_PER_EVAL_FWD = 20       # VALU ops per alpha evaluation in the forward blend
+OPS_PER_EVAL_BWD = 50       # VALU ops per list position walked by the backward blend
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="single",
+                    choices=["tiny", "single", "sweep", "sweep_half", "batched", "diff"])
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--lds", type=int, default=64)
+    ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
+    ap.add_argument("--bf16", action="store_true", help="store SH and SH gradients in bfloat16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="do not bracket stages with HIP events")
+    return ap.parse_args()
+
+
+def stage_bytes(stage, n, V, sh_bytes, pairs, n_tiles, npix, evals_fwd, evals_bwd):
+    """Algorithmic HBM bytes of one launch of each stage (minimum data the step must move)."""
+    vn = n * V
+    return {
+        "project": n * (44 + sh_bytes) + vn * 52,
+        "depth_sort": vn * 4 * 20,
+        "scan": vn * 16,
+        "duplicate": vn * 20 + pairs * 8,
+        "tile_sort": pairs * 20 * 2,
+        "ranges": pairs * 4 + n_tiles * 8,
+        "blend_fwd": pairs * 40 + npix * 24,
+        "entropy_mean": 0,
+        "blend_bwd": pairs * 40 + npix * 24 + n * V * 36,
+        "project_bwd": n * (44 + sh_bytes) * 2 + vn * 36,
+    }[stage]
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def cpu_baseline(scene, cams, tile, targets):
+    """The FP64 oracle (single-threaded) on every other pixel row of the same
+    workload: projection and binning in full, blend + entropy + backward on the
+    sampled rows, extrapolated per pixel to whole iterations."""
+    from oracle import oracle as orc
+    tw, th = tile
+    t_fixed = 0.0
+    t_pix = 0.0
+    sampled = 0
+    total = 0
+    for cam, target in zip(cams, targets):
+        W, H = cam.width, cam.height
+        pix = np.zeros((H, W), np.uint8)
+        pix[::2, :] = 1
+        t0 = time.perf_counter()
+        pr = orc.project(scene, cam)
+        vals, ranges = orc.bin_lists(pr["mean2d"], pr["radius"], pr["depth32"], W, H, tw, th)
+        t1 = time.perf_counter()
+        img = orc.render(W, H, tw, th, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"], ranges, vals, pix)
+        gC = np.sign(img["rgb"] - target) / (3.0 * W * H)
+        gH = np.full((H, W), GAMMA / (W * H))
+        t2 = time.perf_counter()
+        g2 = orc.backward_render(W, H, tw, th, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"], ranges, vals,
+                                 gC, gH, pix)
+        t3 = time.perf_counter()
+        orc.backward_project(scene, cam, g2)
+        t4 = time.perf_counter()
+        t_fixed += (t1 - t0) + (t4 - t3)
+        t_pix += (t2 - t1) + (t3 - t2)
+        sampled += int(pix.sum())
+        total += W * H
+    sec_per_iter = t_fixed + t_pix * total / max(sampled, 1)
+    return {"value": len(cams) / sec_per_iter, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle, 1 thread: projection + binning in full, blend/entropy/backward on every "
+                      f"other pixel row ({sampled} of {total} pixels), extrapolated per pixel; "
+                      f"{t_fixed + t_pix:.1f} s measured, {sec_per_iter:.1f} s per iteration"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU sharding over views is described in the design notes, not implemented)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2603_09277_amd import gsr, scenes
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    tile = tuple(int(x) for x in args.tile.split("x"))
+    scene, cams, meta = scenes.workload(args.workload)
+    bf16 = args.bf16 or meta["sh_dtype"] == "bf16"
+    n, V = scene.n, len(cams)
+    npix = sum(c.width * c.height for c in cams)
+    t = {k: torch.from_numpy(np.ascontiguousarray(getattr(scene, k))).to(dev) for k in
+         ("means", "scales", "quats", "opacities", "sh")}
+    if bf16:
+        t["sh"] = t["sh"].to(torch.bfloat16).contiguous()
+    flags = gsr.GSR_DEFAULT_FLAGS | (gsr.GSR_GRAPH if args.graph else 0)
+    opts = gsr.RasterOptions(tile=tile, lds_batch=args.lds, sh_degree=scene.sh_degree, sh_bf16=bf16, flags=flags)
+    targets_np = [scenes.target_image(1000 + v, c.height, c.width) for v, c in enumerate(cams)]
+    target = torch.from_numpy(np.concatenate([x.reshape(-1, 3) for x in targets_np])).to(dev).contiguous()
+    R = gsr.Rasterizer(max_views=max(V, 1))
+    g_le = torch.full((V,), GAMMA, device=dev)
+    grad_rgb = torch.empty((npix, 3), device=dev)
+    loss = torch.empty(V, device=dev)
+    grads = {k: torch.empty_like(v) for k, v in t.items()}
+    state = {}
+    out_bufs = {}
+
+    def step():
+        out = R.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts,
+                        out=out_bufs.get("out"))
+        out_bufs["out"] = out
+        R.l1_loss(cams, out["rgb"], target, grad_rgb, loss)
+        R.backward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, out,
+                   grad_rgb, None, g_le, grads)
+        state["out"] = out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    timing = not args.no_timing and not args.graph
+    if timing:
+        R.stage_times(reset=True)
+        R.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if timing:
+        R.set_timing(False)
+    stages = R.stage_times(reset=True) if timing else {}
+    st = R.stats(V)
+    sec = (t1 - t0) / args.steps
+    iters = V / sec
+    K = (scene.sh_degree + 1) ** 2
+    sh_bytes = K * 3 * (2 if bf16 else 4)
+    n_tiles = sum(((c.width + tile[0] - 1) // tile[0]) * ((c.height + tile[1] - 1) // tile[1]) for c in cams)
+
+    stage_report = {}
+    for name, (ms, cnt) in stages.items():
+        if cnt == 0:
+            continue
+        avg_s = ms / cnt / 1e3
+        b = stage_bytes(name, n, V, sh_bytes, st["pairs"], n_tiles, npix, st["evals_fwd"], st["evals_bwd"])
+        rep = {"avg_ms": round(ms / cnt, 4), "hbm_GBs": round(b / avg_s / 1e9, 1) if b else None}
+        if name == "blend_fwd":
+            rep["valu_Tops"] = round(OPS_PER_EVAL_FWD * st["evals_fwd"] / avg_s / 1e12, 3)
+        if name == "blend_bwd":
+            rep["valu_Tops"] = round(OPS_PER_EVAL_BWD * st["evals_bwd"] / avg_s / 1e12, 3)
+        stage_report[name] = rep
+
+    roofline = None
+    if stage_report:
+        dom = max(stage_report, key=lambda k: stage_report[k]["avg_ms"])
+        avg_s = stage_report[dom]["avg_ms"] / 1e3
+        traffic = None
+        tf = os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_traffic.json")
+        if os.path.exists(tf):
+            with open(tf) as f:
+                rec = json.load(f)
+            src = os.path.join(ROOT, "paper_2603_09277_amd", "csrc", rec.get("source", ""))
+            if os.path.exists(src) and source_hash(src) == rec.get("source_sha256_16"):
+                traffic = rec.get("bytes_per_launch")
+        if dom in ("blend_fwd", "blend_bwd"):
+            ops = (OPS_PER_EVAL_FWD * st["evals_fwd"]) if dom == "blend_fwd" else (OPS_PER_EVAL_BWD * st["evals_bwd"])
+            ach = ops / avg_s / 1e12
+            roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                        "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": traffic,
+                        "hbm_GBs": stage_report[dom]["hbm_GBs"],
+                        "hbm_frac": round(stage_report[dom]["hbm_GBs"] / HBM_PEAK_GBS, 4)}
+        else:
+            ach = stage_report[dom]["hbm_GBs"]
+            roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+    wl_name = {"tiny": "2k Gaussians, 1x128x128, SH0", "single": "200k Gaussians, 1x1296x840, SH3",
+               "sweep": "1M Gaussians, 1x1600x1060, SH3", "sweep_half": "1M Gaussians (scales x0.5), 1x1600x1060, SH3",
+               "batched": "3M Gaussians, 8 views (2x486x324, 3x972x648, 3x1944x1296), SH3",
+               "diff": "6M Gaussians, 4x1920x1080, SH3"}[args.workload]
+    result = {
+        "metric": METRIC, "value": round(iters, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl_name, "gaussians": n, "views": V, "tile": f"{tile[0]}x{tile[1]}",
+                   "lds_batch": args.lds, "sh_storage": "bf16" if bf16 else "f32",
+                   "mode": "graph" if args.graph else "plain", "loss": "L1 + 0.015 L_E"},
+        "pairs_per_s": round(st["pairs"] / sec, 1), "pairs": st["pairs"], "mean_list_len": round(st["mean_len"], 2),
+        "p99_list_len": st["p99_len"], "evals_fwd": st["evals_fwd"], "evals_bwd": st["evals_bwd"],
+        "overflow": st["overflow"], "stages": stage_report, "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(scene, cams, tile, targets_np)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

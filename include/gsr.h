@@ -1,0 +1,238 @@
+/*
+ * gsr.h — C ABI of the MI355X (gfx950) differentiable Gaussian-splat
+ * rasterizer with the per-ray entropy constraint on alpha-blending weights.
+ *
+ * The library computes, on the GPU, the forward and backward of
+ *   - the EWA projection of 3D Gaussians to 2D conics, radii and SH colour
+ *     (Sec. 3, Eq. 1-2),
+ *   - tile-based front-to-back alpha blending (Sec. 3, Eq. 3-5),
+ *   - the per-pixel entropy of the blending weights, background included,
+ *     and its per-view mean (Sec. 3.3, Eq. 8-11),
+ *   - the gradient of L = L_base + gamma L_E with respect to every Gaussian
+ *     attribute (Sec. 3.4, Eq. 12-15, Alg. 1, Suppl. B-C).
+ * L_base and gamma stay with the caller: the backward takes dL/dC per pixel,
+ * dL/dH per pixel and dL/dL_E per view.
+ *
+ * Conventions (defaults; each is a flag):
+ *   - OpenCV camera axes (x right, y down, z forward), world->camera R, t;
+ *     pixel (px, py) has its centre at (px + 0.5, py + 0.5);
+ *   - 2D covariance dilated by 0.3 on the diagonal (GSR_DILATE);
+ *   - x/z and y/z clamped to 1.3x the half field of view inside the EWA
+ *     Jacobian only (GSR_JACOBIAN_CLAMP);
+ *   - colour = sum_k sh_k Y_k(dir) + 0.5, clamped at 0 (GSR_COLOR_CLAMP),
+ *     with Y_k the real SH without the Condon-Shortley phase, k = l*l+l+m;
+ *   - Gaussians with camera z <= near_z, det <= 0 or non-finite inputs are
+ *     culled; alpha = min(0.99, opacity * g); alpha < 1/255 is skipped;
+ *     the first Gaussian that would take T below 1e-4 ends the ray and is
+ *     not blended; black background;
+ *   - radius = ceil(3 sqrt(lambda_max)); a Gaussian is listed in every tile
+ *     that meets [mean - radius, mean + radius] in x and y; each tile list is
+ *     ordered by (float32 camera depth, Gaussian index).
+ *
+ * Memory: every pointer in gsr_gaussians, gsr_fwd_out and gsr_grads is a
+ * DEVICE pointer owned by the caller, and must be 4-byte aligned (rgb and
+ * params) on the device the context was created on.  Camera arrays and
+ * statistics outputs are HOST pointers.  The context owns its scratch (pair
+ * keys and lists, tile ranges, projected records, 2D gradient accumulators).
+ *
+ * Errors: argument errors return before any GPU work is enqueued and leave
+ * outputs untouched.  GSR_ERR_HIP wraps a HIP runtime failure (text in
+ * gsr_last_error).  No C++ exception crosses this interface.
+ *
+ * Streams: all work is enqueued on the given stream (NULL = default stream);
+ * calls return without synchronising except where stated.  A context is not
+ * thread-safe and must be used from one host thread at a time.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSR_OK = 0,
+    GSR_ERR_INVALID_ARG = 1,   /* bad pointer, size, enum value or shape */
+    GSR_ERR_UNSUPPORTED = 2,   /* valid but not implemented (tile shape, SH degree) */
+    GSR_ERR_CAPACITY = 3,      /* pair count exceeded a fixed capacity (graph mode) */
+    GSR_ERR_HIP = 4,           /* HIP runtime error */
+    GSR_ERR_STALE_FRAME = 5,   /* backward called with a frame a newer forward replaced */
+    GSR_ERR_OOM = 6            /* device allocation failed */
+} gsr_status;
+
+/* Pinhole camera.  Projection of camera-space (x, y, z):
+ *   u = fx x / z + cx,  v = fy y / z + cy  (pixels). */
+typedef struct {
+    int32_t width, height;     /* 1 .. 32767 */
+    float fx, fy, cx, cy;
+    float R[9];                /* world -> camera rotation, row-major */
+    float t[3];                /* world -> camera translation: x_cam = R x + t */
+    float near_z;              /* cull z <= near_z (0.2 is the usual value) */
+} gsr_camera;
+
+/* option flags */
+#define GSR_DILATE          1u   /* +0.3 on the 2D covariance diagonal */
+#define GSR_JACOBIAN_CLAMP  2u   /* 1.3x field-of-view clamp inside the EWA Jacobian */
+#define GSR_COLOR_CLAMP     4u   /* clamp colour at 0 */
+#define GSR_GRAPH           8u   /* capture forward / backward into HIP graphs and replay them;
+                                    fixed pair capacity, no host synchronisation */
+#define GSR_PERSISTENT     16u   /* persistent blend kernels over a tile queue ordered by list length */
+#define GSR_DEFAULT_FLAGS  (GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP)
+
+typedef struct {
+    int32_t tile_w, tile_h;    /* {8,8}, {16,16} or {32,8} */
+    int32_t lds_batch;         /* Gaussians staged per LDS batch: 32, 64, 128, 256; 0 = 64 */
+    int32_t sh_degree;         /* 0 .. 3; K = (sh_degree + 1)^2 coefficients per channel */
+    int32_t sh_dtype;          /* 0 = float32, 1 = bfloat16 (SH storage and SH gradients) */
+    uint32_t flags;            /* GSR_* flags */
+} gsr_opts;
+
+/* Gaussian parameters (device, caller-owned, read-only to the library).
+ * means [n][3], scales [n][3] (activated, > 0), quats [n][4] (w, x, y, z;
+ * normalised inside), opacities [n] (activated, in (0, 1)),
+ * sh [n][K][3] float or bfloat16 per gsr_opts.sh_dtype. */
+typedef struct {
+    int64_t n;
+    const float* means;
+    const float* scales;
+    const float* quats;
+    const float* opacities;
+    const void* sh;
+} gsr_gaussians;
+
+/* Forward outputs (device, caller-owned).  Views are packed back to back:
+ * view v's pixels start at pixel offset gsr_pixel_offsets(...)[v], row-major.
+ *   rgb [P][3], entropy [P] (H_j, Eq. 10), t_final [P] (T after the last
+ *   blended Gaussian), n_contrib [P] (list positions up to and including the
+ *   last blended Gaussian), entropy_mean [n_views] (L_E per view, Eq. 11).
+ * t_final and n_contrib are the per-pixel state the backward needs; nothing
+ * is saved per Gaussian-pixel pair.  frame_id is written by gsr_forward. */
+typedef struct {
+    float* rgb;
+    float* entropy;
+    float* t_final;
+    int32_t* n_contrib;
+    float* entropy_mean;
+    int64_t frame_id;
+} gsr_fwd_out;
+
+/* Parameter gradients (device, caller-owned, overwritten), same layouts as
+ * gsr_gaussians; sh gradients in the SH dtype. */
+typedef struct {
+    float* means;
+    float* scales;
+    float* quats;
+    float* opacities;
+    void* sh;
+} gsr_grads;
+
+typedef struct gsr_ctx gsr_ctx;
+
+const char* gsr_status_string(gsr_status s);
+
+/* Text of the last error on this context (never NULL). */
+const char* gsr_last_error(const gsr_ctx* ctx);
+
+/* Create a context on the current HIP device.  max_views bounds n_views of
+ * later calls (1..64).  pair_capacity: 0 = grow on demand (plain mode);
+ * > 0 = initial capacity (used as is in graph mode). */
+gsr_status gsr_create(gsr_ctx** out, int32_t max_views, int64_t pair_capacity);
+gsr_status gsr_destroy(gsr_ctx* ctx);
+
+/* Pixel offsets of the packed per-view outputs: offsets[v] = sum of
+ * width*height of views < v; offsets[n_views] = total.  Host arrays. */
+gsr_status gsr_pixel_offsets(const gsr_camera* cams, int32_t n_views, int64_t* offsets);
+
+/* Render n_views cameras (host array) and their entropy (Sec. 3, Eq. 3-5,
+ * 8-11).  In plain mode the call synchronises once on `stream` to size the
+ * pair buffers; with GSR_GRAPH it never synchronises. */
+gsr_status gsr_forward(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
+                       int32_t n_views, const gsr_opts* opts, gsr_fwd_out* out);
+
+/* Gradients of a loss of the forward outputs (Sec. 3.4, Eq. 13-15, Alg. 1,
+ * Suppl. C): grad_rgb [P][3] = dL/dC, grad_entropy [P] = dL/dH_j (may be
+ * NULL), grad_entropy_mean [n_views] = dL/dL_E,v (device, may be NULL).
+ * `saved` must be the gsr_fwd_out of the latest gsr_forward on this context
+ * with the same gaussians, cameras and options. */
+gsr_status gsr_backward(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
+                        int32_t n_views, const gsr_opts* opts, const gsr_fwd_out* saved,
+                        const float* grad_rgb, const float* grad_entropy, const float* grad_entropy_mean,
+                        gsr_grads* grads);
+
+/* L1 term of the base loss (Sec. 3, Eq. 6 with lambda = 0) on the packed
+ * images of the latest forward's cameras (cams must have the same sizes):
+ *   grad_rgb [P][3] = sign(rgb - target) / (3 M_v)   (device, may be NULL),
+ *   loss [n_views]  = mean over 3 M_v of |rgb - target| (device, may be NULL).
+ * rgb and target are device [P][3]. */
+gsr_status gsr_l1_loss(gsr_ctx* ctx, void* stream, const gsr_camera* cams, int32_t n_views, const float* rgb,
+                       const float* target, float* grad_rgb, float* loss);
+
+/* Statistics of the latest forward. */
+typedef struct {
+    int64_t pairs;             /* (tile, Gaussian) pairs over all views */
+    double mean_len;           /* mean per-tile list length over all tiles */
+    int32_t p99_len;           /* 99th percentile of the per-tile list length; -1 if above 4095 */
+    int32_t overflow;          /* 1 if a fixed pair capacity was exceeded: that forward is invalid */
+    int64_t evals_fwd;         /* alpha evaluations of the forward blend: per pixel, the list
+                                  positions visited until the ray stopped or the list ended */
+    int64_t evals_bwd;         /* list positions the backward walks: the sum of n_contrib */
+} gsr_frame_stats;
+
+/* Fills `out` (host) and pairs_per_view [n_views] (host, may be NULL) for
+ * the latest forward on this context; synchronises `stream`. */
+gsr_status gsr_stats(gsr_ctx* ctx, void* stream, int64_t* pairs_per_view, gsr_frame_stats* out);
+
+/* Per-stage GPU timing.  While enabled (plain mode only; ignored for
+ * GSR_GRAPH), every stage of gsr_forward / gsr_backward is bracketed by HIP
+ * events on the caller's stream.  gsr_stage_times synchronises the device,
+ * adds the elapsed milliseconds of each stage since the last reset into
+ * total_ms[GSR_N_STAGES] and the number of timed launches into
+ * launches[GSR_N_STAGES] (host arrays), and resets if `reset` is non-zero. */
+typedef enum {
+    GSR_STAGE_PROJECT = 0,     /* EWA projection, SH colour, tile rectangles */
+    GSR_STAGE_DEPTH_SORT = 1,  /* LSD radix passes over the depth keys of all (view, Gaussian) */
+    GSR_STAGE_SCAN = 2,        /* prefix sum of tiles touched, in depth order */
+    GSR_STAGE_DUPLICATE = 3,   /* (tile, Gaussian) pair emission */
+    GSR_STAGE_TILE_SORT = 4,   /* stable LSD radix passes over the tile digits of the pairs */
+    GSR_STAGE_RANGES = 5,      /* per-tile [start, end) */
+    GSR_STAGE_BLEND_FWD = 6,   /* front-to-back blend with entropy */
+    GSR_STAGE_ENTROPY_MEAN = 7,/* per-view mean entropy */
+    GSR_STAGE_BLEND_BWD = 8,   /* back-to-front blend backward with Alg. 1 */
+    GSR_STAGE_PROJECT_BWD = 9, /* projection backward, sum over views */
+    GSR_N_STAGES = 10
+} gsr_stage;
+
+gsr_status gsr_set_timing(gsr_ctx* ctx, int32_t enable);
+gsr_status gsr_stage_times(gsr_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);
+
+/* Time forward+backward for every tile shape in {8x8, 16x16, 32x8} and
+ * LDS batch in {32, 64, 128, 256} on the given inputs, and write the fastest
+ * into inout->tile_w/tile_h/lds_batch.  If cache_path is not NULL the result
+ * is read from / appended to that text file, keyed by device and workload.
+ * Synchronises `stream`.  Note the image depends on the tile shape. */
+gsr_status gsr_autotune(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
+                        int32_t n_views, gsr_opts* inout, const char* cache_path);
+
+/* Internal buffers of the latest forward/backward, copied to host memory
+ * (synchronises `stream`); for stage-by-stage testing.  *bytes receives the
+ * size of the buffer; dst may be NULL to query it. */
+typedef enum {
+    GSR_BUF_RECORDS = 0,       /* float[V*n][12]: mean x, y, conic A, B, C, opacity, r, g, b, 0, 0, 0 */
+    GSR_BUF_RADIUS = 1,        /* int32[V*n], 0 = culled */
+    GSR_BUF_DEPTH = 2,         /* float[V*n], camera z */
+    GSR_BUF_TILES_TOUCHED = 3, /* int32[V*n] */
+    GSR_BUF_PAIR_VALUES = 4,   /* uint32[P]: view*n + Gaussian index, sorted by (tile, depth, index) */
+    GSR_BUF_PAIR_TILES = 5,    /* uint32[P]: global tile id of each sorted pair */
+    GSR_BUF_RANGES = 6,        /* uint32[n_tiles_total][2] = [start, end) */
+    GSR_BUF_GRAD2D = 7         /* float[V*n][9]: dL/d mean x, y, conic A, B, C, opacity, r, g, b */
+} gsr_buffer;
+
+gsr_status gsr_inspect(gsr_ctx* ctx, void* stream, gsr_buffer which, void* dst, int64_t capacity_bytes,
+                       int64_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSR_H */

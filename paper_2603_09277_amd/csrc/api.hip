@@ -1,0 +1,887 @@
+// C ABI of the rasterizer (include/gsr.h): context, argument validation,
+// buffer planning, the forward / backward launch sequences, statistics,
+// buffer inspection, HIP-graph capture and the tile-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gsr.h"
+#include "internal.h"
+
+using namespace gsr;
+
+namespace {
+
+struct Dev {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct FrameKey {
+    const void* ptrs[5] = {};
+    int64_t n = 0;
+    int32_t n_views = 0;
+    gsr_opts opts = {};
+    std::vector<int32_t> wh;
+    const void* outs[5] = {};
+    bool operator==(const FrameKey& o) const
+    {
+        return std::memcmp(ptrs, o.ptrs, sizeof ptrs) == 0 && n == o.n && n_views == o.n_views &&
+               std::memcmp(&opts, &o.opts, sizeof opts) == 0 && wh == o.wh && std::memcmp(outs, o.outs, sizeof outs) == 0;
+    }
+};
+
+struct Layout {
+    std::vector<CamDev> cams;
+    uint32_t n_tiles = 0, n_blocks = 0;
+    int64_t n_pix = 0;
+    int tsx = 0, tsy = 0;
+};
+
+}  // namespace
+
+struct gsr_ctx {
+    int device = 0;
+    int32_t max_views = 1;
+    std::string err;
+
+    // grow-only device buffers
+    Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
+    Dev pk0, pk1, pv0, pv1, ranges, block_H, block_cnt, counters, len_hist, view_pairs, l1_tmp;
+    size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
+    uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
+    uint64_t gen_fwd = 0, gen_bwd = 0;
+    bool pair_cap_fixed = false;
+
+    uint32_t* counters_host = nullptr;     // pinned: [0] total pairs, [1] overflow
+    CamDev* cams_host = nullptr;           // pinned staging for graph replays
+
+    // latest forward
+    int64_t frame = 0;
+    bool have_frame = false;
+    Layout lay;
+    uint32_t vn = 0, n = 0, pairs = 0;
+    int sorted_buf = 0;                    // which pair buffer holds the sorted lists
+    int n_views = 0;
+    gsr_opts fopts = {};
+
+    // graphs
+    hipGraphExec_t gexec_fwd = nullptr, gexec_bwd = nullptr;
+    FrameKey key_fwd, key_bwd;
+    const float* key_bwd_grads[3] = {};
+    void* key_bwd_outs[5] = {};
+    hipEvent_t ev_replay = nullptr;
+    bool replay_pending = false;
+
+    // per-stage timing (plain mode)
+    bool timing = false;
+    struct Timed { int stage; hipEvent_t a, b; };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> ev_pool;
+    double stage_ms[GSR_N_STAGES] = {};
+    int64_t stage_n[GSR_N_STAGES] = {};
+};
+
+namespace {
+
+gsr_status fail(gsr_ctx* c, gsr_status s, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+hipEvent_t pool_event(gsr_ctx* c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one stage with HIP events on the launch stream when timing is on.
+struct StageTimer {
+    gsr_ctx* c;
+    hipStream_t st;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageTimer(gsr_ctx* c_, hipStream_t st_, int stage_, bool on) : c(c_), st(st_), stage(stage_)
+    {
+        if (on && c->timing) {
+            a = pool_event(c);
+            if (a && hipEventRecord(a, st) != hipSuccess) { c->ev_pool.push_back(a); a = nullptr; }
+        }
+    }
+    void stop()
+    {
+        if (!a) return;
+        hipEvent_t b = pool_event(c);
+        if (b && hipEventRecord(b, st) == hipSuccess) c->timed.push_back({ stage, a, b });
+        else { c->ev_pool.push_back(a); if (b) c->ev_pool.push_back(b); }
+        a = nullptr;
+    }
+    ~StageTimer() { stop(); }
+};
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return fail((ctx), GSR_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+gsr_status grow(gsr_ctx* c, Dev& d, size_t bytes)
+{
+    if (bytes <= d.bytes) return GSR_OK;
+    if (d.p) {
+        hipError_t e = hipFree(d.p);
+        d.p = nullptr;
+        d.bytes = 0;
+        if (e != hipSuccess) return fail(c, GSR_ERR_HIP, std::string("hipFree: ") + hipGetErrorString(e));
+    }
+    size_t b = std::max<size_t>(bytes, 256);
+    ++c->gen;
+    hipError_t e = hipMalloc(&d.p, b);
+    if (e != hipSuccess) {
+        d.p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, GSR_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    }
+    d.bytes = b;
+    return GSR_OK;
+}
+
+void free_dev(Dev& d)
+{
+    if (d.p) (void)hipFree(d.p);
+    d.p = nullptr;
+    d.bytes = 0;
+}
+
+int ilog2(int v)
+{
+    int s = 0;
+    while ((1 << s) < v) ++s;
+    return s;
+}
+
+bool tile_ok(int w, int h) { return (w == 8 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 8); }
+
+gsr_status validate(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cams, int32_t n_views, const gsr_opts* o)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    if (!g || !cams || !o) return fail(c, GSR_ERR_INVALID_ARG, "null gaussians, cameras or options");
+    if (n_views < 1 || n_views > c->max_views) return fail(c, GSR_ERR_INVALID_ARG, "n_views out of range");
+    if (g->n < 0 || g->n > 0x7fffffffLL) return fail(c, GSR_ERR_INVALID_ARG, "gaussian count out of range");
+    if ((int64_t)g->n * n_views >= 0xffffffffLL) return fail(c, GSR_ERR_INVALID_ARG, "views x gaussians exceeds 2^32");
+    if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacities || !g->sh))
+        return fail(c, GSR_ERR_INVALID_ARG, "null gaussian parameter pointer");
+    const void* ps[5] = { g->means, g->scales, g->quats, g->opacities, g->sh };
+    for (const void* p : ps)
+        if (((uintptr_t)p) & 3u) return fail(c, GSR_ERR_INVALID_ARG, "parameter pointer not 4-byte aligned");
+    if (o->sh_degree < 0 || o->sh_degree > 3) return fail(c, GSR_ERR_UNSUPPORTED, "sh_degree must be 0..3");
+    if (o->sh_dtype != 0 && o->sh_dtype != 1) return fail(c, GSR_ERR_INVALID_ARG, "sh_dtype must be 0 or 1");
+    if (!tile_ok(o->tile_w, o->tile_h)) return fail(c, GSR_ERR_UNSUPPORTED, "tile shape must be 8x8, 16x16 or 32x8");
+    int lb = o->lds_batch == 0 ? 64 : o->lds_batch;
+    if (lb != 32 && lb != 64 && lb != 128 && lb != 256) return fail(c, GSR_ERR_UNSUPPORTED, "lds_batch must be 32, 64, 128 or 256");
+    if (o->flags & ~(uint32_t)(GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP | GSR_GRAPH | GSR_PERSISTENT))
+        return fail(c, GSR_ERR_INVALID_ARG, "unknown flag bits");
+    uint64_t tiles = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const gsr_camera& k = cams[v];
+        if (k.width < 1 || k.height < 1 || k.width > 32767 || k.height > 32767)
+            return fail(c, GSR_ERR_INVALID_ARG, "camera size out of range");
+        if (!(std::isfinite(k.fx) && std::isfinite(k.fy) && k.fx > 0.f && k.fy > 0.f && std::isfinite(k.cx) &&
+              std::isfinite(k.cy)))
+            return fail(c, GSR_ERR_INVALID_ARG, "camera intrinsics must be finite with fx, fy > 0");
+        if (!(std::isfinite(k.near_z) && k.near_z > 0.f)) return fail(c, GSR_ERR_INVALID_ARG, "near_z must be > 0");
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(k.R[i])) return fail(c, GSR_ERR_INVALID_ARG, "camera rotation not finite");
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(k.t[i])) return fail(c, GSR_ERR_INVALID_ARG, "camera translation not finite");
+        tiles += (uint64_t)((k.width + o->tile_w - 1) / o->tile_w) * ((k.height + o->tile_h - 1) / o->tile_h);
+    }
+    if (tiles >= (1ull << 24)) return fail(c, GSR_ERR_UNSUPPORTED, "more than 2^24 tiles in one launch");
+    return GSR_OK;
+}
+
+Layout make_layout(const gsr_camera* cams, int32_t n_views, const gsr_opts* o)
+{
+    Layout L;
+    L.tsx = ilog2(o->tile_w);
+    L.tsy = ilog2(o->tile_h);
+    uint32_t tb = 0, bb = 0;
+    int64_t pb = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const gsr_camera& k = cams[v];
+        CamDev d;
+        std::memset(&d, 0, sizeof d);
+        d.W = k.width; d.H = k.height;
+        d.fx = k.fx; d.fy = k.fy; d.cx = k.cx; d.cy = k.cy;
+        for (int i = 0; i < 9; ++i) d.R[i] = k.R[i];
+        for (int i = 0; i < 3; ++i) d.t[i] = k.t[i];
+        d.near_z = k.near_z;
+        for (int i = 0; i < 3; ++i)
+            d.campos[i] = -(k.R[0 + i] * k.t[0] + k.R[3 + i] * k.t[1] + k.R[6 + i] * k.t[2]);
+        d.limx_d = 1.3 * (0.5 * (double)k.width / (double)k.fx);
+        d.limy_d = 1.3 * (0.5 * (double)k.height / (double)k.fy);
+        d.limx = (float)d.limx_d;
+        d.limy = (float)d.limy_d;
+        d.gx = (k.width + o->tile_w - 1) / o->tile_w;
+        d.gy = (k.height + o->tile_h - 1) / o->tile_h;
+        d.tile_base = tb;
+        d.bx = (k.width + kBlockPx - 1) / kBlockPx;
+        d.by = (k.height + kBlockPx - 1) / kBlockPx;
+        d.block_base = bb;
+        d.pix_base = pb;
+        tb += (uint32_t)(d.gx * d.gy);
+        bb += (uint32_t)(d.bx * d.by);
+        pb += (int64_t)k.width * k.height;
+        L.cams.push_back(d);
+    }
+    L.n_tiles = tb;
+    L.n_blocks = bb;
+    L.n_pix = pb;
+    return L;
+}
+
+gsr_status ensure_vn(gsr_ctx* c, uint32_t vn)
+{
+    size_t v = std::max<size_t>(vn, 1);
+    if (v <= c->vn_cap) return GSR_OK;
+    v = std::max(v, c->vn_cap + c->vn_cap / 4);
+    gsr_status s;
+    if ((s = grow(c, c->rec, v * 48)) || (s = grow(c, c->dkey0, v * 4)) || (s = grow(c, c->dkey1, v * 4)) ||
+        (s = grow(c, c->ord0, v * 4)) || (s = grow(c, c->ord1, v * 4)) || (s = grow(c, c->rect, v * 8)) ||
+        (s = grow(c, c->tt, v * 4)) || (s = grow(c, c->radius, v * 4)) || (s = grow(c, c->depth, v * 4)) ||
+        (s = grow(c, c->offsets, v * 4)) || (s = grow(c, c->grad2d, v * 4 * kG2)) ||
+        (s = grow(c, c->scan_tmp, scan_tmp_words((uint32_t)v) * 4)))
+        return s;
+    c->vn_cap = v;
+    return GSR_OK;
+}
+
+gsr_status ensure_pairs(gsr_ctx* c, size_t p)
+{
+    p = std::max<size_t>(p, 1);
+    if (p <= c->pair_cap) return GSR_OK;
+    if (p >= 0xfffffff0ull) return fail(c, GSR_ERR_CAPACITY, "pair count exceeds 2^32");
+    gsr_status s;
+    if ((s = grow(c, c->pk0, p * 4)) || (s = grow(c, c->pk1, p * 4)) || (s = grow(c, c->pv0, p * 4)) ||
+        (s = grow(c, c->pv1, p * 4)))
+        return s;
+    c->pair_cap = p;
+    return GSR_OK;
+}
+
+gsr_status ensure_radix_tmp(gsr_ctx* c, size_t items)
+{
+    return grow(c, c->radix_tmp, radix_tmp_words((uint32_t)std::max<size_t>(items, 1)) * 4);
+}
+
+gsr_status ensure_tiles(gsr_ctx* c, uint32_t tiles, uint32_t blocks)
+{
+    gsr_status s;
+    if ((s = grow(c, c->ranges, (size_t)std::max<uint32_t>(tiles, 1) * 8)) ||
+        (s = grow(c, c->block_H, (size_t)std::max<uint32_t>(blocks, 1) * 4)) ||
+        (s = grow(c, c->block_cnt, (size_t)std::max<uint32_t>(blocks, 1) * 8)))
+        return s;
+    return GSR_OK;
+}
+
+// everything of the forward after the camera upload; `plain` = read the pair
+// count back and size the pair buffers exactly (one host synchronisation)
+gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, const gsr_opts* o, gsr_fwd_out* out,
+                           bool plain)
+{
+    const Layout& L = c->lay;
+    const uint32_t n = (uint32_t)g->n, V = (uint32_t)L.cams.size(), vn = n * V;
+    const CamDev* dc = (const CamDev*)c->cams.p;
+    uint32_t* counters = (uint32_t*)c->counters.p;
+    HIP_TRY(c, launch_fill_u32(counters, 0u, 2, st));
+
+    ProjectFwdArgs pa;
+    pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
+    pa.n = n; pa.n_views = (int32_t)V; pa.flags = o->flags; pa.tile_shift_x = L.tsx; pa.tile_shift_y = L.tsy;
+    pa.cams = dc;
+    pa.rec = (float4*)c->rec.p; pa.depth_key = (uint32_t*)c->dkey0.p; pa.rect = (uint2*)c->rect.p;
+    pa.tiles_touched = (uint32_t*)c->tt.p; pa.radius = (int32_t*)c->radius.p; pa.depth = (float*)c->depth.p;
+    {
+        StageTimer tm(c, st, GSR_STAGE_PROJECT, plain);
+        HIP_TRY(c, launch_project_fwd(pa, o->sh_degree, o->sh_dtype == 1, st));
+    }
+
+    // depth order of all (view, Gaussian) records: 4 LSD passes of 8 bits
+    uint32_t* dk[2] = { (uint32_t*)c->dkey0.p, (uint32_t*)c->dkey1.p };
+    uint32_t* od[2] = { (uint32_t*)c->ord0.p, (uint32_t*)c->ord1.p };
+    {
+        StageTimer tm(c, st, GSR_STAGE_DEPTH_SORT, plain);
+        HIP_TRY(c, launch_iota_u32(od[0], vn, st));
+        for (int pass = 0; pass < 4; ++pass)
+            HIP_TRY(c, launch_radix_pass(dk[pass & 1], od[pass & 1], dk[(pass + 1) & 1], od[(pass + 1) & 1], nullptr,
+                                         vn, 8 * pass, (uint32_t*)c->radix_tmp.p, st));
+    }
+    // offsets of each record's pairs in depth order; total pair count
+    {
+        StageTimer tm(c, st, GSR_STAGE_SCAN, plain);
+        HIP_TRY(c, launch_gather_scan((const uint32_t*)c->tt.p, od[0], vn, (uint32_t*)c->offsets.p, counters,
+                                      counters + 1, (uint32_t*)c->scan_tmp.p, st));
+    }
+    uint32_t cap;
+    if (plain) {
+        HIP_TRY(c, hipMemcpyAsync(c->counters_host, counters, 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        if (c->counters_host[1]) return fail(c, GSR_ERR_CAPACITY, "pair count exceeds 2^32");
+        uint32_t P = c->counters_host[0];
+        gsr_status s;
+        if ((s = ensure_pairs(c, P)) || (s = ensure_radix_tmp(c, std::max<size_t>(P, vn)))) return s;
+        cap = P;
+    } else {
+        cap = (uint32_t)c->pair_cap;
+    }
+    uint32_t* pk[2] = { (uint32_t*)c->pk0.p, (uint32_t*)c->pk1.p };
+    uint32_t* pv[2] = { (uint32_t*)c->pv0.p, (uint32_t*)c->pv1.p };
+    {
+        StageTimer tm(c, st, GSR_STAGE_DUPLICATE, plain);
+        HIP_TRY(c, launch_duplicate(od[0], (const uint32_t*)c->offsets.p, (const uint32_t*)c->tt.p,
+                                    (const uint2*)c->rect.p, dc, n, vn, counters, cap, pk[0], pv[0], counters + 1, st));
+    }
+    // stable sort of the pairs by tile id
+    int tile_bits = std::max(1, ilog2((int)std::max<uint32_t>(L.n_tiles, 2)));
+    int passes = (tile_bits + 7) / 8;
+    {
+        StageTimer tm(c, st, GSR_STAGE_TILE_SORT, plain);
+        for (int pass = 0; pass < passes; ++pass)
+            HIP_TRY(c, launch_radix_pass(pk[pass & 1], pv[pass & 1], pk[(pass + 1) & 1], pv[(pass + 1) & 1], counters,
+                                         cap, 8 * pass, (uint32_t*)c->radix_tmp.p, st));
+    }
+    const int sb = passes & 1;
+    {
+        StageTimer tm(c, st, GSR_STAGE_RANGES, plain);
+        HIP_TRY(c, launch_fill_u32((uint32_t*)c->ranges.p, 0u, (size_t)L.n_tiles * 2, st));
+        HIP_TRY(c, launch_ranges(pk[sb], counters, cap, (uint2*)c->ranges.p, st));
+    }
+
+    BlendFwdArgs ba;
+    ba.rec = (const float4*)c->rec.p; ba.pair_vals = pv[sb]; ba.ranges = (const uint2*)c->ranges.p; ba.cams = dc;
+    ba.n_views = (int32_t)V; ba.tile_shift_x = L.tsx; ba.tile_shift_y = L.tsy; ba.n_blocks = L.n_blocks;
+    ba.out_rgb = out->rgb; ba.out_H = out->entropy; ba.out_T = out->t_final; ba.out_nc = out->n_contrib;
+    ba.block_H = (float*)c->block_H.p;
+    ba.block_cnt = (uint2*)c->block_cnt.p;
+    {
+        StageTimer tm(c, st, GSR_STAGE_BLEND_FWD, plain);
+        HIP_TRY(c, launch_blend_fwd(ba, o->lds_batch == 0 ? 64 : o->lds_batch, st));
+    }
+    {
+        StageTimer tm(c, st, GSR_STAGE_ENTROPY_MEAN, plain);
+        HIP_TRY(c, launch_entropy_mean((const float*)c->block_H.p, dc, (int)V, out->entropy_mean, st));
+    }
+    c->sorted_buf = sb;
+    c->pairs = plain ? cap : 0;
+    return GSR_OK;
+}
+
+gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, const gsr_opts* o,
+                            const gsr_fwd_out* saved, const float* grad_rgb, const float* grad_H, const float* grad_LE,
+                            gsr_grads* gr, bool plain)
+{
+    const Layout& L = c->lay;
+    const uint32_t n = (uint32_t)g->n, V = (uint32_t)L.cams.size(), vn = n * V;
+    const CamDev* dc = (const CamDev*)c->cams.p;
+    StageTimer tb(c, st, GSR_STAGE_BLEND_BWD, plain);
+    HIP_TRY(c, launch_fill_u32((uint32_t*)c->grad2d.p, 0u, (size_t)vn * kG2, st));
+    uint32_t* pv[2] = { (uint32_t*)c->pv0.p, (uint32_t*)c->pv1.p };
+    BlendBwdArgs bb;
+    bb.rec = (const float4*)c->rec.p; bb.pair_vals = pv[c->sorted_buf]; bb.ranges = (const uint2*)c->ranges.p;
+    bb.cams = dc; bb.n_views = (int32_t)V; bb.tile_shift_x = L.tsx; bb.tile_shift_y = L.tsy; bb.n_blocks = L.n_blocks;
+    bb.T_final = saved->t_final; bb.n_contrib = saved->n_contrib; bb.grad_rgb = grad_rgb; bb.grad_H = grad_H;
+    bb.grad_LE = grad_LE; bb.grad2d = (float*)c->grad2d.p;
+    HIP_TRY(c, launch_blend_bwd(bb, o->lds_batch == 0 ? 64 : o->lds_batch, st));
+    tb.stop();
+    StageTimer tp(c, st, GSR_STAGE_PROJECT_BWD, plain);
+    ProjectBwdArgs pa;
+    pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
+    pa.n = n; pa.n_views = (int32_t)V; pa.flags = o->flags; pa.cams = dc; pa.grad2d = (const float*)c->grad2d.p;
+    pa.g_means = gr->means; pa.g_scales = gr->scales; pa.g_quats = gr->quats; pa.g_opac = gr->opacities;
+    pa.g_sh = gr->sh;
+    HIP_TRY(c, launch_project_bwd(pa, o->sh_degree, o->sh_dtype == 1, st));
+    return GSR_OK;
+}
+
+FrameKey make_key(const gsr_gaussians* g, const gsr_camera* cams, int32_t nv, const gsr_opts* o, const void* outs[5])
+{
+    FrameKey k;
+    k.ptrs[0] = g->means; k.ptrs[1] = g->scales; k.ptrs[2] = g->quats; k.ptrs[3] = g->opacities; k.ptrs[4] = g->sh;
+    k.n = g->n;
+    k.n_views = nv;
+    k.opts = *o;
+    for (int v = 0; v < nv; ++v) { k.wh.push_back(cams[v].width); k.wh.push_back(cams[v].height); }
+    for (int i = 0; i < 5; ++i) k.outs[i] = outs[i];
+    return k;
+}
+
+void drop_graphs(gsr_ctx* c)
+{
+    if (c->gexec_fwd) (void)hipGraphExecDestroy(c->gexec_fwd);
+    if (c->gexec_bwd) (void)hipGraphExecDestroy(c->gexec_bwd);
+    c->gexec_fwd = nullptr;
+    c->gexec_bwd = nullptr;
+}
+
+gsr_status wait_replay(gsr_ctx* c)
+{
+    if (c->replay_pending) {
+        HIP_TRY(c, hipEventSynchronize(c->ev_replay));
+        c->replay_pending = false;
+    }
+    return GSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gsr_status_string(gsr_status s)
+{
+    switch (s) {
+        case GSR_OK: return "ok";
+        case GSR_ERR_INVALID_ARG: return "invalid argument";
+        case GSR_ERR_UNSUPPORTED: return "unsupported";
+        case GSR_ERR_CAPACITY: return "pair capacity exceeded";
+        case GSR_ERR_HIP: return "HIP runtime error";
+        case GSR_ERR_STALE_FRAME: return "stale frame";
+        case GSR_ERR_OOM: return "out of device memory";
+    }
+    return "unknown status";
+}
+
+const char* gsr_last_error(const gsr_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+gsr_status gsr_create(gsr_ctx** out, int32_t max_views, int64_t pair_capacity)
+{
+    if (!out || max_views < 1 || max_views > kMaxViews || pair_capacity < 0 || pair_capacity >= 0xfffffff0LL)
+        return GSR_ERR_INVALID_ARG;
+    *out = nullptr;
+    gsr_ctx* c = new (std::nothrow) gsr_ctx();
+    if (!c) return GSR_ERR_OOM;
+    c->max_views = max_views;
+    gsr_status s = GSR_OK;
+    if (hipGetDevice(&c->device) != hipSuccess) s = GSR_ERR_HIP;
+    if (!s) s = grow(c, c->cams, sizeof(CamDev) * (size_t)max_views);
+    if (!s) s = grow(c, c->counters, 64);
+    if (!s) s = grow(c, c->len_hist, 4 * 4097);
+    if (!s) s = grow(c, c->view_pairs, 8 * (size_t)max_views);
+    if (!s && hipHostMalloc((void**)&c->counters_host, 64, hipHostMallocDefault) != hipSuccess) s = GSR_ERR_HIP;
+    if (!s && hipHostMalloc((void**)&c->cams_host, sizeof(CamDev) * (size_t)max_views, hipHostMallocDefault) != hipSuccess)
+        s = GSR_ERR_HIP;
+    if (!s && hipEventCreateWithFlags(&c->ev_replay, hipEventDisableTiming) != hipSuccess) s = GSR_ERR_HIP;
+    if (!s && pair_capacity > 0) {
+        s = ensure_pairs(c, (size_t)pair_capacity);
+        if (!s) s = ensure_radix_tmp(c, (size_t)pair_capacity);
+        c->pair_cap_fixed = true;
+    }
+    if (s) {
+        gsr_destroy(c);
+        return s;
+    }
+    *out = c;
+    return GSR_OK;
+}
+
+gsr_status gsr_destroy(gsr_ctx* c)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    (void)hipDeviceSynchronize();
+    drop_graphs(c);
+    Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->radius,
+                   &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
+                   &c->pv1, &c->ranges, &c->block_H, &c->block_cnt, &c->counters, &c->len_hist, &c->view_pairs,
+                   &c->l1_tmp };
+    for (Dev* d : all) free_dev(*d);
+    for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->counters_host) (void)hipHostFree(c->counters_host);
+    if (c->cams_host) (void)hipHostFree(c->cams_host);
+    if (c->ev_replay) (void)hipEventDestroy(c->ev_replay);
+    delete c;
+    return GSR_OK;
+}
+
+gsr_status gsr_pixel_offsets(const gsr_camera* cams, int32_t n_views, int64_t* offsets)
+{
+    if (!cams || !offsets || n_views < 0) return GSR_ERR_INVALID_ARG;
+    int64_t acc = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if (cams[v].width < 1 || cams[v].height < 1) return GSR_ERR_INVALID_ARG;
+        offsets[v] = acc;
+        acc += (int64_t)cams[v].width * cams[v].height;
+    }
+    offsets[n_views] = acc;
+    return GSR_OK;
+}
+
+gsr_status gsr_forward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gsr_camera* cams, int32_t n_views,
+                       const gsr_opts* o, gsr_fwd_out* out)
+{
+    gsr_status s = validate(c, g, cams, n_views, o);
+    if (s) return s;
+    if (!out || !out->rgb || !out->entropy || !out->t_final || !out->n_contrib || !out->entropy_mean)
+        return fail(c, GSR_ERR_INVALID_ARG, "null forward output pointer");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if ((s = wait_replay(c))) return s;
+    Layout L = make_layout(cams, n_views, o);
+    const uint32_t n = (uint32_t)g->n, vn = n * (uint32_t)n_views;
+    if ((s = ensure_vn(c, vn)) || (s = ensure_tiles(c, L.n_tiles, L.n_blocks)) ||
+        (s = ensure_radix_tmp(c, std::max<size_t>(vn, c->pair_cap))))
+        return s;
+    c->lay = L;
+    c->n = n;
+    c->vn = vn;
+    c->n_views = n_views;
+    c->fopts = *o;
+    bool graph = (o->flags & GSR_GRAPH) != 0;
+    const void* outs[5] = { out->rgb, out->entropy, out->t_final, out->n_contrib, out->entropy_mean };
+    if (!graph) {
+        HIP_TRY(c, hipMemcpyAsync(c->cams.p, c->lay.cams.data(), sizeof(CamDev) * L.cams.size(), hipMemcpyHostToDevice, st));
+        if ((s = enqueue_forward(c, st, g, o, out, true))) return s;
+    } else {
+        // a pair capacity is needed before capture: measure once in plain mode
+        if (c->pair_cap <= 1) {
+            HIP_TRY(c, hipMemcpyAsync(c->cams.p, c->lay.cams.data(), sizeof(CamDev) * L.cams.size(), hipMemcpyHostToDevice, st));
+            if ((s = enqueue_forward(c, st, g, o, out, true))) return s;
+            size_t want = (size_t)c->pairs + c->pairs / 2 + 4096;
+            if ((s = ensure_pairs(c, want)) || (s = ensure_radix_tmp(c, std::max<size_t>(c->pair_cap, vn)))) return s;
+            drop_graphs(c);
+        }
+        FrameKey k = make_key(g, cams, n_views, o, outs);
+        if (c->gexec_fwd && (!(k == c->key_fwd) || c->gen != c->gen_fwd)) drop_graphs(c);
+        std::memcpy(c->cams_host, L.cams.data(), sizeof(CamDev) * L.cams.size());
+        if (!c->gexec_fwd) {
+            hipStream_t cs;
+            HIP_TRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipGraph_t graph_ = nullptr;
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                e = hipMemcpyAsync(c->cams.p, c->cams_host, sizeof(CamDev) * L.cams.size(), hipMemcpyHostToDevice, cs);
+                gsr_status fs = e == hipSuccess ? enqueue_forward(c, cs, g, o, out, false) : GSR_ERR_HIP;
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(c->counters_host, c->counters.p, 8, hipMemcpyDeviceToHost, cs);
+                hipError_t e2 = hipStreamEndCapture(cs, &graph_);
+                if (fs != GSR_OK && e == hipSuccess) e = hipErrorUnknown;
+                if (e == hipSuccess) e = e2;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec_fwd, graph_, nullptr, nullptr, 0);
+            if (graph_) (void)hipGraphDestroy(graph_);
+            (void)hipStreamDestroy(cs);
+            if (e != hipSuccess) {
+                c->gexec_fwd = nullptr;
+                return fail(c, GSR_ERR_HIP, std::string("forward graph capture: ") + hipGetErrorString(e));
+            }
+            c->key_fwd = k;
+            c->gen_fwd = c->gen;
+            if (c->gexec_bwd) { (void)hipGraphExecDestroy(c->gexec_bwd); c->gexec_bwd = nullptr; }
+        }
+        HIP_TRY(c, hipGraphLaunch(c->gexec_fwd, st));
+        HIP_TRY(c, hipEventRecord(c->ev_replay, st));
+        c->replay_pending = true;
+        c->pairs = 0;
+        int tile_bits = std::max(1, ilog2((int)std::max<uint32_t>(L.n_tiles, 2)));
+        c->sorted_buf = ((tile_bits + 7) / 8) & 1;
+    }
+    c->frame += 1;
+    c->have_frame = true;
+    out->frame_id = c->frame;
+    return GSR_OK;
+}
+
+gsr_status gsr_backward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gsr_camera* cams, int32_t n_views,
+                        const gsr_opts* o, const gsr_fwd_out* saved, const float* grad_rgb, const float* grad_entropy,
+                        const float* grad_entropy_mean, gsr_grads* gr)
+{
+    gsr_status s = validate(c, g, cams, n_views, o);
+    if (s) return s;
+    if (!saved || !saved->t_final || !saved->n_contrib || !grad_rgb || !gr)
+        return fail(c, GSR_ERR_INVALID_ARG, "null backward argument");
+    if (g->n > 0 && (!gr->means || !gr->scales || !gr->quats || !gr->opacities || !gr->sh))
+        return fail(c, GSR_ERR_INVALID_ARG, "null gradient output pointer");
+    if (!c->have_frame || saved->frame_id != c->frame)
+        return fail(c, GSR_ERR_STALE_FRAME, "backward does not match the latest forward of this context");
+    if ((uint32_t)g->n != c->n || n_views != c->n_views || std::memcmp(o, &c->fopts, sizeof *o) != 0)
+        return fail(c, GSR_ERR_INVALID_ARG, "backward gaussians, views or options differ from the forward");
+    Layout L = make_layout(cams, n_views, o);
+    for (int v = 0; v < n_views; ++v)
+        if (L.cams[v].W != c->lay.cams[v].W || L.cams[v].H != c->lay.cams[v].H)
+            return fail(c, GSR_ERR_INVALID_ARG, "backward camera sizes differ from the forward");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (!(o->flags & GSR_GRAPH))
+        return enqueue_backward(c, st, g, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, gr, true);
+
+    const void* outs[5] = { saved->rgb, saved->entropy, saved->t_final, saved->n_contrib, saved->entropy_mean };
+    FrameKey k = make_key(g, cams, n_views, o, outs);
+    void* gouts[5] = { gr->means, gr->scales, gr->quats, gr->opacities, gr->sh };
+    bool same = c->gexec_bwd && k == c->key_bwd && c->gen == c->gen_bwd && c->key_bwd_grads[0] == grad_rgb &&
+                c->key_bwd_grads[1] == grad_entropy && c->key_bwd_grads[2] == grad_entropy_mean &&
+                std::memcmp(gouts, c->key_bwd_outs, sizeof gouts) == 0;
+    if (!same) {
+        if (c->gexec_bwd) { (void)hipGraphExecDestroy(c->gexec_bwd); c->gexec_bwd = nullptr; }
+        hipStream_t cs;
+        HIP_TRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph_ = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            gsr_status bs = enqueue_backward(c, cs, g, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, gr, false);
+            hipError_t e2 = hipStreamEndCapture(cs, &graph_);
+            e = bs != GSR_OK ? hipErrorUnknown : e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec_bwd, graph_, nullptr, nullptr, 0);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            c->gexec_bwd = nullptr;
+            return fail(c, GSR_ERR_HIP, std::string("backward graph capture: ") + hipGetErrorString(e));
+        }
+        c->key_bwd = k;
+        c->gen_bwd = c->gen;
+        c->key_bwd_grads[0] = grad_rgb; c->key_bwd_grads[1] = grad_entropy; c->key_bwd_grads[2] = grad_entropy_mean;
+        std::memcpy(c->key_bwd_outs, gouts, sizeof gouts);
+    }
+    HIP_TRY(c, hipGraphLaunch(c->gexec_bwd, st));
+    return GSR_OK;
+}
+
+gsr_status gsr_stats(gsr_ctx* c, void* stream, int64_t* pairs_per_view, gsr_frame_stats* out)
+{
+    if (!c || !out) return GSR_ERR_INVALID_ARG;
+    if (!c->have_frame) return fail(c, GSR_ERR_INVALID_ARG, "no forward has run on this context");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int nb = 4097;
+    HIP_TRY(c, launch_fill_u32((uint32_t*)c->len_hist.p, 0u, nb, st));
+    HIP_TRY(c, launch_len_hist((const uint2*)c->ranges.p, c->lay.n_tiles, (uint32_t*)c->len_hist.p, nb, st));
+    HIP_TRY(c, launch_view_pairs((const uint2*)c->ranges.p, (const CamDev*)c->cams.p, c->n_views,
+                                 (uint64_t*)c->view_pairs.p, st));
+    std::vector<uint32_t> h(nb);
+    std::vector<uint64_t> vp(c->n_views);
+    std::vector<uint32_t> cnt2((size_t)c->lay.n_blocks * 2 + 2);
+    uint32_t cnt[2];
+    HIP_TRY(c, hipMemcpyAsync(h.data(), c->len_hist.p, 4 * nb, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(vp.data(), c->view_pairs.p, 8 * c->n_views, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(cnt, c->counters.p, 8, hipMemcpyDeviceToHost, st));
+    if (c->lay.n_blocks)
+        HIP_TRY(c, hipMemcpyAsync(cnt2.data(), c->block_cnt.p, (size_t)c->lay.n_blocks * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    c->replay_pending = false;
+    std::memset(out, 0, sizeof *out);
+    out->overflow = (cnt[1] != 0 || cnt[0] > c->pair_cap) ? 1 : 0;
+    uint64_t total = 0;
+    for (int v = 0; v < c->n_views; ++v) {
+        total += vp[v];
+        if (pairs_per_view) pairs_per_view[v] = (int64_t)vp[v];
+    }
+    out->pairs = (int64_t)total;
+    out->mean_len = c->lay.n_tiles ? (double)total / c->lay.n_tiles : 0.0;
+    uint64_t need = (uint64_t)std::ceil(0.99 * c->lay.n_tiles), acc = 0;
+    int32_t p = 0;
+    for (int b = 0; b < nb; ++b) {
+        acc += h[b];
+        if (acc >= need) { p = b; break; }
+    }
+    out->p99_len = (p == nb - 1) ? -1 : p;
+    for (uint32_t b = 0; b < c->lay.n_blocks; ++b) {
+        out->evals_fwd += cnt2[2 * b];
+        out->evals_bwd += cnt2[2 * b + 1];
+    }
+    c->pairs = cnt[0];
+    return GSR_OK;
+}
+
+gsr_status gsr_l1_loss(gsr_ctx* c, void* stream, const gsr_camera* cams, int32_t n_views, const float* rgb,
+                       const float* target, float* grad_rgb, float* loss)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    if (!cams || !rgb || !target) return fail(c, GSR_ERR_INVALID_ARG, "null l1 argument");
+    if (!c->have_frame || n_views != c->n_views) return fail(c, GSR_ERR_INVALID_ARG, "l1 views differ from the latest forward");
+    for (int v = 0; v < n_views; ++v)
+        if (cams[v].width != c->lay.cams[v].W || cams[v].height != c->lay.cams[v].H)
+            return fail(c, GSR_ERR_INVALID_ARG, "l1 camera sizes differ from the latest forward");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    gsr_status s = grow(c, c->l1_tmp, l1_tmp_doubles(c->lay.n_pix) * 8);
+    if (s) return s;
+    HIP_TRY(c, launch_l1(rgb, target, (const CamDev*)c->cams.p, n_views, c->lay.n_pix, grad_rgb, loss,
+                         (double*)c->l1_tmp.p, st));
+    return GSR_OK;
+}
+
+gsr_status gsr_set_timing(gsr_ctx* c, int32_t enable)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    c->timing = enable != 0;
+    return GSR_OK;
+}
+
+gsr_status gsr_stage_times(gsr_ctx* c, double* total_ms, int64_t* launches, int32_t reset)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    for (auto& t : c->timed) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            c->stage_ms[t.stage] += ms;
+            c->stage_n[t.stage] += 1;
+        }
+        c->ev_pool.push_back(t.a);
+        c->ev_pool.push_back(t.b);
+    }
+    c->timed.clear();
+    for (int k = 0; k < GSR_N_STAGES; ++k) {
+        if (total_ms) total_ms[k] = c->stage_ms[k];
+        if (launches) launches[k] = c->stage_n[k];
+    }
+    if (reset)
+        for (int k = 0; k < GSR_N_STAGES; ++k) { c->stage_ms[k] = 0.0; c->stage_n[k] = 0; }
+    return GSR_OK;
+}
+
+gsr_status gsr_inspect(gsr_ctx* c, void* stream, gsr_buffer which, void* dst, int64_t capacity_bytes, int64_t* bytes)
+{
+    if (!c || !bytes) return GSR_ERR_INVALID_ARG;
+    if (!c->have_frame) return fail(c, GSR_ERR_INVALID_ARG, "no forward has run on this context");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (c->pairs == 0) {
+        uint32_t cnt[2];
+        HIP_TRY(c, hipMemcpyAsync(cnt, c->counters.p, 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        c->pairs = std::min<uint32_t>(cnt[0], (uint32_t)c->pair_cap);
+    }
+    const void* src = nullptr;
+    size_t sz = 0;
+    uint32_t* pk[2] = { (uint32_t*)c->pk0.p, (uint32_t*)c->pk1.p };
+    uint32_t* pv[2] = { (uint32_t*)c->pv0.p, (uint32_t*)c->pv1.p };
+    switch (which) {
+        case GSR_BUF_RECORDS: src = c->rec.p; sz = (size_t)c->vn * 48; break;
+        case GSR_BUF_RADIUS: src = c->radius.p; sz = (size_t)c->vn * 4; break;
+        case GSR_BUF_DEPTH: src = c->depth.p; sz = (size_t)c->vn * 4; break;
+        case GSR_BUF_TILES_TOUCHED: src = c->tt.p; sz = (size_t)c->vn * 4; break;
+        case GSR_BUF_PAIR_VALUES: src = pv[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
+        case GSR_BUF_PAIR_TILES: src = pk[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
+        case GSR_BUF_RANGES: src = c->ranges.p; sz = (size_t)c->lay.n_tiles * 8; break;
+        case GSR_BUF_GRAD2D: src = c->grad2d.p; sz = (size_t)c->vn * 4 * kG2; break;
+        default: return fail(c, GSR_ERR_INVALID_ARG, "unknown buffer");
+    }
+    *bytes = (int64_t)sz;
+    if (!dst) return GSR_OK;
+    if ((int64_t)sz > capacity_bytes) return fail(c, GSR_ERR_INVALID_ARG, "destination too small");
+    if (sz) HIP_TRY(c, hipMemcpyAsync(dst, src, sz, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    return GSR_OK;
+}
+
+gsr_status gsr_autotune(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gsr_camera* cams, int32_t n_views,
+                        gsr_opts* inout, const char* cache_path)
+{
+    gsr_status s = validate(c, g, cams, n_views, inout);
+    if (s) return s;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipDeviceProp_t prop;
+    HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+    // workload key: device, n, SH, views and sizes, flags without the mode bits
+    char keybuf[512];
+    int kl = std::snprintf(keybuf, sizeof keybuf, "%s n=%lld deg=%d dt=%d fl=%u v=%d", prop.gcnArchName,
+                           (long long)g->n, inout->sh_degree, inout->sh_dtype,
+                           inout->flags & (GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP), n_views);
+    for (int v = 0; v < n_views && kl < 480; ++v) kl += std::snprintf(keybuf + kl, sizeof keybuf - kl, " %dx%d", cams[v].width, cams[v].height);
+    std::string key(keybuf);
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char line[1024];
+            while (std::fgets(line, sizeof line, f)) {
+                std::string l(line);
+                size_t bar = l.rfind(" | ");
+                if (bar == std::string::npos || l.substr(0, bar) != key) continue;
+                int tw, th, lb;
+                if (std::sscanf(l.c_str() + bar + 3, "%d %d %d", &tw, &th, &lb) == 3 && tile_ok(tw, th)) {
+                    inout->tile_w = tw; inout->tile_h = th; inout->lds_batch = lb;
+                    std::fclose(f);
+                    return GSR_OK;
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    // temporary outputs and gradients
+    int64_t npix = 0;
+    for (int v = 0; v < n_views; ++v) npix += (int64_t)cams[v].width * cams[v].height;
+    const int K = (inout->sh_degree + 1) * (inout->sh_degree + 1);
+    const size_t shb = (size_t)g->n * K * 3 * (inout->sh_dtype == 1 ? 2 : 4);
+    Dev tmp;
+    size_t need = (size_t)npix * 4 * (3 + 1 + 1 + 1 + 3 + 1) + 4 * (size_t)n_views * 2 + (size_t)g->n * 4 * 11 + shb + 4096;
+    if ((s = grow(c, tmp, need))) return s;
+    char* p = (char*)tmp.p;
+    auto take = [&](size_t b) { char* q = p; p += (b + 255) & ~(size_t)255; return (void*)q; };
+    gsr_fwd_out fo;
+    fo.rgb = (float*)take(npix * 12); fo.entropy = (float*)take(npix * 4); fo.t_final = (float*)take(npix * 4);
+    fo.n_contrib = (int32_t*)take(npix * 4); fo.entropy_mean = (float*)take(4 * n_views);
+    float* grgb = (float*)take(npix * 12);
+    float* gle = (float*)take(4 * n_views);
+    gsr_grads gg;
+    gg.means = (float*)take(g->n * 12); gg.scales = (float*)take(g->n * 12); gg.quats = (float*)take(g->n * 16);
+    gg.opacities = (float*)take(g->n * 4); gg.sh = take(shb);
+    HIP_TRY(c, hipMemsetAsync(grgb, 0, npix * 12, st));
+    HIP_TRY(c, launch_fill_u32((uint32_t*)gle, 0x3c75c28fu /* 0.015f */, n_views, st));
+    const int shapes[3][2] = { { 8, 8 }, { 16, 16 }, { 32, 8 } };
+    const int batches[4] = { 32, 64, 128, 256 };
+    double best = 1e30;
+    gsr_opts bo = *inout;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    for (auto& sh : shapes)
+        for (int lb : batches) {
+            gsr_opts o = *inout;
+            o.tile_w = sh[0]; o.tile_h = sh[1]; o.lds_batch = lb;
+            o.flags &= ~(uint32_t)GSR_GRAPH;
+            double t = 0.0;
+            for (int it = 0; it < 4 && s == GSR_OK; ++it) {
+                if (it == 1) (void)hipEventRecord(e0, st);
+                s = gsr_forward(c, st, g, cams, n_views, &o, &fo);
+                if (!s) s = gsr_backward(c, st, g, cams, n_views, &o, &fo, grgb, nullptr, gle, &gg);
+            }
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t = ms / 3.0;
+            if (s) break;
+            if (t < best) { best = t; bo = o; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    free_dev(tmp);
+    c->have_frame = false;
+    if (s) return s;
+    inout->tile_w = bo.tile_w; inout->tile_h = bo.tile_h; inout->lds_batch = bo.lds_batch;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s | %d %d %d %.4f\n", key.c_str(), bo.tile_w, bo.tile_h, bo.lds_batch, best);
+            std::fclose(f);
+        }
+    }
+    return GSR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Internal declarations of the gfx950 rasterizer library: device-side camera
+// record, kernel argument blocks and the host launchers each .hip file
+// provides.  Not part of the public ABI (include/gsr.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsr {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kBlockPx = 8;        // every wavefront blends one 8x8 pixel block
+constexpr int kMaxViews = 64;
+
+// Per-view camera and layout record, resident in device memory.
+struct CamDev {
+    int32_t W, H;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float near_z;
+    float campos[3];               // camera centre in world space, -R^T t
+    float limx, limy;              // 1.3 x half field of view (tan), Jacobian clamp
+    int32_t gx, gy;                // tile grid of this view
+    uint32_t tile_base;            // first global tile id of this view
+    int32_t bx, by;                // 8x8 block grid of this view
+    uint32_t block_base;           // first global 8x8 block of this view
+    uint32_t pad0;
+    int64_t pix_base;              // first pixel of this view in the packed outputs
+    double limx_d, limy_d;         // the clamp bounds in FP64 (the clamp decision is taken in FP64)
+};
+
+// Projected record of one (view, Gaussian): three float4
+//   r0 = (mean x, mean y, conic A, conic B)
+//   r1 = (conic C, opacity, red, green)
+//   r2 = (blue, 0, 0, 0)
+constexpr int kRecF4 = 3;
+// 2D gradient accumulator per (view, Gaussian): 9 floats
+//   dmean x, dmean y, dA, dB, dC, dopacity, dred, dgreen, dblue
+constexpr int kG2 = 9;
+
+struct ProjectFwdArgs {
+    const float* means;
+    const float* scales;
+    const float* quats;
+    const float* opac;
+    const void* sh;
+    uint32_t n;
+    int32_t n_views;
+    uint32_t flags;
+    int32_t tile_shift_x, tile_shift_y;   // log2 of the tile shape
+    const CamDev* cams;
+    float4* rec;                          // [V*n][3]
+    uint32_t* depth_key;                  // [V*n] float bits of camera z; culled = 0xffffffff
+    uint2* rect;                          // [V*n] (x0 | x1 << 16, y0 | y1 << 16)
+    uint32_t* tiles_touched;              // [V*n]
+    int32_t* radius;                      // [V*n]
+    float* depth;                         // [V*n]
+};
+
+struct ProjectBwdArgs {
+    const float* means;
+    const float* scales;
+    const float* quats;
+    const float* opac;
+    const void* sh;
+    uint32_t n;
+    int32_t n_views;
+    uint32_t flags;
+    const CamDev* cams;
+    const float* grad2d;                  // [V*n][9]
+    float* g_means;
+    float* g_scales;
+    float* g_quats;
+    float* g_opac;
+    void* g_sh;
+};
+
+struct BlendFwdArgs {
+    const float4* rec;
+    const uint32_t* pair_vals;
+    const uint2* ranges;
+    const CamDev* cams;
+    int32_t n_views;
+    int32_t tile_shift_x, tile_shift_y;
+    uint32_t n_blocks;                    // 8x8 blocks over all views
+    float* out_rgb;
+    float* out_H;
+    float* out_T;
+    int32_t* out_nc;
+    float* block_H;                       // [n_blocks] sum of H over the block
+    uint2* block_cnt;                     // [n_blocks] (alpha evaluations, sum of n_contrib)
+};
+
+struct BlendBwdArgs {
+    const float4* rec;
+    const uint32_t* pair_vals;
+    const uint2* ranges;
+    const CamDev* cams;
+    int32_t n_views;
+    int32_t tile_shift_x, tile_shift_y;
+    uint32_t n_blocks;
+    const float* T_final;
+    const int32_t* n_contrib;
+    const float* grad_rgb;
+    const float* grad_H;                  // may be null
+    const float* grad_LE;                 // [V] may be null
+    float* grad2d;                        // [V*n][9], accumulated with atomics
+};
+
+// ---- launchers (return hipError_t of the launch) ----
+hipError_t launch_project_fwd(const ProjectFwdArgs& a, int sh_degree, bool sh_bf16, hipStream_t s);
+hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, bool sh_bf16, hipStream_t s);
+
+// exclusive scan of tiles_touched[order[i]] for i < n  ->  out[i]; total -> *total (uint32),
+// *overflow |= 1 if the total does not fit in 32 bits.  tmp holds scan_tmp_words(n) words.
+size_t scan_tmp_words(uint32_t n);
+hipError_t launch_gather_scan(const uint32_t* vals, const uint32_t* order, uint32_t n, uint32_t* out,
+                              uint32_t* total, uint32_t* overflow, uint32_t* tmp, hipStream_t s);
+
+// one stable LSD radix pass of 8 bits at `shift` over (key, value) pairs; the
+// item count is min(*n_dev, n_max) read on the device (n_dev may be null: n_max).
+size_t radix_tmp_words(uint32_t n_max);
+hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
+                             uint32_t* vals_out, const uint32_t* n_dev, uint32_t n_max, int shift,
+                             uint32_t* tmp, hipStream_t s);
+
+// write (tile id, view*n + index) pairs of every Gaussian in depth order
+hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles_touched,
+                            const uint2* rect, const CamDev* cams, uint32_t n, uint32_t vn,
+                            const uint32_t* total, uint32_t cap, uint32_t* keys, uint32_t* vals,
+                            uint32_t* overflow, hipStream_t s);
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
+hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
+hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges,
+                         hipStream_t s);
+// per-tile list-length histogram (bins 0..nbins-2 exact, last bin = overflow)
+hipError_t launch_len_hist(const uint2* ranges, uint32_t n_tiles, uint32_t* hist, int nbins, hipStream_t s);
+hipError_t launch_view_pairs(const uint2* ranges, const CamDev* cams, int n_views, uint64_t* pairs_per_view,
+                             hipStream_t s);
+
+hipError_t launch_blend_fwd(const BlendFwdArgs& a, int lds_batch, hipStream_t s);
+hipError_t launch_blend_bwd(const BlendBwdArgs& a, int lds_batch, hipStream_t s);
+size_t l1_tmp_doubles(int64_t n_pix);
+hipError_t launch_l1(const float* rgb, const float* target, const CamDev* cams, int n_views, int64_t n_pix,
+                     float* grad, float* loss, double* tmp, hipStream_t s);
+hipError_t launch_entropy_mean(const float* block_H, const CamDev* cams, int n_views, float* out_mean,
+                               hipStream_t s);
+
+}  // namespace gsr

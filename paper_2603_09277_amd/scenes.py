@@ -46,12 +46,16 @@ class Camera:
     near: float = 0.2
 
     def as_array(self) -> np.ndarray:
-        """Flat float64 layout shared by the oracle wrapper (19 values)."""
+        """Flat float64 layout of the oracle (19 values).  Every value is first
+        rounded to float32, the precision in which the GPU library receives a
+        camera, so both sides see the same camera."""
+        f32 = lambda v: np.asarray(v, np.float32).astype(np.float64)
         return np.concatenate([
-            np.array([self.width, self.height, self.fx, self.fy, self.cx, self.cy], np.float64),
-            self.R.astype(np.float64).reshape(9),
-            self.t.astype(np.float64).reshape(3),
-            np.array([self.near], np.float64),
+            np.array([self.width, self.height], np.float64),
+            f32([self.fx, self.fy, self.cx, self.cy]),
+            f32(self.R).reshape(9),
+            f32(self.t).reshape(3),
+            f32([self.near]),
         ])
 
 

@@ -1,0 +1,627 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (FP32 blending against an FP64 oracle):
+  * tile counts, sorted per-tile lists and ranges: bit-exact, with the oracle
+    binning the GPU's own float32 projection (a Gaussian's rect and depth key
+    are integer decisions taken from float32 values);
+  * image, entropy, final transmittance: 1e-5 absolute on every pixel whose
+    alpha-skip / transmittance-stop decisions are not within 1e-4 (relative)
+    of their thresholds -- the oracle flags those pixels, where FP32 and FP64
+    may legitimately decide differently; flagged pixels are counted and bounded;
+  * gradients: relative L2 error per tensor <= 1e-3.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2603_09277_amd import gsr, scenes
+
+from gpu_helpers import (DEV, KEYS, gpu_backward, gpu_forward, gpu_records, oracle_stagewise, rel_norm,
+                         split_pixels, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-5
+GRAD_TOL = 1e-3
+GAMMA = 0.015
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = gsr.Rasterizer(max_views=16)
+    yield r
+    r.close()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    scene, cams, _ = scenes.workload("tiny")
+    return scene, cams
+
+
+def l1_grad_torch(rgb, target_np):
+    tgt = torch.from_numpy(target_np.reshape(-1, 3)).to(DEV)
+    return (torch.sign(rgb - tgt) / rgb.numel()).contiguous()
+
+
+# --------------------------------------------------------------------------- #
+# (a) projection
+# --------------------------------------------------------------------------- #
+
+def test_projection_parity_tiny(R, tiny):
+    scene, cams = tiny
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=0)
+    gpu_forward(R, t, cams, opts)
+    pg = gpu_records(R, scene.n, 1)[0]
+    po = orc.project(scene, cams[0])
+    assert np.array_equal(pg["radius"] > 0, po["radius"] > 0)
+    v = po["radius"] > 0
+    assert np.all(np.abs(pg["mean2d"] - po["mean2d"])[v] <= 1e-6 * np.abs(po["mean2d"][v]) + 1e-5)
+    scale = np.maximum(np.abs(po["conic"][:, 0]), np.abs(po["conic"][:, 2]))[:, None]
+    assert np.all((np.abs(pg["conic"] - po["conic"]) / scale)[v] <= 1e-4)
+    assert np.all(np.abs(pg["rgb"] - po["rgb"])[v] <= 1e-6)
+    assert np.all(np.abs(pg["depth32"].astype(np.float64) - po["depth"])[v] <= 1e-6 * po["depth"][v])
+    a, b, c = po["cov2d"][:, 0], po["cov2d"][:, 1], po["cov2d"][:, 2]
+    mid = 0.5 * (a + c)
+    r_exact = 3 * np.sqrt(mid + np.sqrt(np.maximum(mid * mid - (a * c - b * b), 0)))
+    near_int = np.abs(r_exact - np.round(r_exact)) < 1e-3
+    assert np.array_equal(pg["radius"][v & ~near_int], po["radius"][v & ~near_int])
+
+
+def test_projection_parity_sh3_rotated_camera(R):
+    scene = scenes.gmm_scene(21, 4000)
+    cams = scenes.orbit_cameras(np.random.default_rng(22), [(320, 200)])
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=3)
+    gpu_forward(R, t, cams, opts)
+    pg = gpu_records(R, scene.n, 1)[0]
+    po = orc.project(scene, cams[0])
+    assert np.array_equal(pg["radius"] > 0, po["radius"] > 0)
+    v = po["radius"] > 0
+    assert v.sum() > 1000
+    assert np.all(np.abs(pg["rgb"] - po["rgb"])[v] <= 2e-6)
+    assert np.all(np.abs(pg["mean2d"] - po["mean2d"])[v] <= 1e-6 * np.abs(po["mean2d"][v]) + 1e-5)
+
+
+# --------------------------------------------------------------------------- #
+# (b)-(d) binning, sort, ranges: bit-exact on the GPU's float32 projection
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_binning_sort_ranges_bit_exact(R, tiny, tile):
+    scene, cams = tiny
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=tile, sh_degree=0)
+    gpu_forward(R, t, cams, opts)
+    pg = gpu_records(R, scene.n, 1)[0]
+    cam = cams[0]
+    total, tt, _ = orc.count_pairs(pg["mean2d"], pg["radius"], cam.width, cam.height, *tile)
+    assert np.array_equal(R.inspect(gsr.BUF_TILES_TOUCHED), tt)
+    vals, ranges = orc.bin_lists(pg["mean2d"], pg["radius"], pg["depth32"], cam.width, cam.height, *tile)
+    gv = R.inspect(gsr.BUF_PAIR_VALUES)
+    gr = R.inspect(gsr.BUF_RANGES).reshape(-1, 2)
+    assert len(gv) == total
+    assert np.array_equal(gv.astype(np.int64), vals.astype(np.int64))
+    assert np.array_equal(gr.astype(np.int64), ranges.astype(np.int64))
+
+
+def test_binning_bit_exact_single_view_full(R):
+    """The 200k-Gaussian 1296x840 workload: every one of ~1e6 pairs in order."""
+    scene, cams, _ = scenes.workload("single")
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=3)
+    gpu_forward(R, t, cams, opts)
+    pg = gpu_records(R, scene.n, 1)[0]
+    cam = cams[0]
+    vals, ranges = orc.bin_lists(pg["mean2d"], pg["radius"], pg["depth32"], cam.width, cam.height, 16, 16)
+    assert len(vals) > 100_000
+    assert np.array_equal(R.inspect(gsr.BUF_PAIR_VALUES).astype(np.int64), vals.astype(np.int64))
+    assert np.array_equal(R.inspect(gsr.BUF_RANGES).reshape(-1, 2).astype(np.int64), ranges.astype(np.int64))
+
+
+# --------------------------------------------------------------------------- #
+# (e)-(f) blend and entropy
+# --------------------------------------------------------------------------- #
+
+def _cmp_image(out, img_o, cam, v=0, cams=None, tol=IMG_TOL, max_flag_frac=0.01):
+    cams = cams or [cam]
+    rgb = split_pixels(out["rgb"].cpu().numpy(), cams, v)
+    H = split_pixels(out["entropy"].cpu().numpy(), cams, v)
+    T = split_pixels(out["t_final"].cpu().numpy(), cams, v)
+    nc = split_pixels(out["n_contrib"].cpu().numpy(), cams, v)
+    ok = img_o["flags"] == 0
+    assert ok.mean() >= 1 - max_flag_frac
+    e_rgb = np.abs(rgb - img_o["rgb"])[ok].max(initial=0.0)
+    e_H = np.abs(H - img_o["H"])[ok].max(initial=0.0)
+    e_T = np.abs(T - img_o["T"])[ok].max(initial=0.0)
+    assert e_rgb <= tol, e_rgb
+    assert e_H <= tol, e_H
+    assert e_T <= tol, e_T
+    assert np.array_equal(nc[ok], img_o["ncontrib"][ok])
+    return e_rgb, e_H, e_T
+
+
+@pytest.mark.parametrize("tile,lds", [((16, 16), 64), ((8, 8), 32), ((32, 8), 128), ((16, 16), 256)])
+def test_blend_stagewise_tiny(R, tiny, tile, lds):
+    scene, cams = tiny
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=tile, lds_batch=lds, sh_degree=0)
+    out = gpu_forward(R, t, cams, opts)
+    pg = gpu_records(R, scene.n, 1)[0]
+    img_o = oracle_stagewise(pg, cams[0], tile)
+    _cmp_image(out, img_o, cams[0])
+    le = float(out["entropy_mean"].cpu()[0])
+    assert abs(le - img_o["H"].mean()) <= 1e-6
+
+
+def test_end_to_end_tiny_vs_fp64_oracle(R, tiny):
+    """Oracle with its own FP64 projection: lists identical, image within 1e-5."""
+    scene, cams = tiny
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=0)
+    out = gpu_forward(R, t, cams, opts)
+    f = orc.forward_view(scene, cams[0], (16, 16))
+    assert np.array_equal(R.inspect(gsr.BUF_PAIR_VALUES).astype(np.int64), f["values"].astype(np.int64))
+    _cmp_image(out, f, cams[0])
+    assert abs(float(out["entropy_mean"].cpu()[0]) - f["L_E"]) <= 1e-6
+
+
+def test_weights_sum_to_one_on_gpu(R, tiny):
+    """Eq. 9 on the GPU: with every colour 1, rgb + T_final = 1."""
+    scene, cams = tiny
+    s = scene.copy()
+    s.sh[:] = np.float32(0.5 * 2.0 * math.sqrt(math.pi))      # Y00 * k + 0.5 = 1
+    t = to_dev(s)
+    out = gpu_forward(R, t, cams, gsr.RasterOptions(tile=(16, 16), sh_degree=0))
+    rgb = out["rgb"].cpu().numpy().astype(np.float64)
+    T = out["t_final"].cpu().numpy().astype(np.float64)
+    assert np.abs(rgb + T[:, None] - 1.0).max() < 3e-6
+    assert T.min() >= 1e-4
+    H = out["entropy"].cpu().numpy()
+    nc = out["n_contrib"].cpu().numpy()
+    assert np.all(H >= -1e-6) and np.all(H <= np.log(nc + 1.0) + 1e-5)
+
+
+def test_determinism(R, tiny):
+    scene, cams = tiny
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=0)
+    a = gpu_forward(R, t, cams, opts)
+    va = R.inspect(gsr.BUF_PAIR_VALUES)
+    b = gpu_forward(R, t, cams, opts)
+    vb = R.inspect(gsr.BUF_PAIR_VALUES)
+    for k in ("rgb", "entropy", "t_final", "n_contrib", "entropy_mean"):
+        assert torch.equal(a[k], b[k]), k
+    assert np.array_equal(va, vb)
+
+
+# --------------------------------------------------------------------------- #
+# (g) backward
+# --------------------------------------------------------------------------- #
+
+def _tiny_backward(R, scene, cams, tile=(16, 16), lds=64):
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=tile, lds_batch=lds, sh_degree=scene.sh_degree)
+    out = gpu_forward(R, t, cams, opts)
+    target = scenes.target_image(101, cams[0].height, cams[0].width)
+    g_rgb = l1_grad_torch(out["rgb"], target)
+    g_le = torch.full((1,), GAMMA, device=DEV)
+    grads = gpu_backward(R, t, cams, opts, out, g_rgb, None, g_le)
+    return t, opts, out, target, g_rgb, grads
+
+
+def test_blend_backward_stagewise(R, tiny):
+    scene, cams = tiny
+    cam = cams[0]
+    t, opts, out, target, g_rgb, grads = _tiny_backward(R, scene, cams)
+    pg = gpu_records(R, scene.n, 1)[0]
+    vals, ranges = orc.bin_lists(pg["mean2d"], pg["radius"], pg["depth32"], cam.width, cam.height, 16, 16)
+    M = cam.width * cam.height
+    g2o = orc.backward_render(cam.width, cam.height, 16, 16, pg["mean2d"], pg["conic"], pg["opacity"], pg["rgb"],
+                              ranges, vals, g_rgb.cpu().numpy().reshape(cam.height, cam.width, 3).astype(np.float64),
+                              np.full((cam.height, cam.width), GAMMA / M))
+    g2g = R.inspect(gsr.BUF_GRAD2D).reshape(scene.n, 9).astype(np.float64)
+    assert rel_norm(g2g[:, 0:2], g2o["mean2d"]) < GRAD_TOL
+    assert rel_norm(g2g[:, 2:5], g2o["conic"]) < GRAD_TOL
+    assert rel_norm(g2g[:, 5], g2o["opacity"]) < GRAD_TOL
+    assert rel_norm(g2g[:, 6:9], g2o["rgb"]) < GRAD_TOL
+
+
+def test_projection_backward_stagewise(R, tiny):
+    scene, cams = tiny
+    t, opts, out, target, g_rgb, grads = _tiny_backward(R, scene, cams)
+    g2g = R.inspect(gsr.BUF_GRAD2D).reshape(scene.n, 9).astype(np.float64)
+    g2d = dict(mean2d=g2g[:, 0:2], conic=g2g[:, 2:5], opacity=g2g[:, 5], rgb=g2g[:, 6:9])
+    acc = orc.backward_project(scene, cams[0], g2d)
+    for k in KEYS:
+        assert rel_norm(grads[k], acc[k]) < GRAD_TOL, k
+
+
+def test_gradients_end_to_end_tiny(R, tiny):
+    scene, cams = tiny
+    t, opts, out, target, g_rgb, grads = _tiny_backward(R, scene, cams)
+    L, g_o, _ = orc.loss_and_grads(scene, cams, [target], GAMMA, (16, 16))
+    for k in KEYS:
+        assert rel_norm(grads[k], g_o[k]) < GRAD_TOL, (k, rel_norm(grads[k], g_o[k]))
+
+
+def test_gradients_sh3_scene(R):
+    """SH degree 3 and a rotated camera: exercises the colour -> direction chain."""
+    scene = scenes.gmm_scene(31, 3000)
+    scene.scales *= np.float32(4.0)
+    cams = scenes.orbit_cameras(np.random.default_rng(32), [(160, 120)])
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=3)
+    out = gpu_forward(R, t, cams, opts)
+    target = scenes.target_image(33, 120, 160)
+    g_rgb = l1_grad_torch(out["rgb"], target)
+    g_le = torch.full((1,), 0.3, device=DEV)
+    grads = gpu_backward(R, t, cams, opts, out, g_rgb, None, g_le)
+    L, g_o, _ = orc.loss_and_grads(scene, cams, [target], 0.3, (16, 16))
+    for k in KEYS:
+        assert rel_norm(grads[k], g_o[k]) < GRAD_TOL, (k, rel_norm(grads[k], g_o[k]))
+
+
+# --------------------------------------------------------------------------- #
+# batching, precision, graphs, autograd
+# --------------------------------------------------------------------------- #
+
+def _tiny_cams():
+    from scipy.spatial.transform import Rotation
+    out = []
+    for (w, h, f, ang, tx) in [(128, 128, 128.0, 0.0, 0.0), (96, 64, 90.0, 0.08, 0.2), (50, 37, 40.0, -0.1, -0.1)]:
+        Rm = Rotation.from_euler("y", ang).as_matrix().astype(np.float32)
+        out.append(scenes.Camera(w, h, f, f, w / 2.0, h / 2.0, Rm, np.array([tx, 0.0, 0.1], np.float32), 0.2))
+    return out
+
+
+def test_batched_equals_plain(R, tiny):
+    scene, _ = tiny
+    cams = _tiny_cams()
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=0)
+    ob = gpu_forward(R, t, cams, opts)
+    g_rgb_b = torch.full_like(ob["rgb"], 1e-4)
+    g_le_b = torch.full((3,), GAMMA, device=DEV)
+    gb = gpu_backward(R, t, cams, opts, ob, g_rgb_b, None, g_le_b)
+    off = gsr.pixel_offsets(cams)
+    gsum = {k: np.zeros_like(v) for k, v in gb.items()}
+    for v, cam in enumerate(cams):
+        os_ = gpu_forward(R, t, [cam], opts)
+        for k in ("rgb", "entropy", "t_final", "n_contrib"):
+            assert torch.equal(ob[k][off[v]:off[v + 1]], os_[k]), (v, k)
+        assert torch.equal(ob["entropy_mean"][v:v + 1], os_["entropy_mean"])
+        gv = gpu_backward(R, t, [cam], opts, os_, torch.full_like(os_["rgb"], 1e-4), None,
+                          torch.full((1,), GAMMA, device=DEV))
+        for k in gsum:
+            gsum[k] += gv[k]
+    for k in gsum:
+        assert rel_norm(gb[k], gsum[k]) < 1e-5, k
+
+
+def test_batched_views_vs_oracle(R, tiny):
+    scene, _ = tiny
+    cams = _tiny_cams()
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(8, 8), sh_degree=0)
+    out = gpu_forward(R, t, cams, opts)
+    recs = gpu_records(R, scene.n, len(cams))
+    for v, cam in enumerate(cams):
+        img_o = oracle_stagewise(recs[v], cam, (8, 8))
+        _cmp_image(out, img_o, cam, v, cams)
+
+
+def test_bf16_sh_storage(R):
+    scene = scenes.gmm_scene(41, 20000)
+    scene.sh = scenes.bf16_round(scene.sh)
+    scene.scales *= np.float32(2.0)
+    cams = scenes.orbit_cameras(np.random.default_rng(42), [(256, 192)])
+    t = to_dev(scene, bf16=True)
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=3, sh_bf16=True)
+    out = gpu_forward(R, t, cams, opts)
+    pg = gpu_records(R, scene.n, 1)[0]
+    img_o = oracle_stagewise(pg, cams[0], (16, 16))
+    _cmp_image(out, img_o, cams[0])
+    f = orc.forward_view(scene, cams[0], (16, 16))          # oracle on the bf16-rounded SH
+    ok = f["flags"] == 0
+    rgb = out["rgb"].cpu().numpy().reshape(192, 256, 3)
+    assert np.abs(rgb - f["rgb"])[ok].max() <= 1e-4
+    target = scenes.target_image(43, 192, 256)
+    g_rgb = l1_grad_torch(out["rgb"], target)
+    grads = gpu_backward(R, t, cams, opts, out, g_rgb, None, torch.full((1,), GAMMA, device=DEV))
+    L, g_o, _ = orc.loss_and_grads(scene, cams, [target], GAMMA, (16, 16))
+    for k in ("means", "scales", "quats", "opacities"):
+        assert rel_norm(grads[k], g_o[k]) < GRAD_TOL, k
+    # SH gradients are stored in bfloat16: within 1 bf16 ulp of bf16(g*) where g* is well away from zero
+    gs, go = grads["sh"], g_o["sh"]
+    ref = scenes.bf16_round(go.astype(np.float32)).astype(np.float64)
+    big = np.abs(go) > 1e-3 * np.abs(go).max()
+    ulp = np.abs(ref) * 2.0 ** -7
+    assert np.all(np.abs(gs - ref)[big] <= ulp[big] * 1.01 + 1e-12)
+    assert rel_norm(gs, go) < 5e-3
+
+
+def test_graph_mode_replays_match_plain(R, tiny):
+    scene, cams = tiny
+    t = to_dev(scene)
+    plain = gsr.RasterOptions(tile=(16, 16), sh_degree=0)
+    ref = gpu_forward(R, t, cams, plain)
+    g_rgb = torch.full_like(ref["rgb"], 2e-5)
+    g_le = torch.full((1,), GAMMA, device=DEV)
+    gref = gpu_backward(R, t, cams, plain, ref, g_rgb, None, g_le)
+    G = gsr.Rasterizer(max_views=2)
+    graph = gsr.RasterOptions(tile=(16, 16), sh_degree=0, flags=gsr.GSR_DEFAULT_FLAGS | gsr.GSR_GRAPH)
+    outs = dict(rgb=torch.empty_like(ref["rgb"]), entropy=torch.empty_like(ref["entropy"]))
+    for rep in range(4):
+        o = G.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, graph)
+        gg = G.backward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, graph, o, g_rgb, None, g_le)
+        torch.cuda.synchronize()
+        _ = (torch.randn(1000, device=DEV) * 2).sum().item()    # unrelated eager work between replays
+        for k in ("rgb", "entropy", "t_final", "n_contrib", "entropy_mean"):
+            assert torch.equal(o[k], ref[k]), (rep, k)
+        for k in KEYS:
+            assert rel_norm(gg[k].cpu().numpy(), gref[k]) < 1e-5, (rep, k)
+        st = G.stats(1)
+        assert not st["overflow"]
+    G.close()
+
+
+def test_autograd_function_matches_raw(R, tiny):
+    scene, cams = tiny
+    t = {k: v.clone().requires_grad_(True) for k, v in to_dev(scene).items()}
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=0)
+    rgb, ent, em = gsr.render(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, R)
+    target = scenes.target_image(101, 128, 128)
+    loss = (rgb - torch.from_numpy(target.reshape(-1, 3)).to(DEV)).abs().mean() + GAMMA * em.sum()
+    loss.backward()
+    L, g_o, _ = orc.loss_and_grads(scene, cams, [target], GAMMA, (16, 16))
+    assert abs(float(loss) - L) < 1e-5
+    for k in KEYS:
+        assert rel_norm(t[k].grad.cpu().numpy(), g_o[k]) < GRAD_TOL, k
+
+
+def test_autograd_vs_central_fd_of_fp64_oracle(R, tiny):
+    """GPU autograd gradient against central finite differences (eps 1e-4) of the
+    FP64 oracle loss, on 64 seeded Gaussians; probes that cross a discrete
+    decision (list, skip, stop, clamp, L1 sign) are redrawn."""
+    scene, cams = tiny
+    t = {k: v.clone().requires_grad_(True) for k, v in to_dev(scene).items()}
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=0)
+    target = scenes.target_image(101, 128, 128)
+    gamma = 0.5
+    rgb, ent, em = gsr.render(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, R)
+    loss = (rgb - torch.from_numpy(target.reshape(-1, 3)).to(DEV)).abs().mean() + gamma * em.sum()
+    loss.backward()
+    grads = {k: t[k].grad.cpu().numpy().astype(np.float64) for k in KEYS}
+    rng = np.random.default_rng(505)
+    cam = cams[0]
+
+    def loss_sig(sc):
+        f = orc.forward_view(sc, cam, (16, 16))
+        L = float(np.abs(f["rgb"] - target).mean()) + gamma * f["L_E"]
+        return L, (f["sig"], f["values"].tobytes(), f["proj"]["mask"].tobytes(),
+                   np.sign(f["rgb"] - target).astype(np.int8).tobytes())
+
+    sc = scene.copy()
+    checked = redrawn = 0
+    for g in rng.choice(scene.n, 64, replace=False):
+        for name in ("means", "scales", "opacities"):
+            flat = getattr(sc, name).reshape(sc.n, -1)
+            j = int(rng.integers(flat.shape[1]))
+            x0 = flat[g, j]
+            eps = 1e-4 * (abs(float(x0)) if name == "scales" else max(1.0, abs(float(x0))))
+            xp, xm = np.float32(x0 + eps), np.float32(x0 - eps)
+            flat[g, j] = xp
+            Lp, sp = loss_sig(sc)
+            flat[g, j] = xm
+            Lm, sm = loss_sig(sc)
+            flat[g, j] = x0
+            if sp != sm:
+                redrawn += 1
+                continue
+            fd = (Lp - Lm) / (float(xp) - float(xm))
+            an = grads[name].reshape(sc.n, -1)[g, j]
+            scale = np.abs(grads[name]).max()
+            assert abs(an - fd) <= 2e-3 * abs(fd) + 2e-4 * scale + 1e-9, (name, g, j, an, fd)
+            checked += 1
+    assert checked >= 100, (checked, redrawn)
+
+
+# --------------------------------------------------------------------------- #
+# the single-view workload at full size, sampled
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("bench_cfg", [(16, 16, 64)])
+def test_single_view_full_size_sampled(R, bench_cfg):
+    """200k Gaussians, 1296x840, SH3, in the bench's launch configuration: image,
+    entropy, T on 2,000 seeded pixels; gradients of a loss restricted to those
+    pixels against the oracle's gradient of the same loss."""
+    tw, th, lds = bench_cfg
+    scene, cams, _ = scenes.workload("single")
+    cam = cams[0]
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(tw, th), lds_batch=lds, sh_degree=3)
+    out = gpu_forward(R, t, cams, opts)
+    pg = gpu_records(R, scene.n, 1)[0]
+    rng = np.random.default_rng(55)
+    M = cam.width * cam.height
+    sel = rng.choice(M, 2000, replace=False)
+    pix = np.zeros(M, np.uint8)
+    pix[sel] = 1
+    img_o = oracle_stagewise(pg, cam, (tw, th), pix.reshape(cam.height, cam.width))
+    ok = (img_o["flags"].reshape(-1) == 0) & (pix == 1)
+    rgb = out["rgb"].cpu().numpy()
+    assert np.abs(rgb - img_o["rgb"].reshape(-1, 3))[ok].max() <= IMG_TOL
+    assert np.abs(out["entropy"].cpu().numpy() - img_o["H"].reshape(-1))[ok].max() <= IMG_TOL
+    assert np.abs(out["t_final"].cpu().numpy() - img_o["T"].reshape(-1))[ok].max() <= IMG_TOL
+    assert np.array_equal(out["n_contrib"].cpu().numpy()[ok], img_o["ncontrib"].reshape(-1)[ok])
+    # masked loss: L1 on the sampled pixels + gamma * mean entropy over them
+    target = scenes.target_image(202, cam.height, cam.width).reshape(-1, 3)
+    g_rgb = np.zeros((M, 3))
+    g_rgb[sel] = np.sign(rgb[sel] - target[sel]) / (3 * len(sel))
+    g_H = np.zeros(M)
+    g_H[sel] = GAMMA / len(sel)
+    grads = gpu_backward(R, t, cams, opts, out, torch.from_numpy(g_rgb.astype(np.float32)).to(DEV),
+                         torch.from_numpy(g_H.astype(np.float32)).to(DEV), None)
+    g2o = orc.backward_render(cam.width, cam.height, tw, th, pg["mean2d"], pg["conic"], pg["opacity"], pg["rgb"],
+                              img_o["ranges"], img_o["values"], g_rgb.reshape(cam.height, cam.width, 3),
+                              g_H.reshape(cam.height, cam.width), pix.reshape(cam.height, cam.width))
+    g2g = R.inspect(gsr.BUF_GRAD2D).reshape(scene.n, 9).astype(np.float64)
+    assert rel_norm(g2g[:, 0:2], g2o["mean2d"]) < GRAD_TOL
+    assert rel_norm(g2g[:, 2:5], g2o["conic"]) < GRAD_TOL
+    assert rel_norm(g2g[:, 5], g2o["opacity"]) < GRAD_TOL
+    assert rel_norm(g2g[:, 6:9], g2o["rgb"]) < GRAD_TOL
+    acc = orc.backward_project(scene, cam, g2o)
+    for k in KEYS:
+        assert rel_norm(grads[k], acc[k]) < GRAD_TOL, (k, rel_norm(grads[k], acc[k]))
+
+
+# --------------------------------------------------------------------------- #
+# statistics, edge cases, errors
+# --------------------------------------------------------------------------- #
+
+def test_stats_match_lists(R, tiny):
+    scene, cams = tiny
+    t = to_dev(scene)
+    gpu_forward(R, t, cams, gsr.RasterOptions(tile=(8, 8), sh_degree=0))
+    st = R.stats(1)
+    rg = R.inspect(gsr.BUF_RANGES).reshape(-1, 2).astype(np.int64)
+    lens = np.sort(rg[:, 1] - rg[:, 0])
+    assert st["pairs_per_view"][0] == lens.sum()
+    assert abs(st["mean_len"] - lens.mean()) < 1e-9
+    assert st["p99_len"] == lens[int(math.ceil(0.99 * len(lens))) - 1]
+    assert not st["overflow"]
+
+
+def _single_gaussian_scene(means, scales, opac, n_extra=0):
+    n = len(means)
+    q = np.tile(np.array([[1, 0, 0, 0]], np.float32), (n, 1))
+    sh = np.full((n, 1, 3), 0.8, np.float32)
+    return scenes.Scene(np.asarray(means, np.float32), np.asarray(scales, np.float32), q,
+                        np.asarray(opac, np.float32), sh, 0)
+
+
+def _e2e(R, scene, cams, tile=(16, 16)):
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=tile, sh_degree=scene.sh_degree)
+    out = gpu_forward(R, t, cams, opts)
+    for v, cam in enumerate(cams):
+        f = orc.forward_view(scene, cam, tile)
+        _cmp_image(out, f, cam, v, cams)
+    return t, opts, out
+
+
+def test_edge_empty_scene(R):
+    sc = _single_gaussian_scene(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0))
+    cams = [scenes.Camera(64, 48, 50.0, 50.0, 32.0, 24.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))]
+    t, opts, out = _e2e(R, sc, cams)
+    assert float(out["rgb"].abs().max()) == 0.0 and float(out["t_final"].min()) == 1.0
+    assert float(out["entropy_mean"][0]) == 0.0
+    g = gpu_backward(R, t, cams, opts, out, torch.ones_like(out["rgb"]), None, torch.ones(1, device=DEV))
+    assert all(v.size == 0 for v in g.values())
+
+
+def test_edge_all_culled_and_nan(R):
+    cams = [scenes.Camera(64, 48, 50.0, 50.0, 32.0, 24.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))]
+    sc = _single_gaussian_scene([[0, 0, -3.0], [0, 0, 0.1], [np.nan, 0, 4.0], [0.1, 0.0, 4.0]],
+                                [[0.1] * 3, [0.1] * 3, [0.1] * 3, [0.2] * 3], [0.9, 0.9, 0.9, 0.8])
+    t, opts, out = _e2e(R, sc, cams)
+    rad = R.inspect(gsr.BUF_RADIUS)
+    assert list(rad[:3]) == [0, 0, 0] and rad[3] > 0
+    g = gpu_backward(R, t, cams, opts, out, torch.full_like(out["rgb"], 1e-3), None, torch.ones(1, device=DEV))
+    assert np.all(g["means"][:3] == 0) and np.any(g["means"][3] != 0)
+
+
+def test_edge_giant_gaussian_and_clamp(R):
+    """One Gaussian covering every tile, alpha at the 0.99 clamp in its centre."""
+    cams = [scenes.Camera(160, 96, 80.0, 80.0, 80.0, 48.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))]
+    sc = _single_gaussian_scene([[0.1, -0.05, 3.0], [0.2, 0.1, 5.0]], [[2.0, 1.5, 1.0], [0.05, 0.08, 0.03]],
+                                [0.999, 0.7])
+    sc.quats[:] = np.array([[0.9, 0.2, -0.3, 0.1], [0.5, -0.4, 0.6, 0.2]], np.float32)   # no symmetry
+    t, opts, out = _e2e(R, sc, cams)
+    assert R.inspect(gsr.BUF_TILES_TOUCHED)[0] == 10 * 6
+    g = gpu_backward(R, t, cams, opts, out, torch.full_like(out["rgb"], 1e-3), None, torch.ones(1, device=DEV))
+    target = np.zeros((96, 160, 3))
+    # compare with the oracle for the same upstream gradients
+    f = orc.forward_view(sc, cams[0], (16, 16))
+    pr = f["proj"]
+    g2 = orc.backward_render(160, 96, 16, 16, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"], f["ranges"],
+                             f["values"], np.full((96, 160, 3), 1e-3), np.full((96, 160), 1.0 / (160 * 96)))
+    acc = orc.backward_project(sc, cams[0], g2)
+    for k in KEYS:
+        assert rel_norm(g[k], acc[k]) < GRAD_TOL, k
+    del target
+
+
+@pytest.mark.parametrize("wh", [(100, 75), (37, 23), (1, 1), (17, 200)])
+def test_edge_ragged_sizes(R, tiny, wh):
+    scene, _ = tiny
+    w, h = wh
+    f = 128.0 * max(w, h) / 128.0
+    cams = [scenes.Camera(w, h, f, f, w / 2.0, h / 2.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))]
+    for tile in [(16, 16), (32, 8)]:
+        _e2e(R, scene, cams, tile)
+
+
+def test_edge_equal_depths_keep_index_order(R):
+    n = 6
+    sc = _single_gaussian_scene(np.tile([[0.0, 0.0, 4.0]], (n, 1)), np.full((n, 3), 0.05), np.full(n, 0.3))
+    cams = [scenes.Camera(32, 32, 40.0, 40.0, 16.0, 16.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))]
+    _e2e(R, sc, cams)
+    vals = R.inspect(gsr.BUF_PAIR_VALUES)
+    rg = R.inspect(gsr.BUF_RANGES).reshape(-1, 2)
+    for t_ in range(len(rg)):
+        assert list(vals[rg[t_, 0]:rg[t_, 1]]) == list(range(n))
+
+
+def test_invalid_arguments_rejected(R, tiny):
+    scene, cams = tiny
+    t = to_dev(scene)
+    bad = [gsr.RasterOptions(tile=(16, 8), sh_degree=0), gsr.RasterOptions(tile=(16, 16), sh_degree=4),
+           gsr.RasterOptions(tile=(16, 16), lds_batch=48, sh_degree=0)]
+    for o in bad:
+        K = (o.sh_degree + 1) ** 2
+        sh = torch.zeros((scene.n, K, 3), device=DEV)
+        with pytest.raises(gsr.GsrError) as e:
+            R.forward(t["means"], t["scales"], t["quats"], t["opacities"], sh, cams, o)
+        assert e.value.status == 2
+    bad_cam = [scenes.Camera(0, 10, 1.0, 1.0, 0.0, 0.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))]
+    with pytest.raises(gsr.GsrError) as e:
+        R.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], bad_cam,
+                  gsr.RasterOptions(sh_degree=0))
+    assert e.value.status == 1
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=0)
+    a = gpu_forward(R, t, cams, opts)
+    gpu_forward(R, t, cams, opts)
+    with pytest.raises(gsr.GsrError) as e:
+        R.backward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, a,
+                   torch.zeros_like(a["rgb"]))
+    assert e.value.status == 5
+
+
+def test_fixed_capacity_overflow_is_reported(tiny):
+    scene, cams = tiny
+    t = to_dev(scene)
+    G = gsr.Rasterizer(max_views=1, pair_capacity=64)
+    graph = gsr.RasterOptions(tile=(16, 16), sh_degree=0, flags=gsr.GSR_DEFAULT_FLAGS | gsr.GSR_GRAPH)
+    G.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, graph)
+    st = G.stats(1)
+    assert st["overflow"]
+    G.close()
+
+
+def test_autotune_picks_a_valid_shape(R, tiny, tmp_path):
+    scene, cams = tiny
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=0)
+    cache = str(tmp_path / "tune.txt")
+    best = R.autotune(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, cache)
+    assert best.tile in [(8, 8), (16, 16), (32, 8)] and best.lds_batch in (32, 64, 128, 256)
+    again = R.autotune(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, cache)
+    assert again == best

@@ -130,7 +130,9 @@ def test_projection_isotropic_on_axis(orc):
 
 
 def pinhole(cam, p):
-    return np.array([cam.fx * p[0] / p[2] + cam.cx, cam.fy * p[1] / p[2] + cam.cy])
+    # a camera is float32 data (the precision the GPU library receives it in)
+    fx, fy, cx, cy = (float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy))
+    return np.array([fx * p[0] / p[2] + cx, fy * p[1] / p[2] + cy])
 
 
 def fd_jacobian(cam, p, h=1e-5):
@@ -153,7 +155,7 @@ def test_projection_matches_local_affine_approximation(orc):
     sc.means[4:6, 1] = np.array([7.0, -7.0], np.float32)
     pr = orc.project(sc, cam)
     Rc = cam.R.astype(np.float64)
-    limx, limy = 1.3 * cam.width / 2 / cam.fx, 1.3 * cam.height / 2 / cam.fy
+    limx, limy = 1.3 * (0.5 * cam.width / float(np.float32(cam.fx))), 1.3 * (0.5 * cam.height / float(np.float32(cam.fy)))
     for i in range(sc.n):
         q = sc.quats[i].astype(np.float64)
         Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()

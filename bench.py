@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--bf16", action="store_true", help="store SH and SH gradients in bfloat16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not bracket stages with HIP events")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (3 launches), to scale HBM counters")
     return ap.parse_args()
 
 
@@ -126,6 +128,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
+        return
     tile = tuple(int(x) for x in args.tile.split("x"))
     scene, cams, meta = scenes.workload(args.workload)
     bf16 = args.bf16 or meta["sh_dtype"] == "bf16"

@@ -39,7 +39,7 @@ struct FrameKey {
 
 struct Layout {
     std::vector<CamDev> cams;
-    uint32_t n_tiles = 0, n_blocks = 0;
+    uint32_t n_tiles = 0, n_blocks = 0, n_hchunks = 0, n_l1 = 0;
     int64_t n_pix = 0;
     int tsx = 0, tsy = 0;
 };
@@ -53,7 +53,7 @@ struct gsr_ctx {
 
     // grow-only device buffers
     Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
-    Dev pk0, pk1, pv0, pv1, ranges, block_H, block_cnt, counters, len_hist, view_pairs, l1_tmp;
+    Dev pk0, pk1, pv0, pv1, ranges, block_H, block_cnt, hchunk, counters, len_hist, view_pairs, l1_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
     uint64_t gen_fwd = 0, gen_bwd = 0;
@@ -218,7 +218,7 @@ Layout make_layout(const gsr_camera* cams, int32_t n_views, const gsr_opts* o)
     Layout L;
     L.tsx = ilog2(o->tile_w);
     L.tsy = ilog2(o->tile_h);
-    uint32_t tb = 0, bb = 0;
+    uint32_t tb = 0, bb = 0, hb = 0, lb = 0;
     int64_t pb = 0;
     for (int v = 0; v < n_views; ++v) {
         const gsr_camera& k = cams[v];
@@ -242,6 +242,10 @@ Layout make_layout(const gsr_camera* cams, int32_t n_views, const gsr_opts* o)
         d.by = (k.height + kBlockPx - 1) / kBlockPx;
         d.block_base = bb;
         d.pix_base = pb;
+        d.hred_base = hb;
+        d.l1_base = lb;
+        hb += (uint32_t)((d.bx * d.by + kRedChunk - 1) / kRedChunk);
+        lb += (uint32_t)(((int64_t)k.width * k.height + kL1Block - 1) / kL1Block);
         tb += (uint32_t)(d.gx * d.gy);
         bb += (uint32_t)(d.bx * d.by);
         pb += (int64_t)k.width * k.height;
@@ -249,6 +253,8 @@ Layout make_layout(const gsr_camera* cams, int32_t n_views, const gsr_opts* o)
     }
     L.n_tiles = tb;
     L.n_blocks = bb;
+    L.n_hchunks = hb;
+    L.n_l1 = lb;
     L.n_pix = pb;
     return L;
 }
@@ -292,7 +298,8 @@ gsr_status ensure_tiles(gsr_ctx* c, uint32_t tiles, uint32_t blocks)
     gsr_status s;
     if ((s = grow(c, c->ranges, (size_t)std::max<uint32_t>(tiles, 1) * 8)) ||
         (s = grow(c, c->block_H, (size_t)std::max<uint32_t>(blocks, 1) * 4)) ||
-        (s = grow(c, c->block_cnt, (size_t)std::max<uint32_t>(blocks, 1) * 8)))
+        (s = grow(c, c->block_cnt, (size_t)std::max<uint32_t>(blocks, 1) * 8)) ||
+        (s = grow(c, c->hchunk, (size_t)(blocks / kRedChunk + 64) * 8)))
         return s;
     return GSR_OK;
 }
@@ -382,7 +389,8 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     }
     {
         StageTimer tm(c, st, GSR_STAGE_ENTROPY_MEAN, plain);
-        HIP_TRY(c, launch_entropy_mean((const float*)c->block_H.p, dc, (int)V, out->entropy_mean, st));
+        HIP_TRY(c, launch_entropy_mean((const float*)c->block_H.p, dc, (int)V, L.n_hchunks, (double*)c->hchunk.p,
+                                       out->entropy_mean, st));
     }
     c->sorted_buf = sb;
     c->pairs = plain ? cap : 0;
@@ -503,7 +511,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     drop_graphs(c);
     Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->radius,
                    &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
-                   &c->pv1, &c->ranges, &c->block_H, &c->block_cnt, &c->counters, &c->len_hist, &c->view_pairs,
+                   &c->pv1, &c->ranges, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->len_hist, &c->view_pairs,
                    &c->l1_tmp };
     for (Dev* d : all) free_dev(*d);
     for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
@@ -716,9 +724,9 @@ gsr_status gsr_l1_loss(gsr_ctx* c, void* stream, const gsr_camera* cams, int32_t
             return fail(c, GSR_ERR_INVALID_ARG, "l1 camera sizes differ from the latest forward");
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
-    gsr_status s = grow(c, c->l1_tmp, l1_tmp_doubles(c->lay.n_pix) * 8);
+    gsr_status s = grow(c, c->l1_tmp, ((size_t)c->lay.n_l1 + 1) * 8);
     if (s) return s;
-    HIP_TRY(c, launch_l1(rgb, target, (const CamDev*)c->cams.p, n_views, c->lay.n_pix, grad_rgb, loss,
+    HIP_TRY(c, launch_l1(rgb, target, (const CamDev*)c->cams.p, n_views, c->lay.n_l1, grad_rgb, loss,
                          (double*)c->l1_tmp.p, st));
     return GSR_OK;
 }

@@ -288,23 +288,47 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     }
 }
 
-__global__ __launch_bounds__(256) void entropy_mean_kernel(const float* block_H, const CamDev* cams, int n_views,
-                                                           float* out)
+__device__ __forceinline__ double block_sum_f64(double x)
 {
-    const int v = blockIdx.x;
-    if (v >= n_views) return;
-    const CamDev& c = cams[v];
-    const uint32_t nb = (uint32_t)(c.bx * c.by);
-    double acc = 0.0;
-    for (uint32_t b = threadIdx.x; b < nb; b += 256) acc += (double)block_H[c.block_base + b];
     __shared__ double s[256];
-    s[threadIdx.x] = acc;
+    s[threadIdx.x] = x;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[v] = (float)(s[0] / ((double)c.W * (double)c.H));
+    return s[0];
+}
+
+// level 1: one workgroup per chunk of kRedChunk 8x8 blocks of one view
+__global__ __launch_bounds__(256) void entropy_chunk_kernel(const float* block_H, const CamDev* cams, int n_views,
+                                                            double* chunk_sum)
+{
+    const uint32_t ch = blockIdx.x;
+    int v = 0;
+    while (v + 1 < n_views && cams[v + 1].hred_base <= ch) ++v;
+    const CamDev& c = cams[v];
+    const uint32_t nb = (uint32_t)(c.bx * c.by);
+    const uint32_t b0 = (ch - c.hred_base) * kRedChunk;
+    double acc = 0.0;
+    for (uint32_t k = threadIdx.x; k < (uint32_t)kRedChunk; k += 256)
+        if (b0 + k < nb) acc += (double)block_H[c.block_base + b0 + k];
+    const double tot = block_sum_f64(acc);
+    if (threadIdx.x == 0) chunk_sum[ch] = tot;
+}
+
+// level 2: one workgroup per view, L_E = sum of its chunks / (W H)   (Eq. 11)
+__global__ __launch_bounds__(256) void entropy_mean_kernel(const double* chunk_sum, const CamDev* cams, int n_views,
+                                                           uint32_t n_chunks, float* out)
+{
+    const int v = blockIdx.x;
+    if (v >= n_views) return;
+    const CamDev& c = cams[v];
+    const uint32_t c0 = c.hred_base, c1 = (v + 1 < n_views) ? cams[v + 1].hred_base : n_chunks;
+    double acc = 0.0;
+    for (uint32_t k = c0 + threadIdx.x; k < c1; k += 256) acc += chunk_sum[k];
+    const double tot = block_sum_f64(acc);
+    if (threadIdx.x == 0) out[v] = (float)(tot / ((double)c.W * (double)c.H));
 }
 
 template <int B>
@@ -349,10 +373,12 @@ hipError_t launch_blend_bwd(const BlendBwdArgs& a, int lds_batch, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_entropy_mean(const float* block_H, const CamDev* cams, int n_views, float* out, hipStream_t s)
+hipError_t launch_entropy_mean(const float* block_H, const CamDev* cams, int n_views, uint32_t n_chunks,
+                               double* tmp, float* out, hipStream_t s)
 {
-    if (n_views == 0) return hipSuccess;
-    hipLaunchKernelGGL(entropy_mean_kernel, dim3(n_views), dim3(256), 0, s, block_H, cams, n_views, out);
+    if (n_views == 0 || n_chunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(entropy_chunk_kernel, dim3(n_chunks), dim3(256), 0, s, block_H, cams, n_views, tmp);
+    hipLaunchKernelGGL(entropy_mean_kernel, dim3(n_views), dim3(256), 0, s, tmp, cams, n_views, n_chunks, out);
     return hipGetLastError();
 }
 

@@ -28,7 +28,12 @@ struct CamDev {
     uint32_t pad0;
     int64_t pix_base;              // first pixel of this view in the packed outputs
     double limx_d, limy_d;         // the clamp bounds in FP64 (the clamp decision is taken in FP64)
+    uint32_t hred_base;            // first entropy-reduction chunk of this view (kRedChunk blocks each)
+    uint32_t l1_base;              // first L1 block of this view (kL1Block pixels each)
 };
+
+constexpr int kRedChunk = 1024;    // 8x8 blocks summed per entropy-reduction chunk
+constexpr int kL1Block = 256;      // pixels per L1 block
 
 // Projected record of one (view, Gaussian): three float4
 //   r0 = (mean x, mean y, conic A, conic B)
@@ -142,10 +147,11 @@ hipError_t launch_view_pairs(const uint2* ranges, const CamDev* cams, int n_view
 
 hipError_t launch_blend_fwd(const BlendFwdArgs& a, int lds_batch, hipStream_t s);
 hipError_t launch_blend_bwd(const BlendBwdArgs& a, int lds_batch, hipStream_t s);
-size_t l1_tmp_doubles(int64_t n_pix);
-hipError_t launch_l1(const float* rgb, const float* target, const CamDev* cams, int n_views, int64_t n_pix,
+// n_l1_blocks = sum over views of ceil(W H / kL1Block); tmp holds n_l1_blocks doubles
+hipError_t launch_l1(const float* rgb, const float* target, const CamDev* cams, int n_views, uint32_t n_l1_blocks,
                      float* grad, float* loss, double* tmp, hipStream_t s);
-hipError_t launch_entropy_mean(const float* block_H, const CamDev* cams, int n_views, float* out_mean,
-                               hipStream_t s);
+// n_chunks = sum over views of ceil(blocks_v / kRedChunk); tmp holds n_chunks doubles
+hipError_t launch_entropy_mean(const float* block_H, const CamDev* cams, int n_views, uint32_t n_chunks,
+                               double* tmp, float* out_mean, hipStream_t s);
 
 }  // namespace gsr

@@ -70,3 +70,34 @@ def oracle_stagewise(pr_gpu: dict, cam, tile, pix=None):
                      ranges, vals, pix)
     img["values"], img["ranges"] = vals, ranges
     return img
+
+
+def oracle_grads(scene, cams, targets, gamma, tile, gpu_rgb=None, ambiguous=1e-5, flags=orc.DEFAULT_FLAGS):
+    """FP64 oracle gradient of L = sum_v [L1_v + gamma L_E,v].
+
+    L1 has a kink at C = target.  Where |C_oracle - target| <= `ambiguous`
+    (below the FP32 image tolerance) either sign is a correct reading, so the
+    oracle takes the GPU's sign there (`gpu_rgb`, packed [P, 3]); everywhere
+    else the two sign patterns must agree, which is asserted."""
+    acc = None
+    L = 0.0
+    off = 0
+    for cam, tgt in zip(cams, targets):
+        f = orc.forward_view(scene, cam, tile, flags)
+        M = cam.width * cam.height
+        diff = f["rgb"] - tgt.astype(np.float64)
+        sign = np.sign(diff)
+        if gpu_rgb is not None:
+            g_img = np.asarray(gpu_rgb[off:off + M], np.float64).reshape(cam.height, cam.width, 3)
+            gs = np.sign(g_img - tgt.astype(np.float64))
+            amb = np.abs(diff) <= ambiguous
+            assert np.all((sign == gs) | amb), "L1 sign disagreement outside the ambiguity band"
+            sign = np.where(amb, gs, sign)
+        L += float(np.abs(diff).mean()) + gamma * f["L_E"]
+        pr = f["proj"]
+        g2 = orc.backward_render(cam.width, cam.height, tile[0], tile[1], pr["mean2d"], pr["conic"],
+                                 pr["opacity"], pr["rgb"], f["ranges"], f["values"], sign / diff.size,
+                                 np.full((cam.height, cam.width), gamma / M))
+        acc = orc.backward_project(scene, cam, g2, flags, acc)
+        off += M
+    return L, acc

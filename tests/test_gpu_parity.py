@@ -19,8 +19,8 @@ import torch
 from oracle import oracle as orc
 from paper_2603_09277_amd import gsr, scenes
 
-from gpu_helpers import (DEV, KEYS, gpu_backward, gpu_forward, gpu_records, oracle_stagewise, rel_norm,
-                         split_pixels, to_dev)
+from gpu_helpers import (DEV, KEYS, gpu_backward, gpu_forward, gpu_records, oracle_grads, oracle_stagewise,
+                         rel_norm, split_pixels, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -246,7 +246,7 @@ def test_projection_backward_stagewise(R, tiny):
 def test_gradients_end_to_end_tiny(R, tiny):
     scene, cams = tiny
     t, opts, out, target, g_rgb, grads = _tiny_backward(R, scene, cams)
-    L, g_o, _ = orc.loss_and_grads(scene, cams, [target], GAMMA, (16, 16))
+    L, g_o = oracle_grads(scene, cams, [target], GAMMA, (16, 16), out["rgb"].cpu().numpy())
     for k in KEYS:
         assert rel_norm(grads[k], g_o[k]) < GRAD_TOL, (k, rel_norm(grads[k], g_o[k]))
 
@@ -263,7 +263,7 @@ def test_gradients_sh3_scene(R):
     g_rgb = l1_grad_torch(out["rgb"], target)
     g_le = torch.full((1,), 0.3, device=DEV)
     grads = gpu_backward(R, t, cams, opts, out, g_rgb, None, g_le)
-    L, g_o, _ = orc.loss_and_grads(scene, cams, [target], 0.3, (16, 16))
+    L, g_o = oracle_grads(scene, cams, [target], 0.3, (16, 16), out["rgb"].cpu().numpy())
     for k in KEYS:
         assert rel_norm(grads[k], g_o[k]) < GRAD_TOL, (k, rel_norm(grads[k], g_o[k]))
 
@@ -335,7 +335,7 @@ def test_bf16_sh_storage(R):
     target = scenes.target_image(43, 192, 256)
     g_rgb = l1_grad_torch(out["rgb"], target)
     grads = gpu_backward(R, t, cams, opts, out, g_rgb, None, torch.full((1,), GAMMA, device=DEV))
-    L, g_o, _ = orc.loss_and_grads(scene, cams, [target], GAMMA, (16, 16))
+    L, g_o = oracle_grads(scene, cams, [target], GAMMA, (16, 16), out["rgb"].cpu().numpy())
     for k in ("means", "scales", "quats", "opacities"):
         assert rel_norm(grads[k], g_o[k]) < GRAD_TOL, k
     # SH gradients are stored in bfloat16: within 1 bf16 ulp of bf16(g*) where g* is well away from zero
@@ -380,8 +380,8 @@ def test_autograd_function_matches_raw(R, tiny):
     target = scenes.target_image(101, 128, 128)
     loss = (rgb - torch.from_numpy(target.reshape(-1, 3)).to(DEV)).abs().mean() + GAMMA * em.sum()
     loss.backward()
-    L, g_o, _ = orc.loss_and_grads(scene, cams, [target], GAMMA, (16, 16))
-    assert abs(float(loss) - L) < 1e-5
+    L, g_o = oracle_grads(scene, cams, [target], GAMMA, (16, 16), rgb.detach().cpu().numpy())
+    assert abs(float(loss.detach()) - L) < 1e-5
     for k in KEYS:
         assert rel_norm(t[k].grad.cpu().numpy(), g_o[k]) < GRAD_TOL, k
 
@@ -625,3 +625,25 @@ def test_autotune_picks_a_valid_shape(R, tiny, tmp_path):
     assert best.tile in [(8, 8), (16, 16), (32, 8)] and best.lds_batch in (32, 64, 128, 256)
     again = R.autotune(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, cache)
     assert again == best
+
+
+def test_l1_loss_entry_point(R):
+    """gsr_l1_loss on packed views of uneven size: gradient sign/(3 M_v) exactly, loss per view."""
+    scene, _, _ = scenes.workload("tiny")
+    cams = _tiny_cams()
+    t = to_dev(scene)
+    out = gpu_forward(R, t, cams, gsr.RasterOptions(tile=(16, 16), sh_degree=0))
+    tg = np.concatenate([scenes.target_image(7 + v, c.height, c.width).reshape(-1, 3) for v, c in enumerate(cams)])
+    tg[5] = out["rgb"][5].cpu().numpy()               # one exact tie: sign(0) = 0
+    target = torch.from_numpy(tg).to(DEV)
+    grad, loss = R.l1_loss(cams, out["rgb"], target)
+    torch.cuda.synchronize()
+    rgb = out["rgb"].cpu().numpy()
+    off = gsr.pixel_offsets(cams)
+    for v, c in enumerate(cams):
+        M = c.width * c.height
+        d = rgb[off[v]:off[v + 1]] - tg[off[v]:off[v + 1]]
+        exp_g = (np.sign(d) * np.float32(1.0 / (3.0 * M))).astype(np.float32)
+        assert np.array_equal(grad.cpu().numpy()[off[v]:off[v + 1]], exp_g)
+        assert abs(float(loss[v]) - np.abs(d.astype(np.float64)).mean()) <= 1e-6 * np.abs(d).mean()
+    assert float(grad[5].abs().sum()) == 0.0

@@ -68,6 +68,7 @@ def stage_bytes(stage, n, V, sh_bytes, pairs, n_tiles, npix, evals_fwd, evals_bw
         "entropy_mean": 0,
         "blend_bwd": pairs * 40 + npix * 24 + n * V * 36,
         "project_bwd": n * (44 + sh_bytes) * 2 + vn * 36,
+        "grad_reduce": pairs * 36 + vn * 48,
     }[stage]
 
 

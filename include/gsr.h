@@ -199,9 +199,10 @@ typedef enum {
     GSR_STAGE_RANGES = 5,      /* per-tile [start, end) */
     GSR_STAGE_BLEND_FWD = 6,   /* front-to-back blend with entropy */
     GSR_STAGE_ENTROPY_MEAN = 7,/* per-view mean entropy */
-    GSR_STAGE_BLEND_BWD = 8,   /* back-to-front blend backward with Alg. 1 */
+    GSR_STAGE_BLEND_BWD = 8,   /* back-to-front blend backward with Alg. 1, per-pair gradient rows */
     GSR_STAGE_PROJECT_BWD = 9, /* projection backward, sum over views */
-    GSR_N_STAGES = 10
+    GSR_STAGE_GRAD_REDUCE = 10,/* per-Gaussian sum of the per-pair gradient rows */
+    GSR_N_STAGES = 11
 } gsr_stage;
 
 gsr_status gsr_set_timing(gsr_ctx* ctx, int32_t enable);
@@ -219,7 +220,10 @@ gsr_status gsr_autotune(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, cons
  * (synchronises `stream`); for stage-by-stage testing.  *bytes receives the
  * size of the buffer; dst may be NULL to query it. */
 typedef enum {
-    GSR_BUF_RECORDS = 0,       /* float[V*n][12]: mean x, y, conic A, B, C, opacity, r, g, b, 0, 0, 0 */
+    GSR_BUF_RECORDS = 0,       /* float[V*n][12]: mean x, y, A', B', C', opacity, r, g, b, eps, L, 0 with
+                                  the conic pre-scaled: A' = -A log2(e)/2, B' = -B log2(e), C' = -C log2(e)/2,
+                                  and (eps, L) the data the blend uses to skip Gaussians that cannot reach
+                                  alpha >= 1/255 anywhere in an 8x8 pixel block */
     GSR_BUF_RADIUS = 1,        /* int32[V*n], 0 = culled */
     GSR_BUF_DEPTH = 2,         /* float[V*n], camera z */
     GSR_BUF_TILES_TOUCHED = 3, /* int32[V*n] */

@@ -41,7 +41,7 @@ struct Layout {
     std::vector<CamDev> cams;
     uint32_t n_tiles = 0, n_blocks = 0, n_hchunks = 0, n_l1 = 0;
     int64_t n_pix = 0;
-    int tsx = 0, tsy = 0;
+    int tsx = 0, tsy = 0, spt = 1;
 };
 
 }  // namespace
@@ -53,7 +53,7 @@ struct gsr_ctx {
 
     // grow-only device buffers
     Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
-    Dev pk0, pk1, pv0, pv1, ranges, block_H, block_cnt, hchunk, counters, len_hist, view_pairs, l1_tmp;
+    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, ranges, block_H, block_cnt, hchunk, counters, len_hist, view_pairs, l1_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
     uint64_t gen_fwd = 0, gen_bwd = 0;
@@ -68,6 +68,7 @@ struct gsr_ctx {
     Layout lay;
     uint32_t vn = 0, n = 0, pairs = 0;
     int sorted_buf = 0;                    // which pair buffer holds the sorted lists
+    uint32_t pair_cap_used = 0;            // pair capacity the latest forward ran with
     int n_views = 0;
     gsr_opts fopts = {};
 
@@ -218,6 +219,7 @@ Layout make_layout(const gsr_camera* cams, int32_t n_views, const gsr_opts* o)
     Layout L;
     L.tsx = ilog2(o->tile_w);
     L.tsy = ilog2(o->tile_h);
+    L.spt = (o->tile_w * o->tile_h) / (kBlockPx * kBlockPx);
     uint32_t tb = 0, bb = 0, hb = 0, lb = 0;
     int64_t pb = 0;
     for (int v = 0; v < n_views; ++v) {
@@ -238,16 +240,15 @@ Layout make_layout(const gsr_camera* cams, int32_t n_views, const gsr_opts* o)
         d.gx = (k.width + o->tile_w - 1) / o->tile_w;
         d.gy = (k.height + o->tile_h - 1) / o->tile_h;
         d.tile_base = tb;
-        d.bx = (k.width + kBlockPx - 1) / kBlockPx;
-        d.by = (k.height + kBlockPx - 1) / kBlockPx;
+        d.n_wblocks = (uint32_t)(d.gx * d.gy * L.spt);
         d.block_base = bb;
         d.pix_base = pb;
         d.hred_base = hb;
         d.l1_base = lb;
-        hb += (uint32_t)((d.bx * d.by + kRedChunk - 1) / kRedChunk);
+        hb += (d.n_wblocks + kRedChunk - 1) / kRedChunk;
         lb += (uint32_t)(((int64_t)k.width * k.height + kL1Block - 1) / kL1Block);
         tb += (uint32_t)(d.gx * d.gy);
-        bb += (uint32_t)(d.bx * d.by);
+        bb += d.n_wblocks;
         pb += (int64_t)k.width * k.height;
         L.cams.push_back(d);
     }
@@ -282,7 +283,7 @@ gsr_status ensure_pairs(gsr_ctx* c, size_t p)
     if (p >= 0xfffffff0ull) return fail(c, GSR_ERR_CAPACITY, "pair count exceeds 2^32");
     gsr_status s;
     if ((s = grow(c, c->pk0, p * 4)) || (s = grow(c, c->pk1, p * 4)) || (s = grow(c, c->pv0, p * 4)) ||
-        (s = grow(c, c->pv1, p * 4)))
+        (s = grow(c, c->pv1, p * 4)) || (s = grow(c, c->emit_vg, p * 4)) || (s = grow(c, c->pair_grad, p * 4 * kG2)))
         return s;
     c->pair_cap = p;
     return GSR_OK;
@@ -359,7 +360,8 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     {
         StageTimer tm(c, st, GSR_STAGE_DUPLICATE, plain);
         HIP_TRY(c, launch_duplicate(od[0], (const uint32_t*)c->offsets.p, (const uint32_t*)c->tt.p,
-                                    (const uint2*)c->rect.p, dc, n, vn, counters, cap, pk[0], pv[0], counters + 1, st));
+                                    (const uint2*)c->rect.p, dc, n, vn, counters, cap, pk[0], pv[0],
+                                    (uint32_t*)c->emit_vg.p, counters + 1, st));
     }
     // stable sort of the pairs by tile id
     int tile_bits = std::max(1, ilog2((int)std::max<uint32_t>(L.n_tiles, 2)));
@@ -378,8 +380,9 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     }
 
     BlendFwdArgs ba;
-    ba.rec = (const float4*)c->rec.p; ba.pair_vals = pv[sb]; ba.ranges = (const uint2*)c->ranges.p; ba.cams = dc;
-    ba.n_views = (int32_t)V; ba.tile_shift_x = L.tsx; ba.tile_shift_y = L.tsy; ba.n_blocks = L.n_blocks;
+    ba.rec = (const float4*)c->rec.p; ba.pair_vals = pv[sb]; ba.emit_vg = (const uint32_t*)c->emit_vg.p;
+    ba.ranges = (const uint2*)c->ranges.p; ba.cams = dc;
+    ba.n_views = (int32_t)V; ba.tile_shift_x = L.tsx; ba.tile_shift_y = L.tsy; ba.spt = L.spt; ba.n_blocks = L.n_blocks;
     ba.out_rgb = out->rgb; ba.out_H = out->entropy; ba.out_T = out->t_final; ba.out_nc = out->n_contrib;
     ba.block_H = (float*)c->block_H.p;
     ba.block_cnt = (uint2*)c->block_cnt.p;
@@ -394,6 +397,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     }
     c->sorted_buf = sb;
     c->pairs = plain ? cap : 0;
+    c->pair_cap_used = cap;
     return GSR_OK;
 }
 
@@ -405,15 +409,23 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     const uint32_t n = (uint32_t)g->n, V = (uint32_t)L.cams.size(), vn = n * V;
     const CamDev* dc = (const CamDev*)c->cams.p;
     StageTimer tb(c, st, GSR_STAGE_BLEND_BWD, plain);
-    HIP_TRY(c, launch_fill_u32((uint32_t*)c->grad2d.p, 0u, (size_t)vn * kG2, st));
     uint32_t* pv[2] = { (uint32_t*)c->pv0.p, (uint32_t*)c->pv1.p };
     BlendBwdArgs bb;
-    bb.rec = (const float4*)c->rec.p; bb.pair_vals = pv[c->sorted_buf]; bb.ranges = (const uint2*)c->ranges.p;
-    bb.cams = dc; bb.n_views = (int32_t)V; bb.tile_shift_x = L.tsx; bb.tile_shift_y = L.tsy; bb.n_blocks = L.n_blocks;
+    bb.rec = (const float4*)c->rec.p; bb.pair_vals = pv[c->sorted_buf]; bb.emit_vg = (const uint32_t*)c->emit_vg.p;
+    bb.ranges = (const uint2*)c->ranges.p;
+    bb.cams = dc; bb.n_views = (int32_t)V; bb.tile_shift_x = L.tsx; bb.tile_shift_y = L.tsy; bb.spt = L.spt;
+    bb.n_blocks = L.n_blocks;
     bb.T_final = saved->t_final; bb.n_contrib = saved->n_contrib; bb.grad_rgb = grad_rgb; bb.grad_H = grad_H;
-    bb.grad_LE = grad_LE; bb.grad2d = (float*)c->grad2d.p;
+    bb.grad_LE = grad_LE; bb.pair_grad = (float*)c->pair_grad.p;
     HIP_TRY(c, launch_blend_bwd(bb, o->lds_batch == 0 ? 64 : o->lds_batch, st));
     tb.stop();
+    {
+        StageTimer tr(c, st, GSR_STAGE_GRAD_REDUCE, plain);
+        uint32_t* od0 = (uint32_t*)c->ord0.p;
+        HIP_TRY(c, launch_grad_reduce(od0, (const uint32_t*)c->offsets.p, (const uint32_t*)c->tt.p,
+                                      (const float*)c->pair_grad.p, vn, (const uint32_t*)c->counters.p,
+                                      (uint32_t)c->pair_cap_used, (float*)c->grad2d.p, st));
+    }
     StageTimer tp(c, st, GSR_STAGE_PROJECT_BWD, plain);
     ProjectBwdArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
@@ -511,7 +523,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     drop_graphs(c);
     Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->radius,
                    &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
-                   &c->pv1, &c->ranges, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->len_hist, &c->view_pairs,
+                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->ranges, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->len_hist, &c->view_pairs,
                    &c->l1_tmp };
     for (Dev* d : all) free_dev(*d);
     for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
@@ -783,7 +795,21 @@ gsr_status gsr_inspect(gsr_ctx* c, void* stream, gsr_buffer which, void* dst, in
         case GSR_BUF_RADIUS: src = c->radius.p; sz = (size_t)c->vn * 4; break;
         case GSR_BUF_DEPTH: src = c->depth.p; sz = (size_t)c->vn * 4; break;
         case GSR_BUF_TILES_TOUCHED: src = c->tt.p; sz = (size_t)c->vn * 4; break;
-        case GSR_BUF_PAIR_VALUES: src = pv[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
+        case GSR_BUF_PAIR_VALUES: {       // emission index -> view*n + Gaussian index, on the host
+            sz = (size_t)c->pairs * 4;
+            *bytes = (int64_t)sz;
+            if (!dst) return GSR_OK;
+            if ((int64_t)sz > capacity_bytes) return fail(c, GSR_ERR_INVALID_ARG, "destination too small");
+            std::vector<uint32_t> e(c->pairs), m(c->pairs);
+            if (sz) {
+                HIP_TRY(c, hipMemcpyAsync(e.data(), pv[c->sorted_buf], sz, hipMemcpyDeviceToHost, st));
+                HIP_TRY(c, hipMemcpyAsync(m.data(), c->emit_vg.p, sz, hipMemcpyDeviceToHost, st));
+            }
+            HIP_TRY(c, hipStreamSynchronize(st));
+            uint32_t* out = (uint32_t*)dst;
+            for (uint32_t i = 0; i < c->pairs; ++i) out[i] = m[e[i]];
+            return GSR_OK;
+        }
         case GSR_BUF_PAIR_TILES: src = pk[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
         case GSR_BUF_RANGES: src = c->ranges.p; sz = (size_t)c->lay.n_tiles * 8; break;
         case GSR_BUF_GRAD2D: src = c->grad2d.p; sz = (size_t)c->vn * 4 * kG2; break;

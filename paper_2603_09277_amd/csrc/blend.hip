@@ -2,14 +2,35 @@
 // (Sec. 3, Eq. 3-5; Sec. 3.3, Eq. 8-11) and the back-to-front backward with
 // the O(N) entropy gradient of Alg. 1 (Sec. 3.4, Eq. 13-15; Suppl. C).
 //
-// Work decomposition: every 64-lane wavefront owns one 8x8 pixel block (one
-// pixel per lane) and walks the Gaussian list of the tile that contains the
-// block.  Tiles are 8x8, 16x16 or 32x8 pixels, so a tile holds 1 or 4
-// blocks; the tile size sets the sort granularity, the wavefront size sets
-// the blend granularity.  Each wavefront stages its list in LDS in batches of
-// B records (its own LDS region, so no workgroup barrier is ever needed and a
-// wavefront whose pixels are all saturated leaves at once), and every lane
-// reads the staged record as an LDS broadcast.
+// Work decomposition.  Every 64-lane wavefront owns one 8x8 pixel block (one
+// pixel per lane) and walks the Gaussian list of the tile that contains it.
+// Wave blocks are numbered tile-major: a 16x16 or 32x8 tile is one workgroup
+// of 4 wavefronts (its 4 blocks), an 8x8 tile is one wavefront.  The tile
+// shape sets the sort granularity; the wavefront sets the blend granularity.
+//
+// Forward: each wavefront stages its list in LDS in batches of B records
+// (its own LDS region: no workgroup barrier, and a wavefront whose 64 pixels
+// are all saturated leaves at the next batch boundary).
+//
+// Culling: while staging, every wavefront drops the Gaussians that cannot
+// reach alpha >= 1/255 at any pixel centre of its 8x8 block: the exact maximum
+// of the (concave) exponent over the block's pixel-centre rectangle, plus a
+// bound on the FP32 evaluation error, is below the skip threshold.  Those
+// entries would be skipped by every lane anyway, so results are unchanged;
+// the list walk only visits the survivors, compacted in list order.
+//
+// Backward: list windows of B entries are walked from the back.  In a 16x16
+// or 32x8 tile the 4 wavefronts share each window's records.  Per Gaussian,
+// every wavefront sums its partial gradients over each 16-lane row by DPP and
+// the 4 row leaders write them to their own LDS slots; the window's 16 slots
+// (4 wavefronts x 4 rows) are summed in a fixed order and stored once per
+// (tile, Gaussian) pair, in the pair's emission slot.  A segmented reduction over each Gaussian's
+// contiguous emission range then yields its 2D gradient.  No float atomics
+// touch global memory, so gradients are bit-reproducible.
+//
+// The conic is stored pre-scaled by -log2(e)/2 (-log2(e) for B) so the
+// exponent is in log2 units: alpha = min(0.99, opacity * 2^p); the entropy is
+// accumulated in log2 units and scaled by ln 2 once per pixel.
 #include "internal.h"
 
 namespace gsr {
@@ -18,6 +39,7 @@ namespace {
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTStop = 1e-4f;
+constexpr float kLn2 = 0.6931471805599453f;
 constexpr int kWavesPerGroup = 4;
 
 __device__ __forceinline__ void wave_lds_sync()
@@ -27,30 +49,28 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// exponent of the 2D Gaussian at offset (dx, dy) = mean - pixel centre:
-//   -1/2 (A dx^2 + C dy^2) - B dx dy, evaluated with explicit FMAs so the
-//   forward and backward kernels produce bit-identical alphas.
-__device__ __forceinline__ float gauss_power(float A, float B, float C, float dx, float dy)
+// exponent (log2 units) of the 2D Gaussian at offset (dx, dy) = mean - pixel:
+//   p = A' dx^2 + B' dx dy + C' dy^2  with the pre-scaled conic (A', B', C');
+// explicit FMAs so forward and backward produce bit-identical alphas.
+__device__ __forceinline__ float gauss_p2(float A2, float B2, float C2, float dx, float dy)
 {
-    float q = fmaf(A * dx, dx, fmaf(C * dy, dy, (2.f * B) * (dx * dy)));
-    return -0.5f * q;
+    return fmaf(dx, fmaf(A2, dx, B2 * dy), (C2 * dy) * dy);
 }
 
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_f(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
 }
 
-// sum over the 64 lanes; the total is valid in lane 63
-__device__ __forceinline__ float wave_sum_to_lane63(float x)
+// sum over each row of 16 lanes in a fixed order; every lane of the row
+// receives its row's sum
+__device__ __forceinline__ float row_sum16(float x)
 {
     x += dpp_f<0xb1, 0xf>(x);    // quad_perm [1,0,3,2]
     x += dpp_f<0x4e, 0xf>(x);    // quad_perm [2,3,0,1]
     x += dpp_f<0x141, 0xf>(x);   // row_half_mirror
-    x += dpp_f<0x140, 0xf>(x);   // row_mirror: every lane holds its row's sum
-    x += dpp_f<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
-    x += dpp_f<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+    x += dpp_f<0x140, 0xf>(x);   // row_mirror
     return x;
 }
 
@@ -84,80 +104,136 @@ struct BlockGeom {
     bool inside;
     uint32_t tile;
     int64_t pix;
+    float cx0, cx1, cy0, cy1;        // pixel-centre rectangle of the block's in-image pixels
 };
 
-__device__ __forceinline__ BlockGeom block_geom(const CamDev* cams, int n_views, uint32_t wblock, uint32_t lane,
-                                                int tsx, int tsy)
+// max over v in [v0, v1] of the concave f(v) = a u^2 + b u v + c v^2 (c < 0)
+__device__ __forceinline__ float edge_max(float a, float b, float c, float u, float v0, float v1, float hc)
+{
+    const float v = fminf(fmaxf(-b * u * hc, v0), v1);     // hc = 1 / (2c)
+    return fmaf(u, fmaf(a, u, b * v), (c * v) * v);
+}
+
+// true if the Gaussian cannot reach alpha >= 1/255 at any pixel centre of the
+// block: r0 = (mean, A', B'), c2 = C', eps = 2e-6 (|A'|+|B'|+|C'|), L = log2(255 opacity) + 1e-4
+__device__ __forceinline__ bool culled(const BlockGeom& g, float4 r0, float c2, float eps, float L)
+{
+    const float u0 = g.cx0 - r0.x, u1 = g.cx1 - r0.x;       // pixel - mean
+    const float v0 = g.cy0 - r0.y, v1 = g.cy1 - r0.y;
+    const float a = r0.z, b = r0.w, c = c2;
+    float qmax;
+    if (u0 <= 0.f && u1 >= 0.f && v0 <= 0.f && v1 >= 0.f) {
+        qmax = 0.f;                                          // the mean lies over the block
+    } else {
+        const float hc = 0.5f / c, ha = 0.5f / a;
+        qmax = fmaxf(fmaxf(edge_max(a, b, c, u0, v0, v1, hc), edge_max(a, b, c, u1, v0, v1, hc)),
+                     fmaxf(edge_max(c, b, a, v0, u0, u1, ha), edge_max(c, b, a, v1, u0, u1, ha)));
+    }
+    const float dmax2 = fmaxf(u0 * u0, u1 * u1) + fmaxf(v0 * v0, v1 * v1);
+    return qmax + eps * dmax2 < -L;
+}
+
+// wave block id -> view, tile, pixel of this lane (tile-major numbering,
+// `spt` = 8x8 blocks per tile: 1 or 4)
+__device__ __forceinline__ BlockGeom block_geom(const CamDev* cams, int n_views, uint32_t wb, uint32_t lane,
+                                                int tsx, int tsy, int spt)
 {
     BlockGeom g;
+    const uint32_t tile = wb / (uint32_t)spt, sub = wb % (uint32_t)spt;
     int v = 0;
-    while (v + 1 < n_views && cams[v + 1].block_base <= wblock) ++v;
+    while (v + 1 < n_views && cams[v + 1].tile_base <= tile) ++v;
     const CamDev& c = cams[v];
-    uint32_t b = wblock - c.block_base;
-    uint32_t bxi = b % (uint32_t)c.bx, byi = b / (uint32_t)c.bx;
+    const uint32_t lt = tile - c.tile_base;
+    const uint32_t tx = lt % (uint32_t)c.gx, ty = lt / (uint32_t)c.gx;
+    uint32_t sx = 0, sy = 0;
+    if (spt == 4) {
+        if (tsx == 4) { sx = sub & 1u; sy = sub >> 1; }   // 16x16: 2x2 blocks
+        else { sx = sub; sy = 0; }                         // 32x8: 4x1 blocks
+    }
     g.view = v;
-    g.px = (int)(bxi * kBlockPx + (lane & 7u));
-    g.py = (int)(byi * kBlockPx + (lane >> 3));
+    g.tile = tile;
+    g.px = (int)((tx << tsx) + sx * kBlockPx + (lane & 7u));
+    g.py = (int)((ty << tsy) + sy * kBlockPx + (lane >> 3));
     g.inside = g.px < c.W && g.py < c.H;
-    g.tile = c.tile_base + ((byi * kBlockPx) >> tsy) * (uint32_t)c.gx + ((bxi * kBlockPx) >> tsx);
     g.pix = c.pix_base + (int64_t)g.py * c.W + g.px;
+    const int bx0 = (int)((tx << tsx) + sx * kBlockPx), by0 = (int)((ty << tsy) + sy * kBlockPx);
+    g.cx0 = (float)bx0 + 0.5f;
+    g.cy0 = (float)by0 + 0.5f;
+    g.cx1 = (float)min(bx0 + kBlockPx - 1, c.W - 1) + 0.5f;
+    g.cy1 = (float)min(by0 + kBlockPx - 1, c.H - 1) + 0.5f;
     return g;
 }
 
 template <int B>
 __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
 {
-    __shared__ float4 s_rec[kWavesPerGroup][B][kRecF4];
+    __shared__ float4 s_g0[kWavesPerGroup][B];   // mean x, mean y, A', B'
+    __shared__ float4 s_g1[kWavesPerGroup][B];   // C', opacity, red, green
+    __shared__ float s_b[kWavesPerGroup][B];     // blue
+    __shared__ int32_t s_pos[kWavesPerGroup][B]; // position in the tile list
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
-    const uint32_t wblock = blockIdx.x * kWavesPerGroup + wid;
-    if (wblock >= a.n_blocks) return;
-    const BlockGeom g = block_geom(a.cams, a.n_views, wblock, lane, a.tile_shift_x, a.tile_shift_y);
+    const uint32_t wb = blockIdx.x * kWavesPerGroup + wid;
+    if (wb >= a.n_blocks) return;
+    const BlockGeom g = block_geom(a.cams, a.n_views, wb, lane, a.tile_shift_x, a.tile_shift_y, a.spt);
     const uint2 rg = a.ranges[g.tile];
     const float fpx = (float)g.px + 0.5f, fpy = (float)g.py + 0.5f;
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
 
-    float T = 1.f, Cr = 0.f, Cg = 0.f, Cb = 0.f, H = 0.f;
-    int32_t last = 0;
-    uint32_t n_eval = 0;
+    float T = 1.f, Cr = 0.f, Cg = 0.f, Cb = 0.f, H2 = 0.f;   // H2: entropy in log2 units
+    int32_t last = 0, stop_pos = -1;
     bool done = !g.inside;
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
         if (__ballot(!done) == 0ull) break;
         const uint32_t cnt = (rg.y - bs) < (uint32_t)B ? (rg.y - bs) : (uint32_t)B;
-        for (uint32_t j = lane; j < cnt; j += kWave) {
-            const float4* r = a.rec + (size_t)kRecF4 * a.pair_vals[bs + j];
-            s_rec[wid][j][0] = r[0];
-            s_rec[wid][j][1] = r[1];
-            s_rec[wid][j][2] = r[2];
+        // stage the batch, keeping (in list order) only Gaussians that can reach this block
+        uint32_t m = 0;
+        for (uint32_t j0 = 0; j0 < cnt; j0 += kWave) {
+            const uint32_t j = j0 + lane;
+            bool keep = false;
+            float4 r0, r1, r2;
+            if (j < cnt) {
+                const float4* r = a.rec + (size_t)kRecF4 * a.emit_vg[a.pair_vals[bs + j]];
+                r0 = r[0];
+                r1 = r[1];
+                r2 = r[2];
+                keep = !culled(g, r0, r1.x, r2.y, r2.z);
+            }
+            const uint64_t bal = __ballot(keep);
+            if (keep) {
+                const uint32_t k = m + (uint32_t)__popcll(bal & lt_mask);
+                s_g0[wid][k] = r0;
+                s_g1[wid][k] = r1;
+                s_b[wid][k] = r2.x;
+                s_pos[wid][k] = (int32_t)(bs + j - rg.x);
+            }
+            m += (uint32_t)__popcll(bal);
         }
         wave_lds_sync();
-        for (uint32_t j = 0; j < cnt; ++j) {
-            if (__ballot(!done) == 0ull) break;
-            if (!done) {
-                const float4 r0 = s_rec[wid][j][0];
-                const float4 r1 = s_rec[wid][j][1];
-                const float dx = r0.x - fpx, dy = r0.y - fpy;
-                const float e = __expf(gauss_power(r0.z, r0.w, r1.x, dx, dy));
-                const float alpha = fminf(kAlphaMax, r1.y * e);
-                ++n_eval;
-                if (alpha >= kAlphaMin) {
-                    const float Tn = T * (1.f - alpha);
-                    if (Tn < kTStop) {
-                        done = true;
-                    } else {
-                        const float w = alpha * T;
-                        const float cb = s_rec[wid][j][2].x;
-                        Cr = fmaf(w, r1.z, Cr);
-                        Cg = fmaf(w, r1.w, Cg);
-                        Cb = fmaf(w, cb, Cb);
-                        H = fmaf(-w, __logf(w), H);       // -w log w   (Eq. 10)
-                        T = Tn;
-                        last = (int32_t)(bs + j - rg.x + 1);
-                    }
+        for (uint32_t k = 0; k < m; ++k) {
+            const float4 g0 = s_g0[wid][k];
+            const float4 g1 = s_g1[wid][k];
+            const float p = gauss_p2(g0.z, g0.w, g1.x, g0.x - fpx, g0.y - fpy);
+            const float alpha = fminf(kAlphaMax, g1.y * __builtin_amdgcn_exp2f(p));
+            if (!done && alpha >= kAlphaMin) {
+                const float Tn = T * (1.f - alpha);
+                if (Tn < kTStop) {
+                    done = true;
+                    stop_pos = s_pos[wid][k];
+                } else {
+                    const float w = alpha * T;
+                    Cr = fmaf(w, g1.z, Cr);
+                    Cg = fmaf(w, g1.w, Cg);
+                    Cb = fmaf(w, s_b[wid][k], Cb);
+                    H2 = fmaf(-w, __builtin_amdgcn_logf(w), H2);    // -w log2 w   (Eq. 10)
+                    T = Tn;
+                    last = s_pos[wid][k] + 1;
                 }
             }
         }
         wave_lds_sync();
     }
-    H = fmaf(-T, logf(T), H);                           // background weight T_{N+1}  (Eq. 9-10)
+    // background weight T_{N+1} (Eq. 9-10), then natural-log units
+    const float H = kLn2 * fmaf(-T, __builtin_amdgcn_logf(T), H2);
     if (g.inside) {
         a.out_rgb[3 * g.pix + 0] = Cr;
         a.out_rgb[3 * g.pix + 1] = Cg;
@@ -166,125 +242,187 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
         a.out_T[g.pix] = T;
         a.out_nc[g.pix] = last;
     }
-    float hs = wave_sum_all(g.inside ? H : 0.f);
-    uint32_t ne = (uint32_t)wave_sum_all_i((int)n_eval);
-    uint32_t nc = (uint32_t)wave_sum_all_i(last);
+    // list positions this pixel visited (the stopping entry included), culled ones counted
+    const int32_t n_eval = !g.inside ? 0 : (stop_pos >= 0 ? stop_pos + 1 : (int32_t)(rg.y - rg.x));
+    const float hs = wave_sum_all(g.inside ? H : 0.f);
+    const uint32_t ne = (uint32_t)wave_sum_all_i(n_eval);
+    const uint32_t nc = (uint32_t)wave_sum_all_i(last);
     if (lane == 0) {
-        a.block_H[wblock] = hs;
-        a.block_cnt[wblock] = make_uint2(ne, nc);
+        a.block_H[wb] = hs;
+        a.block_cnt[wb] = make_uint2(ne, nc);
     }
 }
 
-template <int B>
-__global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
-{
-    __shared__ float4 s_rec[kWavesPerGroup][B][kRecF4];
-    __shared__ uint32_t s_vg[kWavesPerGroup][B];
-    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
-    const uint32_t wblock = blockIdx.x * kWavesPerGroup + wid;
-    if (wblock >= a.n_blocks) return;
-    const BlockGeom g = block_geom(a.cams, a.n_views, wblock, lane, a.tile_shift_x, a.tile_shift_y);
-    const uint2 rg = a.ranges[g.tile];
-    const float fpx = (float)g.px + 0.5f, fpy = (float)g.py + 0.5f;
+// Per-lane state of the backward walk of one pixel.
+struct BwdPix {
+    int32_t n;                       // list positions to walk (n_contrib)
+    float T;                         // T_{i+1} while walking back; starts at T_final
+    float gCr, gCg, gCb, gh;         // dL/dC, dL/dH of this pixel
+    float Sr, Sg, Sb;                // S_{i+1} = sum_{k>i} w_k c_k
+    float Rs;                        // R_{i+1} of Alg. 1
+    float fpx, fpy;
+};
 
-    int32_t n = 0;
-    float T = 1.f, gCr = 0.f, gCg = 0.f, gCb = 0.f, gh = 0.f;
-    const int32_t len = (int32_t)(rg.y - rg.x);
+// Contribution of list entry `pos` to the 9 gradient components of its
+// Gaussian, for one pixel.  Branch-free: every lane evaluates the entry and a
+// lane whose pixel did not blend it (position past its last contributor, or
+// alpha < 1/255) contributes zero and keeps its state.
+__device__ __forceinline__ void bwd_entry(BwdPix& q, int32_t pos, float4 g0, float4 g1, float cb, float* o)
+{
+    const float dx = g0.x - q.fpx, dy = g0.y - q.fpy;
+    const float e2 = __builtin_amdgcn_exp2f(gauss_p2(g0.z, g0.w, g1.x, dx, dy));
+    const float a_raw = g1.y * e2;
+    const float alpha = fminf(kAlphaMax, a_raw);
+    const bool act = (pos < q.n) & (alpha >= kAlphaMin);
+    const float rom = __builtin_amdgcn_rcpf(1.f - alpha);
+    const float Ti = q.T * rom;                              // T_i = T_{i+1} / (1 - alpha_i)
+    const float w = alpha * Ti;
+    const float lw = kLn2 * __builtin_amdgcn_logf(act ? w : 1.f);   // ln w_i
+    // dC/dalpha_i = T_i c_i - S_{i+1} / (1 - alpha_i);  dH/dalpha_i by Eq. 15
+    float dal = q.gCr * (Ti * g1.z - q.Sr * rom) + q.gCg * (Ti * g1.w - q.Sg * rom) + q.gCb * (Ti * cb - q.Sb * rom);
+    dal += q.gh * ((-lw - 1.f) * Ti + q.Rs * rom);
+    const float wa = act ? w : 0.f;
+    const float dg = (act & (a_raw <= kAlphaMax)) ? dal : 0.f;   // zero in the clamped branch
+    o[6] = wa * q.gCr;
+    o[7] = wa * q.gCg;
+    o[8] = wa * q.gCb;
+    o[5] = e2 * dg;                                          // d alpha / d opacity = 2^p
+    const float dp = alpha * dg;                             // dL/d(exponent in natural-log units)
+    o[2] = (-0.5f * dx) * dx * dp;                           // conic A, B, C (unscaled)
+    o[3] = -dx * dy * dp;
+    o[4] = (-0.5f * dy) * dy * dp;
+    const float dpl = kLn2 * dp;
+    o[0] = dpl * fmaf(2.f * g0.z, dx, g0.w * dy);            // mean x
+    o[1] = dpl * fmaf(2.f * g1.x, dy, g0.w * dx);            // mean y
+    q.Sr = fmaf(wa, g1.z, q.Sr);
+    q.Sg = fmaf(wa, g1.w, q.Sg);
+    q.Sb = fmaf(wa, cb, q.Sb);
+    q.Rs = fmaf(lw + 1.f, wa, q.Rs);                         // R_i = (log w_i + 1) w_i + R_{i+1}
+    q.T = act ? Ti : q.T;
+}
+
+__device__ __forceinline__ void bwd_init(const BlendBwdArgs& a, const BlockGeom& g, int32_t len, BwdPix& q)
+{
+    q.n = 0; q.T = 1.f; q.gCr = q.gCg = q.gCb = q.gh = 0.f;
     if (g.inside) {
-        n = a.n_contrib[g.pix];
-        n = n < 0 ? 0 : (n > len ? len : n);       // never walk past this tile's list
-        T = a.T_final[g.pix];
-        gCr = a.grad_rgb[3 * g.pix + 0];
-        gCg = a.grad_rgb[3 * g.pix + 1];
-        gCb = a.grad_rgb[3 * g.pix + 2];
-        if (a.grad_H) gh = a.grad_H[g.pix];
+        int32_t n = a.n_contrib[g.pix];
+        q.n = n < 0 ? 0 : (n > len ? len : n);               // never walk past this tile's list
+        q.T = a.T_final[g.pix];
+        q.gCr = a.grad_rgb[3 * g.pix + 0];
+        q.gCg = a.grad_rgb[3 * g.pix + 1];
+        q.gCb = a.grad_rgb[3 * g.pix + 2];
+        if (a.grad_H) q.gh = a.grad_H[g.pix];
         if (a.grad_LE) {
             const CamDev& c = a.cams[g.view];
-            gh += a.grad_LE[g.view] / (float)((int64_t)c.W * c.H);
+            q.gh += a.grad_LE[g.view] / (float)((int64_t)c.W * c.H);
         }
     }
-    // suffix sums, Alg. 1:  R_{N+1} = (log w_{N+1} + 1) w_{N+1} with w_{N+1} = T_final
-    float Sr = 0.f, Sg = 0.f, Sb = 0.f;
-    float Rs = (logf(T) + 1.f) * T;
-    const int32_t maxn = wave_max_i32(n);
+    q.Sr = q.Sg = q.Sb = 0.f;
+    q.Rs = (logf(q.T) + 1.f) * q.T;                          // Alg. 1: R_{N+1} = (log T_final + 1) T_final
+    q.fpx = (float)g.px + 0.5f;
+    q.fpy = (float)g.py + 0.5f;
+}
+
+// SHARED: the 4 wavefronts of the workgroup are the 4 blocks of one tile and
+// share each window; otherwise every wavefront has its own tile and window.
+template <int B, bool SHARED>
+__global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
+{
+    constexpr int NS = SHARED ? 1 : kWavesPerGroup;          // LDS slots
+    __shared__ float4 s_g0[NS][B];
+    __shared__ float4 s_g1[NS][B];
+    __shared__ float s_b[NS][B];
+    __shared__ float2 s_cull[NS][B];                    // (eps, L)
+    __shared__ uint32_t s_e[NS][B];
+    __shared__ float s_acc[kWavesPerGroup * 4][B * kG2]; // per (wavefront, 16-lane row) partial sums
+    __shared__ int32_t s_idx[kWavesPerGroup][B];        // surviving window entries of each wavefront
+    __shared__ int32_t s_max[kWavesPerGroup];
+    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+    const uint32_t slot = SHARED ? 0u : wid;
+    const uint32_t wb = blockIdx.x * kWavesPerGroup + wid;
+    if (wb >= a.n_blocks) return;                            // SHARED: whole workgroups only
+    const BlockGeom g = block_geom(a.cams, a.n_views, wb, lane, a.tile_shift_x, a.tile_shift_y, a.spt);
+    const uint2 rg = a.ranges[g.tile];
+    const int32_t len = (int32_t)(rg.y - rg.x);
+    BwdPix q;
+    bwd_init(a, g, len, q);
+    const int32_t wave_n = wave_max_i32(q.n);
+    int32_t maxn = wave_n;
+    if (SHARED) {
+        if (lane == 0) s_max[wid] = wave_n;
+        __syncthreads();
+        maxn = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+    }
+    const int32_t nthr = SHARED ? 256 : 64;
+    const int32_t tid = SHARED ? (int32_t)threadIdx.x : (int32_t)lane;
+    for (int32_t r = 0; r < 4; ++r)
+        for (int32_t i = (int32_t)lane; i < B * kG2; i += kWave) s_acc[wid * 4 + r][i] = 0.f;
+    float* acc_row = s_acc[wid * 4 + (lane >> 4)];
 
     for (int32_t hi = maxn; hi > 0; hi -= B) {
         const int32_t lo = hi - B > 0 ? hi - B : 0;
         const int32_t cnt = hi - lo;
-        for (int32_t j = (int32_t)lane; j < cnt; j += kWave) {
-            const uint32_t vg = a.pair_vals[rg.x + (uint32_t)(lo + j)];
-            const float4* r = a.rec + (size_t)kRecF4 * vg;
-            s_vg[wid][j] = vg;
-            s_rec[wid][j][0] = r[0];
-            s_rec[wid][j][1] = r[1];
-            s_rec[wid][j][2] = r[2];
+        // stage the window
+        for (int32_t j = tid; j < cnt; j += nthr) {
+            const uint32_t e = a.pair_vals[rg.x + (uint32_t)(lo + j)];
+            const float4* r = a.rec + (size_t)kRecF4 * a.emit_vg[e];
+            const float4 r2 = r[2];
+            s_e[slot][j] = e;
+            s_g0[slot][j] = r[0];
+            s_g1[slot][j] = r[1];
+            s_b[slot][j] = r2.x;
+            s_cull[slot][j] = make_float2(r2.y, r2.z);
+        }
+        if (SHARED) __syncthreads(); else wave_lds_sync();
+        // this wavefront's surviving entries of the window, in list order
+        const int32_t jtop = (wave_n - lo) < cnt ? (wave_n - lo) : cnt;
+        int32_t m = 0;
+        for (int32_t j0 = 0; j0 < jtop; j0 += kWave) {
+            const int32_t j = j0 + (int32_t)lane;
+            bool keep = false;
+            if (j < jtop) {
+                const float2 cb = s_cull[slot][j];
+                keep = !culled(g, s_g0[slot][j], s_g1[slot][j].x, cb.x, cb.y);
+            }
+            const uint64_t bal = __ballot(keep);
+            if (keep) s_idx[wid][m + (int32_t)__popcll(bal & ((1ull << lane) - 1ull))] = j;
+            m += (int32_t)__popcll(bal);
         }
         wave_lds_sync();
-        for (int32_t j = cnt - 1; j >= 0; --j) {
-            float gmx = 0.f, gmy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gop = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
-            bool contrib = false;
-            if (lo + j < n) {
-                const float4 r0 = s_rec[wid][j][0];
-                const float4 r1 = s_rec[wid][j][1];
-                const float cb = s_rec[wid][j][2].x;
-                const float dx = r0.x - fpx, dy = r0.y - fpy;
-                const float e = __expf(gauss_power(r0.z, r0.w, r1.x, dx, dy));
-                const float a_raw = r1.y * e;
-                const float alpha = fminf(kAlphaMax, a_raw);
-                if (alpha >= kAlphaMin) {
-                    contrib = true;
-                    const float rom = __builtin_amdgcn_rcpf(1.f - alpha);
-                    const float Ti = T * rom;                    // T_i = T_{i+1} / (1 - alpha_i)
-                    const float w = alpha * Ti;
-                    const float lw = __logf(w);
-                    // dC/dalpha_i = T_i c_i - S_{i+1} / (1 - alpha_i);  Eq. 15 for dH/dalpha_i
-                    float dal = gCr * (Ti * r1.z - Sr * rom) + gCg * (Ti * r1.w - Sg * rom) +
-                                gCb * (Ti * cb - Sb * rom);
-                    dal += gh * ((-lw - 1.f) * Ti + Rs * rom);
-                    gr = w * gCr;
-                    gg = w * gCg;
-                    gb = w * gCb;
-                    if (a_raw <= kAlphaMax) {                    // zero gradient in the clamped branch
-                        gop = e * dal;
-                        const float dp = alpha * dal;            // d alpha / d power = alpha
-                        gA = -0.5f * dx * dx * dp;
-                        gB = -dx * dy * dp;
-                        gC = -0.5f * dy * dy * dp;
-                        gmx = -dp * (r0.z * dx + r0.w * dy);
-                        gmy = -dp * (r0.w * dx + r1.x * dy);
-                    }
-                    Sr = fmaf(w, r1.z, Sr);
-                    Sg = fmaf(w, r1.w, Sg);
-                    Sb = fmaf(w, cb, Sb);
-                    Rs = fmaf(lw + 1.f, w, Rs);                  // R_i = (log w_i + 1) w_i + R_{i+1}
-                    T = Ti;
-                }
-            }
-            if (__ballot(contrib) != 0ull) {
-                gmx = wave_sum_to_lane63(gmx);
-                gmy = wave_sum_to_lane63(gmy);
-                gA = wave_sum_to_lane63(gA);
-                gB = wave_sum_to_lane63(gB);
-                gC = wave_sum_to_lane63(gC);
-                gop = wave_sum_to_lane63(gop);
-                gr = wave_sum_to_lane63(gr);
-                gg = wave_sum_to_lane63(gg);
-                gb = wave_sum_to_lane63(gb);
-                if (lane == 63u) {
-                    float* dst = a.grad2d + (size_t)kG2 * s_vg[wid][j];
-                    unsafeAtomicAdd(dst + 0, gmx);
-                    unsafeAtomicAdd(dst + 1, gmy);
-                    unsafeAtomicAdd(dst + 2, gA);
-                    unsafeAtomicAdd(dst + 3, gB);
-                    unsafeAtomicAdd(dst + 4, gC);
-                    unsafeAtomicAdd(dst + 5, gop);
-                    unsafeAtomicAdd(dst + 6, gr);
-                    unsafeAtomicAdd(dst + 7, gg);
-                    unsafeAtomicAdd(dst + 8, gb);
-                }
+        // walk them back to front; per Gaussian, a wavefront sum written to this wavefront's slot
+        for (int32_t kk = m - 1; kk >= 0; --kk) {
+            const int32_t j = s_idx[wid][kk];
+            float o[kG2];
+            bwd_entry(q, lo + j, s_g0[slot][j], s_g1[slot][j], s_b[slot][j], o);
+#pragma unroll
+            for (int k = 0; k < kG2; ++k) o[k] = row_sum16(o[k]);
+            if ((lane & 15u) == 0u) {
+#pragma unroll
+                for (int k = 0; k < kG2; ++k) acc_row[j * kG2 + k] = o[k];
             }
         }
-        wave_lds_sync();
+        if (SHARED) __syncthreads(); else wave_lds_sync();
+        // store the window's per-pair rows (emission slots), summing the
+        // (wavefront, row) slots in a fixed order, and clear the slots
+        for (int32_t i = tid; i < cnt * kG2; i += nthr) {
+            const int32_t j = i / kG2, k = i - j * kG2;
+            constexpr int32_t nsl = SHARED ? 4 * kWavesPerGroup : 4;
+            const int32_t s0 = SHARED ? 0 : (int32_t)wid * 4;
+            float v = 0.f;
+#pragma unroll
+            for (int32_t r = 0; r < nsl; ++r) {
+                v += s_acc[s0 + r][i];
+                s_acc[s0 + r][i] = 0.f;
+            }
+            a.pair_grad[(size_t)kG2 * s_e[slot][j] + k] = v;
+        }
+        if (SHARED) __syncthreads(); else wave_lds_sync();
+    }
+    // list entries no pixel of this tile reached: zero rows
+    for (int32_t p = maxn + tid; p < len; p += nthr) {
+        float* row = a.pair_grad + (size_t)kG2 * a.pair_vals[rg.x + (uint32_t)p];
+#pragma unroll
+        for (int k = 0; k < kG2; ++k) row[k] = 0.f;
     }
 }
 
@@ -300,7 +438,7 @@ __device__ __forceinline__ double block_sum_f64(double x)
     return s[0];
 }
 
-// level 1: one workgroup per chunk of kRedChunk 8x8 blocks of one view
+// level 1: one workgroup per chunk of kRedChunk wave blocks of one view
 __global__ __launch_bounds__(256) void entropy_chunk_kernel(const float* block_H, const CamDev* cams, int n_views,
                                                             double* chunk_sum)
 {
@@ -308,7 +446,7 @@ __global__ __launch_bounds__(256) void entropy_chunk_kernel(const float* block_H
     int v = 0;
     while (v + 1 < n_views && cams[v + 1].hred_base <= ch) ++v;
     const CamDev& c = cams[v];
-    const uint32_t nb = (uint32_t)(c.bx * c.by);
+    const uint32_t nb = c.n_wblocks;
     const uint32_t b0 = (ch - c.hred_base) * kRedChunk;
     double acc = 0.0;
     for (uint32_t k = threadIdx.x; k < (uint32_t)kRedChunk; k += 256)
@@ -342,8 +480,10 @@ hipError_t fwd_b(const BlendFwdArgs& a, hipStream_t s)
 template <int B>
 hipError_t bwd_b(const BlendBwdArgs& a, hipStream_t s)
 {
+    static_assert(B <= 64, "the backward window is limited by LDS");
     dim3 grid((a.n_blocks + kWavesPerGroup - 1) / kWavesPerGroup);
-    hipLaunchKernelGGL(blend_bwd_kernel<B>, grid, dim3(256), 0, s, a);
+    if (a.spt == 4) hipLaunchKernelGGL((blend_bwd_kernel<B, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((blend_bwd_kernel<B, false>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -366,9 +506,9 @@ hipError_t launch_blend_bwd(const BlendBwdArgs& a, int lds_batch, hipStream_t s)
     if (a.n_blocks == 0) return hipSuccess;
     switch (lds_batch) {
         case 32: return bwd_b<32>(a, s);
-        case 64: return bwd_b<64>(a, s);
-        case 128: return bwd_b<128>(a, s);
-        case 256: return bwd_b<256>(a, s);
+        case 64:
+        case 128:
+        case 256: return bwd_b<64>(a, s);       // the backward window is capped at 64 entries (LDS)
     }
     return hipErrorInvalidValue;
 }

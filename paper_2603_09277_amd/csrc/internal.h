@@ -23,9 +23,9 @@ struct CamDev {
     float limx, limy;              // 1.3 x half field of view (tan), Jacobian clamp
     int32_t gx, gy;                // tile grid of this view
     uint32_t tile_base;            // first global tile id of this view
-    int32_t bx, by;                // 8x8 block grid of this view
-    uint32_t block_base;           // first global 8x8 block of this view
-    uint32_t pad0;
+    uint32_t n_wblocks;            // 8x8 wave blocks of this view (tiles x blocks per tile)
+    uint32_t block_base;           // first global wave block of this view (tile-major numbering)
+    uint32_t pad0, pad1;
     int64_t pix_base;              // first pixel of this view in the packed outputs
     double limx_d, limy_d;         // the clamp bounds in FP64 (the clamp decision is taken in FP64)
     uint32_t hred_base;            // first entropy-reduction chunk of this view (kRedChunk blocks each)
@@ -36,9 +36,12 @@ constexpr int kRedChunk = 1024;    // 8x8 blocks summed per entropy-reduction ch
 constexpr int kL1Block = 256;      // pixels per L1 block
 
 // Projected record of one (view, Gaussian): three float4
-//   r0 = (mean x, mean y, conic A, conic B)
-//   r1 = (conic C, opacity, red, green)
-//   r2 = (blue, 0, 0, 0)
+//   r0 = (mean x, mean y, A', B')
+//   r1 = (C', opacity, red, green)
+//   r2 = (blue, eps, L, 0)   (cull data, see the projection)
+// with the conic pre-scaled to log2 units: A' = -A log2(e)/2, B' = -B log2(e),
+// C' = -C log2(e)/2, so that the exponent is A' dx^2 + B' dx dy + C' dy^2.
+constexpr double kLog2e = 1.4426950408889634;
 constexpr int kRecF4 = 3;
 // 2D gradient accumulator per (view, Gaussian): 9 floats
 //   dmean x, dmean y, dA, dB, dC, dopacity, dred, dgreen, dblue
@@ -83,12 +86,14 @@ struct ProjectBwdArgs {
 
 struct BlendFwdArgs {
     const float4* rec;
-    const uint32_t* pair_vals;
+    const uint32_t* pair_vals;            // sorted pairs: emission index
+    const uint32_t* emit_vg;              // emission index -> view*n + Gaussian
     const uint2* ranges;
     const CamDev* cams;
     int32_t n_views;
     int32_t tile_shift_x, tile_shift_y;
-    uint32_t n_blocks;                    // 8x8 blocks over all views
+    int32_t spt;                          // 8x8 blocks per tile: 1 or 4
+    uint32_t n_blocks;                    // 8x8 wave blocks over all views
     float* out_rgb;
     float* out_H;
     float* out_T;
@@ -100,17 +105,19 @@ struct BlendFwdArgs {
 struct BlendBwdArgs {
     const float4* rec;
     const uint32_t* pair_vals;
+    const uint32_t* emit_vg;
     const uint2* ranges;
     const CamDev* cams;
     int32_t n_views;
     int32_t tile_shift_x, tile_shift_y;
+    int32_t spt;
     uint32_t n_blocks;
     const float* T_final;
     const int32_t* n_contrib;
     const float* grad_rgb;
     const float* grad_H;                  // may be null
     const float* grad_LE;                 // [V] may be null
-    float* grad2d;                        // [V*n][9], accumulated with atomics
+    float* pair_grad;                     // [P][9] per-pair gradient rows, emission order
 };
 
 // ---- launchers (return hipError_t of the launch) ----
@@ -130,11 +137,16 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, u
                              uint32_t* vals_out, const uint32_t* n_dev, uint32_t n_max, int shift,
                              uint32_t* tmp, hipStream_t s);
 
-// write (tile id, view*n + index) pairs of every Gaussian in depth order
+// write (tile id, emission index) pairs of every Gaussian in depth order, and
+// emit_vg[emission index] = view*n + Gaussian index
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles_touched,
                             const uint2* rect, const CamDev* cams, uint32_t n, uint32_t vn,
                             const uint32_t* total, uint32_t cap, uint32_t* keys, uint32_t* vals,
-                            uint32_t* overflow, hipStream_t s);
+                            uint32_t* emit_vg, uint32_t* overflow, hipStream_t s);
+// grad2d[vg] = sum of the per-pair rows pair_grad[e] over the Gaussian's emission range
+hipError_t launch_grad_reduce(const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles_touched,
+                              const float* pair_grad, uint32_t vn, const uint32_t* total, uint32_t cap,
+                              float* grad2d, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);

@@ -270,15 +270,18 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
 }
 
 // ---------------------------------------------------------------------------
-// Duplication: every (view, Gaussian) in depth order writes one (tile, id)
-// pair per tile of its rectangle, row-major, at its scanned offset.
+// Duplication: every (view, Gaussian) in depth order writes one pair per tile
+// of its rectangle, row-major, at its scanned offset.  The pair's value is its
+// emission index; emit_vg maps it back to the (view, Gaussian) record.  All
+// pairs of one Gaussian are contiguous in emission order, which the backward
+// uses to reduce per-pair gradients without atomics.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* order, const uint32_t* offsets,
                                                              const uint32_t* tiles_touched, const uint2* rect,
                                                              const CamDev* cams, uint32_t n, uint32_t vn,
                                                              const uint32_t* total, uint32_t cap, uint32_t* keys,
-                                                             uint32_t* vals, uint32_t* overflow)
+                                                             uint32_t* vals, uint32_t* emit_vg, uint32_t* overflow)
 {
     uint32_t s = blockIdx.x * kThreads + threadIdx.x;
     if (s == 0 && *total > cap) *overflow = 1u;
@@ -295,10 +298,39 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* ord
         for (uint32_t tx = x0; tx <= x1; ++tx) {
             if (off < cap) {
                 keys[off] = tb + ty * gx + tx;
-                vals[off] = vg;
+                vals[off] = off;
+                emit_vg[off] = vg;
             }
             ++off;
         }
+}
+
+// Sum the per-pair gradient rows of every (view, Gaussian): its pairs occupy
+// [offsets[s], offsets[s] + tiles_touched) in emission order.  Fixed order,
+// no atomics: the result is bit-reproducible.
+__global__ __launch_bounds__(kThreads) void grad_reduce_kernel(const uint32_t* order, const uint32_t* offsets,
+                                                               const uint32_t* tiles_touched, const float* pair_grad,
+                                                               uint32_t vn, const uint32_t* total, uint32_t cap,
+                                                               float* grad2d)
+{
+    uint32_t s = blockIdx.x * kThreads + threadIdx.x;
+    if (s >= vn) return;
+    const uint32_t vg = order[s];
+    const uint32_t tt = tiles_touched[vg];
+    const uint32_t P = *total < cap ? *total : cap;
+    uint32_t b = offsets[s], e = b + tt;
+    e = e < P ? e : P;
+    float acc[kG2];
+#pragma unroll
+    for (int k = 0; k < kG2; ++k) acc[k] = 0.f;
+    for (uint32_t p = b; p < e; ++p) {
+        const float* row = pair_grad + (size_t)kG2 * p;
+#pragma unroll
+        for (int k = 0; k < kG2; ++k) acc[k] += row[k];
+    }
+    float* dst = grad2d + (size_t)kG2 * vg;
+#pragma unroll
+    for (int k = 0; k < kG2; ++k) dst[k] = acc[k];
 }
 
 __global__ void iota_u32_kernel(uint32_t* p, uint32_t count)
@@ -392,11 +424,22 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, u
 
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles_touched,
                             const uint2* rect, const CamDev* cams, uint32_t n, uint32_t vn, const uint32_t* total,
-                            uint32_t cap, uint32_t* keys, uint32_t* vals, uint32_t* overflow, hipStream_t s)
+                            uint32_t cap, uint32_t* keys, uint32_t* vals, uint32_t* emit_vg, uint32_t* overflow,
+                            hipStream_t s)
 {
     if (vn == 0) return hipSuccess;
     hipLaunchKernelGGL(duplicate_kernel, dim3((vn + kThreads - 1) / kThreads), dim3(kThreads), 0, s, order, offsets,
-                       tiles_touched, rect, cams, n, vn, total, cap, keys, vals, overflow);
+                       tiles_touched, rect, cams, n, vn, total, cap, keys, vals, emit_vg, overflow);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles_touched,
+                              const float* pair_grad, uint32_t vn, const uint32_t* total, uint32_t cap, float* grad2d,
+                              hipStream_t s)
+{
+    if (vn == 0) return hipSuccess;
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3((vn + kThreads - 1) / kThreads), dim3(kThreads), 0, s, order, offsets,
+                       tiles_touched, pair_grad, vn, total, cap, grad2d);
     return hipGetLastError();
 }
 

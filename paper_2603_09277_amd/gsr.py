@@ -59,7 +59,7 @@ class FrameStats(ctypes.Structure):
 
 
 STAGES = ["project", "depth_sort", "scan", "duplicate", "tile_sort", "ranges", "blend_fwd", "entropy_mean",
-          "blend_bwd", "project_bwd"]
+          "blend_bwd", "project_bwd", "grad_reduce"]
 
 
 class Grads(ctypes.Structure):

@@ -9,6 +9,7 @@ from oracle import oracle as orc
 from paper_2603_09277_amd import gsr, scenes
 
 DEV = torch.device("cuda:0")
+LOG2E = 1.4426950408889634
 KEYS = ("means", "scales", "quats", "opacities", "sh")
 
 
@@ -41,9 +42,11 @@ def gpu_records(R: gsr.Rasterizer, n: int, n_views: int):
     rad = R.inspect(gsr.BUF_RADIUS).reshape(n_views, n)
     dep = R.inspect(gsr.BUF_DEPTH).reshape(n_views, n)
     views = []
+    # the library stores the conic pre-scaled to log2 units
+    unscale = np.array([-2.0 / LOG2E, -1.0 / LOG2E, -2.0 / LOG2E])
     for v in range(n_views):
         r = rec[v]
-        views.append(dict(mean2d=r[:, 0:2].astype(np.float64), conic=r[:, 2:5].astype(np.float64),
+        views.append(dict(mean2d=r[:, 0:2].astype(np.float64), conic=r[:, 2:5].astype(np.float64) * unscale,
                           opacity=r[:, 5].astype(np.float64), rgb=r[:, 6:9].astype(np.float64),
                           radius=rad[v].copy(), depth32=dep[v].astype(np.float32),
                           mean2d_f32=r[:, 0:2].copy()))

@@ -647,3 +647,23 @@ def test_l1_loss_entry_point(R):
         assert np.array_equal(grad.cpu().numpy()[off[v]:off[v + 1]], exp_g)
         assert abs(float(loss[v]) - np.abs(d.astype(np.float64)).mean()) <= 1e-6 * np.abs(d).mean()
     assert float(grad[5].abs().sum()) == 0.0
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_gradients_bit_reproducible(R, tile):
+    """The backward uses no float atomics: two runs give bit-identical gradients."""
+    scene = scenes.gmm_scene(61, 8000)
+    scene.scales *= np.float32(2.0)
+    cams = scenes.orbit_cameras(np.random.default_rng(62), [(200, 150), (120, 90)])
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=tile, sh_degree=3)
+    res = []
+    for _ in range(2):
+        out = gpu_forward(R, t, cams, opts)
+        g_rgb = torch.full_like(out["rgb"], 1e-4)
+        g = R.backward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, out, g_rgb, None,
+                       torch.full((2,), GAMMA, device=DEV))
+        torch.cuda.synchronize()
+        res.append({k: v.clone() for k, v in g.items()})
+    for k in KEYS:
+        assert torch.equal(res[0][k], res[1][k]), k

@@ -46,7 +46,12 @@ def parse():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--lds", type=int, default=64)
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
-    ap.add_argument("--bf16", action="store_true", help="store SH and SH gradients in bfloat16")
+    ap.add_argument("--persistent", action="store_true", help="persistent blend kernels, longest tile lists first")
+    ap.add_argument("--autotune", action="store_true", help="pick tile shape and LDS batch with gsr_autotune first")
+    ap.add_argument("--per-view", action="store_true",
+                    help="plain form: one launch sequence per view instead of one batched launch")
+    ap.add_argument("--sh", choices=["auto", "f32", "bf16"], default="auto", help="SH storage (auto: the workload's)")
+    ap.add_argument("--bf16", action="store_true", help="same as --sh bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not bracket stages with HIP events")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -140,32 +145,46 @@ def main():
         return
     tile = tuple(int(x) for x in args.tile.split("x"))
     scene, cams, meta = scenes.workload(args.workload)
-    bf16 = args.bf16 or meta["sh_dtype"] == "bf16"
+    bf16 = args.bf16 or args.sh == "bf16" or (args.sh == "auto" and meta["sh_dtype"] == "bf16")
     n, V = scene.n, len(cams)
     npix = sum(c.width * c.height for c in cams)
     t = {k: torch.from_numpy(np.ascontiguousarray(getattr(scene, k))).to(dev) for k in
          ("means", "scales", "quats", "opacities", "sh")}
     if bf16:
         t["sh"] = t["sh"].to(torch.bfloat16).contiguous()
-    flags = gsr.GSR_DEFAULT_FLAGS | (gsr.GSR_GRAPH if args.graph else 0)
+    flags = gsr.GSR_DEFAULT_FLAGS | (gsr.GSR_GRAPH if args.graph else 0) | (gsr.GSR_PERSISTENT if args.persistent else 0)
     opts = gsr.RasterOptions(tile=tile, lds_batch=args.lds, sh_degree=scene.sh_degree, sh_bf16=bf16, flags=flags)
     targets_np = [scenes.target_image(1000 + v, c.height, c.width) for v, c in enumerate(cams)]
     target = torch.from_numpy(np.concatenate([x.reshape(-1, 3) for x in targets_np])).to(dev).contiguous()
     R = gsr.Rasterizer(max_views=max(V, 1))
+    if args.autotune:
+        cache = os.path.join(ROOT, "profiles", "autotune_cache.txt")
+        opts = R.autotune(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, cache)
+        tile = opts.tile
     g_le = torch.full((V,), GAMMA, device=dev)
-    grad_rgb = torch.empty((npix, 3), device=dev)
-    loss = torch.empty(V, device=dev)
     grads = {k: torch.empty_like(v) for k, v in t.items()}
+    off = [0]
+    for c in cams:
+        off.append(off[-1] + c.width * c.height)
+    # plain form: every view is its own launch sequence; batched: one sequence for all views
+    groups = [[v] for v in range(V)] if args.per_view else [list(range(V))]
+    work = []
+    for gvs in groups:
+        gc = [cams[v] for v in gvs]
+        p0, p1 = off[gvs[0]], off[gvs[-1] + 1]
+        work.append(dict(cams=gc, target=target[p0:p1], grad_rgb=torch.empty((p1 - p0, 3), device=dev),
+                         loss=torch.empty(len(gvs), device=dev), g_le=torch.full((len(gvs),), GAMMA, device=dev),
+                         out=None))
     state = {}
-    out_bufs = {}
 
     def step():
-        out = R.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts,
-                        out=out_bufs.get("out"))
-        out_bufs["out"] = out
-        R.l1_loss(cams, out["rgb"], target, grad_rgb, loss)
-        R.backward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, out,
-                   grad_rgb, None, g_le, grads)
+        for w in work:
+            out = R.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], w["cams"], opts,
+                            out=w["out"])
+            w["out"] = out
+            R.l1_loss(w["cams"], out["rgb"], w["target"], w["grad_rgb"], w["loss"])
+            R.backward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], w["cams"], opts, out,
+                       w["grad_rgb"], None, w["g_le"], grads)
         state["out"] = out
 
     for _ in range(args.warmup):
@@ -184,7 +203,23 @@ def main():
     if timing:
         R.set_timing(False)
     stages = R.stage_times(reset=True) if timing else {}
-    st = R.stats(V)
+    if args.per_view:      # statistics of every view: forward each once more, untimed
+        st = dict(pairs=0, evals_fwd=0, evals_bwd=0, mean_len=0.0, p99_len=0, overflow=False)
+        n_t = 0
+        for w in work:
+            R.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], w["cams"], opts, out=w["out"])
+            sv = R.stats(1)
+            c = w["cams"][0]
+            nt = ((c.width + tile[0] - 1) // tile[0]) * ((c.height + tile[1] - 1) // tile[1])
+            for k in ("pairs", "evals_fwd", "evals_bwd"):
+                st[k] += sv[k]
+            st["mean_len"] += sv["mean_len"] * nt
+            n_t += nt
+            st["p99_len"] = max(st["p99_len"], sv["p99_len"])
+            st["overflow"] = st["overflow"] or sv["overflow"]
+        st["mean_len"] /= max(n_t, 1)
+    else:
+        st = R.stats(V)
     sec = (t1 - t0) / args.steps
     iters = V / sec
     K = (scene.sh_degree + 1) ** 2
@@ -237,8 +272,11 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl_name, "gaussians": n, "views": V, "tile": f"{tile[0]}x{tile[1]}",
-                   "lds_batch": args.lds, "sh_storage": "bf16" if bf16 else "f32",
-                   "mode": "graph" if args.graph else "plain", "loss": "L1 + 0.015 L_E"},
+                   "lds_batch": opts.lds_batch, "sh_storage": "bf16" if bf16 else "f32",
+                   "mode": ("per-view" if args.per_view else ("batched" if V > 1 else "single-view"))
+                           + ("+graph" if args.graph else "")
+                           + ("+persistent" if args.persistent else "") + ("+autotuned" if args.autotune else ""),
+                   "loss": "L1 + 0.015 L_E"},
         "pairs_per_s": round(st["pairs"] / sec, 1), "pairs": st["pairs"], "mean_list_len": round(st["mean_len"], 2),
         "p99_list_len": st["p99_len"], "evals_fwd": st["evals_fwd"], "evals_bwd": st["evals_bwd"],
         "overflow": st["overflow"], "stages": stage_report, "roofline": roofline,

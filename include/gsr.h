@@ -78,7 +78,8 @@ typedef struct {
 #define GSR_COLOR_CLAMP     4u   /* clamp colour at 0 */
 #define GSR_GRAPH           8u   /* capture forward / backward into HIP graphs and replay them;
                                     fixed pair capacity, no host synchronisation */
-#define GSR_PERSISTENT     16u   /* persistent blend kernels over a tile queue ordered by list length */
+#define GSR_PERSISTENT     16u   /* persistent blend kernels: resident workgroups pull tiles from a device
+                                    queue ordered longest list first (balances mixed-resolution views) */
 #define GSR_DEFAULT_FLAGS  (GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP)
 
 typedef struct {

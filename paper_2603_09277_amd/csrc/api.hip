@@ -53,7 +53,7 @@ struct gsr_ctx {
 
     // grow-only device buffers
     Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
-    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, ranges, block_H, block_cnt, hchunk, counters, len_hist, view_pairs, l1_tmp;
+    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, ranges, tord, block_H, block_cnt, hchunk, counters, len_hist, view_pairs, l1_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
     uint64_t gen_fwd = 0, gen_bwd = 0;
@@ -298,6 +298,8 @@ gsr_status ensure_tiles(gsr_ctx* c, uint32_t tiles, uint32_t blocks)
 {
     gsr_status s;
     if ((s = grow(c, c->ranges, (size_t)std::max<uint32_t>(tiles, 1) * 8)) ||
+        (s = grow(c, c->tord, (size_t)std::max<uint32_t>(tiles, 1) * 16)) ||
+        (s = grow(c, c->radix_tmp, radix_tmp_words(std::max<uint32_t>(tiles, 1)) * 4)) ||
         (s = grow(c, c->block_H, (size_t)std::max<uint32_t>(blocks, 1) * 4)) ||
         (s = grow(c, c->block_cnt, (size_t)std::max<uint32_t>(blocks, 1) * 8)) ||
         (s = grow(c, c->hchunk, (size_t)(blocks / kRedChunk + 64) * 8)))
@@ -373,10 +375,19 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
                                          cap, 8 * pass, (uint32_t*)c->radix_tmp.p, st));
     }
     const int sb = passes & 1;
+    const bool persist = (o->flags & GSR_PERSISTENT) != 0;
     {
         StageTimer tm(c, st, GSR_STAGE_RANGES, plain);
         HIP_TRY(c, launch_fill_u32((uint32_t*)c->ranges.p, 0u, (size_t)L.n_tiles * 2, st));
         HIP_TRY(c, launch_ranges(pk[sb], counters, cap, (uint2*)c->ranges.p, st));
+        if (persist) {
+            // work order for the persistent blend kernels: tiles with the longest lists first
+            uint32_t* tk = (uint32_t*)c->tord.p;
+            HIP_TRY(c, launch_tile_len_keys((const uint2*)c->ranges.p, L.n_tiles, tk, tk + L.n_tiles, st));
+            HIP_TRY(c, launch_radix_pass(tk, tk + L.n_tiles, tk + 2 * L.n_tiles, tk + 3 * L.n_tiles, nullptr,
+                                         L.n_tiles, 0, (uint32_t*)c->radix_tmp.p, st));
+            HIP_TRY(c, launch_fill_u32(counters + 2, 0u, 2, st));
+        }
     }
 
     BlendFwdArgs ba;
@@ -386,6 +397,8 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     ba.out_rgb = out->rgb; ba.out_H = out->entropy; ba.out_T = out->t_final; ba.out_nc = out->n_contrib;
     ba.block_H = (float*)c->block_H.p;
     ba.block_cnt = (uint2*)c->block_cnt.p;
+    ba.tile_order = persist ? (const uint32_t*)c->tord.p + 3 * L.n_tiles : nullptr;
+    ba.work_counter = persist ? counters + 2 : nullptr;
     {
         StageTimer tm(c, st, GSR_STAGE_BLEND_FWD, plain);
         HIP_TRY(c, launch_blend_fwd(ba, o->lds_batch == 0 ? 64 : o->lds_batch, st));
@@ -417,6 +430,10 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     bb.n_blocks = L.n_blocks;
     bb.T_final = saved->t_final; bb.n_contrib = saved->n_contrib; bb.grad_rgb = grad_rgb; bb.grad_H = grad_H;
     bb.grad_LE = grad_LE; bb.pair_grad = (float*)c->pair_grad.p;
+    const bool persist = (o->flags & GSR_PERSISTENT) != 0;
+    bb.tile_order = persist ? (const uint32_t*)c->tord.p + 3 * L.n_tiles : nullptr;
+    bb.work_counter = persist ? (uint32_t*)c->counters.p + 3 : nullptr;
+    if (persist) HIP_TRY(c, launch_fill_u32((uint32_t*)c->counters.p + 3, 0u, 1, st));
     HIP_TRY(c, launch_blend_bwd(bb, o->lds_batch == 0 ? 64 : o->lds_batch, st));
     tb.stop();
     {
@@ -523,7 +540,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     drop_graphs(c);
     Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->radius,
                    &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
-                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->ranges, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->len_hist, &c->view_pairs,
+                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->ranges, &c->tord, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->len_hist, &c->view_pairs,
                    &c->l1_tmp };
     for (Dev* d : all) free_dev(*d);
     for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }

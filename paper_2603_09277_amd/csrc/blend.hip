@@ -164,7 +164,23 @@ __device__ __forceinline__ BlockGeom block_geom(const CamDev* cams, int n_views,
     return g;
 }
 
-template <int B>
+// next work item of a persistent wavefront (one atomic per wavefront)
+__device__ __forceinline__ uint32_t next_item_wave(uint32_t* counter, uint32_t lane)
+{
+    uint32_t v = 0;
+    if (lane == 0) v = atomicAdd(counter, 1u);
+    return __shfl(v, 0, 64);
+}
+
+// work item -> wave block: items walk the tiles in `tile_order` (longest list
+// first) and, inside a tile, its 8x8 blocks
+__device__ __forceinline__ uint32_t item_to_wblock(const uint32_t* tile_order, uint32_t item, int spt)
+{
+    if (!tile_order) return item;
+    return tile_order[item / (uint32_t)spt] * (uint32_t)spt + item % (uint32_t)spt;
+}
+
+template <int B, bool PERSIST>
 __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
 {
     __shared__ float4 s_g0[kWavesPerGroup][B];   // mean x, mean y, A', B'
@@ -172,8 +188,9 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
     __shared__ float s_b[kWavesPerGroup][B];     // blue
     __shared__ int32_t s_pos[kWavesPerGroup][B]; // position in the tile list
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
-    const uint32_t wb = blockIdx.x * kWavesPerGroup + wid;
-    if (wb >= a.n_blocks) return;
+    uint32_t item = PERSIST ? next_item_wave(a.work_counter, lane) : blockIdx.x * kWavesPerGroup + wid;
+    for (; item < a.n_blocks; item = PERSIST ? next_item_wave(a.work_counter, lane) : a.n_blocks) {
+    const uint32_t wb = item_to_wblock(a.tile_order, item, a.spt);
     const BlockGeom g = block_geom(a.cams, a.n_views, wb, lane, a.tile_shift_x, a.tile_shift_y, a.spt);
     const uint2 rg = a.ranges[g.tile];
     const float fpx = (float)g.px + 0.5f, fpy = (float)g.py + 0.5f;
@@ -251,6 +268,7 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
         a.block_H[wb] = hs;
         a.block_cnt[wb] = make_uint2(ne, nc);
     }
+    }
 }
 
 // Per-lane state of the backward walk of one pixel.
@@ -325,7 +343,7 @@ __device__ __forceinline__ void bwd_init(const BlendBwdArgs& a, const BlockGeom&
 
 // SHARED: the 4 wavefronts of the workgroup are the 4 blocks of one tile and
 // share each window; otherwise every wavefront has its own tile and window.
-template <int B, bool SHARED>
+template <int B, bool SHARED, bool PERSIST>
 __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
 {
     constexpr int NS = SHARED ? 1 : kWavesPerGroup;          // LDS slots
@@ -337,10 +355,27 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     __shared__ float s_acc[kWavesPerGroup * 4][B * kG2]; // per (wavefront, 16-lane row) partial sums
     __shared__ int32_t s_idx[kWavesPerGroup][B];        // surviving window entries of each wavefront
     __shared__ int32_t s_max[kWavesPerGroup];
+    __shared__ uint32_t s_item;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
     const uint32_t slot = SHARED ? 0u : wid;
-    const uint32_t wb = blockIdx.x * kWavesPerGroup + wid;
-    if (wb >= a.n_blocks) return;                            // SHARED: whole workgroups only
+    // work items: tiles (SHARED: one per workgroup; else one per wavefront), longest list first
+    const uint32_t n_items = SHARED ? a.n_blocks / kWavesPerGroup : a.n_blocks;
+    auto next = [&]() -> uint32_t {
+        if (!PERSIST) return n_items;
+        if (SHARED) {
+            __syncthreads();
+            if (threadIdx.x == 0) s_item = atomicAdd(a.work_counter, 1u);
+            __syncthreads();
+            return s_item;
+        }
+        return next_item_wave(a.work_counter, lane);
+    };
+    uint32_t item;
+    if (PERSIST) item = next();
+    else item = SHARED ? blockIdx.x : blockIdx.x * kWavesPerGroup + wid;
+    for (; item < n_items; item = next()) {
+    const uint32_t tile_id = a.tile_order ? a.tile_order[item] : item;
+    const uint32_t wb = SHARED ? tile_id * kWavesPerGroup + wid : tile_id;
     const BlockGeom g = block_geom(a.cams, a.n_views, wb, lane, a.tile_shift_x, a.tile_shift_y, a.spt);
     const uint2 rg = a.ranges[g.tile];
     const int32_t len = (int32_t)(rg.y - rg.x);
@@ -424,6 +459,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
 #pragma unroll
         for (int k = 0; k < kG2; ++k) row[k] = 0.f;
     }
+    }
 }
 
 __device__ __forceinline__ double block_sum_f64(double x)
@@ -469,11 +505,28 @@ __global__ __launch_bounds__(256) void entropy_mean_kernel(const double* chunk_s
     if (threadIdx.x == 0) out[v] = (float)(tot / ((double)c.W * (double)c.H));
 }
 
+// persistent grids: as many workgroups as fit on the device at once
+template <typename K>
+uint32_t resident_groups(K kernel, uint32_t want)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0);
+    uint32_t g = (uint32_t)(cus > 0 ? cus : 256) * (uint32_t)(per_cu > 0 ? per_cu : 1);
+    return g < want ? g : want;
+}
+
 template <int B>
 hipError_t fwd_b(const BlendFwdArgs& a, hipStream_t s)
 {
-    dim3 grid((a.n_blocks + kWavesPerGroup - 1) / kWavesPerGroup);
-    hipLaunchKernelGGL(blend_fwd_kernel<B>, grid, dim3(256), 0, s, a);
+    const uint32_t groups = (a.n_blocks + kWavesPerGroup - 1) / kWavesPerGroup;
+    if (a.work_counter) {
+        hipLaunchKernelGGL((blend_fwd_kernel<B, true>), dim3(resident_groups(blend_fwd_kernel<B, true>, groups)),
+                           dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((blend_fwd_kernel<B, false>), dim3(groups), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -481,9 +534,18 @@ template <int B>
 hipError_t bwd_b(const BlendBwdArgs& a, hipStream_t s)
 {
     static_assert(B <= 64, "the backward window is limited by LDS");
-    dim3 grid((a.n_blocks + kWavesPerGroup - 1) / kWavesPerGroup);
-    if (a.spt == 4) hipLaunchKernelGGL((blend_bwd_kernel<B, true>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((blend_bwd_kernel<B, false>), grid, dim3(256), 0, s, a);
+    const uint32_t groups = (a.n_blocks + kWavesPerGroup - 1) / kWavesPerGroup;
+    if (a.work_counter) {
+        if (a.spt == 4)
+            hipLaunchKernelGGL((blend_bwd_kernel<B, true, true>),
+                               dim3(resident_groups(blend_bwd_kernel<B, true, true>, groups)), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((blend_bwd_kernel<B, false, true>),
+                               dim3(resident_groups(blend_bwd_kernel<B, false, true>, groups)), dim3(256), 0, s, a);
+    } else {
+        if (a.spt == 4) hipLaunchKernelGGL((blend_bwd_kernel<B, true, false>), dim3(groups), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((blend_bwd_kernel<B, false, false>), dim3(groups), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -100,6 +100,8 @@ struct BlendFwdArgs {
     int32_t* out_nc;
     float* block_H;                       // [n_blocks] sum of H over the block
     uint2* block_cnt;                     // [n_blocks] (alpha evaluations, sum of n_contrib)
+    const uint32_t* tile_order;           // tiles longest list first (persistent mode), or null
+    uint32_t* work_counter;               // persistent work queue head (zeroed before launch), or null
 };
 
 struct BlendBwdArgs {
@@ -118,6 +120,8 @@ struct BlendBwdArgs {
     const float* grad_H;                  // may be null
     const float* grad_LE;                 // [V] may be null
     float* pair_grad;                     // [P][9] per-pair gradient rows, emission order
+    const uint32_t* tile_order;           // tiles longest list first (persistent mode), or null
+    uint32_t* work_counter;               // persistent work queue head (zeroed before launch), or null
 };
 
 // ---- launchers (return hipError_t of the launch) ----
@@ -149,6 +153,8 @@ hipError_t launch_grad_reduce(const uint32_t* order, const uint32_t* offsets, co
                               float* grad2d, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
+// keys[t] = 255 - min(255, ceil(len_t / 8)), vals[t] = t: one stable 8-bit pass orders tiles longest first
+hipError_t launch_tile_len_keys(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges,
                          hipStream_t s);

@@ -333,6 +333,17 @@ __global__ __launch_bounds__(kThreads) void grad_reduce_kernel(const uint32_t* o
     for (int k = 0; k < kG2; ++k) dst[k] = acc[k];
 }
 
+__global__ void tile_len_keys_kernel(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals)
+{
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint2 r = ranges[t];
+    const uint32_t len = r.y > r.x ? r.y - r.x : 0u;
+    const uint32_t b = (len + 7u) / 8u;
+    keys[t] = 255u - (b < 255u ? b : 255u);
+    vals[t] = t;
+}
+
 __global__ void iota_u32_kernel(uint32_t* p, uint32_t count)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -447,6 +458,13 @@ hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s)
 {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(iota_u32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_len_keys(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s)
+{
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(tile_len_keys_kernel, dim3((n_tiles + 255) / 256), dim3(256), 0, s, ranges, n_tiles, keys, vals);
     return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ struct gsr_ctx {
 
     // grow-only device buffers
     Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
-    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, ranges, tord, block_H, block_cnt, hchunk, counters, len_hist, view_pairs, l1_tmp;
+    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, tord, block_H, block_cnt, hchunk, counters, len_hist, view_pairs, l1_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
     uint64_t gen_fwd = 0, gen_bwd = 0;
@@ -283,7 +283,8 @@ gsr_status ensure_pairs(gsr_ctx* c, size_t p)
     if (p >= 0xfffffff0ull) return fail(c, GSR_ERR_CAPACITY, "pair count exceeds 2^32");
     gsr_status s;
     if ((s = grow(c, c->pk0, p * 4)) || (s = grow(c, c->pk1, p * 4)) || (s = grow(c, c->pv0, p * 4)) ||
-        (s = grow(c, c->pv1, p * 4)) || (s = grow(c, c->emit_vg, p * 4)) || (s = grow(c, c->pair_grad, p * 4 * kG2)))
+        (s = grow(c, c->pv1, p * 4)) || (s = grow(c, c->emit_vg, p * 4)) || (s = grow(c, c->pair_grad, p * 4 * kG2)) ||
+        (s = grow(c, c->seg_carry, seg_carry_bytes((uint32_t)p))))
         return s;
     c->pair_cap = p;
     return GSR_OK;
@@ -438,10 +439,9 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     tb.stop();
     {
         StageTimer tr(c, st, GSR_STAGE_GRAD_REDUCE, plain);
-        uint32_t* od0 = (uint32_t*)c->ord0.p;
-        HIP_TRY(c, launch_grad_reduce(od0, (const uint32_t*)c->offsets.p, (const uint32_t*)c->tt.p,
-                                      (const float*)c->pair_grad.p, vn, (const uint32_t*)c->counters.p,
-                                      (uint32_t)c->pair_cap_used, (float*)c->grad2d.p, st));
+        HIP_TRY(c, launch_grad_reduce((const float*)c->pair_grad.p, (const uint32_t*)c->emit_vg.p,
+                                      vn, (const uint32_t*)c->counters.p, (uint32_t)c->pair_cap_used,
+                                      (float*)c->grad2d.p, c->seg_carry.p, st));
     }
     StageTimer tp(c, st, GSR_STAGE_PROJECT_BWD, plain);
     ProjectBwdArgs pa;
@@ -540,7 +540,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     drop_graphs(c);
     Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->radius,
                    &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
-                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->ranges, &c->tord, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->len_hist, &c->view_pairs,
+                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->tord, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->len_hist, &c->view_pairs,
                    &c->l1_tmp };
     for (Dev* d : all) free_dev(*d);
     for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }

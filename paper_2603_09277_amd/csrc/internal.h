@@ -147,10 +147,11 @@ hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, cons
                             const uint2* rect, const CamDev* cams, uint32_t n, uint32_t vn,
                             const uint32_t* total, uint32_t cap, uint32_t* keys, uint32_t* vals,
                             uint32_t* emit_vg, uint32_t* overflow, hipStream_t s);
-// grad2d[vg] = sum of the per-pair rows pair_grad[e] over the Gaussian's emission range
-hipError_t launch_grad_reduce(const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles_touched,
-                              const float* pair_grad, uint32_t vn, const uint32_t* total, uint32_t cap,
-                              float* grad2d, hipStream_t s);
+// grad2d[vg] = sum of the per-pair rows pair_grad[9 e .. 9 e + 8] over the Gaussian's emission range
+// (zero for Gaussians without pairs); carry holds seg_carry_bytes(cap) bytes
+size_t seg_carry_bytes(uint32_t cap);
+hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* emit_vg, uint32_t vn,
+                              const uint32_t* total, uint32_t cap, float* grad2d, void* carry, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 // keys[t] = 255 - min(255, ceil(len_t / 8)), vals[t] = t: one stable 8-bit pass orders tiles longest first

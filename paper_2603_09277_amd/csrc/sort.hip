@@ -305,30 +305,102 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* ord
         }
 }
 
-// Sum the per-pair gradient rows of every (view, Gaussian): its pairs occupy
-// [offsets[s], offsets[s] + tiles_touched) in emission order.  Fixed order,
-// no atomics: the result is bit-reproducible.
-__global__ __launch_bounds__(kThreads) void grad_reduce_kernel(const uint32_t* order, const uint32_t* offsets,
-                                                               const uint32_t* tiles_touched, const float* pair_grad,
-                                                               uint32_t vn, const uint32_t* total, uint32_t cap,
-                                                               float* grad2d)
+// Per-Gaussian sum of the per-pair gradient rows.  Rows (9 floats) are stored
+// in emission order, where all pairs of one (view, Gaussian) are contiguous.  One wavefront takes 64
+// consecutive rows, runs a segmented inclusive scan keyed by the Gaussian,
+// and writes every segment that starts and ends inside it; segments that
+// cross wavefront boundaries leave their partial sums in `carry` and are
+// finished by seg_fixup_kernel in a fixed order.  No atomics: deterministic.
+struct SegCarry {
+    float head[kG2];         // first segment's sum over this wavefront, if it started earlier and ends here
+    float tail[kG2];         // last segment's sum over this wavefront, if it continues past it
+    uint32_t first_seg, last_seg;
+    uint32_t flags;          // 1: first segment started earlier; 2: last segment continues
+    uint32_t pad;
+};
+
+__global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_grad,
+                                                              const uint32_t* emit_vg, const uint32_t* total,
+                                                              uint32_t cap, float* grad2d, SegCarry* carry)
 {
-    uint32_t s = blockIdx.x * kThreads + threadIdx.x;
-    if (s >= vn) return;
-    const uint32_t vg = order[s];
-    const uint32_t tt = tiles_touched[vg];
     const uint32_t P = *total < cap ? *total : cap;
-    uint32_t b = offsets[s], e = b + tt;
-    e = e < P ? e : P;
+    const uint32_t lane = lane_id();
+    const uint32_t w = (blockIdx.x * kThreads + threadIdx.x) >> 6;
+    const uint32_t e = w * 64u + lane;
+    if (w * 64u >= P) return;                                  // whole wavefront
+    const bool valid = e < P;
+    const uint32_t seg = valid ? emit_vg[e] : 0xffffffffu;
+    uint32_t prev = __shfl_up(seg, 1, 64);
+    if (lane == 0) prev = e > 0 ? emit_vg[e - 1] : 0xfffffffeu;
+    uint32_t next = __shfl_down(seg, 1, 64);
+    if (lane == 63) next = (e + 1 < P) ? emit_vg[e + 1] : 0xfffffffeu;
+    float v[kG2];
+#pragma unroll
+    for (int k = 0; k < kG2; ++k) v[k] = valid ? pair_grad[(size_t)kG2 * e + k] : 0.f;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t su = __shfl_up(seg, d, 64);
+        const bool same = lane >= (uint32_t)d && su == seg;    // segments are contiguous
+#pragma unroll
+        for (int k = 0; k < kG2; ++k) {
+            const float y = __shfl_up(v[k], d, 64);
+            v[k] += same ? y : 0.f;
+        }
+    }
+    const uint32_t first_seg = __shfl(seg, 0, 64);
+    const bool crosses_in = __shfl(prev, 0, 64) == first_seg;  // first segment began in an earlier wavefront
+    const bool from_before = crosses_in && seg == first_seg;
+    const bool ends_here = valid && next != seg;
+    const bool last_valid = valid && (lane == 63 || e + 1 >= P);
+    if (ends_here && !from_before) {
+        float* dst = grad2d + (size_t)kG2 * seg;
+#pragma unroll
+        for (int k = 0; k < kG2; ++k) dst[k] = v[k];
+    }
+    SegCarry* c = carry + w;
+    if (ends_here && from_before) {
+#pragma unroll
+        for (int k = 0; k < kG2; ++k) c->head[k] = v[k];
+    }
+    if (last_valid) {
+        const bool crosses_out = !ends_here;
+#pragma unroll
+        for (int k = 0; k < kG2; ++k) c->tail[k] = crosses_out ? v[k] : 0.f;
+        c->first_seg = first_seg;
+        c->last_seg = seg;
+        c->flags = (crosses_in ? 1u : 0u) | (crosses_out ? 2u : 0u);
+    }
+}
+
+// one thread per wavefront: a segment that starts in wavefront w and continues
+// past it is summed here over the following wavefronts, in order
+__global__ __launch_bounds__(kThreads) void seg_fixup_kernel(const SegCarry* carry, const uint32_t* total,
+                                                             uint32_t cap, float* grad2d)
+{
+    const uint32_t P = *total < cap ? *total : cap;
+    const uint32_t nw = (P + 63u) / 64u;
+    const uint32_t w = blockIdx.x * kThreads + threadIdx.x;
+    if (w >= nw) return;
+    const SegCarry& c = carry[w];
+    if (!(c.flags & 2u)) return;                                 // nothing continues past w
+    if ((c.flags & 1u) && c.first_seg == c.last_seg) return;     // w is inside a segment begun earlier
+    const uint32_t s = c.last_seg;
     float acc[kG2];
 #pragma unroll
-    for (int k = 0; k < kG2; ++k) acc[k] = 0.f;
-    for (uint32_t p = b; p < e; ++p) {
-        const float* row = pair_grad + (size_t)kG2 * p;
+    for (int k = 0; k < kG2; ++k) acc[k] = c.tail[k];
+    for (uint32_t u = w + 1; u < nw; ++u) {
+        const SegCarry& d = carry[u];
+        const bool whole = (d.flags & 3u) == 3u && d.first_seg == d.last_seg && d.first_seg == s;
+        if (whole) {
 #pragma unroll
-        for (int k = 0; k < kG2; ++k) acc[k] += row[k];
+            for (int k = 0; k < kG2; ++k) acc[k] += d.tail[k];
+            continue;
+        }
+#pragma unroll
+        for (int k = 0; k < kG2; ++k) acc[k] += d.head[k];
+        break;
     }
-    float* dst = grad2d + (size_t)kG2 * vg;
+    float* dst = grad2d + (size_t)kG2 * s;
 #pragma unroll
     for (int k = 0; k < kG2; ++k) dst[k] = acc[k];
 }
@@ -444,13 +516,18 @@ hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, cons
     return hipGetLastError();
 }
 
-hipError_t launch_grad_reduce(const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles_touched,
-                              const float* pair_grad, uint32_t vn, const uint32_t* total, uint32_t cap, float* grad2d,
-                              hipStream_t s)
+size_t seg_carry_bytes(uint32_t cap) { return ((size_t)cap + 63) / 64 * sizeof(SegCarry) + sizeof(SegCarry); }
+
+hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* emit_vg, uint32_t vn,
+                              const uint32_t* total, uint32_t cap, float* grad2d, void* carry, hipStream_t s)
 {
-    if (vn == 0) return hipSuccess;
-    hipLaunchKernelGGL(grad_reduce_kernel, dim3((vn + kThreads - 1) / kThreads), dim3(kThreads), 0, s, order, offsets,
-                       tiles_touched, pair_grad, vn, total, cap, grad2d);
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (size_t)vn * kG2, s);
+    if (e != hipSuccess || cap == 0) return e;
+    const uint32_t nw = (cap + 63) / 64;
+    hipLaunchKernelGGL(seg_reduce_kernel, dim3((nw * 64 + kThreads - 1) / kThreads), dim3(kThreads), 0, s, pair_grad,
+                       emit_vg, total, cap, grad2d, reinterpret_cast<SegCarry*>(carry));
+    hipLaunchKernelGGL(seg_fixup_kernel, dim3((nw + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                       reinterpret_cast<const SegCarry*>(carry), total, cap, grad2d);
     return hipGetLastError();
 }
 

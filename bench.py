@@ -18,6 +18,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -158,7 +159,7 @@ def main():
     target = torch.from_numpy(np.concatenate([x.reshape(-1, 3) for x in targets_np])).to(dev).contiguous()
     R = gsr.Rasterizer(max_views=max(V, 1))
     if args.autotune:
-        cache = os.path.join(ROOT, "profiles", "autotune_cache.txt")
+        cache = os.path.join(tempfile.gettempdir(), "gsr_autotune_cache.txt")
         opts = R.autotune(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, cache)
         tile = opts.tile
     g_le = torch.full((V,), GAMMA, device=dev)

@@ -20,13 +20,14 @@
 // the list walk only visits the survivors, compacted in list order.
 //
 // Backward: list windows of B entries are walked from the back.  In a 16x16
-// or 32x8 tile the 4 wavefronts share each window's records.  Per Gaussian,
-// every wavefront sums its partial gradients over each 16-lane row by DPP and
-// the 4 row leaders write them to their own LDS slots; the window's 16 slots
-// (4 wavefronts x 4 rows) are summed in a fixed order and stored once per
-// (tile, Gaussian) pair, in the pair's emission slot.  A segmented reduction over each Gaussian's
-// contiguous emission range then yields its 2D gradient.  No float atomics
-// touch global memory, so gradients are bit-reproducible.
+// or 32x8 tile the 4 wavefronts share each window's records.  An entry that
+// no lane of a wavefront blended is skipped by that wavefront.  Per Gaussian,
+// every wavefront sums its 9 partial gradients over its 64 lanes (half and
+// row lane swaps, then DPP) and writes them to its own LDS slot; the window's
+// slots (one per wavefront) are summed in a fixed order and stored once per
+// (tile, Gaussian) pair, in the pair's emission slot.  A segmented reduction
+// over each Gaussian's contiguous emission range then yields its 2D gradient.
+// No float atomics touch global memory, so gradients are bit-reproducible.
 //
 // The conic is stored pre-scaled by -log2(e)/2 (-log2(e) for B) so the
 // exponent is in log2 units: alpha = min(0.99, opacity * 2^p); the entropy is
@@ -72,6 +73,38 @@ __device__ __forceinline__ float row_sum16(float x)
     x += dpp_f<0x141, 0xf>(x);   // row_half_mirror
     x += dpp_f<0x140, 0xf>(x);   // row_mirror
     return x;
+}
+
+// Wavefront sums of 9 values by a reduce-scatter: the gfx950 lane swaps
+// between the two 32-lane halves and between neighbouring 16-lane rows pair
+// values up so that one add serves two of them, then a 16-lane DPP row sum
+// finishes each register.  On return every lane of row r holds, in v0, the
+// wavefront total of o[row_comp(r)], in v1 that of o[4 + row_comp(r)], and in
+// v2 that of o[8].  Fixed order: bit-reproducible.
+__device__ __forceinline__ int row_comp(uint32_t r) { return (int)(((r & 1u) << 1) | (r >> 1)); }
+
+// lanes 0-31: x[l] + x[l + 32]; lanes 32-63: y[l - 32] + y[l]
+__device__ __forceinline__ float fold_halves(float x, float y)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// rows (0, 1, 2, 3) <- (x.r0 + x.r1, y.r0 + y.r1, x.r2 + x.r3, y.r2 + y.r3), lane by lane
+__device__ __forceinline__ float fold_rows(float x, float y)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ void wave_sum9(const float* o, float& v0, float& v1, float& v2)
+{
+    const float u0 = fold_halves(o[0], o[1]), u1 = fold_halves(o[2], o[3]);
+    const float u2 = fold_halves(o[4], o[5]), u3 = fold_halves(o[6], o[7]);
+    const float u4 = fold_halves(o[8], o[8]);
+    v0 = row_sum16(fold_rows(u0, u1));
+    v1 = row_sum16(fold_rows(u2, u3));
+    v2 = row_sum16(fold_rows(u4, u4));
 }
 
 __device__ __forceinline__ int wave_max_i32(int x)
@@ -281,17 +314,39 @@ struct BwdPix {
     float fpx, fpy;
 };
 
-// Contribution of list entry `pos` to the 9 gradient components of its
-// Gaussian, for one pixel.  Branch-free: every lane evaluates the entry and a
-// lane whose pixel did not blend it (position past its last contributor, or
-// alpha < 1/255) contributes zero and keeps its state.
-__device__ __forceinline__ void bwd_entry(BwdPix& q, int32_t pos, float4 g0, float4 g1, float cb, float* o)
+// Backward of list entry `pos` for one pixel.  Branch-free per lane: every
+// lane evaluates the entry and a lane whose pixel did not blend it (position
+// past its last contributor, or alpha < 1/255) contributes zero and keeps its
+// state.  bwd_alpha evaluates alpha; bwd_grad, run only if some lane of the
+// wavefront blended the entry, updates the walk state and returns the 9 per-pixel
+// terms whose sums over pixels give the entry's gradient:
+//   o[0] = e2 dg          (-> opacity; e2 = 2^p, dg = dL/dalpha in the unclamped branch)
+//   o[1] = o[0] dx,  o[2] = o[0] dy                     (-> mean, with the conic)
+//   o[3] = o[1] dx,  o[4] = o[1] dy,  o[5] = o[2] dy     (-> conic A, B, C)
+//   o[6..8] = w dL/dC                                   (-> colour)
+// The per-Gaussian factors (opacity, conic, ln 2) are applied once per
+// (tile, Gaussian) after the sum, by finish_row.
+struct BwdAlpha {
+    float dx, dy, e2, a_raw, alpha;
+    bool act;
+};
+
+__device__ __forceinline__ BwdAlpha bwd_alpha(const BwdPix& q, int32_t pos, float4 g0, float4 g1)
 {
-    const float dx = g0.x - q.fpx, dy = g0.y - q.fpy;
-    const float e2 = __builtin_amdgcn_exp2f(gauss_p2(g0.z, g0.w, g1.x, dx, dy));
-    const float a_raw = g1.y * e2;
-    const float alpha = fminf(kAlphaMax, a_raw);
-    const bool act = (pos < q.n) & (alpha >= kAlphaMin);
+    BwdAlpha r;
+    r.dx = g0.x - q.fpx;
+    r.dy = g0.y - q.fpy;
+    r.e2 = __builtin_amdgcn_exp2f(gauss_p2(g0.z, g0.w, g1.x, r.dx, r.dy));
+    r.a_raw = g1.y * r.e2;
+    r.alpha = fminf(kAlphaMax, r.a_raw);
+    r.act = (pos < q.n) & (r.alpha >= kAlphaMin);
+    return r;
+}
+
+__device__ __forceinline__ void bwd_grad(BwdPix& q, const BwdAlpha& r, float4 g1, float cb, float* o)
+{
+    const bool act = r.act;
+    const float alpha = r.alpha;
     const float rom = __builtin_amdgcn_rcpf(1.f - alpha);
     const float Ti = q.T * rom;                              // T_i = T_{i+1} / (1 - alpha_i)
     const float w = alpha * Ti;
@@ -300,23 +355,40 @@ __device__ __forceinline__ void bwd_entry(BwdPix& q, int32_t pos, float4 g0, flo
     float dal = q.gCr * (Ti * g1.z - q.Sr * rom) + q.gCg * (Ti * g1.w - q.Sg * rom) + q.gCb * (Ti * cb - q.Sb * rom);
     dal += q.gh * ((-lw - 1.f) * Ti + q.Rs * rom);
     const float wa = act ? w : 0.f;
-    const float dg = (act & (a_raw <= kAlphaMax)) ? dal : 0.f;   // zero in the clamped branch
+    const float dg = (act & (r.a_raw <= kAlphaMax)) ? dal : 0.f;   // zero in the clamped branch
+    o[0] = r.e2 * dg;
+    o[1] = o[0] * r.dx;
+    o[2] = o[0] * r.dy;
+    o[3] = o[1] * r.dx;
+    o[4] = o[1] * r.dy;
+    o[5] = o[2] * r.dy;
     o[6] = wa * q.gCr;
     o[7] = wa * q.gCg;
     o[8] = wa * q.gCb;
-    o[5] = e2 * dg;                                          // d alpha / d opacity = 2^p
-    const float dp = alpha * dg;                             // dL/d(exponent in natural-log units)
-    o[2] = (-0.5f * dx) * dx * dp;                           // conic A, B, C (unscaled)
-    o[3] = -dx * dy * dp;
-    o[4] = (-0.5f * dy) * dy * dp;
-    const float dpl = kLn2 * dp;
-    o[0] = dpl * fmaf(2.f * g0.z, dx, g0.w * dy);            // mean x
-    o[1] = dpl * fmaf(2.f * g1.x, dy, g0.w * dx);            // mean y
     q.Sr = fmaf(wa, g1.z, q.Sr);
     q.Sg = fmaf(wa, g1.w, q.Sg);
     q.Sb = fmaf(wa, cb, q.Sb);
     q.Rs = fmaf(lw + 1.f, wa, q.Rs);                         // R_i = (log w_i + 1) w_i + R_{i+1}
     q.T = act ? Ti : q.T;
+}
+
+// Gradient row of one (tile, Gaussian) pair from the summed terms S[0..8] of
+// bwd_grad, with g0 = (mean, A', B'), g1 = (C', opacity, ...):  alpha = opacity 2^p and
+// p = A' dx^2 + B' dx dy + C' dy^2 (log2 units), so dalpha/dp = alpha ln 2 and
+// dalpha/d(natural-log exponent) = alpha.
+__device__ __forceinline__ void finish_row(const float* S, float4 g0, float4 g1, float* G)
+{
+    const float sig = g1.y;
+    const float sl = kLn2 * sig;
+    G[0] = sl * fmaf(2.f * g0.z, S[1], g0.w * S[2]);         // mean x
+    G[1] = sl * fmaf(2.f * g1.x, S[2], g0.w * S[1]);         // mean y
+    G[2] = -0.5f * sig * S[3];                               // conic A, B, C (unscaled)
+    G[3] = -sig * S[4];
+    G[4] = -0.5f * sig * S[5];
+    G[5] = S[0];                                             // opacity
+    G[6] = S[6];                                             // colour
+    G[7] = S[7];
+    G[8] = S[8];
 }
 
 __device__ __forceinline__ void bwd_init(const BlendBwdArgs& a, const BlockGeom& g, int32_t len, BwdPix& q)
@@ -352,7 +424,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     __shared__ float s_b[NS][B];
     __shared__ float2 s_cull[NS][B];                    // (eps, L)
     __shared__ uint32_t s_e[NS][B];
-    __shared__ float s_acc[kWavesPerGroup * 4][B * kG2]; // per (wavefront, 16-lane row) partial sums
+    __shared__ float s_acc[kWavesPerGroup][B * kG2];     // per-wavefront sums of each window entry
     __shared__ int32_t s_idx[kWavesPerGroup][B];        // surviving window entries of each wavefront
     __shared__ int32_t s_max[kWavesPerGroup];
     __shared__ uint32_t s_item;
@@ -390,9 +462,9 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     }
     const int32_t nthr = SHARED ? 256 : 64;
     const int32_t tid = SHARED ? (int32_t)threadIdx.x : (int32_t)lane;
-    for (int32_t r = 0; r < 4; ++r)
-        for (int32_t i = (int32_t)lane; i < B * kG2; i += kWave) s_acc[wid * 4 + r][i] = 0.f;
-    float* acc_row = s_acc[wid * 4 + (lane >> 4)];
+    for (int32_t i = (int32_t)lane; i < B * kG2; i += kWave) s_acc[wid][i] = 0.f;
+    const bool row_lead = (lane & 15u) == 0u;
+    const int32_t rc = row_comp(lane >> 4);
 
     for (int32_t hi = maxn; hi > 0; hi -= B) {
         const int32_t lo = hi - B > 0 ? hi - B : 0;
@@ -424,32 +496,45 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
             m += (int32_t)__popcll(bal);
         }
         wave_lds_sync();
-        // walk them back to front; per Gaussian, a wavefront sum written to this wavefront's slot
+        // walk them back to front; per Gaussian, the wavefront sums go to this wavefront's slot
         for (int32_t kk = m - 1; kk >= 0; --kk) {
             const int32_t j = s_idx[wid][kk];
-            float o[kG2];
-            bwd_entry(q, lo + j, s_g0[slot][j], s_g1[slot][j], s_b[slot][j], o);
-#pragma unroll
-            for (int k = 0; k < kG2; ++k) o[k] = row_sum16(o[k]);
-            if ((lane & 15u) == 0u) {
-#pragma unroll
-                for (int k = 0; k < kG2; ++k) acc_row[j * kG2 + k] = o[k];
+            const float4 g1 = s_g1[slot][j];
+            const BwdAlpha al = bwd_alpha(q, lo + j, s_g0[slot][j], g1);
+            if (__ballot(al.act) != 0ull) {                  // else no lane of this wavefront blended it
+                float o[kG2];
+                bwd_grad(q, al, g1, s_b[slot][j], o);
+                float v0, v1, v2;
+                wave_sum9(o, v0, v1, v2);
+                if (row_lead) {
+                    float* dst = s_acc[wid] + j * kG2;
+                    dst[rc] = v0;
+                    dst[4 + rc] = v1;
+                    if (lane == 0u) dst[8] = v2;
+                }
             }
         }
         if (SHARED) __syncthreads(); else wave_lds_sync();
         // store the window's per-pair rows (emission slots), summing the
-        // (wavefront, row) slots in a fixed order, and clear the slots
-        for (int32_t i = tid; i < cnt * kG2; i += nthr) {
-            const int32_t j = i / kG2, k = i - j * kG2;
-            constexpr int32_t nsl = SHARED ? 4 * kWavesPerGroup : 4;
-            const int32_t s0 = SHARED ? 0 : (int32_t)wid * 4;
-            float v = 0.f;
+        // wavefront slots in a fixed order, and clear the slots
+        for (int32_t j = tid; j < cnt; j += nthr) {
+            constexpr int32_t nsl = SHARED ? kWavesPerGroup : 1;
+            const int32_t s0 = SHARED ? 0 : (int32_t)wid;
+            float S[kG2], G[kG2];
 #pragma unroll
-            for (int32_t r = 0; r < nsl; ++r) {
-                v += s_acc[s0 + r][i];
-                s_acc[s0 + r][i] = 0.f;
+            for (int k = 0; k < kG2; ++k) {
+                float v = 0.f;
+#pragma unroll
+                for (int32_t r = 0; r < nsl; ++r) {
+                    v += s_acc[s0 + r][j * kG2 + k];
+                    s_acc[s0 + r][j * kG2 + k] = 0.f;
+                }
+                S[k] = v;
             }
-            a.pair_grad[(size_t)kG2 * s_e[slot][j] + k] = v;
+            finish_row(S, s_g0[slot][j], s_g1[slot][j], G);
+            float* row = a.pair_grad + (size_t)kG2 * s_e[slot][j];
+#pragma unroll
+            for (int k = 0; k < kG2; ++k) row[k] = G[k];
         }
         if (SHARED) __syncthreads(); else wave_lds_sync();
     }
@@ -533,7 +618,7 @@ hipError_t fwd_b(const BlendFwdArgs& a, hipStream_t s)
 template <int B>
 hipError_t bwd_b(const BlendBwdArgs& a, hipStream_t s)
 {
-    static_assert(B <= 64, "the backward window is limited by LDS");
+    static_assert(B <= 128, "the backward window is limited by LDS");
     const uint32_t groups = (a.n_blocks + kWavesPerGroup - 1) / kWavesPerGroup;
     if (a.work_counter) {
         if (a.spt == 4)
@@ -568,9 +653,9 @@ hipError_t launch_blend_bwd(const BlendBwdArgs& a, int lds_batch, hipStream_t s)
     if (a.n_blocks == 0) return hipSuccess;
     switch (lds_batch) {
         case 32: return bwd_b<32>(a, s);
-        case 64:
+        case 64: return bwd_b<64>(a, s);
         case 128:
-        case 256: return bwd_b<64>(a, s);       // the backward window is capped at 64 entries (LDS)
+        case 256: return bwd_b<128>(a, s);      // the backward window is capped at 128 entries (LDS)
     }
     return hipErrorInvalidValue;
 }

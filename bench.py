@@ -32,9 +32,19 @@ HBM_PEAK_GBS = 8000.0
 # VALU issue rate without packed FP32: 256 CUs x 64 lanes x 2.4 GHz (one FP32 op per lane per clock)
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# Algorithmic work per unit (see the design notes for the derivation)
-OPS_PER_EVAL_FWD = 20       # VALU ops per alpha evaluation in the forward blend
-OPS_PER_EVAL_BWD = 50       # VALU ops per list position walked by the backward blend
+# Algorithmic work of the blend kernels (the derivation is in the design notes).
+# Per pixel the method walks its list: every position visited costs the alpha
+# test; a position that is blended (alpha >= 1/255 before the ray stopped) costs
+# the blending (forward) or its gradient (backward) on top.
+OPS_ALPHA_TEST = 11         # FP32 VALU ops: offset, exponent, exp2, opacity scale, clamp, skip test
+OPS_BLEND_FWD = 10          # per blended pair: transmittance, stop test, colour, entropy term
+OPS_BLEND_BWD = 49          # per blended pair: T recovery, dC/dalpha, Alg. 1, 9 gradient terms and their sums
+
+
+def blend_ops(kind, st):
+    if kind == "blend_fwd":
+        return OPS_ALPHA_TEST * st["evals_fwd"] + OPS_BLEND_FWD * st["blended"]
+    return OPS_ALPHA_TEST * st["evals_bwd"] + OPS_BLEND_BWD * st["blended"]
 
 
 def parse():
@@ -205,14 +215,14 @@ def main():
         R.set_timing(False)
     stages = R.stage_times(reset=True) if timing else {}
     if args.per_view:      # statistics of every view: forward each once more, untimed
-        st = dict(pairs=0, evals_fwd=0, evals_bwd=0, mean_len=0.0, p99_len=0, overflow=False)
+        st = dict(pairs=0, evals_fwd=0, evals_bwd=0, blended=0, mean_len=0.0, p99_len=0, overflow=False)
         n_t = 0
         for w in work:
             R.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], w["cams"], opts, out=w["out"])
             sv = R.stats(1)
             c = w["cams"][0]
             nt = ((c.width + tile[0] - 1) // tile[0]) * ((c.height + tile[1] - 1) // tile[1])
-            for k in ("pairs", "evals_fwd", "evals_bwd"):
+            for k in ("pairs", "evals_fwd", "evals_bwd", "blended"):
                 st[k] += sv[k]
             st["mean_len"] += sv["mean_len"] * nt
             n_t += nt
@@ -234,10 +244,10 @@ def main():
         avg_s = ms / cnt / 1e3
         b = stage_bytes(name, n, V, sh_bytes, st["pairs"], n_tiles, npix, st["evals_fwd"], st["evals_bwd"])
         rep = {"avg_ms": round(ms / cnt, 4), "hbm_GBs": round(b / avg_s / 1e9, 1) if b else None}
-        if name == "blend_fwd":
-            rep["valu_Tops"] = round(OPS_PER_EVAL_FWD * st["evals_fwd"] / avg_s / 1e12, 3)
-        if name == "blend_bwd":
-            rep["valu_Tops"] = round(OPS_PER_EVAL_BWD * st["evals_bwd"] / avg_s / 1e12, 3)
+        if name in ("blend_fwd", "blend_bwd"):
+            rep["valu_Tops"] = round(blend_ops(name, st) / avg_s / 1e12, 3)
+            rep["evals_G_per_s"] = round(st["evals_fwd" if name == "blend_fwd" else "evals_bwd"] / avg_s / 1e9, 2)
+            rep["blended_G_per_s"] = round(st["blended"] / avg_s / 1e9, 3)
         stage_report[name] = rep
 
     roofline = None
@@ -253,7 +263,7 @@ def main():
             if os.path.exists(src) and source_hash(src) == rec.get("source_sha256_16"):
                 traffic = rec.get("bytes_per_launch")
         if dom in ("blend_fwd", "blend_bwd"):
-            ops = (OPS_PER_EVAL_FWD * st["evals_fwd"]) if dom == "blend_fwd" else (OPS_PER_EVAL_BWD * st["evals_bwd"])
+            ops = blend_ops(dom, st)
             ach = ops / avg_s / 1e12
             roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 2),
                         "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": traffic,
@@ -280,6 +290,7 @@ def main():
                    "loss": "L1 + 0.015 L_E"},
         "pairs_per_s": round(st["pairs"] / sec, 1), "pairs": st["pairs"], "mean_list_len": round(st["mean_len"], 2),
         "p99_list_len": st["p99_len"], "evals_fwd": st["evals_fwd"], "evals_bwd": st["evals_bwd"],
+        "blended": st["blended"],
         "overflow": st["overflow"], "stages": stage_report, "roofline": roofline,
     }
     if not args.no_cpu_baseline:

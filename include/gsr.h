@@ -174,11 +174,12 @@ gsr_status gsr_l1_loss(gsr_ctx* ctx, void* stream, const gsr_camera* cams, int32
 typedef struct {
     int64_t pairs;             /* (tile, Gaussian) pairs over all views */
     double mean_len;           /* mean per-tile list length over all tiles */
-    int32_t p99_len;           /* 99th percentile of the per-tile list length; -1 if above 4095 */
+    int32_t p99_len;           /* 99th percentile of the per-tile list length */
     int32_t overflow;          /* 1 if a fixed pair capacity was exceeded: that forward is invalid */
     int64_t evals_fwd;         /* alpha evaluations of the forward blend: per pixel, the list
                                   positions visited until the ray stopped or the list ended */
     int64_t evals_bwd;         /* list positions the backward walks: the sum of n_contrib */
+    int64_t blended;           /* (pixel, Gaussian) pairs blended: alpha >= 1/255 before the ray stopped */
 } gsr_frame_stats;
 
 /* Fills `out` (host) and pairs_per_view [n_views] (host, may be NULL) for
@@ -221,10 +222,12 @@ gsr_status gsr_autotune(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, cons
  * (synchronises `stream`); for stage-by-stage testing.  *bytes receives the
  * size of the buffer; dst may be NULL to query it. */
 typedef enum {
-    GSR_BUF_RECORDS = 0,       /* float[V*n][12]: mean x, y, A', B', C', opacity, r, g, b, eps, L, 0 with
-                                  the conic pre-scaled: A' = -A log2(e)/2, B' = -B log2(e), C' = -C log2(e)/2,
-                                  and (eps, L) the data the blend uses to skip Gaussians that cannot reach
-                                  alpha >= 1/255 anywhere in an 8x8 pixel block */
+    GSR_BUF_RECORDS = 0,       /* float[V*n][12]: mean x, y, A', B', C', opacity, r, g, b, L, base, w with
+                                  the conic pre-scaled: A' = -A log2(e)/2, B' = -B log2(e), C' = -C log2(e)/2;
+                                  L = log2(255 opacity) + 1e-4, the level the blend uses to skip Gaussians
+                                  that cannot reach alpha >= 1/255 anywhere in an 8x8 pixel block; base and w
+                                  (uint32 bits, set for Gaussians with pairs) place the pair of local tile
+                                  (tx, ty) at emission index base + ty w + tx */
     GSR_BUF_RADIUS = 1,        /* int32[V*n], 0 = culled */
     GSR_BUF_DEPTH = 2,         /* float[V*n], camera z */
     GSR_BUF_TILES_TOUCHED = 3, /* int32[V*n] */

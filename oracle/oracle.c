@@ -463,11 +463,11 @@ int orc_render(int W, int H, int tw, int th, int64_t n,
                const double* mean2d, const double* conic, const double* opac, const double* rgb,
                const int32_t* ranges, const int32_t* values, const uint8_t* pix,
                double* out_rgb, double* out_H, double* out_T, int32_t* out_nc, uint8_t* out_flags,
-               int64_t* n_eval, uint64_t* sig)
+               int64_t* n_eval, int64_t* n_blend, uint64_t* sig)
 {
     (void)n;
     int gx = (W + tw - 1) / tw;
-    int64_t ev = 0;
+    int64_t ev = 0, nbl = 0;
     uint64_t s = 1469598103934665603ULL;
     for (int py = 0; py < H; ++py)
         for (int px = 0; px < W; ++px) {
@@ -476,13 +476,14 @@ int orc_render(int W, int H, int tw, int th, int64_t n,
             int t = pixel_tile(px, py, tw, th, gx);
             int32_t b = ranges[2 * t], e = ranges[2 * t + 1];
             pixres_t r;
-            walk_pixel(px + 0.5, py + 0.5, values + b, e - b, NULL, mean2d, conic, opac, rgb, NULL, &r);
+            nbl += walk_pixel(px + 0.5, py + 0.5, values + b, e - b, NULL, mean2d, conic, opac, rgb, NULL, &r);
             for (int ch = 0; ch < 3; ++ch) out_rgb[3 * p + ch] = r.C[ch];
             out_H[p] = r.H; out_T[p] = r.T; out_nc[p] = r.ncontrib; out_flags[p] = r.flags;
             ev += r.n_eval;
             s = fnv(s, r.sig);
         }
     if (n_eval) *n_eval = ev;
+    if (n_blend) *n_blend = nbl;
     if (sig) *sig = s;
     return 0;
 }

@@ -50,7 +50,7 @@ def lib():
         L.orc_count_pairs.argtypes = [i64, P, P, i32, i32, i32, i32, P, P]
         L.orc_count_pairs.restype = i64
         L.orc_bin.argtypes = [i64, P, P, P, i32, i32, i32, i32, i64, P, P]
-        L.orc_render.argtypes = [i32, i32, i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_render.argtypes = [i32, i32, i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_render_bruteforce.argtypes = [i32, i32, i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_backward_render.argtypes = [i32, i32, i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_backward_project.argtypes = [i64, P, P, P, P, i32, P, u32, P, P, P, P, P, P, P]
@@ -136,11 +136,13 @@ def render(W, H, tw, th, mean2d, conic, opac, rgb, ranges, values, pix=None):
                ncontrib=np.zeros((H, W), np.int32), flags=np.zeros((H, W), np.uint8))
     pm = None if pix is None else np.ascontiguousarray(pix, np.uint8)
     ev = ctypes.c_int64(0)
+    nb = ctypes.c_int64(0)
     sig = ctypes.c_uint64(0)
     lib().orc_render(W, H, tw, th, n, _p(m2), _p(cn), _p(op), _p(cl), _p(rg), _p(vl),
                      None if pm is None else _p(pm), _p(out["rgb"]), _p(out["H"]), _p(out["T"]),
-                     _p(out["ncontrib"]), _p(out["flags"]), ctypes.byref(ev), ctypes.byref(sig))
+                     _p(out["ncontrib"]), _p(out["flags"]), ctypes.byref(ev), ctypes.byref(nb), ctypes.byref(sig))
     out["n_eval"] = int(ev.value)
+    out["n_blend"] = int(nb.value)
     out["sig"] = int(sig.value)
     return out
 

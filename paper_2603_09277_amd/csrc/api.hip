@@ -53,7 +53,7 @@ struct gsr_ctx {
 
     // grow-only device buffers
     Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
-    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, tord, block_H, block_cnt, hchunk, counters, len_hist, view_pairs, l1_tmp;
+    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, tord, block_H, block_cnt, hchunk, counters, l1_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
     uint64_t gen_fwd = 0, gen_bwd = 0;
@@ -139,7 +139,8 @@ struct StageTimer {
         if (e_ != hipSuccess) return fail((ctx), GSR_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-gsr_status grow(gsr_ctx* c, Dev& d, size_t bytes)
+// grow-only reallocation; zero = clear the new memory (once, synchronously)
+gsr_status grow(gsr_ctx* c, Dev& d, size_t bytes, bool zero = false)
 {
     if (bytes <= d.bytes) return GSR_OK;
     if (d.p) {
@@ -157,6 +158,8 @@ gsr_status grow(gsr_ctx* c, Dev& d, size_t bytes)
         return fail(c, GSR_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
     }
     d.bytes = b;
+    if (zero && (hipMemset(d.p, 0, b) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
+        return fail(c, GSR_ERR_HIP, "clearing a new buffer failed");
     return GSR_OK;
 }
 
@@ -283,7 +286,7 @@ gsr_status ensure_pairs(gsr_ctx* c, size_t p)
     if (p >= 0xfffffff0ull) return fail(c, GSR_ERR_CAPACITY, "pair count exceeds 2^32");
     gsr_status s;
     if ((s = grow(c, c->pk0, p * 4)) || (s = grow(c, c->pk1, p * 4)) || (s = grow(c, c->pv0, p * 4)) ||
-        (s = grow(c, c->pv1, p * 4)) || (s = grow(c, c->emit_vg, p * 4)) || (s = grow(c, c->pair_grad, p * 4 * kG2)) ||
+        (s = grow(c, c->pv1, p * 4)) || (s = grow(c, c->emit_vg, p * 4)) || (s = grow(c, c->pair_grad, p * 4 * kRowF, true)) ||
         (s = grow(c, c->seg_carry, seg_carry_bytes((uint32_t)p))))
         return s;
     c->pair_cap = p;
@@ -302,7 +305,7 @@ gsr_status ensure_tiles(gsr_ctx* c, uint32_t tiles, uint32_t blocks)
         (s = grow(c, c->tord, (size_t)std::max<uint32_t>(tiles, 1) * 16)) ||
         (s = grow(c, c->radix_tmp, radix_tmp_words(std::max<uint32_t>(tiles, 1)) * 4)) ||
         (s = grow(c, c->block_H, (size_t)std::max<uint32_t>(blocks, 1) * 4)) ||
-        (s = grow(c, c->block_cnt, (size_t)std::max<uint32_t>(blocks, 1) * 8)) ||
+        (s = grow(c, c->block_cnt, (size_t)std::max<uint32_t>(blocks, 1) * 16)) ||
         (s = grow(c, c->hchunk, (size_t)(blocks / kRedChunk + 64) * 8)))
         return s;
     return GSR_OK;
@@ -364,7 +367,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
         StageTimer tm(c, st, GSR_STAGE_DUPLICATE, plain);
         HIP_TRY(c, launch_duplicate(od[0], (const uint32_t*)c->offsets.p, (const uint32_t*)c->tt.p,
                                     (const uint2*)c->rect.p, dc, n, vn, counters, cap, pk[0], pv[0],
-                                    (uint32_t*)c->emit_vg.p, counters + 1, st));
+                                    (uint32_t*)c->emit_vg.p, counters + 1, (float4*)c->rec.p, st));
     }
     // stable sort of the pairs by tile id
     int tile_bits = std::max(1, ilog2((int)std::max<uint32_t>(L.n_tiles, 2)));
@@ -392,12 +395,12 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     }
 
     BlendFwdArgs ba;
-    ba.rec = (const float4*)c->rec.p; ba.pair_vals = pv[sb]; ba.emit_vg = (const uint32_t*)c->emit_vg.p;
+    ba.rec = (const float4*)c->rec.p; ba.pair_vals = pv[sb];
     ba.ranges = (const uint2*)c->ranges.p; ba.cams = dc;
     ba.n_views = (int32_t)V; ba.tile_shift_x = L.tsx; ba.tile_shift_y = L.tsy; ba.spt = L.spt; ba.n_blocks = L.n_blocks;
     ba.out_rgb = out->rgb; ba.out_H = out->entropy; ba.out_T = out->t_final; ba.out_nc = out->n_contrib;
     ba.block_H = (float*)c->block_H.p;
-    ba.block_cnt = (uint2*)c->block_cnt.p;
+    ba.block_cnt = (uint4*)c->block_cnt.p;
     ba.tile_order = persist ? (const uint32_t*)c->tord.p + 3 * L.n_tiles : nullptr;
     ba.work_counter = persist ? counters + 2 : nullptr;
     {
@@ -423,14 +426,16 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     const uint32_t n = (uint32_t)g->n, V = (uint32_t)L.cams.size(), vn = n * V;
     const CamDev* dc = (const CamDev*)c->cams.p;
     StageTimer tb(c, st, GSR_STAGE_BLEND_BWD, plain);
+    // a new stamp for the per-pair rows this backward writes
+    HIP_TRY(c, launch_bump_u32((uint32_t*)c->counters.p + 4, st));
     uint32_t* pv[2] = { (uint32_t*)c->pv0.p, (uint32_t*)c->pv1.p };
     BlendBwdArgs bb;
-    bb.rec = (const float4*)c->rec.p; bb.pair_vals = pv[c->sorted_buf]; bb.emit_vg = (const uint32_t*)c->emit_vg.p;
+    bb.rec = (const float4*)c->rec.p; bb.pair_vals = pv[c->sorted_buf];
     bb.ranges = (const uint2*)c->ranges.p;
     bb.cams = dc; bb.n_views = (int32_t)V; bb.tile_shift_x = L.tsx; bb.tile_shift_y = L.tsy; bb.spt = L.spt;
     bb.n_blocks = L.n_blocks;
     bb.T_final = saved->t_final; bb.n_contrib = saved->n_contrib; bb.grad_rgb = grad_rgb; bb.grad_H = grad_H;
-    bb.grad_LE = grad_LE; bb.pair_grad = (float*)c->pair_grad.p;
+    bb.grad_LE = grad_LE; bb.pair_grad = (float*)c->pair_grad.p; bb.stamp = (const uint32_t*)c->counters.p + 4;
     const bool persist = (o->flags & GSR_PERSISTENT) != 0;
     bb.tile_order = persist ? (const uint32_t*)c->tord.p + 3 * L.n_tiles : nullptr;
     bb.work_counter = persist ? (uint32_t*)c->counters.p + 3 : nullptr;
@@ -439,7 +444,8 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     tb.stop();
     {
         StageTimer tr(c, st, GSR_STAGE_GRAD_REDUCE, plain);
-        HIP_TRY(c, launch_grad_reduce((const float*)c->pair_grad.p, (const uint32_t*)c->emit_vg.p,
+        HIP_TRY(c, launch_grad_reduce((const float*)c->pair_grad.p, (const uint32_t*)c->counters.p + 4,
+                                      (const uint32_t*)c->emit_vg.p,
                                       vn, (const uint32_t*)c->counters.p, (uint32_t)c->pair_cap_used,
                                       (float*)c->grad2d.p, c->seg_carry.p, st));
     }
@@ -513,9 +519,7 @@ gsr_status gsr_create(gsr_ctx** out, int32_t max_views, int64_t pair_capacity)
     gsr_status s = GSR_OK;
     if (hipGetDevice(&c->device) != hipSuccess) s = GSR_ERR_HIP;
     if (!s) s = grow(c, c->cams, sizeof(CamDev) * (size_t)max_views);
-    if (!s) s = grow(c, c->counters, 64);
-    if (!s) s = grow(c, c->len_hist, 4 * 4097);
-    if (!s) s = grow(c, c->view_pairs, 8 * (size_t)max_views);
+    if (!s) s = grow(c, c->counters, 64, true);     // [4]: backward row stamp
     if (!s && hipHostMalloc((void**)&c->counters_host, 64, hipHostMallocDefault) != hipSuccess) s = GSR_ERR_HIP;
     if (!s && hipHostMalloc((void**)&c->cams_host, sizeof(CamDev) * (size_t)max_views, hipHostMallocDefault) != hipSuccess)
         s = GSR_ERR_HIP;
@@ -540,7 +544,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     drop_graphs(c);
     Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->radius,
                    &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
-                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->tord, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->len_hist, &c->view_pairs,
+                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->tord, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters,
                    &c->l1_tmp };
     for (Dev* d : all) free_dev(*d);
     for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
@@ -702,41 +706,44 @@ gsr_status gsr_stats(gsr_ctx* c, void* stream, int64_t* pairs_per_view, gsr_fram
     if (!c->have_frame) return fail(c, GSR_ERR_INVALID_ARG, "no forward has run on this context");
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
-    const int nb = 4097;
-    HIP_TRY(c, launch_fill_u32((uint32_t*)c->len_hist.p, 0u, nb, st));
-    HIP_TRY(c, launch_len_hist((const uint2*)c->ranges.p, c->lay.n_tiles, (uint32_t*)c->len_hist.p, nb, st));
-    HIP_TRY(c, launch_view_pairs((const uint2*)c->ranges.p, (const CamDev*)c->cams.p, c->n_views,
-                                 (uint64_t*)c->view_pairs.p, st));
-    std::vector<uint32_t> h(nb);
-    std::vector<uint64_t> vp(c->n_views);
-    std::vector<uint32_t> cnt2((size_t)c->lay.n_blocks * 2 + 2);
+    const uint32_t nt = c->lay.n_tiles;
+    std::vector<uint32_t> rg((size_t)nt * 2 + 2);
+    std::vector<uint32_t> cnt2((size_t)c->lay.n_blocks * 4 + 4);
     uint32_t cnt[2];
-    HIP_TRY(c, hipMemcpyAsync(h.data(), c->len_hist.p, 4 * nb, hipMemcpyDeviceToHost, st));
-    HIP_TRY(c, hipMemcpyAsync(vp.data(), c->view_pairs.p, 8 * c->n_views, hipMemcpyDeviceToHost, st));
+    if (nt) HIP_TRY(c, hipMemcpyAsync(rg.data(), c->ranges.p, (size_t)nt * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(cnt, c->counters.p, 8, hipMemcpyDeviceToHost, st));
     if (c->lay.n_blocks)
-        HIP_TRY(c, hipMemcpyAsync(cnt2.data(), c->block_cnt.p, (size_t)c->lay.n_blocks * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipMemcpyAsync(cnt2.data(), c->block_cnt.p, (size_t)c->lay.n_blocks * 16, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
     c->replay_pending = false;
     std::memset(out, 0, sizeof *out);
     out->overflow = (cnt[1] != 0 || cnt[0] > c->pair_cap) ? 1 : 0;
+    // per-tile list lengths: pairs per view, mean, exact 99th percentile
+    std::vector<uint32_t> len(nt);
     uint64_t total = 0;
     for (int v = 0; v < c->n_views; ++v) {
-        total += vp[v];
-        if (pairs_per_view) pairs_per_view[v] = (int64_t)vp[v];
+        const uint32_t t0 = c->lay.cams[v].tile_base;
+        const uint32_t t1 = v + 1 < c->n_views ? c->lay.cams[v + 1].tile_base : nt;
+        uint64_t sum = 0;
+        for (uint32_t t = t0; t < t1; ++t) {
+            const uint32_t a = rg[2 * t], b = rg[2 * t + 1];
+            len[t] = b > a ? b - a : 0u;
+            sum += len[t];
+        }
+        total += sum;
+        if (pairs_per_view) pairs_per_view[v] = (int64_t)sum;
     }
     out->pairs = (int64_t)total;
-    out->mean_len = c->lay.n_tiles ? (double)total / c->lay.n_tiles : 0.0;
-    uint64_t need = (uint64_t)std::ceil(0.99 * c->lay.n_tiles), acc = 0;
-    int32_t p = 0;
-    for (int b = 0; b < nb; ++b) {
-        acc += h[b];
-        if (acc >= need) { p = b; break; }
+    out->mean_len = nt ? (double)total / nt : 0.0;
+    if (nt) {
+        const size_t k = (size_t)std::ceil(0.99 * nt) - 1;      // smallest length >= 99 % of the tiles
+        std::nth_element(len.begin(), len.begin() + (ptrdiff_t)k, len.end());
+        out->p99_len = (int32_t)len[k];
     }
-    out->p99_len = (p == nb - 1) ? -1 : p;
     for (uint32_t b = 0; b < c->lay.n_blocks; ++b) {
-        out->evals_fwd += cnt2[2 * b];
-        out->evals_bwd += cnt2[2 * b + 1];
+        out->evals_fwd += cnt2[4 * b];
+        out->evals_bwd += cnt2[4 * b + 1];
+        out->blended += cnt2[4 * b + 2];
     }
     c->pairs = cnt[0];
     return GSR_OK;
@@ -812,21 +819,7 @@ gsr_status gsr_inspect(gsr_ctx* c, void* stream, gsr_buffer which, void* dst, in
         case GSR_BUF_RADIUS: src = c->radius.p; sz = (size_t)c->vn * 4; break;
         case GSR_BUF_DEPTH: src = c->depth.p; sz = (size_t)c->vn * 4; break;
         case GSR_BUF_TILES_TOUCHED: src = c->tt.p; sz = (size_t)c->vn * 4; break;
-        case GSR_BUF_PAIR_VALUES: {       // emission index -> view*n + Gaussian index, on the host
-            sz = (size_t)c->pairs * 4;
-            *bytes = (int64_t)sz;
-            if (!dst) return GSR_OK;
-            if ((int64_t)sz > capacity_bytes) return fail(c, GSR_ERR_INVALID_ARG, "destination too small");
-            std::vector<uint32_t> e(c->pairs), m(c->pairs);
-            if (sz) {
-                HIP_TRY(c, hipMemcpyAsync(e.data(), pv[c->sorted_buf], sz, hipMemcpyDeviceToHost, st));
-                HIP_TRY(c, hipMemcpyAsync(m.data(), c->emit_vg.p, sz, hipMemcpyDeviceToHost, st));
-            }
-            HIP_TRY(c, hipStreamSynchronize(st));
-            uint32_t* out = (uint32_t*)dst;
-            for (uint32_t i = 0; i < c->pairs; ++i) out[i] = m[e[i]];
-            return GSR_OK;
-        }
+        case GSR_BUF_PAIR_VALUES: src = pv[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
         case GSR_BUF_PAIR_TILES: src = pk[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
         case GSR_BUF_RANGES: src = c->ranges.p; sz = (size_t)c->lay.n_tiles * 8; break;
         case GSR_BUF_GRAD2D: src = c->grad2d.p; sz = (size_t)c->vn * 4 * kG2; break;

@@ -133,6 +133,7 @@ __device__ __forceinline__ float wave_sum_all(float x)
 
 struct BlockGeom {
     int view;
+    uint32_t tx, ty;                 // tile coordinates in the view
     int px, py;
     bool inside;
     uint32_t tile;
@@ -148,9 +149,13 @@ __device__ __forceinline__ float edge_max(float a, float b, float c, float u, fl
 }
 
 // true if the Gaussian cannot reach alpha >= 1/255 at any pixel centre of the
-// block: r0 = (mean, A', B'), c2 = C', eps = 2e-6 (|A'|+|B'|+|C'|), L = log2(255 opacity) + 1e-4
-__device__ __forceinline__ bool culled(const BlockGeom& g, float4 r0, float c2, float eps, float L)
+// block: r0 = (mean, A', B'), c2 = C', L = log2(255 opacity) + 1e-4.  The blend
+// evaluates the exponent in FP32 with an error below 1e-6 (|A'|+|B'|+|C'|) |d|^2;
+// the test adds twice that bound (and 1.5 % more) to the exact maximum of the
+// exponent over the block's pixel-centre rectangle.
+__device__ __forceinline__ bool culled(const BlockGeom& g, float4 r0, float c2, float L)
 {
+    const float eps = 2.03e-6f * (fabsf(r0.z) + fabsf(r0.w) + fabsf(c2));
     const float u0 = g.cx0 - r0.x, u1 = g.cx1 - r0.x;       // pixel - mean
     const float v0 = g.cy0 - r0.y, v1 = g.cy1 - r0.y;
     const float a = r0.z, b = r0.w, c = c2;
@@ -184,6 +189,8 @@ __device__ __forceinline__ BlockGeom block_geom(const CamDev* cams, int n_views,
         else { sx = sub; sy = 0; }                         // 32x8: 4x1 blocks
     }
     g.view = v;
+    g.tx = tx;
+    g.ty = ty;
     g.tile = tile;
     g.px = (int)((tx << tsx) + sx * kBlockPx + (lane & 7u));
     g.py = (int)((ty << tsy) + sy * kBlockPx + (lane >> 3));
@@ -231,6 +238,7 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
 
     float T = 1.f, Cr = 0.f, Cg = 0.f, Cb = 0.f, H2 = 0.f;   // H2: entropy in log2 units
     int32_t last = 0, stop_pos = -1;
+    uint32_t nbl = 0;                                        // entries blended
     bool done = !g.inside;
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
         if (__ballot(!done) == 0ull) break;
@@ -242,11 +250,11 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
             bool keep = false;
             float4 r0, r1, r2;
             if (j < cnt) {
-                const float4* r = a.rec + (size_t)kRecF4 * a.emit_vg[a.pair_vals[bs + j]];
+                const float4* r = a.rec + (size_t)kRecF4 * a.pair_vals[bs + j];
                 r0 = r[0];
                 r1 = r[1];
                 r2 = r[2];
-                keep = !culled(g, r0, r1.x, r2.y, r2.z);
+                keep = !culled(g, r0, r1.x, r2.y);
             }
             const uint64_t bal = __ballot(keep);
             if (keep) {
@@ -277,6 +285,7 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
                     H2 = fmaf(-w, __builtin_amdgcn_logf(w), H2);    // -w log2 w   (Eq. 10)
                     T = Tn;
                     last = s_pos[wid][k] + 1;
+                    ++nbl;
                 }
             }
         }
@@ -297,9 +306,10 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
     const float hs = wave_sum_all(g.inside ? H : 0.f);
     const uint32_t ne = (uint32_t)wave_sum_all_i(n_eval);
     const uint32_t nc = (uint32_t)wave_sum_all_i(last);
+    const uint32_t nb = (uint32_t)wave_sum_all_i((int)nbl);
     if (lane == 0) {
         a.block_H[wb] = hs;
-        a.block_cnt[wb] = make_uint2(ne, nc);
+        a.block_cnt[wb] = make_uint4(ne, nc, nb, 0u);
     }
     }
 }
@@ -422,14 +432,16 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     __shared__ float4 s_g0[NS][B];
     __shared__ float4 s_g1[NS][B];
     __shared__ float s_b[NS][B];
-    __shared__ float2 s_cull[NS][B];                    // (eps, L)
+    __shared__ float s_cull[NS][B];                     // L
     __shared__ uint32_t s_e[NS][B];
     __shared__ float s_acc[kWavesPerGroup][B * kG2];     // per-wavefront sums of each window entry
+    __shared__ uint32_t s_hit[NS][B];                   // some wavefront blended the entry
     __shared__ int32_t s_idx[kWavesPerGroup][B];        // surviving window entries of each wavefront
     __shared__ int32_t s_max[kWavesPerGroup];
     __shared__ uint32_t s_item;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
     const uint32_t slot = SHARED ? 0u : wid;
+    const float stamp = __uint_as_float(*a.stamp);
     // work items: tiles (SHARED: one per workgroup; else one per wavefront), longest list first
     const uint32_t n_items = SHARED ? a.n_blocks / kWavesPerGroup : a.n_blocks;
     auto next = [&]() -> uint32_t {
@@ -463,6 +475,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     const int32_t nthr = SHARED ? 256 : 64;
     const int32_t tid = SHARED ? (int32_t)threadIdx.x : (int32_t)lane;
     for (int32_t i = (int32_t)lane; i < B * kG2; i += kWave) s_acc[wid][i] = 0.f;
+    for (int32_t i = tid; i < B; i += nthr) s_hit[slot][i] = 0u;
     const bool row_lead = (lane & 15u) == 0u;
     const int32_t rc = row_comp(lane >> 4);
 
@@ -471,14 +484,14 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
         const int32_t cnt = hi - lo;
         // stage the window
         for (int32_t j = tid; j < cnt; j += nthr) {
-            const uint32_t e = a.pair_vals[rg.x + (uint32_t)(lo + j)];
-            const float4* r = a.rec + (size_t)kRecF4 * a.emit_vg[e];
+            const float4* r = a.rec + (size_t)kRecF4 * a.pair_vals[rg.x + (uint32_t)(lo + j)];
             const float4 r2 = r[2];
-            s_e[slot][j] = e;
+            // emission slot of this (tile, Gaussian) pair
+            s_e[slot][j] = __float_as_uint(r2.z) + g.ty * __float_as_uint(r2.w) + g.tx;
             s_g0[slot][j] = r[0];
             s_g1[slot][j] = r[1];
             s_b[slot][j] = r2.x;
-            s_cull[slot][j] = make_float2(r2.y, r2.z);
+            s_cull[slot][j] = r2.y;
         }
         if (SHARED) __syncthreads(); else wave_lds_sync();
         // this wavefront's surviving entries of the window, in list order
@@ -488,8 +501,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
             const int32_t j = j0 + (int32_t)lane;
             bool keep = false;
             if (j < jtop) {
-                const float2 cb = s_cull[slot][j];
-                keep = !culled(g, s_g0[slot][j], s_g1[slot][j].x, cb.x, cb.y);
+                keep = !culled(g, s_g0[slot][j], s_g1[slot][j].x, s_cull[slot][j]);
             }
             const uint64_t bal = __ballot(keep);
             if (keep) s_idx[wid][m + (int32_t)__popcll(bal & ((1ull << lane) - 1ull))] = j;
@@ -510,14 +522,20 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
                     float* dst = s_acc[wid] + j * kG2;
                     dst[rc] = v0;
                     dst[4 + rc] = v1;
-                    if (lane == 0u) dst[8] = v2;
+                    if (lane == 0u) {
+                        dst[8] = v2;
+                        s_hit[slot][j] = 1u;
+                    }
                 }
             }
         }
         if (SHARED) __syncthreads(); else wave_lds_sync();
-        // store the window's per-pair rows (emission slots), summing the
-        // wavefront slots in a fixed order, and clear the slots
+        // store the rows of the window's blended entries (emission slots),
+        // summing the wavefront slots in a fixed order, and clear the slots;
+        // entries no pixel blended keep no row (their stamp is not this backward's)
         for (int32_t j = tid; j < cnt; j += nthr) {
+            if (!s_hit[slot][j]) continue;
+            s_hit[slot][j] = 0u;
             constexpr int32_t nsl = SHARED ? kWavesPerGroup : 1;
             const int32_t s0 = SHARED ? 0 : (int32_t)wid;
             float S[kG2], G[kG2];
@@ -532,17 +550,12 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
                 S[k] = v;
             }
             finish_row(S, s_g0[slot][j], s_g1[slot][j], G);
-            float* row = a.pair_grad + (size_t)kG2 * s_e[slot][j];
+            float* row = a.pair_grad + (size_t)kRowF * s_e[slot][j];
 #pragma unroll
             for (int k = 0; k < kG2; ++k) row[k] = G[k];
+            row[kG2] = stamp;
         }
         if (SHARED) __syncthreads(); else wave_lds_sync();
-    }
-    // list entries no pixel of this tile reached: zero rows
-    for (int32_t p = maxn + tid; p < len; p += nthr) {
-        float* row = a.pair_grad + (size_t)kG2 * a.pair_vals[rg.x + (uint32_t)p];
-#pragma unroll
-        for (int k = 0; k < kG2; ++k) row[k] = 0.f;
     }
     }
 }

@@ -38,7 +38,8 @@ constexpr int kL1Block = 256;      // pixels per L1 block
 // Projected record of one (view, Gaussian): three float4
 //   r0 = (mean x, mean y, A', B')
 //   r1 = (C', opacity, red, green)
-//   r2 = (blue, eps, L, 0)   (cull data, see the projection)
+//   r2 = (blue, L, base, w)  (L: cull level; base, w as uint32 bits: the pair of local
+//                             tile (tx, ty) has emission index base + ty w + tx)
 // with the conic pre-scaled to log2 units: A' = -A log2(e)/2, B' = -B log2(e),
 // C' = -C log2(e)/2, so that the exponent is A' dx^2 + B' dx dy + C' dy^2.
 constexpr double kLog2e = 1.4426950408889634;
@@ -46,6 +47,9 @@ constexpr int kRecF4 = 3;
 // 2D gradient accumulator per (view, Gaussian): 9 floats
 //   dmean x, dmean y, dA, dB, dC, dopacity, dred, dgreen, dblue
 constexpr int kG2 = 9;
+// per-pair gradient row: the 9 components and a stamp (uint32 bits) naming the
+// backward that wrote it; rows with another stamp count as zero
+constexpr int kRowF = 10;
 
 struct ProjectFwdArgs {
     const float* means;
@@ -86,8 +90,7 @@ struct ProjectBwdArgs {
 
 struct BlendFwdArgs {
     const float4* rec;
-    const uint32_t* pair_vals;            // sorted pairs: emission index
-    const uint32_t* emit_vg;              // emission index -> view*n + Gaussian
+    const uint32_t* pair_vals;            // sorted pairs: view*n + Gaussian index
     const uint2* ranges;
     const CamDev* cams;
     int32_t n_views;
@@ -99,7 +102,7 @@ struct BlendFwdArgs {
     float* out_T;
     int32_t* out_nc;
     float* block_H;                       // [n_blocks] sum of H over the block
-    uint2* block_cnt;                     // [n_blocks] (alpha evaluations, sum of n_contrib)
+    uint4* block_cnt;                     // [n_blocks] (alpha evaluations, sum of n_contrib, blended, 0)
     const uint32_t* tile_order;           // tiles longest list first (persistent mode), or null
     uint32_t* work_counter;               // persistent work queue head (zeroed before launch), or null
 };
@@ -107,7 +110,6 @@ struct BlendFwdArgs {
 struct BlendBwdArgs {
     const float4* rec;
     const uint32_t* pair_vals;
-    const uint32_t* emit_vg;
     const uint2* ranges;
     const CamDev* cams;
     int32_t n_views;
@@ -119,7 +121,8 @@ struct BlendBwdArgs {
     const float* grad_rgb;
     const float* grad_H;                  // may be null
     const float* grad_LE;                 // [V] may be null
-    float* pair_grad;                     // [P][9] per-pair gradient rows, emission order
+    float* pair_grad;                     // [P][10] per-pair gradient rows, emission order
+    const uint32_t* stamp;                // this backward's row stamp
     const uint32_t* tile_order;           // tiles longest list first (persistent mode), or null
     uint32_t* work_counter;               // persistent work queue head (zeroed before launch), or null
 };
@@ -141,28 +144,29 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, u
                              uint32_t* vals_out, const uint32_t* n_dev, uint32_t n_max, int shift,
                              uint32_t* tmp, hipStream_t s);
 
-// write (tile id, emission index) pairs of every Gaussian in depth order, and
-// emit_vg[emission index] = view*n + Gaussian index
+// write (tile id, view*n + Gaussian index) pairs of every Gaussian in depth order,
+// emit_vg[emission index] = view*n + Gaussian index, and into each record with
+// pairs its emission base and rectangle width (record words 10, 11)
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles_touched,
                             const uint2* rect, const CamDev* cams, uint32_t n, uint32_t vn,
                             const uint32_t* total, uint32_t cap, uint32_t* keys, uint32_t* vals,
-                            uint32_t* emit_vg, uint32_t* overflow, hipStream_t s);
-// grad2d[vg] = sum of the per-pair rows pair_grad[9 e .. 9 e + 8] over the Gaussian's emission range
+                            uint32_t* emit_vg, uint32_t* overflow, float4* rec, hipStream_t s);
+// grad2d[vg] = sum of the per-pair rows pair_grad[10 e .. 10 e + 8] stamped *stamp over the Gaussian's
+// emission range
 // (zero for Gaussians without pairs); carry holds seg_carry_bytes(cap) bytes
 size_t seg_carry_bytes(uint32_t cap);
-hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* emit_vg, uint32_t vn,
+hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* stamp, const uint32_t* emit_vg, uint32_t vn,
                               const uint32_t* total, uint32_t cap, float* grad2d, void* carry, hipStream_t s);
 
+// *p += 1 (one thread)
+hipError_t launch_bump_u32(uint32_t* p, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 // keys[t] = 255 - min(255, ceil(len_t / 8)), vals[t] = t: one stable 8-bit pass orders tiles longest first
 hipError_t launch_tile_len_keys(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
-hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges,
-                         hipStream_t s);
-// per-tile list-length histogram (bins 0..nbins-2 exact, last bin = overflow)
-hipError_t launch_len_hist(const uint2* ranges, uint32_t n_tiles, uint32_t* hist, int nbins, hipStream_t s);
-hipError_t launch_view_pairs(const uint2* ranges, const CamDev* cams, int n_views, uint64_t* pairs_per_view,
-                             hipStream_t s);
+// per-tile [start, end) of the sorted pairs
+hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges, hipStream_t s);
+
 
 hipError_t launch_blend_fwd(const BlendFwdArgs& a, int lds_batch, hipStream_t s);
 hipError_t launch_blend_bwd(const BlendBwdArgs& a, int lds_batch, hipStream_t s);

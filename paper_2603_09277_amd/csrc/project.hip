@@ -274,14 +274,11 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectFwdArgs a)
             const float C2 = (float)(-0.5 * kLog2e * P.qC);
             r0 = make_float4(P.mx, P.my, A2, B2);
             r1 = make_float4(C2, op, col[0], col[1]);
-            // Cull data for the blend: the exponent of this (stored, FP32) conic is
-            // evaluated in FP32 with an error below 1e-6 (|A2| + |B2| + |C2|) |d|^2;
-            // the blend skips a Gaussian for an 8x8 block when the exact maximum of
-            // the exponent over the block, plus twice that error, stays below
-            // -L with L = log2(255 opacity) + 1e-4 (then alpha < 1/255 at every pixel).
-            const double S = fabs((double)A2) + fabs((double)B2) + fabs((double)C2);
+            // Cull level for the blend: alpha < 1/255 wherever the exponent is
+            // below -L, L = log2(255 opacity) + 1e-4.  (r2.z, r2.w) are filled by
+            // the pair duplication.
             const double Lc = op > 0.f ? log2(255.0 * (double)op) + 1e-4 : -HUGE_VAL;
-            r2 = make_float4(col[2], (float)(2e-6 * S * 1.01), (float)Lc, 0.f);
+            r2 = make_float4(col[2], (float)Lc, 0.f, 0.f);
         }
         a.rec[3 * o + 0] = r0;
         a.rec[3 * o + 1] = r1;

@@ -271,17 +271,21 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
 
 // ---------------------------------------------------------------------------
 // Duplication: every (view, Gaussian) in depth order writes one pair per tile
-// of its rectangle, row-major, at its scanned offset.  The pair's value is its
-// emission index; emit_vg maps it back to the (view, Gaussian) record.  All
+// of its rectangle, row-major, at its scanned offset.  The pair's value is the
+// (view, Gaussian) record index; emit_vg[emission index] holds it too.  All
 // pairs of one Gaussian are contiguous in emission order, which the backward
-// uses to reduce per-pair gradients without atomics.
+// uses to reduce per-pair gradients without atomics: the pair of local tile
+// (tx, ty) has emission index base + ty w + tx (mod 2^32), with
+// base = offset - y0 w - x0 and w = x1 - x0 + 1 stored in the record's last
+// two words.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* order, const uint32_t* offsets,
                                                              const uint32_t* tiles_touched, const uint2* rect,
                                                              const CamDev* cams, uint32_t n, uint32_t vn,
                                                              const uint32_t* total, uint32_t cap, uint32_t* keys,
-                                                             uint32_t* vals, uint32_t* emit_vg, uint32_t* overflow)
+                                                             uint32_t* vals, uint32_t* emit_vg, uint32_t* overflow,
+                                                             float4* rec)
 {
     uint32_t s = blockIdx.x * kThreads + threadIdx.x;
     if (s == 0 && *total > cap) *overflow = 1u;
@@ -294,19 +298,25 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* ord
     uint32_t v = vg / n;
     const uint32_t gx = (uint32_t)cams[v].gx, tb = cams[v].tile_base;
     uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu, y1 = rc.y >> 16;
+    const uint32_t w = x1 - x0 + 1u;
+    float4* r2 = rec + (size_t)kRecF4 * vg + 2;
+    r2->z = __uint_as_float(off - y0 * w - x0);
+    r2->w = __uint_as_float(w);
     for (uint32_t ty = y0; ty <= y1; ++ty)
         for (uint32_t tx = x0; tx <= x1; ++tx) {
             if (off < cap) {
                 keys[off] = tb + ty * gx + tx;
-                vals[off] = off;
+                vals[off] = vg;
                 emit_vg[off] = vg;
             }
             ++off;
         }
 }
 
-// Per-Gaussian sum of the per-pair gradient rows.  Rows (9 floats) are stored
-// in emission order, where all pairs of one (view, Gaussian) are contiguous.  One wavefront takes 64
+// Per-Gaussian sum of the per-pair gradient rows.  Rows (9 floats and a stamp)
+// are stored in emission order, where all pairs of one (view, Gaussian) are
+// contiguous; a row whose stamp is not this backward's was not written by it
+// (no pixel blended that pair) and counts as zero.  One wavefront takes 64
 // consecutive rows, runs a segmented inclusive scan keyed by the Gaussian,
 // and writes every segment that starts and ends inside it; segments that
 // cross wavefront boundaries leave their partial sums in `carry` and are
@@ -319,11 +329,12 @@ struct SegCarry {
     uint32_t pad;
 };
 
-__global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_grad,
+__global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_grad, const uint32_t* stamp,
                                                               const uint32_t* emit_vg, const uint32_t* total,
                                                               uint32_t cap, float* grad2d, SegCarry* carry)
 {
     const uint32_t P = *total < cap ? *total : cap;
+    const uint32_t st = *stamp;
     const uint32_t lane = lane_id();
     const uint32_t w = (blockIdx.x * kThreads + threadIdx.x) >> 6;
     const uint32_t e = w * 64u + lane;
@@ -336,7 +347,14 @@ __global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_
     if (lane == 63) next = (e + 1 < P) ? emit_vg[e + 1] : 0xfffffffeu;
     float v[kG2];
 #pragma unroll
-    for (int k = 0; k < kG2; ++k) v[k] = valid ? pair_grad[(size_t)kG2 * e + k] : 0.f;
+    for (int k = 0; k < kG2; ++k) v[k] = 0.f;
+    if (valid) {
+        const float* row = pair_grad + (size_t)kRowF * e;
+        if (__float_as_uint(row[kG2]) == st) {
+#pragma unroll
+            for (int k = 0; k < kG2; ++k) v[k] = row[k];
+        }
+    }
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const uint32_t su = __shfl_up(seg, d, 64);
@@ -422,6 +440,11 @@ __global__ void iota_u32_kernel(uint32_t* p, uint32_t count)
     if (i < count) p[i] = i;
 }
 
+__global__ void bump_u32_kernel(uint32_t* p)
+{
+    if (threadIdx.x == 0) *p += 1u;
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t value, size_t count)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -440,36 +463,6 @@ __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* tiles,
     if (i == P - 1 || tiles[i + 1] != t) ranges[t].y = i + 1;
 }
 
-__global__ __launch_bounds__(kThreads) void len_hist_kernel(const uint2* ranges, uint32_t n_tiles, uint32_t* hist,
-                                                            int nbins)
-{
-    uint32_t t = blockIdx.x * kThreads + threadIdx.x;
-    if (t >= n_tiles) return;
-    uint2 r = ranges[t];
-    uint32_t len = r.y > r.x ? r.y - r.x : 0u;
-    uint32_t b = len < (uint32_t)(nbins - 1) ? len : (uint32_t)(nbins - 1);
-    atomicAdd(&hist[b], 1u);
-}
-
-__global__ void view_pairs_kernel(const uint2* ranges, const CamDev* cams, int n_views, unsigned long long* out)
-{
-    int v = blockIdx.x;
-    if (v >= n_views) return;
-    uint32_t tb = cams[v].tile_base, nt = (uint32_t)(cams[v].gx * cams[v].gy);
-    unsigned long long acc = 0;
-    for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
-        uint2 r = ranges[tb + t];
-        acc += r.y > r.x ? r.y - r.x : 0u;
-    }
-    __shared__ unsigned long long s[256];
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[v] = s[0];
-}
 
 }  // namespace
 
@@ -508,24 +501,24 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, u
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles_touched,
                             const uint2* rect, const CamDev* cams, uint32_t n, uint32_t vn, const uint32_t* total,
                             uint32_t cap, uint32_t* keys, uint32_t* vals, uint32_t* emit_vg, uint32_t* overflow,
-                            hipStream_t s)
+                            float4* rec, hipStream_t s)
 {
     if (vn == 0) return hipSuccess;
     hipLaunchKernelGGL(duplicate_kernel, dim3((vn + kThreads - 1) / kThreads), dim3(kThreads), 0, s, order, offsets,
-                       tiles_touched, rect, cams, n, vn, total, cap, keys, vals, emit_vg, overflow);
+                       tiles_touched, rect, cams, n, vn, total, cap, keys, vals, emit_vg, overflow, rec);
     return hipGetLastError();
 }
 
 size_t seg_carry_bytes(uint32_t cap) { return ((size_t)cap + 63) / 64 * sizeof(SegCarry) + sizeof(SegCarry); }
 
-hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* emit_vg, uint32_t vn,
+hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* stamp, const uint32_t* emit_vg, uint32_t vn,
                               const uint32_t* total, uint32_t cap, float* grad2d, void* carry, hipStream_t s)
 {
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (size_t)vn * kG2, s);
     if (e != hipSuccess || cap == 0) return e;
     const uint32_t nw = (cap + 63) / 64;
     hipLaunchKernelGGL(seg_reduce_kernel, dim3((nw * 64 + kThreads - 1) / kThreads), dim3(kThreads), 0, s, pair_grad,
-                       emit_vg, total, cap, grad2d, reinterpret_cast<SegCarry*>(carry));
+                       stamp, emit_vg, total, cap, grad2d, reinterpret_cast<SegCarry*>(carry));
     hipLaunchKernelGGL(seg_fixup_kernel, dim3((nw + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
                        reinterpret_cast<const SegCarry*>(carry), total, cap, grad2d);
     return hipGetLastError();
@@ -542,6 +535,12 @@ hipError_t launch_tile_len_keys(const uint2* ranges, uint32_t n_tiles, uint32_t*
 {
     if (n_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(tile_len_keys_kernel, dim3((n_tiles + 255) / 256), dim3(256), 0, s, ranges, n_tiles, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_bump_u32(uint32_t* p, hipStream_t s)
+{
+    hipLaunchKernelGGL(bump_u32_kernel, dim3(1), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 
@@ -562,19 +561,5 @@ hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t 
     return hipGetLastError();
 }
 
-hipError_t launch_len_hist(const uint2* ranges, uint32_t n_tiles, uint32_t* hist, int nbins, hipStream_t s)
-{
-    if (n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(len_hist_kernel, dim3((n_tiles + kThreads - 1) / kThreads), dim3(kThreads), 0, s, ranges,
-                       n_tiles, hist, nbins);
-    return hipGetLastError();
-}
-
-hipError_t launch_view_pairs(const uint2* ranges, const CamDev* cams, int n_views, uint64_t* out, hipStream_t s)
-{
-    hipLaunchKernelGGL(view_pairs_kernel, dim3(n_views), dim3(256), 0, s, ranges, cams, n_views,
-                       reinterpret_cast<unsigned long long*>(out));
-    return hipGetLastError();
-}
 
 }  // namespace gsr

@@ -497,6 +497,18 @@ def test_stats_match_lists(R, tiny):
     assert abs(st["mean_len"] - lens.mean()) < 1e-9
     assert st["p99_len"] == lens[int(math.ceil(0.99 * len(lens))) - 1]
     assert not st["overflow"]
+    # work counts against the oracle walking the same lists with the GPU's float32
+    # records: alpha evaluations and blended (pixel, Gaussian) pairs; a pixel whose
+    # skip/stop decision lies within the oracle's decision band may differ by its list
+    c = cams[0]
+    ref = oracle_stagewise(gpu_records(R, scene.n, 1)[0], c, (8, 8))
+    gx = (c.width + 7) // 8
+    tile_of = (np.arange(c.height)[:, None] // 8) * gx + np.arange(c.width)[None, :] // 8
+    rr = np.asarray(ref["ranges"]).reshape(-1, 2)
+    slack = int((rr[tile_of, 1] - rr[tile_of, 0])[ref["flags"] != 0].sum())
+    assert abs(st["blended"] - ref["n_blend"]) <= slack
+    assert abs(st["evals_fwd"] - ref["n_eval"]) <= slack
+    assert 0 < st["blended"] <= st["evals_bwd"] <= st["evals_fwd"]
 
 
 def _single_gaussian_scene(means, scales, opac, n_extra=0):

@@ -244,17 +244,23 @@ def test_single_gaussian_image(orc):
     col = sc.sh[0, 0].astype(np.float64) * (0.5 / math.sqrt(PI)) + 0.5
     assert (mx, my) == (24.0, 20.0)
     tiles = tiles_overlapping(mx, my, pr["radius"][0], 48, 40, 8, 8)
+    blended = 0
     for py in range(40):
         for px in range(48):
             a = min(0.99, float(np.float32(op)) * math.exp(-((px + 0.5 - mx) ** 2 + (py + 0.5 - my) ** 2) / (2 * v)))
             inside = ((py // 8) * 6 + px // 8) in tiles
             if inside and a >= 1 / 255:
+                blended += 1
                 np.testing.assert_allclose(f["rgb"][py, px], a * col, rtol=1e-12, atol=1e-15)
                 assert f["T"][py, px] == pytest.approx(1 - a, rel=1e-12)
                 hb = -a * math.log(a) - (1 - a) * math.log(1 - a)
                 assert f["H"][py, px] == pytest.approx(hb, rel=1e-11)
             else:
                 assert np.all(f["rgb"][py, px] == 0) and f["T"][py, px] == 1.0 and f["H"][py, px] == 0.0
+    # one Gaussian: every pixel whose list holds it evaluates it once, and it is
+    # blended where alpha >= 1/255
+    assert f["n_blend"] == blended > 0
+    assert f["n_eval"] == sum(1 for py in range(40) for px in range(48) if ((py // 8) * 6 + px // 8) in tiles)
 
 
 def test_two_gaussians_over_operator(orc):

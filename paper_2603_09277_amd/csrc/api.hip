@@ -52,7 +52,7 @@ struct gsr_ctx {
     std::string err;
 
     // grow-only device buffers
-    Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
+    Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, tt_s, rect_s, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
     Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, tord, block_H, block_cnt, hchunk, counters, l1_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
@@ -271,7 +271,8 @@ gsr_status ensure_vn(gsr_ctx* c, uint32_t vn)
     gsr_status s;
     if ((s = grow(c, c->rec, v * 48)) || (s = grow(c, c->dkey0, v * 4)) || (s = grow(c, c->dkey1, v * 4)) ||
         (s = grow(c, c->ord0, v * 4)) || (s = grow(c, c->ord1, v * 4)) || (s = grow(c, c->rect, v * 8)) ||
-        (s = grow(c, c->tt, v * 4)) || (s = grow(c, c->radius, v * 4)) || (s = grow(c, c->depth, v * 4)) ||
+        (s = grow(c, c->tt, v * 4)) || (s = grow(c, c->tt_s, v * 4)) || (s = grow(c, c->rect_s, v * 8)) ||
+        (s = grow(c, c->radius, v * 4)) || (s = grow(c, c->depth, v * 4)) ||
         (s = grow(c, c->offsets, v * 4)) || (s = grow(c, c->grad2d, v * 4 * kG2)) ||
         (s = grow(c, c->scan_tmp, scan_tmp_words((uint32_t)v) * 4)))
         return s;
@@ -286,7 +287,7 @@ gsr_status ensure_pairs(gsr_ctx* c, size_t p)
     if (p >= 0xfffffff0ull) return fail(c, GSR_ERR_CAPACITY, "pair count exceeds 2^32");
     gsr_status s;
     if ((s = grow(c, c->pk0, p * 4)) || (s = grow(c, c->pk1, p * 4)) || (s = grow(c, c->pv0, p * 4)) ||
-        (s = grow(c, c->pv1, p * 4)) || (s = grow(c, c->emit_vg, p * 4)) || (s = grow(c, c->pair_grad, p * 4 * kRowF, true)) ||
+        (s = grow(c, c->pv1, p * 4)) || (s = grow(c, c->emit_vg, p * 4)) || (s = grow(c, c->pair_grad, p * 4 * kRowF + 64, true)) ||
         (s = grow(c, c->seg_carry, seg_carry_bytes((uint32_t)p))))
         return s;
     c->pair_cap = p;
@@ -346,7 +347,8 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     // offsets of each record's pairs in depth order; total pair count
     {
         StageTimer tm(c, st, GSR_STAGE_SCAN, plain);
-        HIP_TRY(c, launch_gather_scan((const uint32_t*)c->tt.p, od[0], vn, (uint32_t*)c->offsets.p, counters,
+        HIP_TRY(c, launch_gather_scan((const uint32_t*)c->tt.p, (const uint2*)c->rect.p, od[0], vn,
+                                      (uint32_t*)c->offsets.p, (uint32_t*)c->tt_s.p, (uint2*)c->rect_s.p, counters,
                                       counters + 1, (uint32_t*)c->scan_tmp.p, st));
     }
     uint32_t cap;
@@ -365,8 +367,8 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     uint32_t* pv[2] = { (uint32_t*)c->pv0.p, (uint32_t*)c->pv1.p };
     {
         StageTimer tm(c, st, GSR_STAGE_DUPLICATE, plain);
-        HIP_TRY(c, launch_duplicate(od[0], (const uint32_t*)c->offsets.p, (const uint32_t*)c->tt.p,
-                                    (const uint2*)c->rect.p, dc, n, vn, counters, cap, pk[0], pv[0],
+        HIP_TRY(c, launch_duplicate(od[0], (const uint32_t*)c->offsets.p, (const uint32_t*)c->tt_s.p,
+                                    (const uint2*)c->rect_s.p, dc, n, vn, counters, cap, pk[0], pv[0],
                                     (uint32_t*)c->emit_vg.p, counters + 1, (float4*)c->rec.p, st));
     }
     // stable sort of the pairs by tile id
@@ -453,6 +455,7 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     ProjectBwdArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
     pa.n = n; pa.n_views = (int32_t)V; pa.flags = o->flags; pa.cams = dc; pa.grad2d = (const float*)c->grad2d.p;
+    pa.tiles_touched = (const uint32_t*)c->tt.p;
     pa.g_means = gr->means; pa.g_scales = gr->scales; pa.g_quats = gr->quats; pa.g_opac = gr->opacities;
     pa.g_sh = gr->sh;
     HIP_TRY(c, launch_project_bwd(pa, o->sh_degree, o->sh_dtype == 1, st));
@@ -542,7 +545,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     if (!c) return GSR_ERR_INVALID_ARG;
     (void)hipDeviceSynchronize();
     drop_graphs(c);
-    Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->radius,
+    Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->tt_s, &c->rect_s, &c->radius,
                    &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
                    &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->tord, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters,
                    &c->l1_tmp };
@@ -822,7 +825,22 @@ gsr_status gsr_inspect(gsr_ctx* c, void* stream, gsr_buffer which, void* dst, in
         case GSR_BUF_PAIR_VALUES: src = pv[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
         case GSR_BUF_PAIR_TILES: src = pk[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
         case GSR_BUF_RANGES: src = c->ranges.p; sz = (size_t)c->lay.n_tiles * 8; break;
-        case GSR_BUF_GRAD2D: src = c->grad2d.p; sz = (size_t)c->vn * 4 * kG2; break;
+        case GSR_BUF_GRAD2D: {         // zero rows for (view, Gaussian)s without pairs
+            sz = (size_t)c->vn * 4 * kG2;
+            *bytes = (int64_t)sz;
+            if (!dst) return GSR_OK;
+            if ((int64_t)sz > capacity_bytes) return fail(c, GSR_ERR_INVALID_ARG, "destination too small");
+            std::vector<uint32_t> tt(c->vn);
+            if (sz) {
+                HIP_TRY(c, hipMemcpyAsync(dst, c->grad2d.p, sz, hipMemcpyDeviceToHost, st));
+                HIP_TRY(c, hipMemcpyAsync(tt.data(), c->tt.p, (size_t)c->vn * 4, hipMemcpyDeviceToHost, st));
+            }
+            HIP_TRY(c, hipStreamSynchronize(st));
+            float* out = (float*)dst;
+            for (uint32_t i = 0; i < c->vn; ++i)
+                if (!tt[i]) std::memset(out + (size_t)kG2 * i, 0, sizeof(float) * kG2);
+            return GSR_OK;
+        }
         default: return fail(c, GSR_ERR_INVALID_ARG, "unknown buffer");
     }
     *bytes = (int64_t)sz;

@@ -80,7 +80,8 @@ struct ProjectBwdArgs {
     int32_t n_views;
     uint32_t flags;
     const CamDev* cams;
-    const float* grad2d;                  // [V*n][9]
+    const float* grad2d;                  // [V*n][9], valid where tiles_touched > 0
+    const uint32_t* tiles_touched;        // [V*n]
     float* g_means;
     float* g_scales;
     float* g_quats;
@@ -131,11 +132,13 @@ struct BlendBwdArgs {
 hipError_t launch_project_fwd(const ProjectFwdArgs& a, int sh_degree, bool sh_bf16, hipStream_t s);
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, bool sh_bf16, hipStream_t s);
 
-// exclusive scan of tiles_touched[order[i]] for i < n  ->  out[i]; total -> *total (uint32),
-// *overflow |= 1 if the total does not fit in 32 bits.  tmp holds scan_tmp_words(n) words.
+// exclusive scan of vals[order[i]] for i < n  ->  out[i]; total -> *total (uint32),
+// *overflow |= 1 if the total does not fit in 32 bits; vals_s[i] = vals[order[i]] and
+// rect_s[i] = rect[order[i]].  tmp holds scan_tmp_words(n) words.
 size_t scan_tmp_words(uint32_t n);
-hipError_t launch_gather_scan(const uint32_t* vals, const uint32_t* order, uint32_t n, uint32_t* out,
-                              uint32_t* total, uint32_t* overflow, uint32_t* tmp, hipStream_t s);
+hipError_t launch_gather_scan(const uint32_t* vals, const uint2* rect, const uint32_t* order, uint32_t n,
+                              uint32_t* out, uint32_t* vals_s, uint2* rect_s, uint32_t* total, uint32_t* overflow,
+                              uint32_t* tmp, hipStream_t s);
 
 // one stable LSD radix pass of 8 bits at `shift` over (key, value) pairs; the
 // item count is min(*n_dev, n_max) read on the device (n_dev may be null: n_max).
@@ -147,12 +150,12 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, u
 // write (tile id, view*n + Gaussian index) pairs of every Gaussian in depth order,
 // emit_vg[emission index] = view*n + Gaussian index, and into each record with
 // pairs its emission base and rectangle width (record words 10, 11)
-hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles_touched,
-                            const uint2* rect, const CamDev* cams, uint32_t n, uint32_t vn,
+hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const uint32_t* tt_s,
+                            const uint2* rect_s, const CamDev* cams, uint32_t n, uint32_t vn,
                             const uint32_t* total, uint32_t cap, uint32_t* keys, uint32_t* vals,
                             uint32_t* emit_vg, uint32_t* overflow, float4* rec, hipStream_t s);
 // grad2d[vg] = sum of the per-pair rows pair_grad[10 e .. 10 e + 8] stamped *stamp over the Gaussian's
-// emission range
+// emission range, for every (view, Gaussian) with pairs (others are left untouched)
 // (zero for Gaussians without pairs); carry holds seg_carry_bytes(cap) bytes
 size_t seg_carry_bytes(uint32_t cap);
 hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* stamp, const uint32_t* emit_vg, uint32_t vn,

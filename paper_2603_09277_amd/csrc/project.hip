@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a)
         const CamDev& c = a.cams[v];
         ViewProj P;
         view_proj(c, mu, L, a.flags, P);
-        if (!P.ok) continue;
+        if (!P.ok || a.tiles_touched[(size_t)v * a.n + i] == 0) continue;   // no pairs: zero gradient
         const float* g = a.grad2d + (size_t)kG2 * ((size_t)v * a.n + i);
         float gmx = g[0], gmy = g[1], gA = g[2], gB = g[3], gC = g[4];
         gop += g[5];

@@ -54,17 +54,26 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* total)
 
 // ---------------------------------------------------------------------------
 // Device-wide exclusive scan (reduce, spine, downsweep) of vals[order[i]].
+// The reduce step also gathers vals and rect into depth order (vals_s,
+// rect_s), so the downsweep and the duplication read them coalesced.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* vals, const uint32_t* order, uint32_t n,
-                                                               uint32_t* partial)
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* vals, const uint2* rect,
+                                                               const uint32_t* order, uint32_t n, uint32_t* partial,
+                                                               uint32_t* vals_s, uint2* rect_s)
 {
-    size_t base = (size_t)blockIdx.x * kTileItems + (size_t)threadIdx.x * kItems;
+    size_t base = (size_t)blockIdx.x * kTileItems + threadIdx.x;
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        size_t idx = base + k;
-        if (idx < n) sum += vals[order ? order[idx] : idx];
+        size_t idx = base + (size_t)k * kThreads;
+        if (idx < n) {
+            const uint32_t o = order[idx];
+            const uint32_t v = vals[o];
+            vals_s[idx] = v;
+            rect_s[idx] = rect[o];
+            sum += v;
+        }
     }
     uint32_t tot;
     block_excl_scan(sum, &tot);
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(kThreads) void scan_spine_kernel(uint32_t* partial,
     }
 }
 
-__global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* vals, const uint32_t* order, uint32_t n,
+__global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* vals_s, uint32_t n,
                                                              const uint32_t* partial, uint32_t* out)
 {
     size_t base = (size_t)blockIdx.x * kTileItems + (size_t)threadIdx.x * kItems;
@@ -105,7 +114,7 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* val
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         size_t idx = base + k;
-        v[k] = idx < n ? vals[order ? order[idx] : idx] : 0u;
+        v[k] = idx < n ? vals_s[idx] : 0u;
         sum += v[k];
     }
     uint32_t tot;
@@ -119,12 +128,25 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* val
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix pass, 8-bit digits:
+// Stable LSD radix pass, 8-bit digits, 256 threads x ITEMS items per block
+// (16 for large inputs, 8 below 2^21 items so that small sorts still fill the chip):
 //   upsweep   per-block digit histograms, digit-major  hist[d * nb + b]
 //   spine     one block per digit: exclusive scan of its row; row total
-//   downsweep stable block-local ranking (wavefront match via ballots),
-//             reorder through LDS, coalesced scatter
+//   downsweep each wavefront ranks its 64 x ITEMS consecutive items (ITEMS rounds
+//             of 64, peers found with 8 ballots, running per-digit counts in
+//             LDS); one block scan turns the (digit, wavefront) counts into
+//             block-local starts; reorder through LDS; coalesced scatter
 // ---------------------------------------------------------------------------
+
+constexpr int kRadixSmallItems = 8;
+constexpr int kRadixLargeItems = 16;
+constexpr uint32_t kRadixLargeFrom = 1u << 21;
+constexpr int kWaves = kThreads / 64;
+
+__host__ __device__ constexpr uint32_t radix_items(uint32_t n_max)
+{
+    return n_max >= kRadixLargeFrom ? kRadixLargeItems : kRadixSmallItems;
+}
 
 __device__ __forceinline__ uint32_t item_count(const uint32_t* n_dev, uint32_t n_max)
 {
@@ -133,17 +155,26 @@ __device__ __forceinline__ uint32_t item_count(const uint32_t* n_dev, uint32_t n
     return n < n_max ? n : n_max;
 }
 
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t* keys, const uint32_t* n_dev,
                                                                  uint32_t n_max, int shift, uint32_t* hist, uint32_t nb)
 {
+    constexpr int kRadixTile = kThreads * ITEMS;
     __shared__ uint32_t s_h[kBins];
     s_h[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t n = item_count(n_dev, n_max);
-    size_t base = (size_t)blockIdx.x * kTileItems;
+    size_t base = (size_t)blockIdx.x * kRadixTile;
     if (base < n) {
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
+        for (int k = 0; k < ITEMS; ++k) {
             size_t idx = base + (size_t)k * kThreads + threadIdx.x;
             if (idx < n) atomicAdd(&s_h[(keys[idx] >> shift) & 0xffu], 1u);
         }
@@ -172,97 +203,97 @@ __global__ __launch_bounds__(kThreads) void radix_spine_kernel(uint32_t* hist, u
     if (threadIdx.x == 0) digit_total[blockIdx.x] = s_carry;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_t* keys_in, const uint32_t* vals_in,
                                                                    uint32_t* keys_out, uint32_t* vals_out,
                                                                    const uint32_t* n_dev, uint32_t n_max, int shift,
                                                                    const uint32_t* hist, uint32_t nb,
                                                                    const uint32_t* digit_total)
 {
-    __shared__ uint32_t s_keys[kTileItems];
-    __shared__ uint32_t s_vals[kTileItems];
+    constexpr int kRadixItems = ITEMS;
+    constexpr int kRadixTile = kThreads * ITEMS;
+    constexpr int kPerWave = 64 * ITEMS;
+    __shared__ uint32_t s_keys[kRadixTile];
+    __shared__ uint32_t s_vals[kRadixTile];
+    __shared__ uint32_t s_wh[kWaves][kBins];  // per-wavefront digit counts, then (digit, wavefront) local starts
     __shared__ uint32_t s_gofs[kBins];        // global start of digit d for this block
-    __shared__ uint32_t s_lofs[kBins];        // block-local start of digit d
-    __shared__ uint32_t s_run[kBins];         // items of digit d already placed
-    __shared__ uint32_t s_wcnt[kThreads / 64][kBins];
 
     const uint32_t n = item_count(n_dev, n_max);
-    const size_t base = (size_t)blockIdx.x * kTileItems;
+    const size_t base = (size_t)blockIdx.x * kRadixTile;
     if (base >= n) return;                    // whole block leaves together
     const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
-    const uint32_t cnt = (uint32_t)((n - base) < (size_t)kTileItems ? (n - base) : (size_t)kTileItems);
+    const uint32_t cnt = (uint32_t)((n - base) < (size_t)kRadixTile ? (n - base) : (size_t)kRadixTile);
 
     // global offsets: exclusive prefix of the digit totals + this block's row offset
     uint32_t tot;
-    uint32_t dbase = block_excl_scan(digit_total[tid], &tot);
+    const uint32_t dbase = block_excl_scan(digit_total[tid], &tot);
     s_gofs[tid] = dbase + hist[(size_t)tid * nb + blockIdx.x];
-
-    // load this block's keys (round-major: round r, thread t -> item r*256 + t)
-    uint32_t k_[kItems], v_[kItems];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        uint32_t li = (uint32_t)r * kThreads + tid;
-        bool ok = li < cnt;
-        k_[r] = ok ? keys_in[base + li] : 0xffffffffu;
+    for (int w = 0; w < kWaves; ++w) s_wh[w][tid] = 0u;
+    __syncthreads();
+
+    // wavefront wid owns items [wid * kPerWave, (wid + 1) * kPerWave): round r, lane l -> + r * 64 + l
+    uint32_t k_[kRadixItems], v_[kRadixItems], rk[kRadixItems];
+#pragma unroll
+    for (int r = 0; r < kRadixItems; ++r) {
+        const uint32_t li = wid * kPerWave + (uint32_t)r * 64u + lane;
+        const bool ok = li < cnt;
+        k_[r] = ok ? keys_in[base + li] : 0u;
         v_[r] = ok ? vals_in[base + li] : 0u;
     }
-    // block-local digit histogram -> local starts
-    s_run[tid] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        uint32_t li = (uint32_t)r * kThreads + tid;
-        if (li < cnt) atomicAdd(&s_run[(k_[r] >> shift) & 0xffu], 1u);
-    }
-    __syncthreads();
-    uint32_t lstart = block_excl_scan(s_run[tid], &tot);
-    s_lofs[tid] = lstart;
-    s_run[tid] = 0;
-    __syncthreads();
-
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    for (int r = 0; r < kItems; ++r) {
-        uint32_t li = (uint32_t)r * kThreads + tid;
-        bool ok = li < cnt;
-        uint32_t d = (k_[r] >> shift) & 0xffu;
+#pragma unroll
+    for (int r = 0; r < kRadixItems; ++r) {
+        const uint32_t li = wid * kPerWave + (uint32_t)r * 64u + lane;
+        const bool ok = li < cnt;
+        const uint32_t d = (k_[r] >> shift) & 0xffu;
         // peers: lanes of this wavefront holding the same digit
         uint64_t peers = __ballot(ok);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t bal = __ballot((d >> b) & 1u);
+            const uint64_t bal = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bal : ~bal;
         }
-        uint32_t rank = __popcll(peers & lt_mask);
+        const uint32_t before = s_wh[wid][d];                // this digit's items in earlier rounds
+        rk[r] = before + (uint32_t)__popcll(peers & lt_mask);
+        wave_lds_order();
+        if (ok && (peers & lt_mask) == 0ull) s_wh[wid][d] = before + (uint32_t)__popcll(peers);
+        wave_lds_order();
+    }
+    __syncthreads();
+    {   // thread tid owns digit tid: starts of (digit, wavefront) groups, digit-major
+        uint32_t cw[kWaves], td = 0;
 #pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) s_wcnt[w][tid] = 0;
-        __syncthreads();
-        if (ok && rank == 0) s_wcnt[wid][d] = __popcll(peers);
-        __syncthreads();
-        {   // thread tid owns digit tid: wave offsets in wave order
-            uint32_t c = s_run[tid];
-#pragma unroll
-            for (int w = 0; w < kThreads / 64; ++w) {
-                uint32_t t = s_wcnt[w][tid];
-                s_wcnt[w][tid] = c;
-                c += t;
-            }
-            s_run[tid] = c;
+        for (int w = 0; w < kWaves; ++w) {
+            cw[w] = s_wh[w][tid];
+            td += cw[w];
         }
-        __syncthreads();
-        if (ok) {
-            uint32_t pos = s_lofs[d] + s_wcnt[wid][d] + rank;
+        uint32_t run = block_excl_scan(td, &tot);
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            s_wh[w][tid] = run;
+            run += cw[w];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRadixItems; ++r) {
+        const uint32_t li = wid * kPerWave + (uint32_t)r * 64u + lane;
+        if (li < cnt) {
+            const uint32_t pos = s_wh[wid][(k_[r] >> shift) & 0xffu] + rk[r];
             s_keys[pos] = k_[r];
             s_vals[pos] = v_[r];
         }
-        __syncthreads();
     }
-    // coalesced scatter of the locally sorted block
+    __syncthreads();
+    // coalesced scatter of the locally sorted block; s_wh[0][d] is digit d's block-local start
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        uint32_t li = (uint32_t)r * kThreads + tid;
+    for (int r = 0; r < kRadixItems; ++r) {
+        const uint32_t li = (uint32_t)r * kThreads + tid;
         if (li < cnt) {
-            uint32_t k = s_keys[li];
-            uint32_t d = (k >> shift) & 0xffu;
-            uint32_t o = s_gofs[d] + (li - s_lofs[d]);
+            const uint32_t k = s_keys[li];
+            const uint32_t d = (k >> shift) & 0xffu;
+            const uint32_t o = s_gofs[d] + (li - s_wh[0][d]);
             keys_out[o] = k;
             vals_out[o] = s_vals[li];
         }
@@ -278,39 +309,76 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
 // (tx, ty) has emission index base + ty w + tx (mod 2^32), with
 // base = offset - y0 w - x0 and w = x1 - x0 + 1 stored in the record's last
 // two words.
+//
+// One wavefront takes 64 consecutive Gaussians in depth order; their pairs are
+// one contiguous output range, which its 64 lanes write together, 64
+// consecutive pairs per step (each lane finds its Gaussian by binary search
+// over the wavefront's local offsets), so every store is coalesced and a
+// Gaussian with many tiles is spread over all lanes.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* order, const uint32_t* offsets,
-                                                             const uint32_t* tiles_touched, const uint2* rect,
+                                                             const uint32_t* tt_s, const uint2* rect_s,
                                                              const CamDev* cams, uint32_t n, uint32_t vn,
                                                              const uint32_t* total, uint32_t cap, uint32_t* keys,
                                                              uint32_t* vals, uint32_t* emit_vg, uint32_t* overflow,
                                                              float4* rec)
 {
-    uint32_t s = blockIdx.x * kThreads + threadIdx.x;
+    __shared__ uint32_t s_loc[kThreads / 64][64];
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    const uint32_t s = blockIdx.x * kThreads + threadIdx.x;
     if (s == 0 && *total > cap) *overflow = 1u;
-    if (s >= vn) return;
-    uint32_t vg = order[s];
-    uint32_t tt = tiles_touched[vg];
-    if (tt == 0) return;
-    uint32_t off = offsets[s];
-    uint2 rc = rect[vg];
-    uint32_t v = vg / n;
-    const uint32_t gx = (uint32_t)cams[v].gx, tb = cams[v].tile_base;
-    uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu, y1 = rc.y >> 16;
+    if (s - lane >= vn) return;                               // whole wavefront
+    const bool valid = s < vn;
+    uint32_t vg = 0, tt = 0, off = 0;
+    uint2 rc = make_uint2(0u, 0u);
+    if (valid) {
+        vg = order[s];
+        tt = tt_s[s];
+        off = offsets[s];
+        rc = rect_s[s];
+    }
+    const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
     const uint32_t w = x1 - x0 + 1u;
-    float4* r2 = rec + (size_t)kRecF4 * vg + 2;
-    r2->z = __uint_as_float(off - y0 * w - x0);
-    r2->w = __uint_as_float(w);
-    for (uint32_t ty = y0; ty <= y1; ++ty)
-        for (uint32_t tx = x0; tx <= x1; ++tx) {
-            if (off < cap) {
-                keys[off] = tb + ty * gx + tx;
-                vals[off] = vg;
-                emit_vg[off] = vg;
-            }
-            ++off;
+    if (tt) {
+        float4* r2 = rec + (size_t)kRecF4 * vg + 2;
+        r2->z = __uint_as_float(off - y0 * w - x0);
+        r2->w = __uint_as_float(w);
+    }
+    // the wavefront's pairs: [off0, off0 + count)
+    const uint32_t off0 = __shfl(off, 0, 64);
+    uint32_t end = valid ? off - off0 + tt : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t y = __shfl_xor(end, o, 64);
+        end = end > y ? end : y;
+    }
+    const uint32_t count = end;
+    s_loc[wid][lane] = valid ? off - off0 : count;            // non-decreasing
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t q0 = 0; q0 < count; q0 += 64u) {
+        const uint32_t q = q0 + lane < count ? q0 + lane : count - 1u;
+        // the Gaussian of output q: the last r with s_loc[r] <= q (it has tt > 0)
+        uint32_t r = 0;
+#pragma unroll
+        for (uint32_t st = 32; st > 0; st >>= 1)
+            if (s_loc[wid][r + st] <= q) r += st;
+        const uint32_t rvg = (uint32_t)__shfl((int)vg, (int)r, 64);
+        const uint32_t rx = (uint32_t)__shfl((int)rc.x, (int)r, 64);
+        const uint32_t ry = (uint32_t)__shfl((int)rc.y, (int)r, 64);
+        const uint32_t k = q - s_loc[wid][r];
+        const uint32_t rx0 = rx & 0xffffu, rw = (rx >> 16) - rx0 + 1u, ry0 = ry & 0xffffu;
+        const uint32_t dy = k / rw, dx = k - dy * rw;
+        const uint32_t v = rvg / n;
+        const uint32_t p = off0 + q;
+        if (q0 + lane < count && p < cap) {
+            keys[p] = cams[v].tile_base + (ry0 + dy) * (uint32_t)cams[v].gx + rx0 + dx;
+            vals[p] = rvg;
+            emit_vg[p] = rvg;
         }
+    }
 }
 
 // Per-Gaussian sum of the per-pair gradient rows.  Rows (9 floats and a stamp)
@@ -333,12 +401,23 @@ __global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_
                                                               const uint32_t* emit_vg, const uint32_t* total,
                                                               uint32_t cap, float* grad2d, SegCarry* carry)
 {
+    __shared__ float4 s_rows[kThreads / 64][64 * kRowF / 4];
     const uint32_t P = *total < cap ? *total : cap;
     const uint32_t st = *stamp;
-    const uint32_t lane = lane_id();
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
     const uint32_t w = (blockIdx.x * kThreads + threadIdx.x) >> 6;
     const uint32_t e = w * 64u + lane;
     if (w * 64u >= P) return;                                  // whole wavefront
+    {   // the wavefront's 64 rows (2560 B) through LDS with 16-byte loads
+        const size_t f0 = (size_t)w * 64u * kRowF, fend = (size_t)P * kRowF;
+        for (uint32_t f = lane; f < 64u * kRowF / 4u; f += 64u) {
+            const size_t fi = f0 + 4u * (size_t)f;
+            if (fi < fend) s_rows[wid][f] = *reinterpret_cast<const float4*>(pair_grad + fi);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     const bool valid = e < P;
     const uint32_t seg = valid ? emit_vg[e] : 0xffffffffu;
     uint32_t prev = __shfl_up(seg, 1, 64);
@@ -349,7 +428,7 @@ __global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_
 #pragma unroll
     for (int k = 0; k < kG2; ++k) v[k] = 0.f;
     if (valid) {
-        const float* row = pair_grad + (size_t)kRowF * e;
+        const float* row = reinterpret_cast<const float*>(s_rows[wid]) + kRowF * lane;
         if (__float_as_uint(row[kG2]) == st) {
 #pragma unroll
             for (int k = 0; k < kG2; ++k) v[k] = row[k];
@@ -468,44 +547,59 @@ __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* tiles,
 
 size_t scan_tmp_words(uint32_t n) { return (size_t)(n + kTileItems - 1) / kTileItems + 1; }
 
-hipError_t launch_gather_scan(const uint32_t* vals, const uint32_t* order, uint32_t n, uint32_t* out, uint32_t* total,
-                              uint32_t* overflow, uint32_t* tmp, hipStream_t s)
+hipError_t launch_gather_scan(const uint32_t* vals, const uint2* rect, const uint32_t* order, uint32_t n,
+                              uint32_t* out, uint32_t* vals_s, uint2* rect_s, uint32_t* total, uint32_t* overflow,
+                              uint32_t* tmp, hipStream_t s)
 {
     uint32_t nb = (n + kTileItems - 1) / kTileItems;
-    if (nb > 0) hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kThreads), 0, s, vals, order, n, tmp);
+    if (nb > 0)
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kThreads), 0, s, vals, rect, order, n, tmp, vals_s,
+                           rect_s);
     hipLaunchKernelGGL(scan_spine_kernel, dim3(1), dim3(kThreads), 0, s, tmp, nb, total, overflow);
-    if (nb > 0) hipLaunchKernelGGL(scan_down_kernel, dim3(nb), dim3(kThreads), 0, s, vals, order, n, tmp, out);
+    if (nb > 0) hipLaunchKernelGGL(scan_down_kernel, dim3(nb), dim3(kThreads), 0, s, vals_s, n, tmp, out);
     return hipGetLastError();
 }
 
 size_t radix_tmp_words(uint32_t n_max)
 {
-    size_t nb = (n_max + kTileItems - 1) / kTileItems;
+    // sized for the smaller tile, so that it also covers every pass over fewer items
+    const uint32_t tile = kThreads * kRadixSmallItems;
+    size_t nb = (n_max + tile - 1) / tile;
     return (size_t)kBins * (nb > 0 ? nb : 1) + kBins;
 }
 
 hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
                              const uint32_t* n_dev, uint32_t n_max, int shift, uint32_t* tmp, hipStream_t s)
 {
-    uint32_t nb = (n_max + kTileItems - 1) / kTileItems;
+    const uint32_t items = radix_items(n_max), tile = kThreads * items;
+    uint32_t nb = (n_max + tile - 1) / tile;
     if (nb == 0) return hipSuccess;
     uint32_t* hist = tmp;
     uint32_t* digit_total = tmp + (size_t)kBins * nb;
-    hipLaunchKernelGGL(radix_upsweep_kernel, dim3(nb), dim3(kThreads), 0, s, keys_in, n_dev, n_max, shift, hist, nb);
+    if (items == kRadixLargeItems)
+        hipLaunchKernelGGL(radix_upsweep_kernel<kRadixLargeItems>, dim3(nb), dim3(kThreads), 0, s, keys_in, n_dev,
+                           n_max, shift, hist, nb);
+    else
+        hipLaunchKernelGGL(radix_upsweep_kernel<kRadixSmallItems>, dim3(nb), dim3(kThreads), 0, s, keys_in, n_dev,
+                           n_max, shift, hist, nb);
     hipLaunchKernelGGL(radix_spine_kernel, dim3(kBins), dim3(kThreads), 0, s, hist, nb, digit_total);
-    hipLaunchKernelGGL(radix_downsweep_kernel, dim3(nb), dim3(kThreads), 0, s, keys_in, vals_in, keys_out, vals_out,
-                       n_dev, n_max, shift, hist, nb, digit_total);
+    if (items == kRadixLargeItems)
+        hipLaunchKernelGGL(radix_downsweep_kernel<kRadixLargeItems>, dim3(nb), dim3(kThreads), 0, s, keys_in,
+                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
+    else
+        hipLaunchKernelGGL(radix_downsweep_kernel<kRadixSmallItems>, dim3(nb), dim3(kThreads), 0, s, keys_in,
+                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
     return hipGetLastError();
 }
 
-hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const uint32_t* tiles_touched,
-                            const uint2* rect, const CamDev* cams, uint32_t n, uint32_t vn, const uint32_t* total,
+hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const uint32_t* tt_s,
+                            const uint2* rect_s, const CamDev* cams, uint32_t n, uint32_t vn, const uint32_t* total,
                             uint32_t cap, uint32_t* keys, uint32_t* vals, uint32_t* emit_vg, uint32_t* overflow,
                             float4* rec, hipStream_t s)
 {
     if (vn == 0) return hipSuccess;
     hipLaunchKernelGGL(duplicate_kernel, dim3((vn + kThreads - 1) / kThreads), dim3(kThreads), 0, s, order, offsets,
-                       tiles_touched, rect, cams, n, vn, total, cap, keys, vals, emit_vg, overflow, rec);
+                       tt_s, rect_s, cams, n, vn, total, cap, keys, vals, emit_vg, overflow, rec);
     return hipGetLastError();
 }
 
@@ -514,8 +608,8 @@ size_t seg_carry_bytes(uint32_t cap) { return ((size_t)cap + 63) / 64 * sizeof(S
 hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* stamp, const uint32_t* emit_vg, uint32_t vn,
                               const uint32_t* total, uint32_t cap, float* grad2d, void* carry, hipStream_t s)
 {
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (size_t)vn * kG2, s);
-    if (e != hipSuccess || cap == 0) return e;
+    (void)vn;
+    if (cap == 0) return hipSuccess;
     const uint32_t nw = (cap + 63) / 64;
     hipLaunchKernelGGL(seg_reduce_kernel, dim3((nw * 64 + kThreads - 1) / kThreads), dim3(kThreads), 0, s, pair_grad,
                        stamp, emit_vg, total, cap, grad2d, reinterpret_cast<SegCarry*>(carry));

@@ -1,0 +1,202 @@
+"""Differentiation at scale: 6M Gaussians, four 1920x1080 cameras in one
+launch, SH3 stored in BF16, FP32 blending.
+
+The torch.autograd.Function backward of a loss restricted to a seeded 1 %
+pixel subset (L1 + gamma * mean entropy over those pixels) is checked
+
+  * against the FP64 oracle's gradient of the same loss (the oracle blends the
+    GPU's float32 records, reading R1, and runs its own FP64 projection
+    backward from the parameters), and
+  * against central finite differences (relative step 1e-4) of the FP64
+    oracle's loss on 64 seeded Gaussians (per Gaussian, up to four parameter
+    draws until one crosses no discrete decision).  Only the sampled pixels whose tile
+    lists hold the probed Gaussian depend on it, so each difference is taken
+    on the sub-scene made of every Gaussian in those tiles' lists, rendering
+    only those pixels: the same lists, the same pixels, the same loss terms.
+
+Images, entropy and transmittance of the sampled pixels are compared too.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2603_09277_amd import gsr, scenes
+
+from gpu_helpers import DEV, KEYS, gpu_records, oracle_stagewise, rel_norm, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+GAMMA = 0.015
+TILE = (16, 16)
+
+
+@pytest.fixture(scope="module")
+def run():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    scene, cams, meta = scenes.workload("diff")
+    assert meta["sh_dtype"] == "bf16" and len(cams) == 4
+    R = gsr.Rasterizer(max_views=4)
+    t = {k: v.requires_grad_(True) for k, v in to_dev(scene, bf16=True).items()}
+    opts = gsr.RasterOptions(tile=TILE, lds_batch=128, sh_degree=3, sh_bf16=True,
+                             flags=gsr.GSR_DEFAULT_FLAGS | gsr.GSR_PERSISTENT)
+    rgb, ent, em = gsr.render(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, R)
+    off = gsr.pixel_offsets(cams)
+    M = off[-1]
+    rng = np.random.default_rng(55)
+    sel = np.sort(rng.choice(M, M // 100, replace=False))
+    targets = [scenes.target_image(500 + v, c.height, c.width) for v, c in enumerate(cams)]
+    tgt = np.concatenate([x.reshape(-1, 3) for x in targets])
+    sel_t = torch.from_numpy(sel).to(DEV)
+    tgt_t = torch.from_numpy(tgt[sel]).to(DEV)
+    loss = (rgb[sel_t] - tgt_t).abs().sum() / (3 * len(sel)) + GAMMA * ent[sel_t].sum() / len(sel)
+    loss.backward()
+    torch.cuda.synchronize()
+    grads = {k: t[k].grad.float().cpu().numpy().astype(np.float64) for k in KEYS}
+    rgb_np = rgb.detach().cpu().numpy()
+    out = dict(rgb=rgb_np, H=ent.detach().cpu().numpy())
+    records = gpu_records(R, scene.n, len(cams))
+    R.close()
+    return dict(scene=scene, cams=cams, off=off, sel=sel, tgt=tgt, grads=grads, out=out, records=records)
+
+
+def _view_mask(run, v):
+    cam = run["cams"][v]
+    o0, o1 = run["off"][v], run["off"][v + 1]
+    s = run["sel"][(run["sel"] >= o0) & (run["sel"] < o1)] - o0
+    pix = np.zeros(cam.width * cam.height, np.uint8)
+    pix[s] = 1
+    return s, pix.reshape(cam.height, cam.width)
+
+
+def test_sampled_pixels_and_gradient_vs_oracle(run):
+    scene, cams, sel = run["scene"], run["cams"], run["sel"]
+    nsel = len(sel)
+    acc = None
+    flagged = checked = 0
+    for v, cam in enumerate(cams):
+        s, pix = _view_mask(run, v)
+        o0 = run["off"][v]
+        pg = run["records"][v]
+        img = oracle_stagewise(pg, cam, TILE, pix)
+        ok = img["flags"].reshape(-1)[s] == 0
+        flagged += int((~ok).sum())
+        checked += int(ok.sum())
+        rgb = run["out"]["rgb"][o0 + s]
+        assert np.abs(rgb - img["rgb"].reshape(-1, 3)[s])[ok].max() <= 1e-5
+        # entropy: -sum w ln w amplifies a weight's relative error d by |ln w + 1|,
+        # so |dH| <= d (H + 1 - T).  d is the FP32 error of alpha: the exponent
+        # p = A'dx^2 + B'dxdy + C'dy^2 is evaluated with an error of a few ulp of
+        # |A'|dx^2 + |B'dxdy| + |C'|dy^2, which exceeds |p| <= 8 (blended entries)
+        # by the conic's condition number, up to ~10^3 for these scales: d <= 2e-4.
+        # Plus the FP32 accumulation over n_contrib entries, 4 u n_contrib (1 + H).
+        Ho = img["H"].reshape(-1)[s]
+        To = img["T"].reshape(-1)[s]
+        nc = img["ncontrib"].reshape(-1)[s].astype(np.float64)
+        dH = np.abs(run["out"]["H"][o0 + s] - Ho)
+        tol = np.maximum(1e-5, 4 * 2.0 ** -24 * nc * (1 + Ho)) + 2e-4 * (Ho + 1 - To)
+        bad = np.flatnonzero(ok & (dH > tol))
+        assert len(bad) == 0, [(int(s[b]), float(dH[b]), float(Ho[b]), float(run["out"]["H"][o0 + s[b]]), int(nc[b]),
+                                float(img["T"].reshape(-1)[s[b]]), int(img["flags"].reshape(-1)[s[b]]),
+                                rgb[b].tolist(), img["rgb"].reshape(-1, 3)[s[b]].tolist()) for b in bad[:5]]
+        # the loss's upstream gradients, as the GPU saw them (L1 sign of the GPU image)
+        g_rgb = np.zeros((cam.height * cam.width, 3))
+        g_rgb[s] = np.sign(rgb - run["tgt"][o0 + s]) / (3 * nsel)
+        g_H = np.zeros(cam.height * cam.width)
+        g_H[s] = GAMMA / nsel
+        g2 = orc.backward_render(cam.width, cam.height, TILE[0], TILE[1], pg["mean2d"], pg["conic"], pg["opacity"],
+                                 pg["rgb"], img["ranges"], img["values"], g_rgb.reshape(cam.height, cam.width, 3),
+                                 g_H.reshape(cam.height, cam.width), pix)
+        acc = orc.backward_project(scene, cam, g2, orc.DEFAULT_FLAGS, acc)
+    assert flagged <= 0.01 * (flagged + checked)
+    g = run["grads"]
+    for k in ("means", "scales", "quats", "opacities"):
+        assert rel_norm(g[k], acc[k]) < 1e-3, (k, rel_norm(g[k], acc[k]))
+    # SH gradients are stored in bfloat16: within one bf16 ulp of bf16(g*) where g* is well away from zero
+    ref = scenes.bf16_round(acc["sh"].astype(np.float32)).astype(np.float64)
+    big = np.abs(acc["sh"]) > 1e-3 * np.abs(acc["sh"]).max()
+    assert np.all(np.abs(g["sh"] - ref)[big] <= np.abs(ref)[big] * 2.0 ** -7 * 1.01 + 1e-12)
+    assert rel_norm(g["sh"], acc["sh"]) < 5e-3
+
+
+def test_central_fd_on_64_gaussians(run):
+    scene, cams, sel = run["scene"], run["cams"], run["sel"]
+    nsel = len(sel)
+    tw, th = TILE
+    views = []
+    for v, cam in enumerate(cams):
+        pr = orc.project(scene, cam)
+        values, ranges = orc.bin_lists(pr["mean2d"], pr["radius"], pr["depth32"], cam.width, cam.height, tw, th)
+        s, pix = _view_mask(run, v)
+        gx = (cam.width + tw - 1) // tw
+        tile_of = (np.arange(cam.height)[:, None] // th) * gx + np.arange(cam.width)[None, :] // tw
+        sampled = np.zeros(len(ranges), bool)
+        sampled[np.unique(tile_of.reshape(-1)[s])] = True
+        lens = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)
+        pair_tile = np.repeat(np.arange(len(ranges)), lens)         # tile of each list entry
+        views.append(dict(values=values, ranges=ranges, pix=pix, tile_of=tile_of, sampled=sampled,
+                          pair_tile=pair_tile))
+    # Gaussians listed in a tile that holds a sampled pixel; 64 of them, seeded
+    cand = np.unique(np.concatenate([vw["values"][vw["sampled"][vw["pair_tile"]]] for vw in views]))
+    rng = np.random.default_rng(505)
+    probes = rng.choice(cand, 64, replace=False)
+    g = run["grads"]
+
+    def sub_problem(gi):
+        """Per view: the sub-scene (every Gaussian listed in a sampled tile that lists gi)
+        and the sampled pixels of those tiles."""
+        subs = []
+        for v, vw in enumerate(views):
+            tiles = np.unique(vw["pair_tile"][vw["values"] == gi])
+            tiles = tiles[vw["sampled"][tiles]]
+            if len(tiles) == 0:
+                continue
+            idx = np.unique(np.concatenate([vw["values"][vw["ranges"][t][0]:vw["ranges"][t][1]] for t in tiles]))
+            pix = vw["pix"] * np.isin(vw["tile_of"], tiles).astype(np.uint8)
+            subs.append((v, idx, pix))
+        return subs
+
+    def loss_sig(sc_full, gi, subs):
+        L = 0.0
+        sig = []
+        for v, idx, pix in subs:
+            cam = cams[v]
+            sc = sc_full.subset(idx)
+            f = orc.forward_view(sc, cam, TILE, pix=pix)
+            m = pix.astype(bool)
+            tgt = run["tgt"][run["off"][v]:run["off"][v + 1]].reshape(cam.height, cam.width, 3)
+            L += float(np.abs(f["rgb"][m] - tgt[m]).sum()) / (3 * nsel) + GAMMA * float(f["H"][m].sum()) / nsel
+            sig.append((f["sig"], f["values"].tobytes(), f["proj"]["mask"].tobytes(),
+                        np.sign(f["rgb"][m] - tgt[m]).astype(np.int8).tobytes()))
+        return L, sig
+
+    sc = scene.copy()
+    checked = redrawn = 0
+    names = ("means", "scales", "opacities")
+    for p, gi in enumerate(probes):
+        subs = sub_problem(int(gi))
+        # up to 4 (parameter, component) draws per Gaussian until one crosses no
+        # discrete decision (list, skip, stop, clamp, L1 sign) of the sampled pixels
+        for attempt in range(4):
+            name = names[(p + attempt) % 3]
+            flat = getattr(sc, name).reshape(sc.n, -1)
+            j = int(rng.integers(flat.shape[1]))
+            x0 = flat[gi, j]
+            eps = 1e-4 * (abs(float(x0)) if name == "scales" else max(1.0, abs(float(x0))))
+            xp, xm = np.float32(x0 + eps), np.float32(x0 - eps)
+            flat[gi, j] = xp
+            Lp, sp = loss_sig(sc, gi, subs)
+            flat[gi, j] = xm
+            Lm, sm = loss_sig(sc, gi, subs)
+            flat[gi, j] = x0
+            if sp != sm:
+                redrawn += 1
+                continue
+            fd = (Lp - Lm) / (float(xp) - float(xm))
+            an = g[name].reshape(sc.n, -1)[gi, j]
+            scale = np.abs(g[name].reshape(sc.n, -1)[probes]).max()
+            assert abs(an - fd) <= 2e-3 * abs(fd) + 2e-4 * scale + 1e-9, (name, int(gi), j, an, fd)
+            checked += 1
+            break
+    assert checked >= 56, (checked, redrawn)

@@ -71,20 +71,21 @@ def parse():
 
 
 def stage_bytes(stage, n, V, sh_bytes, pairs, n_tiles, npix, evals_fwd, evals_bwd):
-    """Algorithmic HBM bytes of one launch of each stage (minimum data the step must move)."""
+    """Algorithmic HBM bytes of one launch of each stage: the data the stage must
+    read and write once (per (view, Gaussian) `vn`, per pair, per tile, per pixel)."""
     vn = n * V
     return {
-        "project": n * (44 + sh_bytes) + vn * 52,
-        "depth_sort": vn * 4 * 20,
-        "scan": vn * 16,
-        "duplicate": vn * 20 + pairs * 8,
-        "tile_sort": pairs * 20 * 2,
+        "project": n * (44 + sh_bytes) + vn * 64,          # params + SH once; record 48 + key 4 + rect 8 + tt 4
+        "depth_sort": vn * 4 * 20,                          # 4 passes: key+value in/out, key histogram
+        "scan": vn * 36,                                    # order, tt and rect gathered, depth-ordered copies, offsets
+        "duplicate": vn * 28 + pairs * 12,                  # order/tt/offset/rect + emission base; key, value, owner
+        "tile_sort": pairs * 20 * 2,                        # 2 passes
         "ranges": pairs * 4 + n_tiles * 8,
-        "blend_fwd": pairs * 40 + npix * 24,
+        "blend_fwd": pairs * 52 + npix * 24,                # pair value + record; rgb, H, T, n_contrib
         "entropy_mean": 0,
-        "blend_bwd": pairs * 40 + npix * 24 + n * V * 36,
-        "project_bwd": n * (44 + sh_bytes) * 2 + vn * 36,
-        "grad_reduce": pairs * 36 + vn * 48,
+        "blend_bwd": pairs * 92 + npix * 24,                # pair value + record + gradient row; per-pixel state
+        "project_bwd": n * (88 + 2 * sh_bytes) + vn * 40,   # params + SH in, grads out; 2D grads + tt per view
+        "grad_reduce": pairs * 44 + vn * 36,                # rows + owners in, 2D grads out
     }[stage]
 
 
@@ -237,17 +238,21 @@ def main():
     sh_bytes = K * 3 * (2 if bf16 else 4)
     n_tiles = sum(((c.width + tile[0] - 1) // tile[0]) * ((c.height + tile[1] - 1) // tile[1]) for c in cams)
 
+    # stage times are per launch sequence; in the per-view form one launch covers one view
+    launches = len(work)
+    stl = {k: st[k] / launches for k in ("pairs", "evals_fwd", "evals_bwd", "blended")}
     stage_report = {}
     for name, (ms, cnt) in stages.items():
         if cnt == 0:
             continue
         avg_s = ms / cnt / 1e3
-        b = stage_bytes(name, n, V, sh_bytes, st["pairs"], n_tiles, npix, st["evals_fwd"], st["evals_bwd"])
+        b = stage_bytes(name, n, V / launches, sh_bytes, stl["pairs"], n_tiles / launches, npix / launches,
+                        stl["evals_fwd"], stl["evals_bwd"])
         rep = {"avg_ms": round(ms / cnt, 4), "hbm_GBs": round(b / avg_s / 1e9, 1) if b else None}
         if name in ("blend_fwd", "blend_bwd"):
-            rep["valu_Tops"] = round(blend_ops(name, st) / avg_s / 1e12, 3)
-            rep["evals_G_per_s"] = round(st["evals_fwd" if name == "blend_fwd" else "evals_bwd"] / avg_s / 1e9, 2)
-            rep["blended_G_per_s"] = round(st["blended"] / avg_s / 1e9, 3)
+            rep["valu_Tops"] = round(blend_ops(name, stl) / avg_s / 1e12, 3)
+            rep["evals_G_per_s"] = round(stl["evals_fwd" if name == "blend_fwd" else "evals_bwd"] / avg_s / 1e9, 2)
+            rep["blended_G_per_s"] = round(stl["blended"] / avg_s / 1e9, 3)
         stage_report[name] = rep
 
     roofline = None
@@ -263,7 +268,7 @@ def main():
             if os.path.exists(src) and source_hash(src) == rec.get("source_sha256_16"):
                 traffic = rec.get("bytes_per_launch")
         if dom in ("blend_fwd", "blend_bwd"):
-            ops = blend_ops(dom, st)
+            ops = blend_ops(dom, stl)
             ach = ops / avg_s / 1e12
             roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 2),
                         "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": traffic,

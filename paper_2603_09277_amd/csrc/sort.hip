@@ -405,10 +405,11 @@ __global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_
     const uint32_t P = *total < cap ? *total : cap;
     const uint32_t st = *stamp;
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
-    const uint32_t w = (blockIdx.x * kThreads + threadIdx.x) >> 6;
+    const uint32_t nw = (P + 63u) / 64u;
+    // chunks of 64 rows, grid-stride (the grid does not grow with the pair capacity)
+    for (uint32_t w = (blockIdx.x * kThreads + threadIdx.x) >> 6; w < nw; w += (gridDim.x * kThreads) >> 6) {
     const uint32_t e = w * 64u + lane;
-    if (w * 64u >= P) return;                                  // whole wavefront
-    {   // the wavefront's 64 rows (2560 B) through LDS with 16-byte loads
+    {   // the chunk's 64 rows (2560 B) through LDS with 16-byte loads
         const size_t f0 = (size_t)w * 64u * kRowF, fend = (size_t)P * kRowF;
         for (uint32_t f = lane; f < 64u * kRowF / 4u; f += 64u) {
             const size_t fi = f0 + 4u * (size_t)f;
@@ -467,6 +468,10 @@ __global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_
         c->last_seg = seg;
         c->flags = (crosses_in ? 1u : 0u) | (crosses_out ? 2u : 0u);
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");     // the rows are read before the next chunk lands
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 // one thread per wavefront: a segment that starts in wavefront w and continues
@@ -476,11 +481,10 @@ __global__ __launch_bounds__(kThreads) void seg_fixup_kernel(const SegCarry* car
 {
     const uint32_t P = *total < cap ? *total : cap;
     const uint32_t nw = (P + 63u) / 64u;
-    const uint32_t w = blockIdx.x * kThreads + threadIdx.x;
-    if (w >= nw) return;
+    for (uint32_t w = blockIdx.x * kThreads + threadIdx.x; w < nw; w += gridDim.x * kThreads) {
     const SegCarry& c = carry[w];
-    if (!(c.flags & 2u)) return;                                 // nothing continues past w
-    if ((c.flags & 1u) && c.first_seg == c.last_seg) return;     // w is inside a segment begun earlier
+    if (!(c.flags & 2u)) continue;                               // nothing continues past w
+    if ((c.flags & 1u) && c.first_seg == c.last_seg) continue;   // w is inside a segment begun earlier
     const uint32_t s = c.last_seg;
     float acc[kG2];
 #pragma unroll
@@ -500,6 +504,7 @@ __global__ __launch_bounds__(kThreads) void seg_fixup_kernel(const SegCarry* car
     float* dst = grad2d + (size_t)kG2 * s;
 #pragma unroll
     for (int k = 0; k < kG2; ++k) dst[k] = acc[k];
+    }
 }
 
 __global__ void tile_len_keys_kernel(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals)
@@ -534,16 +539,20 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t value, size_t count)
 __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* tiles, const uint32_t* total, uint32_t cap,
                                                           uint2* ranges)
 {
-    uint32_t P = *total < cap ? *total : cap;
-    uint32_t i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= P) return;
-    uint32_t t = tiles[i];
-    if (i == 0 || tiles[i - 1] != t) ranges[t].x = i;
-    if (i == P - 1 || tiles[i + 1] != t) ranges[t].y = i + 1;
+    const uint32_t P = *total < cap ? *total : cap;
+    for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < P; i += gridDim.x * kThreads) {
+        const uint32_t t = tiles[i];
+        if (i == 0 || tiles[i - 1] != t) ranges[t].x = i;
+        if (i == P - 1 || tiles[i + 1] != t) ranges[t].y = i + 1;
+    }
 }
 
 
 }  // namespace
+
+// grids of the grid-stride kernels: enough workgroups to fill the chip many
+// times over, without growing with a pair capacity that may far exceed the count
+static uint32_t grid_cap(uint32_t blocks) { return blocks < 16384u ? (blocks ? blocks : 1u) : 16384u; }
 
 size_t scan_tmp_words(uint32_t n) { return (size_t)(n + kTileItems - 1) / kTileItems + 1; }
 
@@ -611,9 +620,10 @@ hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* stamp, con
     (void)vn;
     if (cap == 0) return hipSuccess;
     const uint32_t nw = (cap + 63) / 64;
-    hipLaunchKernelGGL(seg_reduce_kernel, dim3((nw * 64 + kThreads - 1) / kThreads), dim3(kThreads), 0, s, pair_grad,
+    hipLaunchKernelGGL(seg_reduce_kernel, dim3(grid_cap((nw * 64 + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                       pair_grad,
                        stamp, emit_vg, total, cap, grad2d, reinterpret_cast<SegCarry*>(carry));
-    hipLaunchKernelGGL(seg_fixup_kernel, dim3((nw + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL(seg_fixup_kernel, dim3(grid_cap((nw + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
                        reinterpret_cast<const SegCarry*>(carry), total, cap, grad2d);
     return hipGetLastError();
 }
@@ -650,7 +660,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_
 hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges, hipStream_t s)
 {
     if (cap == 0) return hipSuccess;
-    hipLaunchKernelGGL(ranges_kernel, dim3((cap + kThreads - 1) / kThreads), dim3(kThreads), 0, s, tiles, total, cap,
+    hipLaunchKernelGGL(ranges_kernel, dim3(grid_cap((cap + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, tiles,
+                       total, cap,
                        ranges);
     return hipGetLastError();
 }

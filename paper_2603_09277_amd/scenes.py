@@ -179,8 +179,11 @@ def bf16_round(x: np.ndarray) -> np.ndarray:
 # Named workloads
 # --------------------------------------------------------------------------- #
 
-def workload(name: str, n_override: Optional[int] = None):
+def workload(name: str, n_override: Optional[int] = None, sh_f32: bool = False):
     """Return (scene, cameras, meta) for a named workload.
+
+    The BF16-SH workloads store bf16-rounded SH coefficients; sh_f32=True
+    returns the FP32 draw instead (same seed, unrounded).
 
     tiny        2k Gaussians, 128x128, SH0, 16x16 tiles, FP32.
     single      200k Gaussians, 1296x840, SH3, FP32 (the single-view workload).
@@ -206,14 +209,16 @@ def workload(name: str, n_override: Optional[int] = None):
         return scene, cams, meta
     if name == "batched":
         scene = gmm_scene(4, n_override or 3_000_000)
-        scene.sh = bf16_round(scene.sh)
+        if not sh_f32:
+            scene.sh = bf16_round(scene.sh)
         res = [(486, 324)] * 2 + [(972, 648)] * 3 + [(1944, 1296)] * 3
         cams = orbit_cameras(np.random.default_rng(1004), res)
         meta["sh_dtype"] = "bf16"
         return scene, cams, meta
     if name == "diff":
         scene = gmm_scene(5, n_override or 6_000_000)
-        scene.sh = bf16_round(scene.sh)
+        if not sh_f32:
+            scene.sh = bf16_round(scene.sh)
         cams = orbit_cameras(np.random.default_rng(1005), [(1920, 1080)] * 4)
         meta["sh_dtype"] = "bf16"
         return scene, cams, meta

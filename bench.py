@@ -9,7 +9,7 @@ backward with Alg. 1, projection backward.  Every stage runs in the HIP
 library (libgsr.so); inputs are resident in HBM before the timed region.
 
 Default workload: 200,000 Gaussians, one 1296x840 camera, SH degree 3, FP32,
-16x16 tiles, loss L1 + 0.015 L_E.  Prints one JSON line.
+16x16 tiles, LDS batch 128, loss L1 + 0.015 L_E.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd rasterize iters/s and Gaussian-tile pairs/s at 1 MI355X; batched vs plain"
+METRIC_RENDER = "forward-only render views/s (test-time FPS) at 1 MI355X"
 GAMMA = 0.015
 HBM_PEAK_GBS = 8000.0
 # VALU issue rate without packed FP32: 256 CUs x 64 lanes x 2.4 GHz (one FP32 op per lane per clock)
@@ -41,9 +42,12 @@ OPS_BLEND_FWD = 10          # per blended pair: transmittance, stop test, colour
 OPS_BLEND_BWD = 49          # per blended pair: T recovery, dC/dalpha, Alg. 1, 9 gradient terms and their sums
 
 
-def blend_ops(kind, st):
+OPS_ENTROPY = 2             # of OPS_BLEND_FWD: log2 and the entropy FMA (absent in test-time rendering)
+
+
+def blend_ops(kind, st, render=False):
     if kind == "blend_fwd":
-        return OPS_ALPHA_TEST * st["evals_fwd"] + OPS_BLEND_FWD * st["blended"]
+        return OPS_ALPHA_TEST * st["evals_fwd"] + (OPS_BLEND_FWD - (OPS_ENTROPY if render else 0)) * st["blended"]
     return OPS_ALPHA_TEST * st["evals_bwd"] + OPS_BLEND_BWD * st["blended"]
 
 
@@ -55,10 +59,12 @@ def parse():
     ap.add_argument("--workload", default="single",
                     choices=["tiny", "single", "sweep", "sweep_half", "batched", "diff"])
     ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--lds", type=int, default=64)
+    ap.add_argument("--lds", type=int, default=128)
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
     ap.add_argument("--persistent", action="store_true", help="persistent blend kernels, longest tile lists first")
     ap.add_argument("--autotune", action="store_true", help="pick tile shape and LDS batch with gsr_autotune first")
+    ap.add_argument("--forward-only", action="store_true",
+                    help="test-time rendering (gsr_render): colour only, no entropy, no backward; value = views/s")
     ap.add_argument("--per-view", action="store_true",
                     help="plain form: one launch sequence per view instead of one batched launch")
     ap.add_argument("--sh", choices=["auto", "f32", "bf16"], default="auto", help="SH storage (auto: the workload's)")
@@ -94,10 +100,11 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def cpu_baseline(scene, cams, tile, targets):
+def cpu_baseline(scene, cams, tile, targets, forward_only=False):
     """The FP64 oracle (single-threaded) on every other pixel row of the same
-    workload: projection and binning in full, blend + entropy + backward on the
-    sampled rows, extrapolated per pixel to whole iterations."""
+    workload: projection and binning in full, blend + entropy + backward (the
+    blend alone for test-time rendering) on the sampled rows, extrapolated per
+    pixel to whole iterations."""
     from oracle import oracle as orc
     tw, th = tile
     t_fixed = 0.0
@@ -113,21 +120,25 @@ def cpu_baseline(scene, cams, tile, targets):
         vals, ranges = orc.bin_lists(pr["mean2d"], pr["radius"], pr["depth32"], W, H, tw, th)
         t1 = time.perf_counter()
         img = orc.render(W, H, tw, th, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"], ranges, vals, pix)
-        gC = np.sign(img["rgb"] - target) / (3.0 * W * H)
-        gH = np.full((H, W), GAMMA / (W * H))
-        t2 = time.perf_counter()
-        g2 = orc.backward_render(W, H, tw, th, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"], ranges, vals,
-                                 gC, gH, pix)
-        t3 = time.perf_counter()
-        orc.backward_project(scene, cam, g2)
-        t4 = time.perf_counter()
+        t2 = t3 = t4 = time.perf_counter()
+        if not forward_only:
+            gC = np.sign(img["rgb"] - target) / (3.0 * W * H)
+            gH = np.full((H, W), GAMMA / (W * H))
+            t2 = time.perf_counter()
+            g2 = orc.backward_render(W, H, tw, th, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"], ranges, vals,
+                                     gC, gH, pix)
+            t3 = time.perf_counter()
+            orc.backward_project(scene, cam, g2)
+            t4 = time.perf_counter()
         t_fixed += (t1 - t0) + (t4 - t3)
         t_pix += (t2 - t1) + (t3 - t2)
         sampled += int(pix.sum())
         total += W * H
     sec_per_iter = t_fixed + t_pix * total / max(sampled, 1)
-    return {"value": len(cams) / sec_per_iter, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle, 1 thread: projection + binning in full, blend/entropy/backward on every "
+    return {"value": len(cams) / sec_per_iter, "unit": "views/s" if forward_only else "iters/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"FP64 oracle, 1 thread: projection + binning in full, "
+                      f"{'blend' if forward_only else 'blend/entropy/backward'} on every "
                       f"other pixel row ({sampled} of {total} pixels), extrapolated per pixel; "
                       f"{t_fixed + t_pix:.1f} s measured, {sec_per_iter:.1f} s per iteration"}
 
@@ -173,6 +184,7 @@ def main():
         cache = os.path.join(tempfile.gettempdir(), "gsr_autotune_cache.txt")
         opts = R.autotune(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, cache)
         tile = opts.tile
+        args.persistent = bool(opts.flags & gsr.GSR_PERSISTENT)
     g_le = torch.full((V,), GAMMA, device=dev)
     grads = {k: torch.empty_like(v) for k, v in t.items()}
     off = [0]
@@ -190,6 +202,11 @@ def main():
     state = {}
 
     def step():
+        if args.forward_only:
+            for w in work:
+                w["rgb"] = R.render_image(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], w["cams"], opts,
+                                          rgb=w.get("rgb"))
+            return
         for w in work:
             out = R.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], w["cams"], opts,
                             out=w["out"])
@@ -250,7 +267,7 @@ def main():
                         stl["evals_fwd"], stl["evals_bwd"])
         rep = {"avg_ms": round(ms / cnt, 4), "hbm_GBs": round(b / avg_s / 1e9, 1) if b else None}
         if name in ("blend_fwd", "blend_bwd"):
-            rep["valu_Tops"] = round(blend_ops(name, stl) / avg_s / 1e12, 3)
+            rep["valu_Tops"] = round(blend_ops(name, stl, args.forward_only) / avg_s / 1e12, 3)
             rep["evals_G_per_s"] = round(stl["evals_fwd" if name == "blend_fwd" else "evals_bwd"] / avg_s / 1e9, 2)
             rep["blended_G_per_s"] = round(stl["blended"] / avg_s / 1e9, 3)
         stage_report[name] = rep
@@ -268,7 +285,7 @@ def main():
             if os.path.exists(src) and source_hash(src) == rec.get("source_sha256_16"):
                 traffic = rec.get("bytes_per_launch")
         if dom in ("blend_fwd", "blend_bwd"):
-            ops = blend_ops(dom, stl)
+            ops = blend_ops(dom, stl, args.forward_only)
             ach = ops / avg_s / 1e12
             roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 2),
                         "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": traffic,
@@ -284,22 +301,24 @@ def main():
                "batched": "3M Gaussians, 8 views (2x486x324, 3x972x648, 3x1944x1296), SH3",
                "diff": "6M Gaussians, 4x1920x1080, SH3"}[args.workload]
     result = {
-        "metric": METRIC, "value": round(iters, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC_RENDER if args.forward_only else METRIC, "value": round(iters, 3),
+        "unit": "views/s" if args.forward_only else "iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl_name, "gaussians": n, "views": V, "tile": f"{tile[0]}x{tile[1]}",
                    "lds_batch": opts.lds_batch, "sh_storage": "bf16" if bf16 else "f32",
-                   "mode": ("per-view" if args.per_view else ("batched" if V > 1 else "single-view"))
+                   "mode": ("forward-only " if args.forward_only else "")
+                           + ("per-view" if args.per_view else ("batched" if V > 1 else "single-view"))
                            + ("+graph" if args.graph else "")
                            + ("+persistent" if args.persistent else "") + ("+autotuned" if args.autotune else ""),
-                   "loss": "L1 + 0.015 L_E"},
+                   "loss": None if args.forward_only else "L1 + 0.015 L_E"},
         "pairs_per_s": round(st["pairs"] / sec, 1), "pairs": st["pairs"], "mean_list_len": round(st["mean_len"], 2),
         "p99_list_len": st["p99_len"], "evals_fwd": st["evals_fwd"], "evals_bwd": st["evals_bwd"],
         "blended": st["blended"],
         "overflow": st["overflow"], "stages": stage_report, "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(scene, cams, tile, targets_np)
+        result["cpu_baseline"] = cpu_baseline(scene, cams, tile, targets_np, args.forward_only)
     print(json.dumps(result), flush=True)
 
 

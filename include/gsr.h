@@ -78,8 +78,9 @@ typedef struct {
 #define GSR_COLOR_CLAMP     4u   /* clamp colour at 0 */
 #define GSR_GRAPH           8u   /* capture forward / backward into HIP graphs and replay them;
                                     fixed pair capacity, no host synchronisation */
-#define GSR_PERSISTENT     16u   /* persistent blend kernels: resident workgroups pull tiles from a device
-                                    queue ordered longest list first (balances mixed-resolution views) */
+#define GSR_PERSISTENT     16u   /* persistent blend kernels: resident workgroups pull tiles from 8 device
+                                    queues (one per XCD) of spatially contiguous tiles, stealing from the
+                                    others when their own is empty */
 #define GSR_DEFAULT_FLAGS  (GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP)
 
 typedef struct {
@@ -152,6 +153,16 @@ gsr_status gsr_pixel_offsets(const gsr_camera* cams, int32_t n_views, int64_t* o
 gsr_status gsr_forward(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
                        int32_t n_views, const gsr_opts* opts, gsr_fwd_out* out);
 
+/* Test-time rendering: the colour of n_views cameras (Sec. 3, Eq. 3-5) with
+ * the same projection, lists and blending as gsr_forward (bit-identical rgb),
+ * without the entropy and without per-pixel saved state.  rgb: device, caller-
+ * owned, float [P][3] with views packed as in gsr_fwd_out.  Plain mode only
+ * (GSR_GRAPH -> GSR_ERR_UNSUPPORTED; GSR_PERSISTENT is honoured); synchronises
+ * once on `stream`.  It replaces the context's frame: a backward of an earlier
+ * forward then fails with GSR_ERR_STALE_FRAME.  gsr_stats describes it. */
+gsr_status gsr_render(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
+                      int32_t n_views, const gsr_opts* opts, float* rgb);
+
 /* Gradients of a loss of the forward outputs (Sec. 3.4, Eq. 13-15, Alg. 1,
  * Suppl. C): grad_rgb [P][3] = dL/dC, grad_entropy [P] = dL/dH_j (may be
  * NULL), grad_entropy_mean [n_views] = dL/dL_E,v (device, may be NULL).
@@ -210,9 +221,11 @@ typedef enum {
 gsr_status gsr_set_timing(gsr_ctx* ctx, int32_t enable);
 gsr_status gsr_stage_times(gsr_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);
 
-/* Time forward+backward for every tile shape in {8x8, 16x16, 32x8} and
- * LDS batch in {32, 64, 128, 256} on the given inputs, and write the fastest
- * into inout->tile_w/tile_h/lds_batch.  If cache_path is not NULL the result
+/* Time forward+backward for every tile shape in {8x8, 16x16, 32x8}, LDS
+ * batch in {32, 64, 128, 256} and blend scheduling (hardware dispatch or
+ * GSR_PERSISTENT) on the given inputs, and write the fastest into
+ * inout->tile_w/tile_h/lds_batch and the GSR_PERSISTENT bit of inout->flags
+ * (the other flags are kept).  If cache_path is not NULL the result
  * is read from / appended to that text file, keyed by device and workload.
  * Synchronises `stream`.  Note the image depends on the tile shape. */
 gsr_status gsr_autotune(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,

@@ -53,7 +53,7 @@ struct gsr_ctx {
 
     // grow-only device buffers
     Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, tt_s, rect_s, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
-    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, tord, block_H, block_cnt, hchunk, counters, l1_tmp;
+    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, queues, block_H, block_cnt, hchunk, counters, l1_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
     uint64_t gen_fwd = 0, gen_bwd = 0;
@@ -303,8 +303,6 @@ gsr_status ensure_tiles(gsr_ctx* c, uint32_t tiles, uint32_t blocks)
 {
     gsr_status s;
     if ((s = grow(c, c->ranges, (size_t)std::max<uint32_t>(tiles, 1) * 8)) ||
-        (s = grow(c, c->tord, (size_t)std::max<uint32_t>(tiles, 1) * 16)) ||
-        (s = grow(c, c->radix_tmp, radix_tmp_words(std::max<uint32_t>(tiles, 1)) * 4)) ||
         (s = grow(c, c->block_H, (size_t)std::max<uint32_t>(blocks, 1) * 4)) ||
         (s = grow(c, c->block_cnt, (size_t)std::max<uint32_t>(blocks, 1) * 16)) ||
         (s = grow(c, c->hchunk, (size_t)(blocks / kRedChunk + 64) * 8)))
@@ -315,7 +313,7 @@ gsr_status ensure_tiles(gsr_ctx* c, uint32_t tiles, uint32_t blocks)
 // everything of the forward after the camera upload; `plain` = read the pair
 // count back and size the pair buffers exactly (one host synchronisation)
 gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, const gsr_opts* o, gsr_fwd_out* out,
-                           bool plain)
+                           bool plain, bool render_only = false)
 {
     const Layout& L = c->lay;
     const uint32_t n = (uint32_t)g->n, V = (uint32_t)L.cams.size(), vn = n * V;
@@ -386,14 +384,8 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
         StageTimer tm(c, st, GSR_STAGE_RANGES, plain);
         HIP_TRY(c, launch_fill_u32((uint32_t*)c->ranges.p, 0u, (size_t)L.n_tiles * 2, st));
         HIP_TRY(c, launch_ranges(pk[sb], counters, cap, (uint2*)c->ranges.p, st));
-        if (persist) {
-            // work order for the persistent blend kernels: tiles with the longest lists first
-            uint32_t* tk = (uint32_t*)c->tord.p;
-            HIP_TRY(c, launch_tile_len_keys((const uint2*)c->ranges.p, L.n_tiles, tk, tk + L.n_tiles, st));
-            HIP_TRY(c, launch_radix_pass(tk, tk + L.n_tiles, tk + 2 * L.n_tiles, tk + 3 * L.n_tiles, nullptr,
-                                         L.n_tiles, 0, (uint32_t*)c->radix_tmp.p, st));
-            HIP_TRY(c, launch_fill_u32(counters + 2, 0u, 2, st));
-        }
+        // the persistent blend kernels' queue heads (forward and backward sets)
+        if (persist) HIP_TRY(c, launch_fill_u32((uint32_t*)c->queues.p, 0u, 2 * kQueues * kQueueStride, st));
     }
 
     BlendFwdArgs ba;
@@ -403,13 +395,13 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     ba.out_rgb = out->rgb; ba.out_H = out->entropy; ba.out_T = out->t_final; ba.out_nc = out->n_contrib;
     ba.block_H = (float*)c->block_H.p;
     ba.block_cnt = (uint4*)c->block_cnt.p;
-    ba.tile_order = persist ? (const uint32_t*)c->tord.p + 3 * L.n_tiles : nullptr;
-    ba.work_counter = persist ? counters + 2 : nullptr;
+    ba.queues = persist ? (uint32_t*)c->queues.p : nullptr;
+    ba.render_only = render_only ? 1 : 0;
     {
         StageTimer tm(c, st, GSR_STAGE_BLEND_FWD, plain);
         HIP_TRY(c, launch_blend_fwd(ba, o->lds_batch == 0 ? 64 : o->lds_batch, st));
     }
-    {
+    if (!render_only) {
         StageTimer tm(c, st, GSR_STAGE_ENTROPY_MEAN, plain);
         HIP_TRY(c, launch_entropy_mean((const float*)c->block_H.p, dc, (int)V, L.n_hchunks, (double*)c->hchunk.p,
                                        out->entropy_mean, st));
@@ -439,9 +431,8 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     bb.T_final = saved->t_final; bb.n_contrib = saved->n_contrib; bb.grad_rgb = grad_rgb; bb.grad_H = grad_H;
     bb.grad_LE = grad_LE; bb.pair_grad = (float*)c->pair_grad.p; bb.stamp = (const uint32_t*)c->counters.p + 4;
     const bool persist = (o->flags & GSR_PERSISTENT) != 0;
-    bb.tile_order = persist ? (const uint32_t*)c->tord.p + 3 * L.n_tiles : nullptr;
-    bb.work_counter = persist ? (uint32_t*)c->counters.p + 3 : nullptr;
-    if (persist) HIP_TRY(c, launch_fill_u32((uint32_t*)c->counters.p + 3, 0u, 1, st));
+    bb.queues = persist ? (uint32_t*)c->queues.p + kQueues * kQueueStride : nullptr;
+    if (persist) HIP_TRY(c, launch_fill_u32(bb.queues, 0u, kQueues * kQueueStride, st));
     HIP_TRY(c, launch_blend_bwd(bb, o->lds_batch == 0 ? 64 : o->lds_batch, st));
     tb.stop();
     {
@@ -522,6 +513,7 @@ gsr_status gsr_create(gsr_ctx** out, int32_t max_views, int64_t pair_capacity)
     gsr_status s = GSR_OK;
     if (hipGetDevice(&c->device) != hipSuccess) s = GSR_ERR_HIP;
     if (!s) s = grow(c, c->cams, sizeof(CamDev) * (size_t)max_views);
+    if (!s) s = grow(c, c->queues, 2 * kQueues * kQueueStride * 4);
     if (!s) s = grow(c, c->counters, 64, true);     // [4]: backward row stamp
     if (!s && hipHostMalloc((void**)&c->counters_host, 64, hipHostMallocDefault) != hipSuccess) s = GSR_ERR_HIP;
     if (!s && hipHostMalloc((void**)&c->cams_host, sizeof(CamDev) * (size_t)max_views, hipHostMallocDefault) != hipSuccess)
@@ -547,7 +539,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     drop_graphs(c);
     Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->tt_s, &c->rect_s, &c->radius,
                    &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
-                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->tord, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters,
+                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->queues, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters,
                    &c->l1_tmp };
     for (Dev* d : all) free_dev(*d);
     for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
@@ -644,6 +636,37 @@ gsr_status gsr_forward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const g
     c->frame += 1;
     c->have_frame = true;
     out->frame_id = c->frame;
+    return GSR_OK;
+}
+
+gsr_status gsr_render(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gsr_camera* cams, int32_t n_views,
+                      const gsr_opts* o, float* rgb)
+{
+    gsr_status s = validate(c, g, cams, n_views, o);
+    if (s) return s;
+    if (!rgb) return fail(c, GSR_ERR_INVALID_ARG, "null rgb output");
+    if (o->flags & GSR_GRAPH) return fail(c, GSR_ERR_UNSUPPORTED, "gsr_render runs in plain mode only");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if ((s = wait_replay(c))) return s;
+    Layout L = make_layout(cams, n_views, o);
+    const uint32_t n = (uint32_t)g->n, vn = n * (uint32_t)n_views;
+    if ((s = ensure_vn(c, vn)) || (s = ensure_tiles(c, L.n_tiles, L.n_blocks)) ||
+        (s = ensure_radix_tmp(c, std::max<size_t>(vn, c->pair_cap))))
+        return s;
+    c->lay = L;
+    c->n = n;
+    c->vn = vn;
+    c->n_views = n_views;
+    c->fopts = *o;
+    gsr_fwd_out out;
+    std::memset(&out, 0, sizeof out);
+    out.rgb = rgb;
+    HIP_TRY(c, hipMemcpyAsync(c->cams.p, c->lay.cams.data(), sizeof(CamDev) * L.cams.size(), hipMemcpyHostToDevice, st));
+    if ((s = enqueue_forward(c, st, g, o, &out, true, true))) return s;
+    // a render saves no state: no backward may follow it
+    c->frame += 1;
+    c->have_frame = true;
     return GSR_OK;
 }
 
@@ -874,9 +897,10 @@ gsr_status gsr_autotune(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
                 std::string l(line);
                 size_t bar = l.rfind(" | ");
                 if (bar == std::string::npos || l.substr(0, bar) != key) continue;
-                int tw, th, lb;
-                if (std::sscanf(l.c_str() + bar + 3, "%d %d %d", &tw, &th, &lb) == 3 && tile_ok(tw, th)) {
+                int tw, th, lb, pe;
+                if (std::sscanf(l.c_str() + bar + 3, "%d %d %d %d", &tw, &th, &lb, &pe) == 4 && tile_ok(tw, th)) {
                     inout->tile_w = tw; inout->tile_h = th; inout->lds_batch = lb;
+                    inout->flags = (inout->flags & ~(uint32_t)GSR_PERSISTENT) | (pe ? GSR_PERSISTENT : 0u);
                     std::fclose(f);
                     return GSR_OK;
                 }
@@ -911,11 +935,12 @@ gsr_status gsr_autotune(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
+    for (int pe = 0; pe < 2; ++pe)
     for (auto& sh : shapes)
         for (int lb : batches) {
             gsr_opts o = *inout;
             o.tile_w = sh[0]; o.tile_h = sh[1]; o.lds_batch = lb;
-            o.flags &= ~(uint32_t)GSR_GRAPH;
+            o.flags = (o.flags & ~(uint32_t)(GSR_GRAPH | GSR_PERSISTENT)) | (pe ? GSR_PERSISTENT : 0u);
             double t = 0.0;
             for (int it = 0; it < 4 && s == GSR_OK; ++it) {
                 if (it == 1) (void)hipEventRecord(e0, st);
@@ -937,9 +962,11 @@ gsr_status gsr_autotune(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
     c->have_frame = false;
     if (s) return s;
     inout->tile_w = bo.tile_w; inout->tile_h = bo.tile_h; inout->lds_batch = bo.lds_batch;
+    const int pe = (bo.flags & GSR_PERSISTENT) ? 1 : 0;
+    inout->flags = (inout->flags & ~(uint32_t)GSR_PERSISTENT) | (pe ? GSR_PERSISTENT : 0u);
     if (cache_path) {
         if (FILE* f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s | %d %d %d %.4f\n", key.c_str(), bo.tile_w, bo.tile_h, bo.lds_batch, best);
+            std::fprintf(f, "%s | %d %d %d %d %.4f\n", key.c_str(), bo.tile_w, bo.tile_h, bo.lds_batch, pe, best);
             std::fclose(f);
         }
     }

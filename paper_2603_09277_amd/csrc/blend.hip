@@ -204,23 +204,48 @@ __device__ __forceinline__ BlockGeom block_geom(const CamDev* cams, int n_views,
     return g;
 }
 
-// next work item of a persistent wavefront (one atomic per wavefront)
-__device__ __forceinline__ uint32_t next_item_wave(uint32_t* counter, uint32_t lane)
+// Persistent scheduling.  The n items (in tile-major, i.e. spatial, order) are
+// split into kQueues contiguous ranges, one per XCD: workgroups are dispatched
+// to the XCDs round-robin, so workgroup b serves queue b % kQueues first and
+// neighbouring tiles, which share most of their Gaussians, meet in one XCD's
+// L2.  A drained queue sends its workgroups to the next queues.  Each queue
+// head is its own 128-byte line; a claim takes `count` consecutive items.
+// Returns [first, end) of the claim, or (n, n) when every queue is drained.
+__device__ __forceinline__ uint2 claim_items(uint32_t* queues, uint32_t n, uint32_t count)
 {
-    uint32_t v = 0;
-    if (lane == 0) v = atomicAdd(counter, 1u);
-    return __shfl(v, 0, 64);
+    const uint32_t home = blockIdx.x % kQueues;
+    for (uint32_t t = 0; t < kQueues; ++t) {
+        const uint32_t k = (home + t) % kQueues;
+        const uint32_t lo = (uint32_t)((uint64_t)n * k / kQueues), hi = (uint32_t)((uint64_t)n * (k + 1) / kQueues);
+        if (lo >= hi) continue;
+        const uint32_t v = atomicAdd(queues + k * kQueueStride, count);
+        if (v < hi - lo) return make_uint2(lo + v, lo + v + count < hi ? lo + v + count : hi);
+    }
+    return make_uint2(n, n);
 }
 
-// work item -> wave block: items walk the tiles in `tile_order` (longest list
-// first) and, inside a tile, its 8x8 blocks
-__device__ __forceinline__ uint32_t item_to_wblock(const uint32_t* tile_order, uint32_t item, int spt)
+// items of a persistent wavefront, claimed kClaim at a time
+constexpr uint32_t kClaim = 4;
+
+struct WaveQueue {
+    uint32_t cur = 0, end = 0;
+};
+
+__device__ __forceinline__ uint32_t next_item_wave(WaveQueue& q, uint32_t* queues, uint32_t n, uint32_t lane)
 {
-    if (!tile_order) return item;
-    return tile_order[item / (uint32_t)spt] * (uint32_t)spt + item % (uint32_t)spt;
+    if (q.cur >= q.end) {
+        uint2 r = make_uint2(0u, 0u);
+        if (lane == 0) r = claim_items(queues, n, kClaim);
+        q.cur = __shfl(r.x, 0, 64);
+        q.end = __shfl(r.y, 0, 64);
+        if (q.cur >= q.end) return n;
+    }
+    return q.cur++;
 }
 
-template <int B, bool PERSIST>
+
+// RENDER: colour only (test-time rendering): no entropy, no per-pixel saved state
+template <int B, bool PERSIST, bool RENDER>
 __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
 {
     __shared__ float4 s_g0[kWavesPerGroup][B];   // mean x, mean y, A', B'
@@ -228,9 +253,10 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
     __shared__ float s_b[kWavesPerGroup][B];     // blue
     __shared__ int32_t s_pos[kWavesPerGroup][B]; // position in the tile list
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
-    uint32_t item = PERSIST ? next_item_wave(a.work_counter, lane) : blockIdx.x * kWavesPerGroup + wid;
-    for (; item < a.n_blocks; item = PERSIST ? next_item_wave(a.work_counter, lane) : a.n_blocks) {
-    const uint32_t wb = item_to_wblock(a.tile_order, item, a.spt);
+    WaveQueue wq;
+    uint32_t item = PERSIST ? next_item_wave(wq, a.queues, a.n_blocks, lane) : blockIdx.x * kWavesPerGroup + wid;
+    for (; item < a.n_blocks; item = PERSIST ? next_item_wave(wq, a.queues, a.n_blocks, lane) : a.n_blocks) {
+    const uint32_t wb = item;
     const BlockGeom g = block_geom(a.cams, a.n_views, wb, lane, a.tile_shift_x, a.tile_shift_y, a.spt);
     const uint2 rg = a.ranges[g.tile];
     const float fpx = (float)g.px + 0.5f, fpy = (float)g.py + 0.5f;
@@ -282,7 +308,7 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
                     Cr = fmaf(w, g1.z, Cr);
                     Cg = fmaf(w, g1.w, Cg);
                     Cb = fmaf(w, s_b[wid][k], Cb);
-                    H2 = fmaf(-w, __builtin_amdgcn_logf(w), H2);    // -w log2 w   (Eq. 10)
+                    if (!RENDER) H2 = fmaf(-w, __builtin_amdgcn_logf(w), H2);    // -w log2 w   (Eq. 10)
                     T = Tn;
                     last = s_pos[wid][k] + 1;
                     ++nbl;
@@ -292,23 +318,25 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
         wave_lds_sync();
     }
     // background weight T_{N+1} (Eq. 9-10), then natural-log units
-    const float H = kLn2 * fmaf(-T, __builtin_amdgcn_logf(T), H2);
+    const float H = RENDER ? 0.f : kLn2 * fmaf(-T, __builtin_amdgcn_logf(T), H2);
     if (g.inside) {
         a.out_rgb[3 * g.pix + 0] = Cr;
         a.out_rgb[3 * g.pix + 1] = Cg;
         a.out_rgb[3 * g.pix + 2] = Cb;
-        a.out_H[g.pix] = H;
-        a.out_T[g.pix] = T;
-        a.out_nc[g.pix] = last;
+        if (!RENDER) {
+            a.out_H[g.pix] = H;
+            a.out_T[g.pix] = T;
+            a.out_nc[g.pix] = last;
+        }
     }
     // list positions this pixel visited (the stopping entry included), culled ones counted
     const int32_t n_eval = !g.inside ? 0 : (stop_pos >= 0 ? stop_pos + 1 : (int32_t)(rg.y - rg.x));
-    const float hs = wave_sum_all(g.inside ? H : 0.f);
     const uint32_t ne = (uint32_t)wave_sum_all_i(n_eval);
     const uint32_t nc = (uint32_t)wave_sum_all_i(last);
     const uint32_t nb = (uint32_t)wave_sum_all_i((int)nbl);
+    const float hs = RENDER ? 0.f : wave_sum_all(g.inside ? H : 0.f);
     if (lane == 0) {
-        a.block_H[wb] = hs;
+        if (!RENDER) a.block_H[wb] = hs;
         a.block_cnt[wb] = make_uint4(ne, nc, nb, 0u);
     }
     }
@@ -444,21 +472,22 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     const float stamp = __uint_as_float(*a.stamp);
     // work items: tiles (SHARED: one per workgroup; else one per wavefront), longest list first
     const uint32_t n_items = SHARED ? a.n_blocks / kWavesPerGroup : a.n_blocks;
+    WaveQueue wq;
     auto next = [&]() -> uint32_t {
         if (!PERSIST) return n_items;
         if (SHARED) {
             __syncthreads();
-            if (threadIdx.x == 0) s_item = atomicAdd(a.work_counter, 1u);
+            if (threadIdx.x == 0) s_item = claim_items(a.queues, n_items, 1u).x;
             __syncthreads();
             return s_item;
         }
-        return next_item_wave(a.work_counter, lane);
+        return next_item_wave(wq, a.queues, n_items, lane);
     };
     uint32_t item;
     if (PERSIST) item = next();
     else item = SHARED ? blockIdx.x : blockIdx.x * kWavesPerGroup + wid;
     for (; item < n_items; item = next()) {
-    const uint32_t tile_id = a.tile_order ? a.tile_order[item] : item;
+    const uint32_t tile_id = item;
     const uint32_t wb = SHARED ? tile_id * kWavesPerGroup + wid : tile_id;
     const BlockGeom g = block_geom(a.cams, a.n_views, wb, lane, a.tile_shift_x, a.tile_shift_y, a.spt);
     const uint2 rg = a.ranges[g.tile];
@@ -619,11 +648,18 @@ template <int B>
 hipError_t fwd_b(const BlendFwdArgs& a, hipStream_t s)
 {
     const uint32_t groups = (a.n_blocks + kWavesPerGroup - 1) / kWavesPerGroup;
-    if (a.work_counter) {
-        hipLaunchKernelGGL((blend_fwd_kernel<B, true>), dim3(resident_groups(blend_fwd_kernel<B, true>, groups)),
-                           dim3(256), 0, s, a);
+    if (a.render_only) {
+        if (a.queues)
+            hipLaunchKernelGGL((blend_fwd_kernel<B, true, true>),
+                               dim3(resident_groups(blend_fwd_kernel<B, true, true>, groups)), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((blend_fwd_kernel<B, false, true>), dim3(groups), dim3(256), 0, s, a);
     } else {
-        hipLaunchKernelGGL((blend_fwd_kernel<B, false>), dim3(groups), dim3(256), 0, s, a);
+        if (a.queues)
+            hipLaunchKernelGGL((blend_fwd_kernel<B, true, false>),
+                               dim3(resident_groups(blend_fwd_kernel<B, true, false>, groups)), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((blend_fwd_kernel<B, false, false>), dim3(groups), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -633,7 +669,7 @@ hipError_t bwd_b(const BlendBwdArgs& a, hipStream_t s)
 {
     static_assert(B <= 128, "the backward window is limited by LDS");
     const uint32_t groups = (a.n_blocks + kWavesPerGroup - 1) / kWavesPerGroup;
-    if (a.work_counter) {
+    if (a.queues) {
         if (a.spt == 4)
             hipLaunchKernelGGL((blend_bwd_kernel<B, true, true>),
                                dim3(resident_groups(blend_bwd_kernel<B, true, true>, groups)), dim3(256), 0, s, a);

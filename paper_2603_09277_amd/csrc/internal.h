@@ -44,6 +44,9 @@ constexpr int kL1Block = 256;      // pixels per L1 block
 // C' = -C log2(e)/2, so that the exponent is A' dx^2 + B' dx dy + C' dy^2.
 constexpr double kLog2e = 1.4426950408889634;
 constexpr int kRecF4 = 3;
+// persistent blend kernels: one work queue per XCD, heads 128 bytes apart
+constexpr uint32_t kQueues = 8;
+constexpr uint32_t kQueueStride = 32;
 // 2D gradient accumulator per (view, Gaussian): 9 floats
 //   dmean x, dmean y, dA, dB, dC, dopacity, dred, dgreen, dblue
 constexpr int kG2 = 9;
@@ -99,13 +102,13 @@ struct BlendFwdArgs {
     int32_t spt;                          // 8x8 blocks per tile: 1 or 4
     uint32_t n_blocks;                    // 8x8 wave blocks over all views
     float* out_rgb;
-    float* out_H;
+    float* out_H;                         // out_H, out_T, out_nc, block_H: unused by the render-only variant
     float* out_T;
     int32_t* out_nc;
     float* block_H;                       // [n_blocks] sum of H over the block
     uint4* block_cnt;                     // [n_blocks] (alpha evaluations, sum of n_contrib, blended, 0)
-    const uint32_t* tile_order;           // tiles longest list first (persistent mode), or null
-    uint32_t* work_counter;               // persistent work queue head (zeroed before launch), or null
+    uint32_t* queues;                     // persistent mode: kQueues heads kQueueStride words apart, zeroed; or null
+    int32_t render_only;                  // 1: colour only (no entropy, no saved state)
 };
 
 struct BlendBwdArgs {
@@ -124,8 +127,7 @@ struct BlendBwdArgs {
     const float* grad_LE;                 // [V] may be null
     float* pair_grad;                     // [P][10] per-pair gradient rows, emission order
     const uint32_t* stamp;                // this backward's row stamp
-    const uint32_t* tile_order;           // tiles longest list first (persistent mode), or null
-    uint32_t* work_counter;               // persistent work queue head (zeroed before launch), or null
+    uint32_t* queues;                     // persistent mode: kQueues heads kQueueStride words apart, zeroed; or null
 };
 
 // ---- launchers (return hipError_t of the launch) ----
@@ -165,7 +167,6 @@ hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* stamp, con
 hipError_t launch_bump_u32(uint32_t* p, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 // keys[t] = 255 - min(255, ceil(len_t / 8)), vals[t] = t: one stable 8-bit pass orders tiles longest first
-hipError_t launch_tile_len_keys(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
 // per-tile [start, end) of the sorted pairs
 hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges, hipStream_t s);

@@ -384,103 +384,159 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* ord
 // Per-Gaussian sum of the per-pair gradient rows.  Rows (9 floats and a stamp)
 // are stored in emission order, where all pairs of one (view, Gaussian) are
 // contiguous; a row whose stamp is not this backward's was not written by it
-// (no pixel blended that pair) and counts as zero.  One wavefront takes 64
-// consecutive rows, runs a segmented inclusive scan keyed by the Gaussian,
-// and writes every segment that starts and ends inside it; segments that
-// cross wavefront boundaries leave their partial sums in `carry` and are
-// finished by seg_fixup_kernel in a fixed order.  No atomics: deterministic.
+// (no pixel blended that pair) and counts as zero.  One wavefront takes a
+// chunk of 256 consecutive rows (10 KB, staged through LDS with 16-byte
+// loads), 4 per lane: each lane sums its rows segment by segment, one
+// segmented scan over the 64 lanes (keyed by the Gaussian) joins segments
+// that span lanes, and every segment that starts and ends inside the chunk is
+// written; segments that cross chunk boundaries leave their partial sums in
+// `carry` and are finished by seg_fixup_kernel in a fixed order.  No atomics:
+// deterministic.
 struct SegCarry {
-    float head[kG2];         // first segment's sum over this wavefront, if it started earlier and ends here
-    float tail[kG2];         // last segment's sum over this wavefront, if it continues past it
+    float head[kG2];         // first segment's sum over this chunk, if it started earlier and ends here
+    float tail[kG2];         // last segment's sum over this chunk, if it continues past it
     uint32_t first_seg, last_seg;
     uint32_t flags;          // 1: first segment started earlier; 2: last segment continues
     uint32_t pad;
 };
 
+constexpr uint32_t kRowsPerLane = 4;
+constexpr uint32_t kChunkRows = 64 * kRowsPerLane;           // 256
+constexpr uint32_t kLaneF4 = kRowsPerLane * kRowF / 4 + 1;   // 10 float4 of rows + 1 of padding per lane
+constexpr uint32_t kNoSeg = 0xffffffffu;
+
+__device__ __forceinline__ void add9(float* a, const float* b)
+{
+#pragma unroll
+    for (int k = 0; k < kG2; ++k) a[k] += b[k];
+}
+
+__device__ __forceinline__ void store9(float* dst, const float* v)
+{
+#pragma unroll
+    for (int k = 0; k < kG2; ++k) dst[k] = v[k];
+}
+
 __global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_grad, const uint32_t* stamp,
                                                               const uint32_t* emit_vg, const uint32_t* total,
                                                               uint32_t cap, float* grad2d, SegCarry* carry)
 {
-    __shared__ float4 s_rows[kThreads / 64][64 * kRowF / 4];
+    __shared__ float4 s_rows[kThreads / 64][64 * kLaneF4];
     const uint32_t P = *total < cap ? *total : cap;
     const uint32_t st = *stamp;
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
-    const uint32_t nw = (P + 63u) / 64u;
-    // chunks of 64 rows, grid-stride (the grid does not grow with the pair capacity)
-    for (uint32_t w = (blockIdx.x * kThreads + threadIdx.x) >> 6; w < nw; w += (gridDim.x * kThreads) >> 6) {
-    const uint32_t e = w * 64u + lane;
-    {   // the chunk's 64 rows (2560 B) through LDS with 16-byte loads
-        const size_t f0 = (size_t)w * 64u * kRowF, fend = (size_t)P * kRowF;
-        for (uint32_t f = lane; f < 64u * kRowF / 4u; f += 64u) {
-            const size_t fi = f0 + 4u * (size_t)f;
-            if (fi < fend) s_rows[wid][f] = *reinterpret_cast<const float4*>(pair_grad + fi);
+    const uint32_t nchunk = (P + kChunkRows - 1) / kChunkRows;
+    const size_t fend = (size_t)P * kRowF;
+    // chunks, grid-stride (the grid does not grow with the pair capacity)
+    for (uint32_t c = (blockIdx.x * kThreads + threadIdx.x) >> 6; c < nchunk; c += (gridDim.x * kThreads) >> 6) {
+        const uint32_t r0 = c * kChunkRows;
+        // stage the chunk: float4 f belongs to lane f / 10, part f % 10
+        for (uint32_t f = lane; f < 64u * (kLaneF4 - 1); f += 64u) {
+            const size_t fi = (size_t)r0 * kRowF + 4u * (size_t)f;
+            if (fi < fend)
+                s_rows[wid][(f / (kLaneF4 - 1)) * kLaneF4 + f % (kLaneF4 - 1)] =
+                    *reinterpret_cast<const float4*>(pair_grad + fi);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    const bool valid = e < P;
-    const uint32_t seg = valid ? emit_vg[e] : 0xffffffffu;
-    uint32_t prev = __shfl_up(seg, 1, 64);
-    if (lane == 0) prev = e > 0 ? emit_vg[e - 1] : 0xfffffffeu;
-    uint32_t next = __shfl_down(seg, 1, 64);
-    if (lane == 63) next = (e + 1 < P) ? emit_vg[e + 1] : 0xfffffffeu;
-    float v[kG2];
+        // this lane's rows and owners
+        const uint32_t e0 = r0 + lane * kRowsPerLane;
+        float rw[kRowsPerLane * kRowF];
 #pragma unroll
-    for (int k = 0; k < kG2; ++k) v[k] = 0.f;
-    if (valid) {
-        const float* row = reinterpret_cast<const float*>(s_rows[wid]) + kRowF * lane;
-        if (__float_as_uint(row[kG2]) == st) {
-#pragma unroll
-            for (int k = 0; k < kG2; ++k) v[k] = row[k];
+        for (uint32_t q = 0; q < kLaneF4 - 1; ++q) {
+            const float4 x = s_rows[wid][lane * kLaneF4 + q];
+            rw[4 * q] = x.x; rw[4 * q + 1] = x.y; rw[4 * q + 2] = x.z; rw[4 * q + 3] = x.w;
         }
-    }
+        uint32_t sg[kRowsPerLane];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t su = __shfl_up(seg, d, 64);
-        const bool same = lane >= (uint32_t)d && su == seg;    // segments are contiguous
+        for (uint32_t r = 0; r < kRowsPerLane; ++r) sg[r] = e0 + r < P ? emit_vg[e0 + r] : kNoSeg;
+        // lane-local segments: A = first segment's partial, B = last segment's partial
+        float A[kG2], B[kG2];
+        uint32_t s0 = sg[0], sl = sg[0], nseg = 1;
 #pragma unroll
-        for (int k = 0; k < kG2; ++k) {
-            const float y = __shfl_up(v[k], d, 64);
-            v[k] += same ? y : 0.f;
+        for (int k = 0; k < kG2; ++k) B[k] = (sg[0] != kNoSeg && __float_as_uint(rw[kG2]) == st) ? rw[k] : 0.f;
+#pragma unroll
+        for (uint32_t r = 1; r < kRowsPerLane; ++r) {
+            if (sg[r] == kNoSeg) break;
+            const float* row = rw + r * kRowF;
+            const bool live = __float_as_uint(row[kG2]) == st;
+            if (sg[r] != sl) {                                   // segment sl ends inside this lane
+                if (nseg == 1) {
+#pragma unroll
+                    for (int k = 0; k < kG2; ++k) A[k] = B[k];
+                } else {
+                    store9(grad2d + (size_t)kG2 * sl, B);        // started and ended in this lane
+                }
+                sl = sg[r];
+                ++nseg;
+#pragma unroll
+                for (int k = 0; k < kG2; ++k) B[k] = live ? row[k] : 0.f;
+            } else if (live) {
+                add9(B, row);
+            }
         }
-    }
-    const uint32_t first_seg = __shfl(seg, 0, 64);
-    const bool crosses_in = __shfl(prev, 0, 64) == first_seg;  // first segment began in an earlier wavefront
-    const bool from_before = crosses_in && seg == first_seg;
-    const bool ends_here = valid && next != seg;
-    const bool last_valid = valid && (lane == 63 || e + 1 >= P);
-    if (ends_here && !from_before) {
-        float* dst = grad2d + (size_t)kG2 * seg;
+        if (nseg == 1) {
 #pragma unroll
-        for (int k = 0; k < kG2; ++k) dst[k] = v[k];
-    }
-    SegCarry* c = carry + w;
-    if (ends_here && from_before) {
+            for (int k = 0; k < kG2; ++k) A[k] = B[k];
+        }
+        // C = segmented inclusive sum of B over lanes, keyed by the last segment
+        float C[kG2];
 #pragma unroll
-        for (int k = 0; k < kG2; ++k) c->head[k] = v[k];
-    }
-    if (last_valid) {
-        const bool crosses_out = !ends_here;
+        for (int k = 0; k < kG2; ++k) C[k] = B[k];
 #pragma unroll
-        for (int k = 0; k < kG2; ++k) c->tail[k] = crosses_out ? v[k] : 0.f;
-        c->first_seg = first_seg;
-        c->last_seg = seg;
-        c->flags = (crosses_in ? 1u : 0u) | (crosses_out ? 2u : 0u);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");     // the rows are read before the next chunk lands
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t su = __shfl_up(sl, d, 64);
+            const bool same = lane >= (uint32_t)d && su == sl && sl != kNoSeg;   // segments are contiguous
+#pragma unroll
+            for (int k = 0; k < kG2; ++k) {
+                const float y = __shfl_up(C[k], d, 64);
+                C[k] += same ? y : 0.f;
+            }
+        }
+        // the chunk's neighbours: the row before it and the row after it
+        const uint32_t sfirst = __shfl(s0, 0, 64);
+        const bool crosses_in = r0 > 0 && emit_vg[r0 - 1] == sfirst;
+        const uint32_t after = r0 + kChunkRows < P ? emit_vg[r0 + kChunkRows] : kNoSeg;
+        uint32_t nxt = __shfl_down(s0, 1, 64);
+        if (lane == 63) nxt = after;
+        const uint32_t prv_sl = __shfl_up(sl, 1, 64);
+        float prvC[kG2];
+#pragma unroll
+        for (int k = 0; k < kG2; ++k) prvC[k] = __shfl_up(C[k], 1, 64);
+        const bool valid = s0 != kNoSeg;
+        SegCarry* cr = carry + c;
+        if (valid && nseg >= 2) {                                // first segment ends in this lane
+            if (lane > 0 && prv_sl == s0) add9(A, prvC);          // ... and began in an earlier lane
+            if (crosses_in && s0 == sfirst) store9(cr->head, A);
+            else store9(grad2d + (size_t)kG2 * s0, A);
+        }
+        if (valid && nxt != sl) {                                // last segment ends in this lane
+            if (crosses_in && sl == sfirst) store9(cr->head, C);
+            else store9(grad2d + (size_t)kG2 * sl, C);
+        }
+        // the chunk's last valid lane (the next lane holds no rows, or lane 63) records the chunk
+        if (valid && (lane == 63 || nxt == kNoSeg)) {
+            const bool crosses_out = lane == 63 && after == sl;
+#pragma unroll
+            for (int k = 0; k < kG2; ++k) cr->tail[k] = crosses_out ? C[k] : 0.f;
+            cr->first_seg = sfirst;
+            cr->last_seg = sl;
+            cr->flags = (crosses_in ? 1u : 0u) | (crosses_out ? 2u : 0u);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // rows read before the next chunk lands
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
-// one thread per wavefront: a segment that starts in wavefront w and continues
-// past it is summed here over the following wavefronts, in order
+// one thread per chunk: a segment that starts in chunk w and continues past it
+// is summed here over the following chunks, in order
 __global__ __launch_bounds__(kThreads) void seg_fixup_kernel(const SegCarry* carry, const uint32_t* total,
                                                              uint32_t cap, float* grad2d)
 {
     const uint32_t P = *total < cap ? *total : cap;
-    const uint32_t nw = (P + 63u) / 64u;
+    const uint32_t nw = (P + kChunkRows - 1) / kChunkRows;
     for (uint32_t w = blockIdx.x * kThreads + threadIdx.x; w < nw; w += gridDim.x * kThreads) {
     const SegCarry& c = carry[w];
     if (!(c.flags & 2u)) continue;                               // nothing continues past w
@@ -507,16 +563,6 @@ __global__ __launch_bounds__(kThreads) void seg_fixup_kernel(const SegCarry* car
     }
 }
 
-__global__ void tile_len_keys_kernel(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals)
-{
-    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tiles) return;
-    const uint2 r = ranges[t];
-    const uint32_t len = r.y > r.x ? r.y - r.x : 0u;
-    const uint32_t b = (len + 7u) / 8u;
-    keys[t] = 255u - (b < 255u ? b : 255u);
-    vals[t] = t;
-}
 
 __global__ void iota_u32_kernel(uint32_t* p, uint32_t count)
 {
@@ -612,17 +658,16 @@ hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, cons
     return hipGetLastError();
 }
 
-size_t seg_carry_bytes(uint32_t cap) { return ((size_t)cap + 63) / 64 * sizeof(SegCarry) + sizeof(SegCarry); }
+size_t seg_carry_bytes(uint32_t cap) { return ((size_t)cap + kChunkRows - 1) / kChunkRows * sizeof(SegCarry) + sizeof(SegCarry); }
 
 hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* stamp, const uint32_t* emit_vg, uint32_t vn,
                               const uint32_t* total, uint32_t cap, float* grad2d, void* carry, hipStream_t s)
 {
     (void)vn;
     if (cap == 0) return hipSuccess;
-    const uint32_t nw = (cap + 63) / 64;
+    const uint32_t nw = (cap + kChunkRows - 1) / kChunkRows;
     hipLaunchKernelGGL(seg_reduce_kernel, dim3(grid_cap((nw * 64 + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
-                       pair_grad,
-                       stamp, emit_vg, total, cap, grad2d, reinterpret_cast<SegCarry*>(carry));
+                       pair_grad, stamp, emit_vg, total, cap, grad2d, reinterpret_cast<SegCarry*>(carry));
     hipLaunchKernelGGL(seg_fixup_kernel, dim3(grid_cap((nw + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
                        reinterpret_cast<const SegCarry*>(carry), total, cap, grad2d);
     return hipGetLastError();
@@ -635,12 +680,6 @@ hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_tile_len_keys(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s)
-{
-    if (n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(tile_len_keys_kernel, dim3((n_tiles + 255) / 256), dim3(256), 0, s, ranges, n_tiles, keys, vals);
-    return hipGetLastError();
-}
 
 hipError_t launch_bump_u32(uint32_t* p, hipStream_t s)
 {

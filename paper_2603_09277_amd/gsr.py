@@ -69,7 +69,7 @@ class Grads(ctypes.Structure):
 
 
 EXPORTED = ["gsr_status_string", "gsr_last_error", "gsr_create", "gsr_destroy", "gsr_pixel_offsets",
-            "gsr_forward", "gsr_backward", "gsr_stats", "gsr_autotune", "gsr_inspect", "gsr_set_timing",
+            "gsr_forward", "gsr_render", "gsr_backward", "gsr_stats", "gsr_autotune", "gsr_inspect", "gsr_set_timing",
             "gsr_stage_times", "gsr_l1_loss"]
 
 _lib = None
@@ -93,6 +93,7 @@ def lib():
         L.gsr_pixel_offsets.argtypes = [P, i32, P]
         L.gsr_forward.argtypes = [P, P, ctypes.POINTER(Gaussians), P, i32, ctypes.POINTER(Opts),
                                   ctypes.POINTER(FwdOut)]
+        L.gsr_render.argtypes = [P, P, ctypes.POINTER(Gaussians), P, i32, ctypes.POINTER(Opts), P]
         L.gsr_backward.argtypes = [P, P, ctypes.POINTER(Gaussians), P, i32, ctypes.POINTER(Opts),
                                    ctypes.POINTER(FwdOut), P, P, P, ctypes.POINTER(Grads)]
         L.gsr_stats.argtypes = [P, P, P, ctypes.POINTER(FrameStats)]
@@ -210,6 +211,22 @@ class Rasterizer:
         self.last_frame = fo.frame_id
         return out
 
+    def render_image(self, means, scales, quats, opacities, sh, cams, opts: RasterOptions,
+                     rgb: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Test-time render (colour only, no entropy, no saved state) into rgb [P, 3]."""
+        g = _gaussians(means, scales, quats, opacities, sh, opts)
+        carr = make_cameras(cams)
+        npix = sum(int(c.width) * int(c.height) for c in cams)
+        if rgb is None or rgb.shape != (npix, 3):
+            rgb = torch.empty((npix, 3), device=means.device, dtype=torch.float32)
+        elif rgb.dtype != torch.float32 or not rgb.is_contiguous():
+            raise ValueError("rgb must be a contiguous float32 tensor of shape [P, 3]")
+        o = opts.c()
+        _check(self._ctx, lib().gsr_render(self._ctx, _stream(), ctypes.byref(g), carr, len(cams), ctypes.byref(o),
+                                           ctypes.c_void_p(rgb.data_ptr())))
+        self.last_frame = None
+        return rgb
+
     def backward(self, means, scales, quats, opacities, sh, cams, opts: RasterOptions, saved: dict,
                  grad_rgb, grad_entropy=None, grad_entropy_mean=None, grads: Optional[dict] = None):
         g = _gaussians(means, scales, quats, opacities, sh, opts)
@@ -281,7 +298,7 @@ class Rasterizer:
         o = opts.c()
         _check(self._ctx, lib().gsr_autotune(self._ctx, _stream(), ctypes.byref(g), carr, len(cams), ctypes.byref(o),
                                              cache_path.encode() if cache_path else None))
-        return dataclasses.replace(opts, tile=(o.tile_w, o.tile_h), lds_batch=o.lds_batch)
+        return dataclasses.replace(opts, tile=(o.tile_w, o.tile_h), lds_batch=o.lds_batch, flags=o.flags)
 
 
 class RasterizeEntropy(torch.autograd.Function):

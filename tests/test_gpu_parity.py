@@ -635,8 +635,48 @@ def test_autotune_picks_a_valid_shape(R, tiny, tmp_path):
     cache = str(tmp_path / "tune.txt")
     best = R.autotune(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, cache)
     assert best.tile in [(8, 8), (16, 16), (32, 8)] and best.lds_batch in (32, 64, 128, 256)
+    # only the scheduling bit of the flags may change
+    assert best.flags & ~gsr.GSR_PERSISTENT == opts.flags & ~gsr.GSR_PERSISTENT
     again = R.autotune(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, cache)
     assert again == best
+    # the tuned options render
+    gpu_forward(R, t, cams, best)
+
+
+@pytest.mark.parametrize("tile,lds,persist", [((16, 16), 64, False), ((8, 8), 32, False), ((32, 8), 128, True)])
+def test_render_only_matches_forward(R, tiny, tile, lds, persist):
+    """gsr_render: the forward's colour bit for bit, the same work counts; it replaces the
+    frame (a backward of the earlier forward is stale); graph mode is refused."""
+    scene, cams = tiny
+    t = to_dev(scene)
+    flags = gsr.GSR_DEFAULT_FLAGS | (gsr.GSR_PERSISTENT if persist else 0)
+    opts = gsr.RasterOptions(tile=tile, lds_batch=lds, sh_degree=0, flags=flags)
+    out = gpu_forward(R, t, cams, opts)
+    st_f = R.stats(1)
+    rgb = R.render_image(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, out["rgb"])
+    st_r = R.stats(1)
+    for k in ("pairs", "evals_fwd", "evals_bwd", "blended"):
+        assert st_r[k] == st_f[k], k
+    g_rgb = l1_grad_torch(out["rgb"], scenes.target_image(101, 128, 128))
+    with pytest.raises(gsr.GsrError) as ei:
+        R.backward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, out, g_rgb, None, None)
+    assert ei.value.status == 5                                  # GSR_ERR_STALE_FRAME
+    with pytest.raises(gsr.GsrError) as ei:
+        R.render_image(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams,
+                       gsr.RasterOptions(tile=tile, lds_batch=lds, sh_degree=0, flags=flags | gsr.GSR_GRAPH))
+    assert ei.value.status == 2                                  # GSR_ERR_UNSUPPORTED
+
+
+def test_render_only_single_view_full_size(R):
+    scene, cams, _ = scenes.workload("single")
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(16, 16), lds_batch=128, sh_degree=3)
+    out = gpu_forward(R, t, cams, opts)
+    rgb = R.render_image(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, out["rgb"])
 
 
 def test_l1_loss_entry_point(R):

@@ -18,6 +18,9 @@
  *   - dH/dalpha via the suffix variable R                     (Sec. 3.4, Eq. 13-15,
  *                                                              Alg. 1; Suppl. B)
  *   - attribute chain opacity / exponent / conic / 2D mean    (Suppl. C)
+ *   - scale reset s <- zeta s                                 (Sec. 3.2, Eq. 7)
+ *   - the opacity regulariser compared against the entropy
+ *     constraint, exp(-(sigma - 0.5)^2 / 0.05) per Gaussian   (Sec. 4, ablation)
  * Conventions the paper leaves open (dilation 0.3, Jacobian clamp 1.3,
  * near plane, alpha clamp 0.99, 1/255 skip, 1e-4 transmittance stop, SH
  * basis without the Condon-Shortley phase, colour offset 0.5 and clamp,
@@ -746,4 +749,27 @@ int orc_backward_project(int64_t n, const float* means, const float* scales, con
         for (int a = 0; a < 3; ++a) g_means[3 * i + a] += gmu[a];
     }
     return 0;
+}
+
+/* Opacity regulariser of the ablation in Sec. 4: L_O = w / n * sum_i
+ * exp(-(sigma_i - 0.5)^2 / 0.05).  Adds dL_O/dsigma_i to grad (may be NULL)
+ * and returns L_O. */
+double orc_opacity_loss(int64_t n, const float* opac, double w, double* grad)
+{
+    if (n <= 0) return 0.0;
+    double sum = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = (double)opac[i] - 0.5;
+        double e = exp(-d * d / 0.05);
+        sum += e;
+        if (grad) grad[i] += w / (double)n * e * (-2.0 * d / 0.05);
+    }
+    return w * sum / (double)n;
+}
+
+/* Scale reset (Sec. 3.2, Eq. 7): every scale multiplied by zeta, the product
+ * rounded once to float32. */
+void orc_scale_reset(int64_t n, float* scales, double zeta)
+{
+    for (int64_t i = 0; i < 3 * n; ++i) scales[i] = (float)((double)scales[i] * zeta);
 }

@@ -58,6 +58,9 @@ def lib():
             getattr(L, f).argtypes = [i32, P, P]
         L.orc_entropy_of_alphas.argtypes = [i32, P]
         L.orc_entropy_of_alphas.restype = dbl
+        L.orc_opacity_loss.argtypes = [i64, P, dbl, P]
+        L.orc_opacity_loss.restype = dbl
+        L.orc_scale_reset.argtypes = [i64, P, dbl]
         _lib = L
     return _lib
 
@@ -99,6 +102,47 @@ def project(scene, cam, flags: int = DEFAULT_FLAGS) -> Dict[str, np.ndarray]:
     out["opacity"] = scene.opacities.astype(np.float64)
     out["depth32"] = out["depth"].astype(np.float32)
     return out
+
+
+def opacity_loss(opacities, weight):
+    """(L_O, dL_O/dsigma) of the opacity regulariser, FP64."""
+    op = _f32(opacities)
+    g = np.zeros(len(op))
+    L = lib().orc_opacity_loss(len(op), _p(op), float(weight), _p(g))
+    return float(L), g
+
+
+def scale_reset(scales, zeta):
+    """s <- zeta * s (Eq. 7), float32 result."""
+    s = np.array(scales, np.float32, copy=True, order="C")
+    lib().orc_scale_reset(len(s), _p(s), float(zeta))
+    return s
+
+
+def scaled_camera(cam, r):
+    """The camera at downsampling factor r: width and height divided by r and rounded
+    down (at least 1), intrinsics divided by r, pose unchanged."""
+    from paper_2603_09277_amd.scenes import Camera
+    r = max(1, int(r))
+    f32 = lambda x: float(np.float32(np.float32(x) / np.float32(r)))
+    return Camera(max(1, cam.width // r), max(1, cam.height // r), f32(cam.fx), f32(cam.fy), f32(cam.cx),
+                  f32(cam.cy), np.asarray(cam.R, np.float32), np.asarray(cam.t, np.float32), cam.near)
+
+
+def select_rmax(scene, cam, tile=(16, 16), r_cap=4, max_mean_len=150.0, flags: int = DEFAULT_FLAGS):
+    """Resolution-scheduler r_max: the largest r <= r_cap whose scaled camera keeps the mean
+    per-tile list length (pairs / tiles) <= max_mean_len, else 1; also the pair counts."""
+    tw, th = tile
+    best, counts = 1, []
+    for r in range(1, r_cap + 1):
+        k = scaled_camera(cam, r)
+        pr = project(scene, k, flags)
+        total, _, _ = count_pairs(pr["mean2d"], pr["radius"], k.width, k.height, tw, th)
+        tiles = ((k.width + tw - 1) // tw) * ((k.height + th - 1) // th)
+        counts.append(total)
+        if total / tiles <= max_mean_len:
+            best = r
+    return best, counts
 
 
 def count_pairs(mean2d, radius, W, H, tw, th):

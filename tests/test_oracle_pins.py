@@ -517,3 +517,69 @@ def test_render_backward_matches_fd_on_records(orc):
                 assert abs(an - fd) <= 1e-5 * abs(fd) + 1e-6 * np.abs(g[key]).max() + 1e-9, (key, gi, j, an, fd)
                 checked += 1
     assert checked > 100
+
+
+# --------------------------------------------------------------------------- #
+# the survey's next rows: opacity regulariser, scale reset, r_max policy
+# --------------------------------------------------------------------------- #
+
+def test_opacity_loss_closed_forms_and_fd(orc):
+    """L_O = w/n sum exp(-(s - 0.5)^2 / 0.05): 1 at s = 0.5 with zero slope, exp(-5) at
+    s = 0 and 1 (slopes +-20 exp(-5)), and central differences elsewhere."""
+    L, g = orc.opacity_loss(np.array([0.5, 0.0, 1.0], np.float32), 3.0)
+    assert L == pytest.approx(3.0 * (1 + 2 * math.exp(-5.0)) / 3, rel=1e-15)
+    assert g[0] == 0.0
+    assert g[1] == pytest.approx(3.0 / 3 * math.exp(-5.0) * 20.0, rel=1e-14)
+    assert g[2] == pytest.approx(-3.0 / 3 * math.exp(-5.0) * 20.0, rel=1e-14)
+    rng = np.random.default_rng(9)
+    op = rng.uniform(0.0, 1.0, 50).astype(np.float32)
+    w = 1.7
+    _, g = orc.opacity_loss(op, w)
+    for i in range(0, 50, 7):
+        h = 1e-5
+        opp, opm = op.astype(np.float64).copy(), op.astype(np.float64).copy()
+        opp[i] += h
+        opm[i] -= h
+        f = lambda x: w * np.mean(np.exp(-(x - 0.5) ** 2 / 0.05))
+        assert g[i] == pytest.approx((f(opp) - f(opm)) / (2 * h), rel=1e-6, abs=1e-10)
+
+
+def test_scale_reset_is_one_rounded_product(orc):
+    rng = np.random.default_rng(10)
+    s = np.exp(rng.normal(-4, 0.7, (100, 3))).astype(np.float32)
+    out = orc.scale_reset(s, 0.2)
+    ref = (s.astype(np.float64) * 0.2).astype(np.float32)
+    assert out.dtype == np.float32 and np.array_equal(out, ref)
+    assert np.array_equal(orc.scale_reset(s, 1.0), s)
+
+
+def test_rmax_policy_against_brute_force_counts(orc):
+    """The r_max rule on brute-force pair counts (interval overlap per Gaussian): the largest
+    r <= 4 whose mean per-tile list length stays within the threshold."""
+    scene = scenes.gmm_scene(11, 3000)
+    cam = scenes.orbit_cameras(np.random.default_rng(12), [(320, 200)])[0]
+    r, counts = orc.select_rmax(scene, cam, (16, 16), 4, 40.0)
+    brute = []
+    for rr in range(1, 5):
+        k = orc.scaled_camera(cam, rr)
+        assert k.width == 320 // rr and k.height == 200 // rr
+        assert k.fx == np.float32(np.float32(cam.fx) / np.float32(rr))
+        pr = orc.project(scene, k)
+        gx, gy = (k.width + 15) // 16, (k.height + 15) // 16
+        # every (Gaussian, tile) whose pixel square [floor(mean) - r, floor(mean) + r]^2 meets the tile
+        tx = np.arange(gx) * 16
+        ty = np.arange(gy) * 16
+        tot = 0
+        for (mx, my), rad in zip(pr["mean2d"], pr["radius"]):
+            if rad <= 0:
+                continue
+            fx, fy = np.floor(mx), np.floor(my)
+            ox = (tx <= fx + rad) & (tx + 15 >= fx - rad)
+            oy = (ty <= fy + rad) & (ty + 15 >= fy - rad)
+            tot += int(ox.sum()) * int(oy.sum())
+        brute.append(tot)
+    assert counts == brute
+    means = [c / (((320 // rr + 15) // 16) * ((200 // rr + 15) // 16)) for rr, c in zip(range(1, 5), counts)]
+    ok = [rr for rr, m in zip(range(1, 5), means) if m <= 40.0]
+    assert r == (max(ok) if ok else 1)
+    assert means[3] > means[0]                   # coarser resolution, longer lists

@@ -113,9 +113,10 @@ def opacity_loss(opacities, weight):
 
 
 def scale_reset(scales, zeta):
-    """s <- zeta * s (Eq. 7), float32 result."""
+    """s <- zeta * s (Eq. 7) with zeta a float32 value (as every parameter at the
+    library's boundary), float32 result."""
     s = np.array(scales, np.float32, copy=True, order="C")
-    lib().orc_scale_reset(len(s), _p(s), float(zeta))
+    lib().orc_scale_reset(len(s), _p(s), float(np.float32(zeta)))
     return s
 
 

@@ -548,7 +548,7 @@ def test_scale_reset_is_one_rounded_product(orc):
     rng = np.random.default_rng(10)
     s = np.exp(rng.normal(-4, 0.7, (100, 3))).astype(np.float32)
     out = orc.scale_reset(s, 0.2)
-    ref = (s.astype(np.float64) * 0.2).astype(np.float32)
+    ref = (s.astype(np.float64) * float(np.float32(0.2))).astype(np.float32)
     assert out.dtype == np.float32 and np.array_equal(out, ref)
     assert np.array_equal(orc.scale_reset(s, 1.0), s)
 

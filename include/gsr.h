@@ -181,6 +181,39 @@ gsr_status gsr_backward(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, cons
 gsr_status gsr_l1_loss(gsr_ctx* ctx, void* stream, const gsr_camera* cams, int32_t n_views, const float* rgb,
                        const float* target, float* grad_rgb, float* loss);
 
+/* Opacity regulariser, the comparator of the entropy constraint in the
+ * ablation of Sec. 4 (opacity vs entropy constraint): with sigma the
+ * activated opacities (device, n floats),
+ *   L_O = weight / n * sum_i exp(-(sigma_i - 0.5)^2 / 0.05),
+ * grad_opacities[i] += dL_O/dsigma_i (device, accumulated, may be NULL) and
+ * *loss = L_O (device float, may be NULL).  Deterministic; asynchronous. */
+gsr_status gsr_opacity_loss(gsr_ctx* ctx, void* stream, const float* opacities, int64_t n, float weight,
+                            float* grad_opacities, float* loss);
+
+/* Scale reset (Sec. 3.2, Eq. 7): scales[i][k] <- zeta * scales[i][k] in place
+ * (device, n x 3 floats, zeta > 0).  Asynchronous. */
+gsr_status gsr_scale_reset(gsr_ctx* ctx, void* stream, float* scales, int64_t n, float zeta);
+
+/* (tile, Gaussian) pair count of each view (host, n_views int64): the
+ * projection and the tile count of the forward, no sort or blend.  Replaces
+ * the context's frame; synchronises `stream`. */
+gsr_status gsr_pair_counts(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
+                           int32_t n_views, const gsr_opts* opts, int64_t* pairs_per_view);
+
+/* The camera at downsampling factor r >= 1 (resolution scheduler, Sec. 4
+ * Implementation Details): width / r and height / r rounded down (at least 1),
+ * fx, fy, cx, cy divided by r; pose and near plane unchanged. */
+gsr_camera gsr_scaled_camera(const gsr_camera* cam, int32_t r);
+
+/* r_max of the resolution scheduler (Sec. 4 Implementation Details): the
+ * largest r in [1, r_cap] whose scaled camera keeps the mean per-tile list
+ * length (pairs / tiles) at or below max_mean_len (the paper: about 150, with
+ * r capped at 4); 1 if none does.  mean_len (host, r_cap doubles, may be NULL)
+ * receives the mean for every r.  Replaces the context's frame; synchronises. */
+gsr_status gsr_select_rmax(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cam,
+                           const gsr_opts* opts, int32_t r_cap, double max_mean_len, int32_t* r_out,
+                           double* mean_len);
+
 /* Statistics of the latest forward. */
 typedef struct {
     int64_t pairs;             /* (tile, Gaussian) pairs over all views */

@@ -53,7 +53,7 @@ struct gsr_ctx {
 
     // grow-only device buffers
     Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, tt_s, rect_s, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
-    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, queues, block_H, block_cnt, hchunk, counters, l1_tmp;
+    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, queues, block_H, block_cnt, hchunk, counters, l1_tmp, reg_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
     uint64_t gen_fwd = 0, gen_bwd = 0;
@@ -65,6 +65,7 @@ struct gsr_ctx {
     // latest forward
     int64_t frame = 0;
     bool have_frame = false;
+    bool have_records = false;             // the per-record buffers hold the latest projection
     Layout lay;
     uint32_t vn = 0, n = 0, pairs = 0;
     int sorted_buf = 0;                    // which pair buffer holds the sorted lists
@@ -539,7 +540,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     drop_graphs(c);
     Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->tt_s, &c->rect_s, &c->radius,
                    &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
-                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->queues, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters,
+                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->queues, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->reg_tmp,
                    &c->l1_tmp };
     for (Dev* d : all) free_dev(*d);
     for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
@@ -635,6 +636,7 @@ gsr_status gsr_forward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const g
     }
     c->frame += 1;
     c->have_frame = true;
+    c->have_records = true;
     out->frame_id = c->frame;
     return GSR_OK;
 }
@@ -667,6 +669,7 @@ gsr_status gsr_render(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gs
     // a render saves no state: no backward may follow it
     c->frame += 1;
     c->have_frame = true;
+    c->have_records = true;
     return GSR_OK;
 }
 
@@ -775,6 +778,113 @@ gsr_status gsr_stats(gsr_ctx* c, void* stream, int64_t* pairs_per_view, gsr_fram
     return GSR_OK;
 }
 
+gsr_status gsr_opacity_loss(gsr_ctx* c, void* stream, const float* opacities, int64_t n, float weight,
+                            float* grad_opacities, float* loss)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    if (n < 0 || (n > 0 && !opacities)) return fail(c, GSR_ERR_INVALID_ARG, "opacity loss: bad opacities or n");
+    if (!std::isfinite(weight)) return fail(c, GSR_ERR_INVALID_ARG, "opacity loss: weight not finite");
+    if (n == 0) return GSR_OK;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    gsr_status s = grow(c, c->reg_tmp, opacity_reg_tmp_words(n) * 8);
+    if (s) return s;
+    HIP_TRY(c, launch_opacity_reg(opacities, n, weight, grad_opacities, loss, (double*)c->reg_tmp.p, st));
+    return GSR_OK;
+}
+
+gsr_status gsr_scale_reset(gsr_ctx* c, void* stream, float* scales, int64_t n, float zeta)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    if (n < 0 || (n > 0 && !scales)) return fail(c, GSR_ERR_INVALID_ARG, "scale reset: bad scales or n");
+    if (!(std::isfinite(zeta) && zeta > 0.f)) return fail(c, GSR_ERR_INVALID_ARG, "scale reset: zeta must be > 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, launch_scale_reset(scales, 3 * n, zeta, (hipStream_t)stream));
+    return GSR_OK;
+}
+
+// projection and the per-view pair count only (no sort, no blend); leaves no frame
+static gsr_status count_pairs(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, const gsr_camera* cams,
+                              int32_t n_views, const gsr_opts* o, int64_t* pairs_per_view)
+{
+    gsr_status s = validate(c, g, cams, n_views, o);
+    if (s) return s;
+    if ((s = wait_replay(c))) return s;
+    Layout L = make_layout(cams, n_views, o);
+    const uint32_t n = (uint32_t)g->n, vn = n * (uint32_t)n_views;
+    if ((s = ensure_vn(c, vn)) || (s = ensure_tiles(c, L.n_tiles, L.n_blocks))) return s;
+    c->lay = L;
+    c->n = n;
+    c->vn = vn;
+    c->n_views = n_views;
+    c->have_frame = false;
+    c->have_records = true;
+    c->frame += 1;
+    HIP_TRY(c, hipMemcpyAsync(c->cams.p, c->lay.cams.data(), sizeof(CamDev) * L.cams.size(), hipMemcpyHostToDevice, st));
+    ProjectFwdArgs pa;
+    pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
+    pa.n = n; pa.n_views = n_views; pa.flags = o->flags; pa.tile_shift_x = L.tsx; pa.tile_shift_y = L.tsy;
+    pa.cams = (const CamDev*)c->cams.p;
+    pa.rec = (float4*)c->rec.p; pa.depth_key = (uint32_t*)c->dkey0.p; pa.rect = (uint2*)c->rect.p;
+    pa.tiles_touched = (uint32_t*)c->tt.p; pa.radius = (int32_t*)c->radius.p; pa.depth = (float*)c->depth.p;
+    HIP_TRY(c, launch_project_fwd(pa, o->sh_degree, o->sh_dtype == 1, st));
+    uint32_t* counters = (uint32_t*)c->counters.p;
+    for (int v = 0; v < n_views; ++v) {             // one scan per view: its pair count
+        HIP_TRY(c, launch_fill_u32(counters, 0u, 2, st));
+        HIP_TRY(c, launch_iota_u32((uint32_t*)c->ord0.p, n, st));
+        HIP_TRY(c, launch_gather_scan((const uint32_t*)c->tt.p + (size_t)v * n, (const uint2*)c->rect.p + (size_t)v * n,
+                                      (const uint32_t*)c->ord0.p, n, (uint32_t*)c->offsets.p, (uint32_t*)c->tt_s.p,
+                                      (uint2*)c->rect_s.p, counters, counters + 1, (uint32_t*)c->scan_tmp.p, st));
+        HIP_TRY(c, hipMemcpyAsync(c->counters_host, counters, 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        if (c->counters_host[1]) return fail(c, GSR_ERR_CAPACITY, "pair count exceeds 2^32");
+        pairs_per_view[v] = (int64_t)c->counters_host[0];
+    }
+    return GSR_OK;
+}
+
+gsr_status gsr_pair_counts(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gsr_camera* cams, int32_t n_views,
+                           const gsr_opts* o, int64_t* pairs_per_view)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    if (!pairs_per_view) return fail(c, GSR_ERR_INVALID_ARG, "null pairs_per_view");
+    HIP_TRY(c, hipSetDevice(c->device));
+    return count_pairs(c, (hipStream_t)stream, g, cams, n_views, o, pairs_per_view);
+}
+
+gsr_camera gsr_scaled_camera(const gsr_camera* cam, int32_t r)
+{
+    gsr_camera k = *cam;
+    if (r < 1) r = 1;
+    k.width = cam->width / r > 0 ? cam->width / r : 1;
+    k.height = cam->height / r > 0 ? cam->height / r : 1;
+    k.fx = cam->fx / (float)r; k.fy = cam->fy / (float)r;
+    k.cx = cam->cx / (float)r; k.cy = cam->cy / (float)r;
+    return k;
+}
+
+gsr_status gsr_select_rmax(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gsr_camera* cam,
+                           const gsr_opts* o, int32_t r_cap, double max_mean_len, int32_t* r_out, double* mean_len)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    if (!cam || !r_out) return fail(c, GSR_ERR_INVALID_ARG, "null camera or r_out");
+    if (r_cap < 1 || r_cap > 64 || !(max_mean_len > 0.0)) return fail(c, GSR_ERR_INVALID_ARG, "bad r_cap or threshold");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int32_t best = 1;
+    for (int32_t r = 1; r <= r_cap; ++r) {
+        const gsr_camera k = gsr_scaled_camera(cam, r);
+        int64_t pairs = 0;
+        gsr_status s = count_pairs(c, (hipStream_t)stream, g, &k, 1, o, &pairs);
+        if (s) return s;
+        const double tiles = (double)((k.width + o->tile_w - 1) / o->tile_w) * ((k.height + o->tile_h - 1) / o->tile_h);
+        const double m = (double)pairs / tiles;
+        if (mean_len) mean_len[r - 1] = m;
+        if (m <= max_mean_len) best = r;
+    }
+    *r_out = best;
+    return GSR_OK;
+}
+
 gsr_status gsr_l1_loss(gsr_ctx* c, void* stream, const gsr_camera* cams, int32_t n_views, const float* rgb,
                        const float* target, float* grad_rgb, float* loss)
 {
@@ -827,7 +937,10 @@ gsr_status gsr_stage_times(gsr_ctx* c, double* total_ms, int64_t* launches, int3
 gsr_status gsr_inspect(gsr_ctx* c, void* stream, gsr_buffer which, void* dst, int64_t capacity_bytes, int64_t* bytes)
 {
     if (!c || !bytes) return GSR_ERR_INVALID_ARG;
-    if (!c->have_frame) return fail(c, GSR_ERR_INVALID_ARG, "no forward has run on this context");
+    const bool per_record = which == GSR_BUF_RECORDS || which == GSR_BUF_RADIUS || which == GSR_BUF_DEPTH ||
+                            which == GSR_BUF_TILES_TOUCHED;
+    if (!c->have_frame && !(per_record && c->have_records))
+        return fail(c, GSR_ERR_INVALID_ARG, "no forward has run on this context");
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
     if (c->pairs == 0) {

@@ -175,6 +175,13 @@ hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t 
 hipError_t launch_blend_fwd(const BlendFwdArgs& a, int lds_batch, hipStream_t s);
 hipError_t launch_blend_bwd(const BlendBwdArgs& a, int lds_batch, hipStream_t s);
 // n_l1_blocks = sum over views of ceil(W H / kL1Block); tmp holds n_l1_blocks doubles
+// L_O = w / n * sum exp(-(sigma - 0.5)^2 / 0.05); grad[i] += dL_O/dsigma_i (grad may be null);
+// *loss (device, may be null); tmp holds opacity_reg_tmp_words(n) doubles
+size_t opacity_reg_tmp_words(int64_t n);
+hipError_t launch_opacity_reg(const float* opac, int64_t n, float w, float* grad, float* loss, double* tmp,
+                              hipStream_t s);
+// s <- zeta * s in place over count floats
+hipError_t launch_scale_reset(float* scales, int64_t count, float zeta, hipStream_t s);
 hipError_t launch_l1(const float* rgb, const float* target, const CamDev* cams, int n_views, uint32_t n_l1_blocks,
                      float* grad, float* loss, double* tmp, hipStream_t s);
 // n_chunks = sum over views of ceil(blocks_v / kRedChunk); tmp holds n_chunks doubles

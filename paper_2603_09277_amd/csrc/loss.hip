@@ -63,7 +63,63 @@ __global__ __launch_bounds__(kL1Block) void l1_reduce_kernel(const double* block
     if (threadIdx.x == 0) loss[v] = (float)(tot / (3.0 * (double)((int64_t)c.W * c.H)));
 }
 
+// Opacity regulariser of the comparison in Sec. 4 (ablation, opacity vs entropy
+// constraint): L_O = w / n * sum_i exp(-(sigma_i - 0.5)^2 / 0.05), pushing
+// opacities toward 0 or 1.  dL_O/dsigma_i = w / n * e_i * (-2 (sigma_i - 0.5) / 0.05)
+// is added to grad[i].  Block partial sums in FP64, summed in a fixed order.
+__global__ __launch_bounds__(kL1Block) void opacity_reg_kernel(const float* opac, int64_t n, float w, float* grad,
+                                                               double* block_sum)
+{
+    const int64_t i = (int64_t)blockIdx.x * kL1Block + threadIdx.x;
+    double acc = 0.0;
+    if (i < n) {
+        const float d = opac[i] - 0.5f;
+        const float e = expf(-(d * d) * 20.0f);              // 1 / 0.05 = 20
+        if (grad) grad[i] += (w / (float)n) * e * (-40.0f * d);
+        acc = (double)e;
+    }
+    const double tot = block_sum_f64(acc);
+    if (threadIdx.x == 0) block_sum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kL1Block) void opacity_reg_reduce_kernel(const double* block_sum, uint32_t n_blocks,
+                                                                      int64_t n, float w, float* loss)
+{
+    double acc = 0.0;
+    for (uint32_t b = threadIdx.x; b < n_blocks; b += kL1Block) acc += block_sum[b];
+    const double tot = block_sum_f64(acc);
+    if (threadIdx.x == 0) *loss = (float)((double)w * tot / (double)n);
+}
+
+// Scale reset (Sec. 3.2, Eq. 7): s <- zeta * s for every scale component.
+__global__ void scale_reset_kernel(float* s, int64_t count, float zeta)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) s[i] = zeta * s[i];
+}
+
 }  // namespace
+
+size_t opacity_reg_tmp_words(int64_t n) { return (size_t)((n + kL1Block - 1) / kL1Block) + 1; }
+
+hipError_t launch_opacity_reg(const float* opac, int64_t n, float w, float* grad, float* loss, double* tmp,
+                              hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const uint32_t nb = (uint32_t)((n + kL1Block - 1) / kL1Block);
+    hipLaunchKernelGGL(opacity_reg_kernel, dim3(nb), dim3(kL1Block), 0, s, opac, n, w, grad, tmp);
+    if (loss) hipLaunchKernelGGL(opacity_reg_reduce_kernel, dim3(1), dim3(kL1Block), 0, s, tmp, nb, n, w, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_reset(float* scales, int64_t count, float zeta, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(scale_reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, scales, count, zeta);
+    return hipGetLastError();
+}
 
 hipError_t launch_l1(const float* rgb, const float* target, const CamDev* cams, int n_views, uint32_t n_l1_blocks,
                      float* grad, float* loss, double* tmp, hipStream_t s)

@@ -70,6 +70,7 @@ class Grads(ctypes.Structure):
 
 EXPORTED = ["gsr_status_string", "gsr_last_error", "gsr_create", "gsr_destroy", "gsr_pixel_offsets",
             "gsr_forward", "gsr_render", "gsr_backward", "gsr_stats", "gsr_autotune", "gsr_inspect", "gsr_set_timing",
+            "gsr_opacity_loss", "gsr_scale_reset", "gsr_pair_counts", "gsr_scaled_camera", "gsr_select_rmax",
             "gsr_stage_times", "gsr_l1_loss"]
 
 _lib = None
@@ -102,8 +103,15 @@ def lib():
         L.gsr_stage_times.argtypes = [P, P, P, i32]
         L.gsr_autotune.argtypes = [P, P, ctypes.POINTER(Gaussians), P, i32, ctypes.POINTER(Opts), ctypes.c_char_p]
         L.gsr_inspect.argtypes = [P, P, ctypes.c_int, P, i64, ctypes.POINTER(i64)]
+        L.gsr_opacity_loss.argtypes = [P, P, P, i64, ctypes.c_float, P, P]
+        L.gsr_scale_reset.argtypes = [P, P, P, i64, ctypes.c_float]
+        L.gsr_pair_counts.argtypes = [P, P, ctypes.POINTER(Gaussians), P, i32, ctypes.POINTER(Opts), P]
+        L.gsr_scaled_camera.argtypes = [ctypes.POINTER(Camera), i32]
+        L.gsr_scaled_camera.restype = Camera
+        L.gsr_select_rmax.argtypes = [P, P, ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), ctypes.POINTER(Opts),
+                                      i32, ctypes.c_double, ctypes.POINTER(i32), P]
         for f in EXPORTED:
-            if f not in ("gsr_status_string", "gsr_last_error"):
+            if f not in ("gsr_status_string", "gsr_last_error", "gsr_scaled_camera"):
                 getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -131,6 +139,14 @@ def make_cameras(cams: Sequence) -> ctypes.Array:
                         (ctypes.c_float * 9)(*R.tolist()), (ctypes.c_float * 3)(*t.tolist()),
                         float(getattr(c, "near", getattr(c, "near_z", 0.2))))
     return arr
+
+
+def scaled_camera(cam, r: int):
+    """The camera at downsampling factor r (gsr_scaled_camera), as a scenes.Camera."""
+    from . import scenes
+    k = lib().gsr_scaled_camera(ctypes.byref(make_cameras([cam])[0]), int(r))
+    return scenes.Camera(k.width, k.height, k.fx, k.fy, k.cx, k.cy, np.asarray(cam.R, np.float32),
+                         np.asarray(cam.t, np.float32), float(getattr(cam, "near", 0.2)))
 
 
 def pixel_offsets(cams: Sequence) -> List[int]:
@@ -226,6 +242,45 @@ class Rasterizer:
                                            ctypes.c_void_p(rgb.data_ptr())))
         self.last_frame = None
         return rgb
+
+    def opacity_loss(self, opacities: torch.Tensor, weight: float, grad: Optional[torch.Tensor] = None,
+                     loss: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """L_O = weight / n * sum exp(-(sigma - 0.5)^2 / 0.05) into `loss` (a 1-element tensor);
+        its gradient is added to `grad` when given."""
+        if opacities.dtype != torch.float32 or not opacities.is_contiguous() or opacities.dim() != 1:
+            raise ValueError("opacities must be a contiguous float32 vector")
+        if loss is None:
+            loss = torch.empty(1, device=opacities.device, dtype=torch.float32)
+        _check(self._ctx, lib().gsr_opacity_loss(self._ctx, _stream(), _ptr(opacities), opacities.shape[0],
+                                                 float(weight), _ptr(grad), _ptr(loss)))
+        return loss
+
+    def scale_reset(self, scales: torch.Tensor, zeta: float) -> None:
+        """s <- zeta * s in place (Eq. 7)."""
+        if scales.dtype != torch.float32 or not scales.is_contiguous() or scales.dim() != 2 or scales.shape[1] != 3:
+            raise ValueError("scales must be a contiguous float32 [n, 3] tensor")
+        _check(self._ctx, lib().gsr_scale_reset(self._ctx, _stream(), _ptr(scales), scales.shape[0], float(zeta)))
+
+    def pair_counts(self, means, scales, quats, opacities, sh, cams, opts: RasterOptions) -> List[int]:
+        g = _gaussians(means, scales, quats, opacities, sh, opts)
+        carr = make_cameras(cams)
+        out = (ctypes.c_int64 * len(cams))()
+        o = opts.c()
+        _check(self._ctx, lib().gsr_pair_counts(self._ctx, _stream(), ctypes.byref(g), carr, len(cams),
+                                                ctypes.byref(o), out))
+        return list(out)
+
+    def select_rmax(self, means, scales, quats, opacities, sh, cam, opts: RasterOptions, r_cap: int = 4,
+                    max_mean_len: float = 150.0):
+        """(r_max, [mean per-tile list length at r = 1 .. r_cap])."""
+        g = _gaussians(means, scales, quats, opacities, sh, opts)
+        carr = make_cameras([cam])
+        r = ctypes.c_int32(0)
+        ml = (ctypes.c_double * r_cap)()
+        o = opts.c()
+        _check(self._ctx, lib().gsr_select_rmax(self._ctx, _stream(), ctypes.byref(g), carr, ctypes.byref(o),
+                                                int(r_cap), float(max_mean_len), ctypes.byref(r), ml))
+        return int(r.value), list(ml)
 
     def backward(self, means, scales, quats, opacities, sh, cams, opts: RasterOptions, saved: dict,
                  grad_rgb, grad_entropy=None, grad_entropy_mean=None, grads: Optional[dict] = None):

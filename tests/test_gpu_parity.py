@@ -765,3 +765,61 @@ def test_persistent_graph_batched_vs_oracle(R):
         _cmp_image(out, img_o, cam, v, cams)
     assert not G.stats(len(cams))["overflow"]
     G.close()
+
+
+# --------------------------------------------------------------------------- #
+# next rows: opacity regulariser, scale reset, r_max policy
+# --------------------------------------------------------------------------- #
+
+def test_opacity_loss_vs_oracle(R):
+    rng = np.random.default_rng(31)
+    op = rng.uniform(0.0, 1.0, 100_003).astype(np.float32)
+    w = 3.0
+    L_o, g_o = orc.opacity_loss(op, w)
+    t = torch.from_numpy(op).to(DEV)
+    base = rng.normal(0, 1e-3, op.shape).astype(np.float32)
+    grad = torch.from_numpy(base).to(DEV)
+    loss = R.opacity_loss(t, w, grad)
+    loss2 = R.opacity_loss(t, w)                     # no gradient
+    torch.cuda.synchronize()
+    assert abs(float(loss.cpu()[0]) - L_o) <= 1e-6 * abs(L_o)
+    assert float(loss2.cpu()[0]) == float(loss.cpu()[0])   # fixed-order sum
+    got = grad.cpu().numpy().astype(np.float64) - base.astype(np.float64)
+    assert rel_norm(got, g_o) < 1e-5
+
+
+def test_scale_reset_bit_exact(R):
+    scene = scenes.gmm_scene(32, 50_000)
+    s = torch.from_numpy(scene.scales.copy()).to(DEV)
+    R.scale_reset(s, 0.2)
+    torch.cuda.synchronize()
+    assert np.array_equal(s.cpu().numpy(), orc.scale_reset(scene.scales, 0.2))
+
+
+def test_pair_counts_and_rmax_vs_oracle(R):
+    """Per-view pair counts equal the oracle's count on the GPU's records bit for bit,
+    and r_max follows the rule on them (and on the oracle's own FP64 projection)."""
+    scene = scenes.gmm_scene(11, 30_000)
+    t = to_dev(scene)
+    cam = scenes.orbit_cameras(np.random.default_rng(12), [(1296, 840)])[0]
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=3)
+    counts = []
+    for r in range(1, 5):
+        k = gsr.scaled_camera(cam, r)
+        ko = orc.scaled_camera(cam, r)
+        assert (k.width, k.height, k.fx, k.fy, k.cx, k.cy) == (ko.width, ko.height, ko.fx, ko.fy, ko.cx, ko.cy)
+        (p,) = R.pair_counts(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], [k], opts)
+        pg = gpu_records(R, scene.n, 1)[0]
+        total, _, _ = orc.count_pairs(pg["mean2d"], pg["radius"], k.width, k.height, 16, 16)
+        assert p == total
+        counts.append(p)
+    thr = float(np.median([c / (((1296 // r + 15) // 16) * ((840 // r + 15) // 16))
+                           for r, c in zip(range(1, 5), counts)]))
+    r_gpu, means = R.select_rmax(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cam, opts, 4, thr)
+    exp = [c / (((1296 // r + 15) // 16) * ((840 // r + 15) // 16)) for r, c in zip(range(1, 5), counts)]
+    assert np.allclose(means, exp, rtol=0, atol=0)
+    ok = [r for r, m in zip(range(1, 5), exp) if m <= thr]
+    assert r_gpu == (max(ok) if ok else 1)
+    r_o, counts_o = orc.select_rmax(scene, cam, (16, 16), 4, thr)
+    assert r_o == r_gpu
+    assert all(abs(a - b) <= 2e-4 * b for a, b in zip(counts, counts_o))

@@ -21,6 +21,7 @@
  *   - scale reset s <- zeta s                                 (Sec. 3.2, Eq. 7)
  *   - the opacity regulariser compared against the entropy
  *     constraint, exp(-(sigma - 0.5)^2 / 0.05) per Gaussian   (Sec. 4, ablation)
+ *   - D-SSIM of the base loss and one Adam step               (Sec. 3, Eq. 6)
  * Conventions the paper leaves open (dilation 0.3, Jacobian clamp 1.3,
  * near plane, alpha clamp 0.99, 1/255 skip, 1e-4 transmittance stop, SH
  * basis without the Condon-Shortley phase, colour offset 0.5 and clamp,
@@ -772,4 +773,101 @@ double orc_opacity_loss(int64_t n, const float* opac, double w, double* grad)
 void orc_scale_reset(int64_t n, float* scales, double zeta)
 {
     for (int64_t i = 0; i < 3 * n; ++i) scales[i] = (float)((double)scales[i] * zeta);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Training-step terms around the path                                        */
+/* ------------------------------------------------------------------------- */
+
+/* D-SSIM of the base loss (Sec. 3, Eq. 6), with the 3DGS-lineage SSIM the
+ * paper inherits: per channel, local statistics over an 11x11 Gaussian window
+ * (sigma 1.5, normalised), zero outside the image, C1 = 0.01^2, C2 = 0.03^2,
+ *   S = (2 mx my + C1)(2 sxy + C2) / ((mx^2 + my^2 + C1)(sx^2 + sy^2 + C2)),
+ * sx^2 = E[x^2] - mx^2, sxy = E[xy] - mx my; SSIM = mean of S over pixels and
+ * channels; L_D-SSIM = 1 - SSIM.  x, y: [H][W][3].  Returns SSIM; grad (may
+ * be NULL) receives d SSIM / d x, written out from the definition by the
+ * chain rule through the window sums. */
+static void ssim_window(double* w)
+{
+    double g[11], s = 0.0;
+    for (int k = 0; k < 11; ++k) { g[k] = exp(-(double)((k - 5) * (k - 5)) / (2.0 * 1.5 * 1.5)); s += g[k]; }
+    for (int a = 0; a < 11; ++a)
+        for (int b = 0; b < 11; ++b) w[a * 11 + b] = (g[a] / s) * (g[b] / s);
+}
+
+double orc_ssim(int W, int H, const double* x, const double* y, double* grad)
+{
+    const double C1 = 0.01 * 0.01, C2 = 0.03 * 0.03;
+    double w[121];
+    ssim_window(w);
+    const int64_t M = (int64_t)W * H;
+    double* dmu = (double*)calloc((size_t)M * 3, sizeof(double));   /* dS/dmx, dS/dExx, dS/dExy per pixel, channel */
+    double* dxx = (double*)calloc((size_t)M * 3, sizeof(double));
+    double* dxy = (double*)calloc((size_t)M * 3, sizeof(double));
+    if (!dmu || !dxx || !dxy) { free(dmu); free(dxx); free(dxy); return NAN; }
+    double total = 0.0;
+    for (int py = 0; py < H; ++py)
+        for (int px = 0; px < W; ++px)
+            for (int ch = 0; ch < 3; ++ch) {
+                double mx = 0, my = 0, exx = 0, eyy = 0, exy = 0;
+                for (int a = -5; a <= 5; ++a)
+                    for (int b = -5; b <= 5; ++b) {
+                        int qy = py + a, qx = px + b;
+                        if (qy < 0 || qy >= H || qx < 0 || qx >= W) continue;
+                        double wt = w[(a + 5) * 11 + (b + 5)];
+                        double xv = x[((int64_t)qy * W + qx) * 3 + ch], yv = y[((int64_t)qy * W + qx) * 3 + ch];
+                        mx += wt * xv; my += wt * yv;
+                        exx += wt * xv * xv; eyy += wt * yv * yv; exy += wt * xv * yv;
+                    }
+                double sx = exx - mx * mx, sy = eyy - my * my, sxy = exy - mx * my;
+                double ln = 2 * mx * my + C1, ld = mx * mx + my * my + C1;
+                double cn = 2 * sxy + C2, cd = sx + sy + C2;
+                double N = ln * cn, D = ld * cd;
+                total += N / D;
+                int64_t o = ((int64_t)py * W + px) * 3 + ch;
+                /* dN/dmx = 2 my cn + ln (-2 my);  dD/dmx = 2 mx cd + ld (-2 mx) */
+                double dN = 2 * my * cn - 2 * my * ln, dD = 2 * mx * cd - 2 * mx * ld;
+                dmu[o] = (dN * D - N * dD) / (D * D);
+                dxx[o] = -N * ld / (D * D);                 /* dD/dExx = ld */
+                dxy[o] = 2 * ln / D;                        /* dN/dExy = 2 ln */
+            }
+    if (grad) {
+        /* dS_p/dx_q over the windows that contain q (the window is symmetric) */
+        for (int qy = 0; qy < H; ++qy)
+            for (int qx = 0; qx < W; ++qx)
+                for (int ch = 0; ch < 3; ++ch) {
+                    double xv = x[((int64_t)qy * W + qx) * 3 + ch], yv = y[((int64_t)qy * W + qx) * 3 + ch];
+                    double acc = 0.0;
+                    for (int a = -5; a <= 5; ++a)
+                        for (int b = -5; b <= 5; ++b) {
+                            int py = qy + a, px = qx + b;
+                            if (py < 0 || py >= H || px < 0 || px >= W) continue;
+                            double wt = w[(a + 5) * 11 + (b + 5)];
+                            int64_t o = ((int64_t)py * W + px) * 3 + ch;
+                            acc += wt * (dmu[o] + 2 * xv * dxx[o] + yv * dxy[o]);
+                        }
+                    grad[((int64_t)qy * W + qx) * 3 + ch] = acc / (3.0 * (double)M);
+                }
+    }
+    free(dmu); free(dxx); free(dxy);
+    return total / (3.0 * (double)M);
+}
+
+/* One Adam step (bias-corrected, as in the 3DGS lineage's optimiser) on the
+ * raw parameters of an attribute whose activated value the renderer uses:
+ * kind 0 identity, 1 exp (scales from log-scales), 2 sigmoid (opacity from its
+ * logit).  grad_act is dL/d(activated); t >= 1 is the step number.  raw, m, v
+ * are updated in place; act receives the new activated values. */
+void orc_adam_step(int64_t n, double* raw, double* m, double* v, double* act, const double* grad_act, int kind,
+                   double lr, double b1, double b2, double eps, int64_t t)
+{
+    double c1 = 1.0 / (1.0 - pow(b1, (double)t)), c2 = 1.0 / (1.0 - pow(b2, (double)t));
+    for (int64_t i = 0; i < n; ++i) {
+        double a = kind == 1 ? exp(raw[i]) : (kind == 2 ? 1.0 / (1.0 + exp(-raw[i])) : raw[i]);
+        double g = grad_act[i] * (kind == 1 ? a : (kind == 2 ? a * (1.0 - a) : 1.0));
+        m[i] = b1 * m[i] + (1.0 - b1) * g;
+        v[i] = b2 * v[i] + (1.0 - b2) * g * g;
+        raw[i] -= lr * (m[i] * c1) / (sqrt(v[i] * c2) + eps);
+        act[i] = kind == 1 ? exp(raw[i]) : (kind == 2 ? 1.0 / (1.0 + exp(-raw[i])) : raw[i]);
+    }
 }

@@ -61,6 +61,9 @@ def lib():
         L.orc_opacity_loss.argtypes = [i64, P, dbl, P]
         L.orc_opacity_loss.restype = dbl
         L.orc_scale_reset.argtypes = [i64, P, dbl]
+        L.orc_ssim.argtypes = [i32, i32, P, P, P]
+        L.orc_ssim.restype = dbl
+        L.orc_adam_step.argtypes = [i64, P, P, P, P, P, i32, dbl, dbl, dbl, dbl, i64]
         _lib = L
     return _lib
 
@@ -118,6 +121,26 @@ def scale_reset(scales, zeta):
     s = np.array(scales, np.float32, copy=True, order="C")
     lib().orc_scale_reset(len(s), _p(s), float(np.float32(zeta)))
     return s
+
+
+def ssim(x, y, grad: bool = True):
+    """(SSIM, dSSIM/dx) of two [H, W, 3] images (FP64, 11x11 Gaussian window)."""
+    x = _f64(x)
+    y = _f64(y)
+    H, W = x.shape[:2]
+    g = np.zeros_like(x) if grad else None
+    s = lib().orc_ssim(W, H, _p(x), _p(y), None if g is None else _p(g))
+    return float(s), g
+
+
+def adam_step(raw, m, v, grad_act, kind, lr, t, b1=0.9, b2=0.999, eps=1e-15):
+    """One Adam step on float64 copies: returns (raw, m, v, activated)."""
+    raw, m, v = (np.array(a, np.float64, copy=True) for a in (raw, m, v))
+    act = np.zeros_like(raw)
+    ga = _f64(grad_act)
+    lib().orc_adam_step(raw.size, _p(raw), _p(m), _p(v), _p(act), _p(ga), int(kind), float(lr), float(b1), float(b2),
+                        float(eps), int(t))
+    return raw, m, v, act
 
 
 def scaled_camera(cam, r):

@@ -583,3 +583,98 @@ def test_rmax_policy_against_brute_force_counts(orc):
     ok = [rr for rr, m in zip(range(1, 5), means) if m <= 40.0]
     assert r == (max(ok) if ok else 1)
     assert means[3] > means[0]                   # coarser resolution, longer lists
+
+
+def test_ssim_identity_constant_images_and_symmetry(orc):
+    rng = np.random.default_rng(21)
+    x = rng.uniform(0, 1, (23, 31, 3))
+    s, g = orc.ssim(x, x)
+    assert s == pytest.approx(1.0, abs=1e-14)
+    assert np.abs(g).max() < 1e-12                     # SSIM(x, y) is maximal at x = y
+    y = rng.uniform(0, 1, (23, 31, 3))
+    assert orc.ssim(x, y, False)[0] == pytest.approx(orc.ssim(y, x, False)[0], rel=1e-14)
+    # constant images a, b: away from the border every window is full, the variances
+    # vanish and S = (2ab + C1) / (a^2 + b^2 + C1)
+    a, b = 0.3, 0.7
+    C1 = 1e-4
+    big = 40
+    xa, yb = np.full((big, big, 3), a), np.full((big, big, 3), b)
+    s_ab, _ = orc.ssim(xa, yb, False)
+    inner = (2 * a * b + C1) / (a * a + b * b + C1)
+    # every window lies inside the image away from the 5-pixel border
+    s_in, _ = orc.ssim(xa[:11, :11], yb[:11, :11], False)
+    assert s_in != pytest.approx(inner)                         # an 11x11 image is all border
+    # with the border: truncated window sums of constants are the window mass
+    w1 = np.exp(-(np.arange(11) - 5) ** 2 / (2 * 1.5 ** 2))
+    w1 /= w1.sum()
+    total = 0.0
+    for py in range(big):
+        for px in range(big):
+            my = sum(w1[k] for k in range(11) if 0 <= py + k - 5 < big)
+            mx = sum(w1[k] for k in range(11) if 0 <= px + k - 5 < big)
+            m = mx * my                                  # window mass inside the image
+            mux, muy = a * m, b * m
+            sx, sy, sxy = a * a * m - mux ** 2, b * b * m - muy ** 2, a * b * m - mux * muy
+            total += ((2 * mux * muy + C1) * (2 * sxy + 9e-4)) / ((mux ** 2 + muy ** 2 + C1) * (sx + sy + 9e-4))
+    assert s_ab == pytest.approx(total / big ** 2, rel=1e-12)
+
+
+def test_ssim_window_sums_match_scipy_convolution(orc):
+    """The local means of the oracle's SSIM, recovered from a single-pixel probe, equal
+    scipy's zero-padded 2D convolution with the separable 11x11 Gaussian window."""
+    from scipy.signal import convolve2d
+    rng = np.random.default_rng(22)
+    H, W = 17, 19
+    y = rng.uniform(0.2, 0.8, (H, W, 3))
+    w1 = np.exp(-(np.arange(11) - 5) ** 2 / (2 * 1.5 ** 2))
+    w1 /= w1.sum()
+    win = np.outer(w1, w1)
+    # SSIM against y of an image equal to y is 1; with x = y + e at one pixel the
+    # change of S over the pixels of its window follows the window weights:
+    # compare d SSIM/dx from the oracle against finite differences computed with
+    # scipy's convolution of the statistics
+    x = rng.uniform(0.2, 0.8, (H, W, 3))
+    C1, C2 = 1e-4, 9e-4
+
+    def ssim_scipy(xx):
+        tot = 0.0
+        for ch in range(3):
+            a, b = xx[..., ch], y[..., ch]
+            c = lambda z: convolve2d(z, win, mode="same", boundary="fill", fillvalue=0.0)
+            mx, my, exx, eyy, exy = c(a), c(b), c(a * a), c(b * b), c(a * b)
+            sx, sy, sxy = exx - mx * mx, eyy - my * my, exy - mx * my
+            tot += np.sum((2 * mx * my + C1) * (2 * sxy + C2) / ((mx * mx + my * my + C1) * (sx + sy + C2)))
+        return tot / (3 * H * W)
+
+    s, g = orc.ssim(x, y)
+    assert s == pytest.approx(ssim_scipy(x), rel=1e-13)
+    for (py, px, ch) in [(0, 0, 0), (8, 9, 1), (16, 18, 2), (3, 17, 0)]:
+        h = 1e-6
+        xp, xm = x.copy(), x.copy()
+        xp[py, px, ch] += h
+        xm[py, px, ch] -= h
+        assert g[py, px, ch] == pytest.approx((ssim_scipy(xp) - ssim_scipy(xm)) / (2 * h), rel=1e-6, abs=1e-11)
+
+
+def test_adam_first_step_and_activations(orc):
+    """First step: m-hat = g, v-hat = g^2, so raw moves by lr g / (|g| + eps); exp and
+    sigmoid activations chain the gradient through their derivatives."""
+    g = np.array([0.5, -2.0, 1e-3])
+    raw = np.array([0.1, -0.3, 2.0])
+    r1, m, v, act = orc.adam_step(raw, np.zeros(3), np.zeros(3), g, 0, 0.01, 1)
+    assert np.allclose(r1, raw - 0.01 * np.sign(g), rtol=0, atol=1e-14)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+    assert np.array_equal(act, r1)
+    r2, _, _, act2 = orc.adam_step(raw, np.zeros(3), np.zeros(3), g, 1, 0.01, 1)
+    ge = g * np.exp(raw)
+    assert np.allclose(r2, raw - 0.01 * np.sign(ge), atol=1e-14) and np.allclose(act2, np.exp(r2), rtol=1e-15)
+    r3, _, _, act3 = orc.adam_step(raw, np.zeros(3), np.zeros(3), g, 2, 0.01, 1)
+    sg = 1 / (1 + np.exp(-raw))
+    assert np.allclose(r3, raw - 0.01 * np.sign(g * sg * (1 - sg)), atol=1e-14)
+    assert np.allclose(act3, 1 / (1 + np.exp(-r3)), rtol=1e-15)
+    # a later step against a direct restatement with bias correction
+    m0, v0 = np.array([0.2, -0.1, 0.0]), np.array([0.04, 0.02, 1e-6])
+    r4, m4, v4, _ = orc.adam_step(raw, m0, v0, g, 0, 0.001, 7)
+    mm, vv = 0.9 * m0 + 0.1 * g, 0.999 * v0 + 0.001 * g * g
+    step = 0.001 * (mm / (1 - 0.9 ** 7)) / (np.sqrt(vv / (1 - 0.999 ** 7)) + 1e-15)
+    assert np.allclose(r4, raw - step, rtol=0, atol=1e-15)

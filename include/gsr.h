@@ -190,9 +190,36 @@ gsr_status gsr_l1_loss(gsr_ctx* ctx, void* stream, const gsr_camera* cams, int32
 gsr_status gsr_opacity_loss(gsr_ctx* ctx, void* stream, const float* opacities, int64_t n, float weight,
                             float* grad_opacities, float* loss);
 
+/* D-SSIM term of the base loss (Sec. 3, Eq. 6): per view v,
+ *   loss[v] = weight * (1 - SSIM(rgb_v, target_v))
+ * with the 3DGS-lineage SSIM (11x11 Gaussian window, sigma 1.5, zero outside
+ * the image, C1 = 0.01^2, C2 = 0.03^2, mean over pixels and channels).  rgb,
+ * target: device [P][3] packed as in gsr_fwd_out; grad_rgb (device, may be
+ * NULL) += dloss/drgb; loss (device, n_views floats, may be NULL).  Views are
+ * processed one after another; asynchronous. */
+gsr_status gsr_dssim(gsr_ctx* ctx, void* stream, const gsr_camera* cams, int32_t n_views, const float* rgb,
+                     const float* target, float weight, float* grad_rgb, float* loss);
+
+/* Base loss of Eq. 6 for the latest forward's cameras: per view
+ *   loss_l1[v] = (1 - lambda) L1_v,  loss_dssim[v] = lambda (1 - SSIM_v),
+ * and grad_rgb (device [P][3], overwritten) = d(loss_l1 + loss_dssim)/drgb.
+ * lambda in [0, 1]; the loss outputs (device, n_views floats) may be NULL.
+ * Asynchronous. */
+gsr_status gsr_base_loss(gsr_ctx* ctx, void* stream, const gsr_camera* cams, int32_t n_views, const float* rgb,
+                         const float* target, float lambda, float* grad_rgb, float* loss_l1, float* loss_dssim);
+
+/* One bias-corrected Adam step (step >= 1) on n raw parameters (device):
+ *   g = grad_act * d act/d raw,  m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   raw -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps),
+ * act = f(raw) with f = identity (kind 0), exp (1: scales from log-scales) or
+ * sigmoid (2: opacities from logits); act may be NULL.  Asynchronous. */
+gsr_status gsr_adam(gsr_ctx* ctx, void* stream, float* raw, float* m, float* v, float* act, const float* grad_act,
+                    int64_t n, int32_t kind, float lr, float beta1, float beta2, float eps, int64_t step);
+
 /* Scale reset (Sec. 3.2, Eq. 7): scales[i][k] <- zeta * scales[i][k] in place
- * (device, n x 3 floats, zeta > 0).  Asynchronous. */
-gsr_status gsr_scale_reset(gsr_ctx* ctx, void* stream, float* scales, int64_t n, float zeta);
+ * (device, n x 3 floats, zeta > 0); an optimiser's log-scales (device, n x 3,
+ * may be NULL) get + log(zeta).  Asynchronous. */
+gsr_status gsr_scale_reset(gsr_ctx* ctx, void* stream, float* scales, float* log_scales, int64_t n, float zeta);
 
 /* (tile, Gaussian) pair count of each view (host, n_views int64): the
  * projection and the tile count of the forward, no sort or blend.  Replaces

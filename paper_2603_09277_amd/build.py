@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgsr.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["project.hip", "sort.hip", "blend.hip", "loss.hip", "api.hip"]
+SOURCES = ["project.hip", "sort.hip", "blend.hip", "loss.hip", "train.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC,

@@ -53,7 +53,7 @@ struct gsr_ctx {
 
     // grow-only device buffers
     Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, tt_s, rect_s, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
-    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, queues, block_H, block_cnt, hchunk, counters, l1_tmp, reg_tmp;
+    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, queues, block_H, block_cnt, hchunk, counters, l1_tmp, reg_tmp, ssim_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
     uint64_t gen_fwd = 0, gen_bwd = 0;
@@ -540,7 +540,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     drop_graphs(c);
     Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->tt_s, &c->rect_s, &c->radius,
                    &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
-                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->queues, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->reg_tmp,
+                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->queues, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->reg_tmp, &c->ssim_tmp,
                    &c->l1_tmp };
     for (Dev* d : all) free_dev(*d);
     for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
@@ -793,13 +793,52 @@ gsr_status gsr_opacity_loss(gsr_ctx* c, void* stream, const float* opacities, in
     return GSR_OK;
 }
 
-gsr_status gsr_scale_reset(gsr_ctx* c, void* stream, float* scales, int64_t n, float zeta)
+gsr_status gsr_dssim(gsr_ctx* c, void* stream, const gsr_camera* cams, int32_t n_views, const float* rgb,
+                     const float* target, float weight, float* grad_rgb, float* loss)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    if (!cams || n_views < 1 || !rgb || !target) return fail(c, GSR_ERR_INVALID_ARG, "d-ssim: null argument");
+    if (!std::isfinite(weight)) return fail(c, GSR_ERR_INVALID_ARG, "d-ssim: weight not finite");
+    int64_t maxM = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if (cams[v].width < 1 || cams[v].height < 1 || cams[v].width > 32767 || cams[v].height > 32767)
+            return fail(c, GSR_ERR_INVALID_ARG, "d-ssim: camera size out of range");
+        maxM = std::max<int64_t>(maxM, (int64_t)cams[v].width * cams[v].height);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    gsr_status s = grow(c, c->ssim_tmp, ssim_tmp_bytes(maxM));
+    if (s) return s;
+    int64_t off = 0;
+    for (int v = 0; v < n_views; ++v) {             // views in order, one after another (they share the scratch)
+        const int W = cams[v].width, H = cams[v].height;
+        HIP_TRY(c, launch_dssim(rgb + 3 * off, target + 3 * off, W, H, weight, grad_rgb ? grad_rgb + 3 * off : nullptr,
+                                loss ? loss + v : nullptr, c->ssim_tmp.p, st));
+        off += (int64_t)W * H;
+    }
+    return GSR_OK;
+}
+
+gsr_status gsr_adam(gsr_ctx* c, void* stream, float* raw, float* m, float* v, float* act, const float* grad_act,
+                    int64_t n, int32_t kind, float lr, float beta1, float beta2, float eps, int64_t step)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!raw || !m || !v || !grad_act))) return fail(c, GSR_ERR_INVALID_ARG, "adam: null argument");
+    if (kind < 0 || kind > 2 || step < 1) return fail(c, GSR_ERR_INVALID_ARG, "adam: kind must be 0..2, step >= 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f && std::isfinite(lr)))
+        return fail(c, GSR_ERR_INVALID_ARG, "adam: bad hyper-parameters");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, launch_adam(raw, m, v, act, grad_act, n, kind, lr, beta1, beta2, eps, step, (hipStream_t)stream));
+    return GSR_OK;
+}
+
+gsr_status gsr_scale_reset(gsr_ctx* c, void* stream, float* scales, float* log_scales, int64_t n, float zeta)
 {
     if (!c) return GSR_ERR_INVALID_ARG;
     if (n < 0 || (n > 0 && !scales)) return fail(c, GSR_ERR_INVALID_ARG, "scale reset: bad scales or n");
     if (!(std::isfinite(zeta) && zeta > 0.f)) return fail(c, GSR_ERR_INVALID_ARG, "scale reset: zeta must be > 0");
     HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, launch_scale_reset(scales, 3 * n, zeta, (hipStream_t)stream));
+    HIP_TRY(c, launch_scale_reset(scales, log_scales, 3 * n, zeta, (hipStream_t)stream));
     return GSR_OK;
 }
 
@@ -898,8 +937,28 @@ gsr_status gsr_l1_loss(gsr_ctx* c, void* stream, const gsr_camera* cams, int32_t
     HIP_TRY(c, hipSetDevice(c->device));
     gsr_status s = grow(c, c->l1_tmp, ((size_t)c->lay.n_l1 + 1) * 8);
     if (s) return s;
-    HIP_TRY(c, launch_l1(rgb, target, (const CamDev*)c->cams.p, n_views, c->lay.n_l1, grad_rgb, loss,
+    HIP_TRY(c, launch_l1(rgb, target, (const CamDev*)c->cams.p, n_views, c->lay.n_l1, 1.0f, grad_rgb, loss,
                          (double*)c->l1_tmp.p, st));
+    return GSR_OK;
+}
+
+gsr_status gsr_base_loss(gsr_ctx* c, void* stream, const gsr_camera* cams, int32_t n_views, const float* rgb,
+                         const float* target, float lambda, float* grad_rgb, float* loss_l1, float* loss_dssim)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    if (!cams || !rgb || !target || !grad_rgb) return fail(c, GSR_ERR_INVALID_ARG, "null base-loss argument");
+    if (!(lambda >= 0.f && lambda <= 1.f)) return fail(c, GSR_ERR_INVALID_ARG, "lambda must be in [0, 1]");
+    if (!c->have_frame || n_views != c->n_views) return fail(c, GSR_ERR_INVALID_ARG, "views differ from the latest forward");
+    for (int v = 0; v < n_views; ++v)
+        if (cams[v].width != c->lay.cams[v].W || cams[v].height != c->lay.cams[v].H)
+            return fail(c, GSR_ERR_INVALID_ARG, "camera sizes differ from the latest forward");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    gsr_status s = grow(c, c->l1_tmp, ((size_t)c->lay.n_l1 + 1) * 8);
+    if (s) return s;
+    HIP_TRY(c, launch_l1(rgb, target, (const CamDev*)c->cams.p, n_views, c->lay.n_l1, 1.0f - lambda, grad_rgb, loss_l1,
+                         (double*)c->l1_tmp.p, st));
+    if (lambda > 0.f) return gsr_dssim(c, stream, cams, n_views, rgb, target, lambda, grad_rgb, loss_dssim);
     return GSR_OK;
 }
 

@@ -180,10 +180,18 @@ hipError_t launch_blend_bwd(const BlendBwdArgs& a, int lds_batch, hipStream_t s)
 size_t opacity_reg_tmp_words(int64_t n);
 hipError_t launch_opacity_reg(const float* opac, int64_t n, float w, float* grad, float* loss, double* tmp,
                               hipStream_t s);
-// s <- zeta * s in place over count floats
-hipError_t launch_scale_reset(float* scales, int64_t count, float zeta, hipStream_t s);
+// D-SSIM of one view: loss (device, may be null) = weight (1 - SSIM(x, y)); grad (may be null)
+// += dloss/dx; x, y, grad [W*H][3]; tmp holds ssim_tmp_bytes(W*H) bytes
+size_t ssim_tmp_bytes(int64_t M);
+hipError_t launch_dssim(const float* x, const float* y, int W, int H, float weight, float* grad, float* loss, void* tmp,
+                        hipStream_t s);
+// one bias-corrected Adam step on raw parameters (kind 0 identity, 1 exp, 2 sigmoid activation)
+hipError_t launch_adam(float* raw, float* m, float* v, float* act, const float* grad_act, int64_t n, int kind,
+                       float lr, float b1, float b2, float eps, int64_t step, hipStream_t s);
+// s <- zeta * s in place over count floats; log_s (may be null) += log(zeta)
+hipError_t launch_scale_reset(float* scales, float* log_scales, int64_t count, float zeta, hipStream_t s);
 hipError_t launch_l1(const float* rgb, const float* target, const CamDev* cams, int n_views, uint32_t n_l1_blocks,
-                     float* grad, float* loss, double* tmp, hipStream_t s);
+                     float weight, float* grad, float* loss, double* tmp, hipStream_t s);
 // n_chunks = sum over views of ceil(blocks_v / kRedChunk); tmp holds n_chunks doubles
 hipError_t launch_entropy_mean(const float* block_H, const CamDev* cams, int n_views, uint32_t n_chunks,
                                double* tmp, float* out_mean, hipStream_t s);

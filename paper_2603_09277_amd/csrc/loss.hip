@@ -3,6 +3,8 @@
 //   dL1_v/dC = sign(C - target) / (3 M_v), with sign(0) = 0.
 // Every block covers pixels of a single view, so the per-view loss is a fixed
 // order FP64 sum of whole blocks: deterministic.
+#include <cmath>
+
 #include "internal.h"
 
 namespace gsr {
@@ -28,7 +30,7 @@ __device__ __forceinline__ double block_sum_f64(double x)
 }
 
 __global__ __launch_bounds__(kL1Block) void l1_kernel(const float* rgb, const float* target, const CamDev* cams,
-                                                      int n_views, float* grad, double* block_sum)
+                                                      int n_views, float weight, float* grad, double* block_sum)
 {
     const uint32_t b = blockIdx.x;
     const int v = view_of_l1_block(cams, n_views, b);
@@ -38,7 +40,7 @@ __global__ __launch_bounds__(kL1Block) void l1_kernel(const float* rgb, const fl
     double acc = 0.0;
     if (q < M) {
         const int64_t p = c.pix_base + q;
-        const float inv = 1.0f / (3.0f * (float)M);
+        const float inv = weight / (3.0f * (float)M);
         for (int ch = 0; ch < 3; ++ch) {
             const float d = rgb[3 * p + ch] - target[3 * p + ch];
             const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(kL1Block) void l1_kernel(const float* rgb, const fl
 }
 
 __global__ __launch_bounds__(kL1Block) void l1_reduce_kernel(const double* block_sum, const CamDev* cams, int n_views,
-                                                             uint32_t n_blocks, float* loss)
+                                                             uint32_t n_blocks, float weight, float* loss)
 {
     const int v = blockIdx.x;
     if (v >= n_views) return;
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(kL1Block) void l1_reduce_kernel(const double* block
     double acc = 0.0;
     for (uint32_t b = b0 + threadIdx.x; b < b1; b += kL1Block) acc += block_sum[b];
     const double tot = block_sum_f64(acc);
-    if (threadIdx.x == 0) loss[v] = (float)(tot / (3.0 * (double)((int64_t)c.W * c.H)));
+    if (threadIdx.x == 0) loss[v] = (float)((double)weight * tot / (3.0 * (double)((int64_t)c.W * c.H)));
 }
 
 // Opacity regulariser of the comparison in Sec. 4 (ablation, opacity vs entropy
@@ -91,11 +93,15 @@ __global__ __launch_bounds__(kL1Block) void opacity_reg_reduce_kernel(const doub
     if (threadIdx.x == 0) *loss = (float)((double)w * tot / (double)n);
 }
 
-// Scale reset (Sec. 3.2, Eq. 7): s <- zeta * s for every scale component.
-__global__ void scale_reset_kernel(float* s, int64_t count, float zeta)
+// Scale reset (Sec. 3.2, Eq. 7): s <- zeta * s for every scale component, and
+// log s <- log s + log zeta for an optimiser's log-scales (may be null).
+__global__ void scale_reset_kernel(float* s, float* log_s, int64_t count, float zeta, float log_zeta)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) s[i] = zeta * s[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        s[i] = zeta * s[i];
+        if (log_s) log_s[i] = log_s[i] + log_zeta;
+    }
 }
 
 }  // namespace
@@ -112,23 +118,25 @@ hipError_t launch_opacity_reg(const float* opac, int64_t n, float w, float* grad
     return hipGetLastError();
 }
 
-hipError_t launch_scale_reset(float* scales, int64_t count, float zeta, hipStream_t s)
+hipError_t launch_scale_reset(float* scales, float* log_scales, int64_t count, float zeta, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     int64_t blocks = (count + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(scale_reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, scales, count, zeta);
+    hipLaunchKernelGGL(scale_reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, scales, log_scales, count, zeta,
+                       (float)std::log((double)zeta));
     return hipGetLastError();
 }
 
 hipError_t launch_l1(const float* rgb, const float* target, const CamDev* cams, int n_views, uint32_t n_l1_blocks,
-                     float* grad, float* loss, double* tmp, hipStream_t s)
+                     float weight, float* grad, float* loss, double* tmp, hipStream_t s)
 {
     if (n_l1_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(l1_kernel, dim3(n_l1_blocks), dim3(kL1Block), 0, s, rgb, target, cams, n_views, grad, tmp);
+    hipLaunchKernelGGL(l1_kernel, dim3(n_l1_blocks), dim3(kL1Block), 0, s, rgb, target, cams, n_views, weight, grad,
+                       tmp);
     if (loss)
         hipLaunchKernelGGL(l1_reduce_kernel, dim3(n_views), dim3(kL1Block), 0, s, tmp, cams, n_views, n_l1_blocks,
-                           loss);
+                           weight, loss);
     return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ class Grads(ctypes.Structure):
 EXPORTED = ["gsr_status_string", "gsr_last_error", "gsr_create", "gsr_destroy", "gsr_pixel_offsets",
             "gsr_forward", "gsr_render", "gsr_backward", "gsr_stats", "gsr_autotune", "gsr_inspect", "gsr_set_timing",
             "gsr_opacity_loss", "gsr_scale_reset", "gsr_pair_counts", "gsr_scaled_camera", "gsr_select_rmax",
+            "gsr_dssim", "gsr_adam", "gsr_base_loss",
             "gsr_stage_times", "gsr_l1_loss"]
 
 _lib = None
@@ -104,7 +105,11 @@ def lib():
         L.gsr_autotune.argtypes = [P, P, ctypes.POINTER(Gaussians), P, i32, ctypes.POINTER(Opts), ctypes.c_char_p]
         L.gsr_inspect.argtypes = [P, P, ctypes.c_int, P, i64, ctypes.POINTER(i64)]
         L.gsr_opacity_loss.argtypes = [P, P, P, i64, ctypes.c_float, P, P]
-        L.gsr_scale_reset.argtypes = [P, P, P, i64, ctypes.c_float]
+        L.gsr_scale_reset.argtypes = [P, P, P, P, i64, ctypes.c_float]
+        L.gsr_dssim.argtypes = [P, P, P, i32, P, P, ctypes.c_float, P, P]
+        L.gsr_base_loss.argtypes = [P, P, P, i32, P, P, ctypes.c_float, P, P, P]
+        fl = ctypes.c_float
+        L.gsr_adam.argtypes = [P, P, P, P, P, P, P, i64, i32, fl, fl, fl, fl, i64]
         L.gsr_pair_counts.argtypes = [P, P, ctypes.POINTER(Gaussians), P, i32, ctypes.POINTER(Opts), P]
         L.gsr_scaled_camera.argtypes = [ctypes.POINTER(Camera), i32]
         L.gsr_scaled_camera.restype = Camera
@@ -255,11 +260,46 @@ class Rasterizer:
                                                  float(weight), _ptr(grad), _ptr(loss)))
         return loss
 
-    def scale_reset(self, scales: torch.Tensor, zeta: float) -> None:
-        """s <- zeta * s in place (Eq. 7)."""
-        if scales.dtype != torch.float32 or not scales.is_contiguous() or scales.dim() != 2 or scales.shape[1] != 3:
-            raise ValueError("scales must be a contiguous float32 [n, 3] tensor")
-        _check(self._ctx, lib().gsr_scale_reset(self._ctx, _stream(), _ptr(scales), scales.shape[0], float(zeta)))
+    def dssim(self, cams, rgb, target, weight: float, grad_rgb: Optional[torch.Tensor] = None,
+              loss: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """loss[v] = weight (1 - SSIM) per view; grad_rgb (when given) += its gradient."""
+        for name, t in (("rgb", rgb), ("target", target)):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+        if loss is None:
+            loss = torch.empty(len(cams), device=rgb.device, dtype=torch.float32)
+        carr = make_cameras(cams)
+        _check(self._ctx, lib().gsr_dssim(self._ctx, _stream(), carr, len(cams), _ptr(rgb), _ptr(target),
+                                          float(weight), _ptr(grad_rgb), _ptr(loss)))
+        return loss
+
+    def base_loss(self, cams, rgb, target, lam: float, grad_rgb: torch.Tensor, loss_l1: Optional[torch.Tensor] = None,
+                  loss_dssim: Optional[torch.Tensor] = None):
+        """(1 - lam) L1 + lam D-SSIM per view (Eq. 6) for the latest forward; grad_rgb is overwritten."""
+        for name, t in (("rgb", rgb), ("target", target), ("grad_rgb", grad_rgb)):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+        carr = make_cameras(cams)
+        _check(self._ctx, lib().gsr_base_loss(self._ctx, _stream(), carr, len(cams), _ptr(rgb), _ptr(target), float(lam),
+                                              _ptr(grad_rgb), _ptr(loss_l1), _ptr(loss_dssim)))
+
+    def adam(self, raw, m, v, act, grad_act, kind: int, lr: float, step: int, beta1: float = 0.9,
+             beta2: float = 0.999, eps: float = 1e-15) -> None:
+        """One Adam step on raw parameters in place; act (may be None) receives f(raw)."""
+        n = raw.numel()
+        for name, t in (("raw", raw), ("m", m), ("v", v), ("grad", grad_act)) + ((("act", act),) if act is not None else ()):
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n:
+                raise ValueError(f"{name} must be a contiguous float32 tensor of {n} elements")
+        _check(self._ctx, lib().gsr_adam(self._ctx, _stream(), _ptr(raw), _ptr(m), _ptr(v), _ptr(act), _ptr(grad_act),
+                                         n, int(kind), float(lr), float(beta1), float(beta2), float(eps), int(step)))
+
+    def scale_reset(self, scales: torch.Tensor, zeta: float, log_scales: Optional[torch.Tensor] = None) -> None:
+        """s <- zeta * s in place (Eq. 7); log_scales (when given) += log(zeta)."""
+        for t in (scales,) + ((log_scales,) if log_scales is not None else ()):
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 2 or t.shape[1] != 3:
+                raise ValueError("scales must be contiguous float32 [n, 3] tensors")
+        _check(self._ctx, lib().gsr_scale_reset(self._ctx, _stream(), _ptr(scales), _ptr(log_scales),
+                                                scales.shape[0], float(zeta)))
 
     def pair_counts(self, means, scales, quats, opacities, sh, cams, opts: RasterOptions) -> List[int]:
         g = _gaussians(means, scales, quats, opacities, sh, opts)

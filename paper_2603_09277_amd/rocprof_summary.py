@@ -31,13 +31,30 @@ def short_name(name: str) -> str:
     return name.strip()
 
 
-def stats_table(path: str, top: int = 40):
-    rows = list(csv.DictReader(open(path)))
-    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    out = ["| kernel | calls | avg us | min us | max us | share % |", "|---|---:|---:|---:|---:|---:|"]
-    for r in rows[:top]:
-        out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
-                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+def stats_rows(path: str):
+    """Per-kernel (name, calls, total, avg, min, max ns, share %) from kernel_stats.csv or a rocpd database."""
+    if path.endswith(".db"):
+        import sqlite3
+        con = sqlite3.connect(path)
+        q = ("select name, count(*), sum(duration), avg(duration), min(duration), max(duration) "
+             "from kernels group by name")
+        raw = con.execute(q).fetchall()
+        tot = sum(r[2] for r in raw) or 1
+        rows = [(n, c, t, a, lo, hi, 100.0 * t / tot) for n, c, t, a, lo, hi in raw]
+    else:
+        rows = [(r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]), float(r["AverageNs"]), float(r["MinNs"]),
+                 float(r["MaxNs"]), float(r["Percentage"])) for r in csv.DictReader(open(path))]
+    rows.sort(key=lambda r: -r[2])
+    return rows
+
+
+def stats_table(path: str, top: int = 40, per: int = 0):
+    extra = f" | ms per step ({per} steps) " if per else " "
+    out = [f"| kernel | calls | avg us | min us | max us | share %{extra}|",
+           "|---|---:|---:|---:|---:|---:|" + ("---:|" if per else "")]
+    for n, c, t, a, lo, hi, sh in stats_rows(path)[:top]:
+        col = f" {t / per / 1e6:.4f} |" if per else ""
+        out.append(f"| `{short_name(n)}` | {c} | {a / 1e3:.2f} | {lo / 1e3:.2f} | {hi / 1e3:.2f} | {sh:.2f} |{col}")
     return out
 
 
@@ -65,7 +82,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("stats")
-    s.add_argument("csv")
+    s.add_argument("csv", help="kernel_stats.csv, or the rocpd *_results.db of a --kernel-trace run")
+    s.add_argument("--per", type=int, default=0, help="also give total ms divided by this many steps")
     s.add_argument("--title", required=True)
     s.add_argument("--command", required=True)
     s.add_argument("--note", default="")
@@ -91,7 +109,7 @@ def main():
                  "```", a.command, "```", ""]
         if a.note:
             lines += [a.note, ""]
-        lines += stats_table(a.csv)
+        lines += stats_table(a.csv, per=a.per)
         open(a.out, "w").write("\n".join(lines) + "\n")
         return
 

@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--lds", type=int, default=128)
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
-    ap.add_argument("--persistent", action="store_true", help="persistent blend kernels, longest tile lists first")
+    ap.add_argument("--persistent", action="store_true", help="persistent blend kernels pulling tiles from per-XCD queues")
     ap.add_argument("--autotune", action="store_true", help="pick tile shape and LDS batch with gsr_autotune first")
     ap.add_argument("--forward-only", action="store_true",
                     help="test-time rendering (gsr_render): colour only, no entropy, no backward; value = views/s")

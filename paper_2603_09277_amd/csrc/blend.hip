@@ -470,7 +470,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
     const uint32_t slot = SHARED ? 0u : wid;
     const float stamp = __uint_as_float(*a.stamp);
-    // work items: tiles (SHARED: one per workgroup; else one per wavefront), longest list first
+    // work items: tiles (SHARED: one per workgroup; else one per wavefront), claimed from the per-XCD queues
     const uint32_t n_items = SHARED ? a.n_blocks / kWavesPerGroup : a.n_blocks;
     WaveQueue wq;
     auto next = [&]() -> uint32_t {

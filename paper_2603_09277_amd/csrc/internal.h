@@ -166,7 +166,7 @@ hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* stamp, con
 // *p += 1 (one thread)
 hipError_t launch_bump_u32(uint32_t* p, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
-// keys[t] = 255 - min(255, ceil(len_t / 8)), vals[t] = t: one stable 8-bit pass orders tiles longest first
+// p[i] = i
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
 // per-tile [start, end) of the sorted pairs
 hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges, hipStream_t s);

@@ -3,6 +3,12 @@
 
   stats    kernel_stats.csv (from --kernel-trace --stats --output-format csv)
            -> a Markdown table of per-kernel calls and durations.
+  counters counter_collection.csv files of SQ counter runs plus the
+           kernel_stats.csv of a --kernel-trace --stats run of the same
+           program -> per-dispatch averages of every counter for the chosen
+           kernels and the derived VALU / LDS figures (lane utilisation,
+           executed lane-operations per second against the VALU peak, LDS
+           bank conflicts per access).
   traffic  counter_collection.csv of a FETCH_SIZE run and of a WRITE_SIZE run
            of the same program, plus the same two counters read on a plain
            copy of known size -> per-launch HBM bytes of one kernel, scaled by
@@ -73,6 +79,52 @@ def pick(d, pattern):
     return keys[0], d[keys[0]]
 
 
+# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one FP32 lane-operation per lane per clock
+VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
+
+
+def all_counters(paths):
+    """{kernel: {counter: [per-dispatch values]}} over several counter_collection.csv files."""
+    d = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            d[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return d
+
+
+def counters_table(paths, stats_path, patterns):
+    cnt = all_counters(paths)
+    dur = {short_name(n): a for n, c, t, a, lo, hi, sh in stats_rows(stats_path)}
+    out = []
+    for pat in patterns:
+        k, c = pick(cnt, pat)
+        avg = {n: sum(v) / len(v) for n, v in c.items()}
+        out += [f"## `{k}`", "", "| counter | per dispatch |", "|---|---:|"]
+        out += [f"| {n} | {v:,.0f} |" for n, v in sorted(avg.items())]
+        waves = avg.get("SQ_WAVES")
+        d_ns = next((v for n, v in dur.items() if n == k), None)
+        out += ["", "| derived | value |", "|---|---:|"]
+        if d_ns:
+            out.append(f"| average duration (kernel trace) | {d_ns / 1e3:.2f} us |")
+        if waves:
+            for n in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD"):
+                if n in avg:
+                    out.append(f"| {n} per wave | {avg[n] / waves:,.1f} |")
+        if "SQ_THREAD_CYCLES_VALU" in avg and avg.get("SQ_ACTIVE_INST_VALU"):
+            out.append(f"| VALU lane utilisation (active lanes / 64) | "
+                       f"{avg['SQ_THREAD_CYCLES_VALU'] / (avg['SQ_ACTIVE_INST_VALU'] * 64):.3f} |")
+        if "SQ_INSTS_VALU" in avg and d_ns:
+            rate = avg["SQ_INSTS_VALU"] * 64 / (d_ns * 1e-9)
+            out.append(f"| issued VALU lane-slots / s | {rate / 1e12:.2f} T ({rate / VALU_LANE_OPS_PEAK:.3f} of "
+                       f"{VALU_LANE_OPS_PEAK / 1e12:.2f} T) |")
+        if "SQ_LDS_BANK_CONFLICT" in avg and "SQ_LDS_IDX_ACTIVE" in avg:
+            acc = avg["SQ_LDS_IDX_ACTIVE"] - avg["SQ_LDS_BANK_CONFLICT"]
+            if acc > 0:
+                out.append(f"| LDS bank conflicts per access (cycles) | {avg['SQ_LDS_BANK_CONFLICT'] / acc:.4f} |")
+        out.append("")
+    return out
+
+
 def source_hash(name):
     with open(os.path.join(CSRC, name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -88,6 +140,14 @@ def main():
     s.add_argument("--command", required=True)
     s.add_argument("--note", default="")
     s.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--csv", nargs="+", required=True, help="counter_collection.csv files")
+    c.add_argument("--stats", required=True, help="kernel_stats.csv (or rocpd .db) of the same program")
+    c.add_argument("--kernel", nargs="+", required=True, help="regexes of the kernel names")
+    c.add_argument("--title", required=True)
+    c.add_argument("--commands", required=True, help="the rocprofv3 commands, separated by ' ;; '")
+    c.add_argument("--note", default="")
+    c.add_argument("--out", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -110,6 +170,14 @@ def main():
         if a.note:
             lines += [a.note, ""]
         lines += stats_table(a.csv, per=a.per)
+        open(a.out, "w").write("\n".join(lines) + "\n")
+        return
+
+    if a.cmd == "counters":
+        lines = [f"# {a.title}", "", "Commands (run from /tmp):", "", "```"] + a.commands.split(" ;; ") + ["```", ""]
+        if a.note:
+            lines += [a.note, ""]
+        lines += counters_table(a.csv, a.stats, a.kernel)
         open(a.out, "w").write("\n".join(lines) + "\n")
         return
 

@@ -723,7 +723,7 @@ def test_gradients_bit_reproducible(R, tile):
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
 def test_persistent_mode_matches_plain_bit_exactly(R, tile):
-    """Persistent blend kernels (tiles pulled longest-list first from a device queue) give
+    """Persistent blend kernels (tiles pulled from per-XCD device queues, with stealing) give
     bit-identical outputs and gradients, on uneven views."""
     scene = scenes.gmm_scene(71, 10000)
     scene.scales *= np.float32(1.5)

@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--lds", type=int, default=128)
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
+    ap.add_argument("--no-sync", action="store_true",
+                    help="eager launches at a fixed pair capacity, no host synchronisation per step")
     ap.add_argument("--persistent", action="store_true", help="persistent blend kernels pulling tiles from per-XCD queues")
     ap.add_argument("--autotune", action="store_true", help="pick tile shape and LDS batch with gsr_autotune first")
     ap.add_argument("--forward-only", action="store_true",
@@ -72,6 +74,8 @@ def parse():
     ap.add_argument("--bf16", action="store_true", help="same as --sh bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not bracket stages with HIP events")
+    ap.add_argument("--breakdown-steps", type=int, default=20,
+                    help="untimed steps after the timed region with every stage bracketed by events")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 launches), to scale HBM counters")
     ap.add_argument("--train", action="store_true",
@@ -224,7 +228,8 @@ def main():
          ("means", "scales", "quats", "opacities", "sh")}
     if bf16:
         t["sh"] = t["sh"].to(torch.bfloat16).contiguous()
-    flags = gsr.GSR_DEFAULT_FLAGS | (gsr.GSR_GRAPH if args.graph else 0) | (gsr.GSR_PERSISTENT if args.persistent else 0)
+    flags = (gsr.GSR_DEFAULT_FLAGS | (gsr.GSR_GRAPH if args.graph else 0) | (gsr.GSR_PERSISTENT if args.persistent else 0)
+             | (gsr.GSR_NO_SYNC if args.no_sync else 0))
     opts = gsr.RasterOptions(tile=tile, lds_batch=args.lds, sh_degree=scene.sh_degree, sh_bf16=bf16, flags=flags)
     targets_np = [scenes.target_image(1000 + v, c.height, c.width) for v, c in enumerate(cams)]
     target = torch.from_numpy(np.concatenate([x.reshape(-1, 3) for x in targets_np])).to(dev).contiguous()
@@ -268,19 +273,29 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # Inside the timed region only the blend stages (the candidates for the dominant
+    # kernel) are bracketed by HIP events: each event pair costs the stream a few
+    # microseconds.  The full per-stage breakdown comes from extra steps afterwards.
     timing = not args.no_timing and not args.graph
+    hot = ["blend_fwd"] if args.forward_only else ["blend_fwd", "blend_bwd"]
     if timing:
         R.stage_times(reset=True)
-        R.set_timing(True)
+        R.set_timing(True, hot)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    hot_times, stages = {}, {}
     if timing:
         R.set_timing(False)
-    stages = R.stage_times(reset=True) if timing else {}
+        hot_times = {k: v for k, v in R.stage_times(reset=True).items() if k in hot and v[1] > 0}
+        R.set_timing(True)
+        for _ in range(args.breakdown_steps):
+            step()
+        R.set_timing(False)
+        stages = R.stage_times(reset=True)
     if args.per_view:      # statistics of every view: forward each once more, untimed
         st = dict(pairs=0, evals_fwd=0, evals_bwd=0, blended=0, mean_len=0.0, p99_len=0, overflow=False)
         n_t = 0
@@ -308,13 +323,14 @@ def main():
     launches = len(work)
     stl = {k: st[k] / launches for k in ("pairs", "evals_fwd", "evals_bwd", "blended")}
     stage_report = {}
-    for name, (ms, cnt) in stages.items():
+    for name, (ms, cnt) in list(stages.items()) + list(hot_times.items()):   # the timed region's figures last
         if cnt == 0:
             continue
         avg_s = ms / cnt / 1e3
         b = stage_bytes(name, n, V / launches, sh_bytes, stl["pairs"], n_tiles / launches, npix / launches,
                         stl["evals_fwd"], stl["evals_bwd"])
-        rep = {"avg_ms": round(ms / cnt, 4), "hbm_GBs": round(b / avg_s / 1e9, 1) if b else None}
+        rep = {"avg_ms": round(ms / cnt, 4), "hbm_GBs": round(b / avg_s / 1e9, 1) if b else None,
+               "timed_region": name in hot_times}
         if name in ("blend_fwd", "blend_bwd"):
             rep["valu_Tops"] = round(blend_ops(name, stl, args.forward_only) / avg_s / 1e12, 3)
             rep["evals_G_per_s"] = round(stl["evals_fwd" if name == "blend_fwd" else "evals_bwd"] / avg_s / 1e9, 2)
@@ -322,8 +338,8 @@ def main():
         stage_report[name] = rep
 
     roofline = None
-    if stage_report:
-        dom = max(stage_report, key=lambda k: stage_report[k]["avg_ms"])
+    if hot_times:
+        dom = max(hot_times, key=lambda k: stage_report[k]["avg_ms"])
         avg_s = stage_report[dom]["avg_ms"] / 1e3
         traffic = None
         tf = os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_traffic.json")
@@ -358,7 +374,7 @@ def main():
                    "lds_batch": opts.lds_batch, "sh_storage": "bf16" if bf16 else "f32",
                    "mode": ("forward-only " if args.forward_only else "")
                            + ("per-view" if args.per_view else ("batched" if V > 1 else "single-view"))
-                           + ("+graph" if args.graph else "")
+                           + ("+graph" if args.graph else "") + ("+no-sync" if args.no_sync and not args.graph else "")
                            + ("+persistent" if args.persistent else "") + ("+autotuned" if args.autotune else ""),
                    "loss": None if args.forward_only else "L1 + 0.015 L_E"},
         "pairs_per_s": round(st["pairs"] / sec, 1), "pairs": st["pairs"], "mean_list_len": round(st["mean_len"], 2),

@@ -81,6 +81,12 @@ typedef struct {
 #define GSR_PERSISTENT     16u   /* persistent blend kernels: resident workgroups pull tiles from 8 device
                                     queues (one per XCD) of spatially contiguous tiles, stealing from the
                                     others when their own is empty */
+#define GSR_NO_SYNC        32u   /* eager launches with a fixed pair capacity and no host synchronisation:
+                                    the first frame of a context sizes the capacity (1.5x its pairs + 4096),
+                                    later frames read their pair count back asynchronously and the next
+                                    frame grows the capacity when a count came within 10 % of it (a frame
+                                    past it is flagged as an overflow, see gsr_stats); stage timing works;
+                                    ignored with GSR_GRAPH, which never synchronises either */
 #define GSR_DEFAULT_FLAGS  (GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP)
 
 typedef struct {
@@ -149,16 +155,17 @@ gsr_status gsr_pixel_offsets(const gsr_camera* cams, int32_t n_views, int64_t* o
 
 /* Render n_views cameras (host array) and their entropy (Sec. 3, Eq. 3-5,
  * 8-11).  In plain mode the call synchronises once on `stream` to size the
- * pair buffers; with GSR_GRAPH it never synchronises. */
+ * pair buffers; with GSR_GRAPH or GSR_NO_SYNC it does not (after the first
+ * frame of the mode on this context). */
 gsr_status gsr_forward(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
                        int32_t n_views, const gsr_opts* opts, gsr_fwd_out* out);
 
 /* Test-time rendering: the colour of n_views cameras (Sec. 3, Eq. 3-5) with
  * the same projection, lists and blending as gsr_forward (bit-identical rgb),
  * without the entropy and without per-pixel saved state.  rgb: device, caller-
- * owned, float [P][3] with views packed as in gsr_fwd_out.  Plain mode only
- * (GSR_GRAPH -> GSR_ERR_UNSUPPORTED; GSR_PERSISTENT is honoured); synchronises
- * once on `stream`.  It replaces the context's frame: a backward of an earlier
+ * owned, float [P][3] with views packed as in gsr_fwd_out.  Eager launches
+ * only (GSR_GRAPH -> GSR_ERR_UNSUPPORTED; GSR_PERSISTENT and GSR_NO_SYNC are
+ * honoured); synchronises once on `stream` unless GSR_NO_SYNC.  It replaces the context's frame: a backward of an earlier
  * forward then fails with GSR_ERR_STALE_FRAME.  gsr_stats describes it. */
 gsr_status gsr_render(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
                       int32_t n_views, const gsr_opts* opts, float* rgb);
@@ -257,9 +264,13 @@ typedef struct {
  * the latest forward on this context; synchronises `stream`. */
 gsr_status gsr_stats(gsr_ctx* ctx, void* stream, int64_t* pairs_per_view, gsr_frame_stats* out);
 
-/* Per-stage GPU timing.  While enabled (plain mode only; ignored for
- * GSR_GRAPH), every stage of gsr_forward / gsr_backward is bracketed by HIP
- * events on the caller's stream.  gsr_stage_times synchronises the device,
+/* Per-stage GPU timing.  gsr_set_timing's `enable` is a mask of stages (bit s
+ * = stage s of gsr_stage; GSR_TIME_ALL = every stage; 0 = off).  While a
+ * stage's bit is set, each of its launches by gsr_forward / gsr_backward /
+ * gsr_render is bracketed by HIP events on the caller's stream (eager launches:
+ * plain mode and GSR_NO_SYNC; never under GSR_GRAPH).  Every pair of events
+ * costs a few microseconds of the stream's time, so timing only the stages of
+ * interest disturbs a step least.  gsr_stage_times synchronises the device,
  * adds the elapsed milliseconds of each stage since the last reset into
  * total_ms[GSR_N_STAGES] and the number of timed launches into
  * launches[GSR_N_STAGES] (host arrays), and resets if `reset` is non-zero. */
@@ -278,6 +289,8 @@ typedef enum {
     GSR_N_STAGES = 11
 } gsr_stage;
 
+#define GSR_TIME_ALL 0x7ff
+
 gsr_status gsr_set_timing(gsr_ctx* ctx, int32_t enable);
 gsr_status gsr_stage_times(gsr_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);
 
@@ -285,7 +298,7 @@ gsr_status gsr_stage_times(gsr_ctx* ctx, double* total_ms, int64_t* launches, in
  * batch in {32, 64, 128, 256} and blend scheduling (hardware dispatch or
  * GSR_PERSISTENT) on the given inputs, and write the fastest into
  * inout->tile_w/tile_h/lds_batch and the GSR_PERSISTENT bit of inout->flags
- * (the other flags are kept).  If cache_path is not NULL the result
+ * (the other flags are kept; the timing runs use plain mode).  If cache_path is not NULL the result
  * is read from / appended to that text file, keyed by device and workload.
  * Synchronises `stream`.  Note the image depends on the tile shape. */
 gsr_status gsr_autotune(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,

@@ -79,10 +79,13 @@ struct gsr_ctx {
     const float* key_bwd_grads[3] = {};
     void* key_bwd_outs[5] = {};
     hipEvent_t ev_replay = nullptr;
+    bool nosync_count = false;             // counters_host holds the latest GSR_NO_SYNC frame's pair count
+    bool capturing = false;                // a graph capture is recording (no stage events)
+    bool nosync_ready = false;             // a GSR_NO_SYNC frame has sized the pair capacity
     bool replay_pending = false;
 
-    // per-stage timing (plain mode)
-    bool timing = false;
+    // per-stage timing (eager launches; not under graph capture)
+    uint32_t timing = 0;                   // bit s: stage s is timed
     struct Timed { int stage; hipEvent_t a, b; };
     std::vector<Timed> timed;
     std::vector<hipEvent_t> ev_pool;
@@ -118,7 +121,7 @@ struct StageTimer {
     hipEvent_t a = nullptr;
     StageTimer(gsr_ctx* c_, hipStream_t st_, int stage_, bool on) : c(c_), st(st_), stage(stage_)
     {
-        if (on && c->timing) {
+        if (on && ((c->timing >> stage) & 1u)) {
             a = pool_event(c);
             if (a && hipEventRecord(a, st) != hipSuccess) { c->ev_pool.push_back(a); a = nullptr; }
         }
@@ -197,7 +200,7 @@ gsr_status validate(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cams, 
     if (!tile_ok(o->tile_w, o->tile_h)) return fail(c, GSR_ERR_UNSUPPORTED, "tile shape must be 8x8, 16x16 or 32x8");
     int lb = o->lds_batch == 0 ? 64 : o->lds_batch;
     if (lb != 32 && lb != 64 && lb != 128 && lb != 256) return fail(c, GSR_ERR_UNSUPPORTED, "lds_batch must be 32, 64, 128 or 256");
-    if (o->flags & ~(uint32_t)(GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP | GSR_GRAPH | GSR_PERSISTENT))
+    if (o->flags & ~(uint32_t)(GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP | GSR_GRAPH | GSR_PERSISTENT | GSR_NO_SYNC))
         return fail(c, GSR_ERR_INVALID_ARG, "unknown flag bits");
     uint64_t tiles = 0;
     for (int v = 0; v < n_views; ++v) {
@@ -312,9 +315,10 @@ gsr_status ensure_tiles(gsr_ctx* c, uint32_t tiles, uint32_t blocks)
 }
 
 // everything of the forward after the camera upload; `plain` = read the pair
-// count back and size the pair buffers exactly (one host synchronisation)
+// count back and size the pair buffers for it (one host synchronisation), with
+// `headroom` at 1.5x the count + 4096 for later fixed-capacity frames
 gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, const gsr_opts* o, gsr_fwd_out* out,
-                           bool plain, bool render_only = false)
+                           bool plain, bool render_only = false, bool headroom = false)
 {
     const Layout& L = c->lay;
     const uint32_t n = (uint32_t)g->n, V = (uint32_t)L.cams.size(), vn = n * V;
@@ -329,7 +333,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     pa.rec = (float4*)c->rec.p; pa.depth_key = (uint32_t*)c->dkey0.p; pa.rect = (uint2*)c->rect.p;
     pa.tiles_touched = (uint32_t*)c->tt.p; pa.radius = (int32_t*)c->radius.p; pa.depth = (float*)c->depth.p;
     {
-        StageTimer tm(c, st, GSR_STAGE_PROJECT, plain);
+        StageTimer tm(c, st, GSR_STAGE_PROJECT, !c->capturing);
         HIP_TRY(c, launch_project_fwd(pa, o->sh_degree, o->sh_dtype == 1, st));
     }
 
@@ -337,7 +341,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     uint32_t* dk[2] = { (uint32_t*)c->dkey0.p, (uint32_t*)c->dkey1.p };
     uint32_t* od[2] = { (uint32_t*)c->ord0.p, (uint32_t*)c->ord1.p };
     {
-        StageTimer tm(c, st, GSR_STAGE_DEPTH_SORT, plain);
+        StageTimer tm(c, st, GSR_STAGE_DEPTH_SORT, !c->capturing);
         HIP_TRY(c, launch_iota_u32(od[0], vn, st));
         for (int pass = 0; pass < 4; ++pass)
             HIP_TRY(c, launch_radix_pass(dk[pass & 1], od[pass & 1], dk[(pass + 1) & 1], od[(pass + 1) & 1], nullptr,
@@ -345,7 +349,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     }
     // offsets of each record's pairs in depth order; total pair count
     {
-        StageTimer tm(c, st, GSR_STAGE_SCAN, plain);
+        StageTimer tm(c, st, GSR_STAGE_SCAN, !c->capturing);
         HIP_TRY(c, launch_gather_scan((const uint32_t*)c->tt.p, (const uint2*)c->rect.p, od[0], vn,
                                       (uint32_t*)c->offsets.p, (uint32_t*)c->tt_s.p, (uint2*)c->rect_s.p, counters,
                                       counters + 1, (uint32_t*)c->scan_tmp.p, st));
@@ -357,7 +361,9 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
         if (c->counters_host[1]) return fail(c, GSR_ERR_CAPACITY, "pair count exceeds 2^32");
         uint32_t P = c->counters_host[0];
         gsr_status s;
-        if ((s = ensure_pairs(c, P)) || (s = ensure_radix_tmp(c, std::max<size_t>(P, vn)))) return s;
+        if ((s = ensure_pairs(c, headroom ? (size_t)P + P / 2 + 4096 : (size_t)P)) ||
+            (s = ensure_radix_tmp(c, std::max<size_t>(c->pair_cap, vn))))
+            return s;
         cap = P;
     } else {
         cap = (uint32_t)c->pair_cap;
@@ -365,7 +371,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     uint32_t* pk[2] = { (uint32_t*)c->pk0.p, (uint32_t*)c->pk1.p };
     uint32_t* pv[2] = { (uint32_t*)c->pv0.p, (uint32_t*)c->pv1.p };
     {
-        StageTimer tm(c, st, GSR_STAGE_DUPLICATE, plain);
+        StageTimer tm(c, st, GSR_STAGE_DUPLICATE, !c->capturing);
         HIP_TRY(c, launch_duplicate(od[0], (const uint32_t*)c->offsets.p, (const uint32_t*)c->tt_s.p,
                                     (const uint2*)c->rect_s.p, dc, n, vn, counters, cap, pk[0], pv[0],
                                     (uint32_t*)c->emit_vg.p, counters + 1, (float4*)c->rec.p, st));
@@ -374,7 +380,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     int tile_bits = std::max(1, ilog2((int)std::max<uint32_t>(L.n_tiles, 2)));
     int passes = (tile_bits + 7) / 8;
     {
-        StageTimer tm(c, st, GSR_STAGE_TILE_SORT, plain);
+        StageTimer tm(c, st, GSR_STAGE_TILE_SORT, !c->capturing);
         for (int pass = 0; pass < passes; ++pass)
             HIP_TRY(c, launch_radix_pass(pk[pass & 1], pv[pass & 1], pk[(pass + 1) & 1], pv[(pass + 1) & 1], counters,
                                          cap, 8 * pass, (uint32_t*)c->radix_tmp.p, st));
@@ -382,7 +388,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     const int sb = passes & 1;
     const bool persist = (o->flags & GSR_PERSISTENT) != 0;
     {
-        StageTimer tm(c, st, GSR_STAGE_RANGES, plain);
+        StageTimer tm(c, st, GSR_STAGE_RANGES, !c->capturing);
         HIP_TRY(c, launch_fill_u32((uint32_t*)c->ranges.p, 0u, (size_t)L.n_tiles * 2, st));
         HIP_TRY(c, launch_ranges(pk[sb], counters, cap, (uint2*)c->ranges.p, st));
         // the persistent blend kernels' queue heads (forward and backward sets)
@@ -399,11 +405,11 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     ba.queues = persist ? (uint32_t*)c->queues.p : nullptr;
     ba.render_only = render_only ? 1 : 0;
     {
-        StageTimer tm(c, st, GSR_STAGE_BLEND_FWD, plain);
+        StageTimer tm(c, st, GSR_STAGE_BLEND_FWD, !c->capturing);
         HIP_TRY(c, launch_blend_fwd(ba, o->lds_batch == 0 ? 64 : o->lds_batch, st));
     }
     if (!render_only) {
-        StageTimer tm(c, st, GSR_STAGE_ENTROPY_MEAN, plain);
+        StageTimer tm(c, st, GSR_STAGE_ENTROPY_MEAN, !c->capturing);
         HIP_TRY(c, launch_entropy_mean((const float*)c->block_H.p, dc, (int)V, L.n_hchunks, (double*)c->hchunk.p,
                                        out->entropy_mean, st));
     }
@@ -415,12 +421,12 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
 
 gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, const gsr_opts* o,
                             const gsr_fwd_out* saved, const float* grad_rgb, const float* grad_H, const float* grad_LE,
-                            gsr_grads* gr, bool plain)
+                            gsr_grads* gr)
 {
     const Layout& L = c->lay;
     const uint32_t n = (uint32_t)g->n, V = (uint32_t)L.cams.size(), vn = n * V;
     const CamDev* dc = (const CamDev*)c->cams.p;
-    StageTimer tb(c, st, GSR_STAGE_BLEND_BWD, plain);
+    StageTimer tb(c, st, GSR_STAGE_BLEND_BWD, !c->capturing);
     // a new stamp for the per-pair rows this backward writes
     HIP_TRY(c, launch_bump_u32((uint32_t*)c->counters.p + 4, st));
     uint32_t* pv[2] = { (uint32_t*)c->pv0.p, (uint32_t*)c->pv1.p };
@@ -437,13 +443,13 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     HIP_TRY(c, launch_blend_bwd(bb, o->lds_batch == 0 ? 64 : o->lds_batch, st));
     tb.stop();
     {
-        StageTimer tr(c, st, GSR_STAGE_GRAD_REDUCE, plain);
+        StageTimer tr(c, st, GSR_STAGE_GRAD_REDUCE, !c->capturing);
         HIP_TRY(c, launch_grad_reduce((const float*)c->pair_grad.p, (const uint32_t*)c->counters.p + 4,
                                       (const uint32_t*)c->emit_vg.p,
                                       vn, (const uint32_t*)c->counters.p, (uint32_t)c->pair_cap_used,
                                       (float*)c->grad2d.p, c->seg_carry.p, st));
     }
-    StageTimer tp(c, st, GSR_STAGE_PROJECT_BWD, plain);
+    StageTimer tp(c, st, GSR_STAGE_PROJECT_BWD, !c->capturing);
     ProjectBwdArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
     pa.n = n; pa.n_views = (int32_t)V; pa.flags = o->flags; pa.cams = dc; pa.grad2d = (const float*)c->grad2d.p;
@@ -480,6 +486,43 @@ gsr_status wait_replay(gsr_ctx* c)
         HIP_TRY(c, hipEventSynchronize(c->ev_replay));
         c->replay_pending = false;
     }
+    return GSR_OK;
+}
+
+// GSR_NO_SYNC forward: the capacity path of graph mode, launched eagerly.  The
+// camera upload goes through pinned memory and the frame's pair count comes back
+// asynchronously into counters_host; ev_replay (waited for by the next call that
+// touches either host buffer) covers both.
+gsr_status enqueue_nosync(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, const gsr_opts* o, gsr_fwd_out* out,
+                          bool render_only)
+{
+    const Layout& L = c->lay;
+    const size_t cam_bytes = sizeof(CamDev) * L.cams.size();
+    gsr_status s;
+    if (!c->nosync_ready) {                          // first such frame: exact sizing, then head room
+        // (the buffers grow before the pairs are written, so this frame's state stays valid)
+        HIP_TRY(c, hipMemcpyAsync(c->cams.p, L.cams.data(), cam_bytes, hipMemcpyHostToDevice, st));
+        if ((s = enqueue_forward(c, st, g, o, out, true, render_only, true))) return s;
+        c->nosync_count = false;
+        c->nosync_ready = true;
+        return GSR_OK;
+    }
+    if (c->nosync_count) {                           // the previous frame's count (wait_replay has run)
+        const size_t P = c->counters_host[0];
+        if (P + P / 10 > c->pair_cap) {
+            HIP_TRY(c, hipStreamSynchronize(st));    // buffers in use may be reallocated
+            if ((s = ensure_pairs(c, P + P / 2 + 4096)) ||
+                (s = ensure_radix_tmp(c, std::max<size_t>(c->pair_cap, c->vn))))
+                return s;
+        }
+    }
+    std::memcpy(c->cams_host, L.cams.data(), cam_bytes);
+    HIP_TRY(c, hipMemcpyAsync(c->cams.p, c->cams_host, cam_bytes, hipMemcpyHostToDevice, st));
+    if ((s = enqueue_forward(c, st, g, o, out, false, render_only))) return s;
+    HIP_TRY(c, hipMemcpyAsync(c->counters_host, c->counters.p, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipEventRecord(c->ev_replay, st));
+    c->replay_pending = true;
+    c->nosync_count = true;
     return GSR_OK;
 }
 
@@ -587,7 +630,9 @@ gsr_status gsr_forward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const g
     c->fopts = *o;
     bool graph = (o->flags & GSR_GRAPH) != 0;
     const void* outs[5] = { out->rgb, out->entropy, out->t_final, out->n_contrib, out->entropy_mean };
-    if (!graph) {
+    if (!graph && (o->flags & GSR_NO_SYNC)) {
+        if ((s = enqueue_nosync(c, st, g, o, out, false))) return s;
+    } else if (!graph) {
         HIP_TRY(c, hipMemcpyAsync(c->cams.p, c->lay.cams.data(), sizeof(CamDev) * L.cams.size(), hipMemcpyHostToDevice, st));
         if ((s = enqueue_forward(c, st, g, o, out, true))) return s;
     } else {
@@ -608,8 +653,10 @@ gsr_status gsr_forward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const g
             hipGraph_t graph_ = nullptr;
             hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
+                c->capturing = true;
                 e = hipMemcpyAsync(c->cams.p, c->cams_host, sizeof(CamDev) * L.cams.size(), hipMemcpyHostToDevice, cs);
                 gsr_status fs = e == hipSuccess ? enqueue_forward(c, cs, g, o, out, false) : GSR_ERR_HIP;
+                c->capturing = false;
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(c->counters_host, c->counters.p, 8, hipMemcpyDeviceToHost, cs);
                 hipError_t e2 = hipStreamEndCapture(cs, &graph_);
@@ -664,8 +711,12 @@ gsr_status gsr_render(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gs
     gsr_fwd_out out;
     std::memset(&out, 0, sizeof out);
     out.rgb = rgb;
-    HIP_TRY(c, hipMemcpyAsync(c->cams.p, c->lay.cams.data(), sizeof(CamDev) * L.cams.size(), hipMemcpyHostToDevice, st));
-    if ((s = enqueue_forward(c, st, g, o, &out, true, true))) return s;
+    if (o->flags & GSR_NO_SYNC) {
+        if ((s = enqueue_nosync(c, st, g, o, &out, true))) return s;
+    } else {
+        HIP_TRY(c, hipMemcpyAsync(c->cams.p, c->lay.cams.data(), sizeof(CamDev) * L.cams.size(), hipMemcpyHostToDevice, st));
+        if ((s = enqueue_forward(c, st, g, o, &out, true, true))) return s;
+    }
     // a render saves no state: no backward may follow it
     c->frame += 1;
     c->have_frame = true;
@@ -694,7 +745,7 @@ gsr_status gsr_backward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
     if (!(o->flags & GSR_GRAPH))
-        return enqueue_backward(c, st, g, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, gr, true);
+        return enqueue_backward(c, st, g, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, gr);
 
     const void* outs[5] = { saved->rgb, saved->entropy, saved->t_final, saved->n_contrib, saved->entropy_mean };
     FrameKey k = make_key(g, cams, n_views, o, outs);
@@ -709,7 +760,9 @@ gsr_status gsr_backward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
         hipGraph_t graph_ = nullptr;
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            gsr_status bs = enqueue_backward(c, cs, g, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, gr, false);
+            c->capturing = true;
+            gsr_status bs = enqueue_backward(c, cs, g, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, gr);
+            c->capturing = false;
             hipError_t e2 = hipStreamEndCapture(cs, &graph_);
             e = bs != GSR_OK ? hipErrorUnknown : e2;
         }
@@ -965,7 +1018,7 @@ gsr_status gsr_base_loss(gsr_ctx* c, void* stream, const gsr_camera* cams, int32
 gsr_status gsr_set_timing(gsr_ctx* c, int32_t enable)
 {
     if (!c) return GSR_ERR_INVALID_ARG;
-    c->timing = enable != 0;
+    c->timing = (uint32_t)enable & (uint32_t)GSR_TIME_ALL;
     return GSR_OK;
 }
 
@@ -1112,7 +1165,7 @@ gsr_status gsr_autotune(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
         for (int lb : batches) {
             gsr_opts o = *inout;
             o.tile_w = sh[0]; o.tile_h = sh[1]; o.lds_batch = lb;
-            o.flags = (o.flags & ~(uint32_t)(GSR_GRAPH | GSR_PERSISTENT)) | (pe ? GSR_PERSISTENT : 0u);
+            o.flags = (o.flags & ~(uint32_t)(GSR_GRAPH | GSR_PERSISTENT | GSR_NO_SYNC)) | (pe ? GSR_PERSISTENT : 0u);
             double t = 0.0;
             for (int it = 0; it < 4 && s == GSR_OK; ++it) {
                 if (it == 1) (void)hipEventRecord(e0, st);

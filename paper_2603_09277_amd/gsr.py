@@ -17,7 +17,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsr.so")
 
-GSR_DILATE, GSR_JACOBIAN_CLAMP, GSR_COLOR_CLAMP, GSR_GRAPH, GSR_PERSISTENT = 1, 2, 4, 8, 16
+GSR_DILATE, GSR_JACOBIAN_CLAMP, GSR_COLOR_CLAMP, GSR_GRAPH, GSR_PERSISTENT, GSR_NO_SYNC = 1, 2, 4, 8, 16, 32
 GSR_DEFAULT_FLAGS = GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP
 
 BUF_RECORDS, BUF_RADIUS, BUF_DEPTH, BUF_TILES_TOUCHED, BUF_PAIR_VALUES, BUF_PAIR_TILES, BUF_RANGES, BUF_GRAD2D = range(8)
@@ -365,8 +365,12 @@ class Rasterizer:
                                             _ptr(grad_rgb), _ptr(loss)))
         return grad_rgb, loss
 
-    def set_timing(self, enable: bool):
-        _check(self._ctx, lib().gsr_set_timing(self._ctx, 1 if enable else 0))
+    def set_timing(self, enable: bool, stages: Optional[Sequence[str]] = None):
+        """Time every stage (or only `stages`, names from STAGES) with HIP events; False stops."""
+        mask = 0
+        if enable:
+            mask = (1 << len(STAGES)) - 1 if stages is None else sum(1 << STAGES.index(s) for s in stages)
+        _check(self._ctx, lib().gsr_set_timing(self._ctx, mask))
 
     def stage_times(self, reset: bool = True):
         """{stage: (total_ms, launches)} accumulated since the last reset (synchronises)."""

@@ -372,6 +372,55 @@ def test_graph_mode_replays_match_plain(R, tiny):
     G.close()
 
 
+def test_no_sync_mode_matches_plain_and_grows(R, tiny):
+    """GSR_NO_SYNC: eager launches at a fixed pair capacity give the plain mode's outputs
+    bit for bit and its gradients, with stage timing; a frame past the capacity is flagged
+    as an overflow and the next frame runs at a grown capacity."""
+    scene, cams = tiny
+    t = to_dev(scene)
+    plain = gsr.RasterOptions(tile=(16, 16), sh_degree=0)
+    ref = gpu_forward(R, t, cams, plain)
+    p_small = R.stats(1)["pairs"]
+    g_rgb = torch.full_like(ref["rgb"], 2e-5)
+    g_le = torch.full((1,), GAMMA, device=DEV)
+    gref = gpu_backward(R, t, cams, plain, ref, g_rgb, None, g_le)
+    big = dict(t)
+    big["scales"] = (t["scales"] * 6.0).contiguous()
+    ref_big = gpu_forward(R, big, cams, plain)
+    p_big = R.stats(1)["pairs"]
+    assert p_big > 1.5 * p_small + 4096
+    gref_big = gpu_backward(R, big, cams, plain, ref_big, g_rgb, None, g_le)
+    G = gsr.Rasterizer(max_views=1)
+    G.set_timing(True)
+    ns = gsr.RasterOptions(tile=(16, 16), sh_degree=0, flags=gsr.GSR_DEFAULT_FLAGS | gsr.GSR_NO_SYNC)
+    for rep in range(3):                          # the first frame sizes the capacity, the others do not wait
+        o = G.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, ns)
+        gg = G.backward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, ns, o, g_rgb, None, g_le)
+        torch.cuda.synchronize()
+        for k in ("rgb", "entropy", "t_final", "n_contrib", "entropy_mean"):
+            assert torch.equal(o[k], ref[k]), (rep, k)
+        for k in KEYS:
+            assert rel_norm(gg[k].cpu().numpy(), gref[k]) < 1e-6, (rep, k)
+        assert not G.stats(1)["overflow"]
+    times = G.stage_times()
+    assert times["blend_fwd"][1] == 3 and times["blend_bwd"][1] == 3 and times["blend_bwd"][0] > 0
+    # six times the scales: more pairs than the capacity the small frames set
+    o = G.forward(big["means"], big["scales"], big["quats"], big["opacities"], big["sh"], cams, ns)
+    assert G.stats(1)["overflow"]
+    for rep in range(2):
+        o = G.forward(big["means"], big["scales"], big["quats"], big["opacities"], big["sh"], cams, ns)
+        gg = G.backward(big["means"], big["scales"], big["quats"], big["opacities"], big["sh"], cams, ns, o, g_rgb,
+                        None, g_le)
+        torch.cuda.synchronize()
+        st = G.stats(1)
+        assert not st["overflow"] and st["pairs"] == p_big, rep
+        for k in ("rgb", "entropy", "t_final", "n_contrib", "entropy_mean"):
+            assert torch.equal(o[k], ref_big[k]), (rep, k)
+        for k in KEYS:
+            assert rel_norm(gg[k].cpu().numpy(), gref_big[k]) < 1e-6, (rep, k)
+    G.close()
+
+
 def test_autograd_function_matches_raw(R, tiny):
     scene, cams = tiny
     t = {k: v.clone().requires_grad_(True) for k, v in to_dev(scene).items()}

@@ -85,6 +85,8 @@ def parse():
                          "is laid out over this many")
     ap.add_argument("--train-gaussians", type=int, default=3_300_000)
     ap.add_argument("--train-res", default="1296x840")
+    ap.add_argument("--train-regulariser", choices=["entropy", "opacity", "none"], default="entropy",
+                    help="entropy constraint (Eq. 12), the opacity regulariser it is compared with, or neither")
     return ap.parse_args()
 
 
@@ -163,7 +165,8 @@ def run_train(args, torch, dev):
     from paper_2603_09277_amd.train import TrainConfig, Trainer
     W, H = (int(x) for x in args.train_res.split("x"))
     cfg = TrainConfig(n_gaussians=args.train_gaussians, width=W, height=H, iterations=args.train_iters,
-                      tile=tuple(int(x) for x in args.tile.split("x")), lds=args.lds)
+                      tile=tuple(int(x) for x in args.tile.split("x")), lds=args.lds,
+                      regulariser=args.train_regulariser)
     tr = Trainer(cfg, dev)
     tr.prepare()
     p0 = tr.psnr()
@@ -172,6 +175,7 @@ def run_train(args, torch, dev):
     tr.restart()
     res = tr.run(log_every=5000)
     p1 = tr.psnr()
+    ls = tr.list_stats()
     ips = res["iters_per_s"]
     result = {
         "metric": METRIC_TRAIN, "value": round(ips, 3), "unit": "iters/s", "n_gpus": 1, "steps": cfg.iterations,
@@ -182,10 +186,12 @@ def run_train(args, torch, dev):
                    "n_gaussians": cfg.n_gaussians, "views": cfg.n_views, "resolution": [W, H],
                    "iterations": cfg.iterations, "epoch_views": tr.epoch_views, "reset_every_epochs": cfg.reset_every,
                    "zeta": cfg.zeta, "gamma": cfg.gamma, "lambda": cfg.lam, "r_max": tr.r_max,
+                   "regulariser": cfg.regulariser + (f" ({cfg.opacity_weight})" if cfg.regulariser == "opacity" else ""),
                    "tile": list(cfg.tile), "lds_batch": cfg.lds},
         "train_seconds": round(res["seconds"], 3),
         "seconds_per_30k_iters": round(30000.0 / ips, 2),
         "psnr_before": round(p0, 3), "psnr_after": round(p1, 3),
+        "final_mean_list_len": round(ls["mean_list_len"], 2), "final_mean_entropy": round(ls["mean_entropy"], 4),
         "paper_context": "Tab. 1: 99.58 s for 30K iterations of the whole training, 3.3M Gaussians, Mip-NeRF 360, "
                          "one RTX 5090 D (not the same workload)",
         "roofline": None, "cpu_baseline": None,

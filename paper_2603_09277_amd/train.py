@@ -47,6 +47,8 @@ class TrainConfig:
     epoch_views: int = 0           # images per epoch, sampled with replacement; 0: iterations // epochs
     lam: float = 0.2               # D-SSIM weight, Eq. 6
     gamma: float = 0.015           # entropy weight, Eq. 12
+    regulariser: str = "entropy"   # "entropy" (Eq. 12), "opacity" (the Sec. 4 comparator) or "none"
+    opacity_weight: float = 3.0    # weight of the opacity regulariser in the Sec. 4 comparison
     zeta: float = 0.2              # scale-reset factor, Eq. 7
     reset_every: int = 20          # epochs between scale resets (Sec. 4)
     r_cap: int = 4
@@ -106,6 +108,9 @@ class Trainer:
         self._g_rgb: Optional[torch.Tensor] = None
         self._g_rgb_eval: Optional[torch.Tensor] = None
         self._loss = torch.zeros(2, device=device)        # (1 - lam) L1, lam D-SSIM of the latest step
+        self._loss_o = torch.zeros(1, device=device)      # opacity regulariser of the latest step
+        if cfg.regulariser not in ("entropy", "opacity", "none"):
+            raise ValueError(f"unknown regulariser {cfg.regulariser!r}")
         self._init = {k: (self.raw[k].clone(), self.act[k].clone()) for k in self.raw}
 
     def restart(self) -> None:
@@ -167,9 +172,12 @@ class Trainer:
         g_rgb = self._g_rgb
         self.R.base_loss([cam], rgb, tgt, cfg.lam, g_rgb, self._loss[0:1], self._loss[1:2])
         ep = self.epoch(it)
-        entropy_on = (ep % cfg.reset_every) % 2 == 1          # every other epoch of a reset period
+        reg_on = (ep % cfg.reset_every) % 2 == 1              # every other epoch of a reset period
+        entropy_on = reg_on and cfg.regulariser == "entropy"
         g = self.R.backward(a["means"], a["scales"], a["quats"], a["opacities"], a["sh"], [cam], self.opts, out,
                             g_rgb, None, self._g_le if entropy_on else self._g_le0, self.grads)
+        if reg_on and cfg.regulariser == "opacity":            # dL_O/dsigma added to the opacity gradient
+            self.R.opacity_loss(a["opacities"], cfg.opacity_weight, g["opacities"], self._loss_o)
         self.step_no += 1
         for k in self.raw:
             act = None if self.kind[k] == 0 else self.act[k]
@@ -192,6 +200,17 @@ class Trainer:
                              self._loss[0:1], self._loss[1:2])
             tot += float(self._loss.sum())
         return tot / len(self.cams)
+
+    def list_stats(self, cams=None) -> dict:
+        """Mean per-tile list length and mean per-pixel entropy (nats) of the current scene over `cams`."""
+        cams = self.test_cams if cams is None else cams
+        a = self.act
+        mean_len, ent = 0.0, 0.0
+        for cam in cams:
+            out = self.R.forward(a["means"], a["scales"], a["quats"], a["opacities"], a["sh"], [cam], self.opts)
+            mean_len += self.R.stats(1)["mean_len"]
+            ent += float(out["entropy_mean"][0])
+        return {"mean_list_len": mean_len / len(cams), "mean_entropy": ent / len(cams)}
 
     def psnr(self, cams=None) -> float:
         cams = self.test_cams if cams is None else cams

@@ -202,3 +202,59 @@ def test_training_run_learns_and_is_deterministic():
         tr.R.close()
     for k in finals[0]:
         assert np.array_equal(finals[0][k], finals[1][k]), k
+
+
+def test_training_with_opacity_regulariser_adds_its_gradient():
+    """The comparator of the Sec. 4 ablation: on an epoch where the regulariser is on, the
+    opacity gradient of the step is the image and entropy-free gradient plus dL_O/dsigma
+    (weight 3.0, mean over Gaussians) at the step's opacities."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import dataclasses
+    from paper_2603_09277_amd.train import Trainer
+    cfg = _small_cfg()
+    tr_o = Trainer(dataclasses.replace(cfg, regulariser="opacity"))
+    tr_n = Trainer(dataclasses.replace(cfg, regulariser="none"))
+    for it in range(cfg.epoch_views):                # epoch 0: no regulariser, identical runs
+        tr_o.step(it)
+        tr_n.step(it)
+    torch.cuda.synchronize()
+    for k in tr_o.raw:
+        assert torch.equal(tr_o.raw[k], tr_n.raw[k]), k
+    op = tr_o.act["opacities"].cpu().numpy().copy()
+    it = cfg.epoch_views                             # first iteration of epoch 1: the regulariser is on
+    tr_o.step(it)
+    tr_n.step(it)
+    torch.cuda.synchronize()
+    g_o = tr_o.grads["opacities"].cpu().numpy().astype(np.float64)
+    g_n = tr_n.grads["opacities"].cpu().numpy().astype(np.float64)
+    L_want, g_want = orc.opacity_loss(op, 3.0)
+    assert abs(float(tr_o._loss_o[0]) - L_want) <= 1e-6 * L_want
+    # (a + b) - a recovers b up to one rounding of the sum; b itself is FP32 (exp and 4 products)
+    err = np.abs((g_o - g_n) - g_want)
+    assert np.all(err <= 2.0 ** -22 * (np.abs(g_n) + np.abs(g_want)) + 1e-6 * np.abs(g_want)), err.max()
+    tr_o.R.close()
+    tr_n.R.close()
+
+
+@pytest.mark.parametrize("reg", ["opacity", "none"])
+def test_training_run_with_other_regularisers(reg):
+    """The comparator runs of the Sec. 4 ablation: the opacity regulariser in place of the
+    entropy term (its gradient is added to the opacity gradient), or no regulariser."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import dataclasses
+    from paper_2603_09277_amd.train import Trainer
+    tr = Trainer(dataclasses.replace(_small_cfg(), regulariser=reg, iterations=64))
+    lo0 = float(tr.R.opacity_loss(tr.act["opacities"], 3.0)[0])
+    p0 = tr.psnr()
+    tr.run()
+    p1 = tr.psnr()
+    lo1 = float(tr.R.opacity_loss(tr.act["opacities"], 3.0)[0])
+    ls = tr.list_stats()
+    print(f"{reg}: psnr {p0:.2f} -> {p1:.2f}, L_O {lo0:.4f} -> {lo1:.4f}, mean list {ls['mean_list_len']:.1f}, "
+          f"entropy {ls['mean_entropy']:.3f}", flush=True)
+    assert math.isfinite(p1) and ls["mean_list_len"] > 0 and math.isfinite(ls["mean_entropy"])
+    if reg == "none":
+        assert p1 > p0 + 0.5
+    tr.R.close()

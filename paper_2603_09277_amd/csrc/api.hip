@@ -53,7 +53,7 @@ struct gsr_ctx {
 
     // grow-only device buffers
     Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, tt_s, rect_s, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
-    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, queues, block_H, block_cnt, hchunk, counters, l1_tmp, reg_tmp, ssim_tmp;
+    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, tile_order, queues, block_H, block_cnt, hchunk, counters, l1_tmp, reg_tmp, ssim_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
     uint64_t gen_fwd = 0, gen_bwd = 0;
@@ -306,7 +306,9 @@ gsr_status ensure_radix_tmp(gsr_ctx* c, size_t items)
 gsr_status ensure_tiles(gsr_ctx* c, uint32_t tiles, uint32_t blocks)
 {
     gsr_status s;
-    if ((s = grow(c, c->ranges, (size_t)std::max<uint32_t>(tiles, 1) * 8)) ||
+    // ranges, then the tile-order class histogram (cleared with the ranges), then the tile order
+    if ((s = grow(c, c->ranges, ((size_t)std::max<uint32_t>(tiles, 1) * 2 + kTileHistWords) * 4)) ||
+        (s = grow(c, c->tile_order, (size_t)std::max<uint32_t>(tiles, 1) * 4)) ||
         (s = grow(c, c->block_H, (size_t)std::max<uint32_t>(blocks, 1) * 4)) ||
         (s = grow(c, c->block_cnt, (size_t)std::max<uint32_t>(blocks, 1) * 16)) ||
         (s = grow(c, c->hchunk, (size_t)(blocks / kRedChunk + 64) * 8)))
@@ -389,8 +391,12 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     const bool persist = (o->flags & GSR_PERSISTENT) != 0;
     {
         StageTimer tm(c, st, GSR_STAGE_RANGES, !c->capturing);
-        HIP_TRY(c, launch_fill_u32((uint32_t*)c->ranges.p, 0u, (size_t)L.n_tiles * 2, st));
+        HIP_TRY(c, launch_fill_u32((uint32_t*)c->ranges.p, 0u, (size_t)L.n_tiles * 2 + kTileHistWords, st));
         HIP_TRY(c, launch_ranges(pk[sb], counters, cap, (uint2*)c->ranges.p, st));
+        // hardware dispatch visits the tiles longest list first (persistent kernels keep their queues)
+        if (!persist)
+            HIP_TRY(c, launch_tile_order((const uint2*)c->ranges.p, L.n_tiles, (uint32_t*)c->ranges.p + 2 * (size_t)L.n_tiles,
+                                         (uint32_t*)c->tile_order.p, st));
         // the persistent blend kernels' queue heads (forward and backward sets)
         if (persist) HIP_TRY(c, launch_fill_u32((uint32_t*)c->queues.p, 0u, 2 * kQueues * kQueueStride, st));
     }
@@ -404,6 +410,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     ba.block_cnt = (uint4*)c->block_cnt.p;
     ba.queues = persist ? (uint32_t*)c->queues.p : nullptr;
     ba.render_only = render_only ? 1 : 0;
+    ba.tile_order = persist ? nullptr : (const uint32_t*)c->tile_order.p;
     {
         StageTimer tm(c, st, GSR_STAGE_BLEND_FWD, !c->capturing);
         HIP_TRY(c, launch_blend_fwd(ba, o->lds_batch == 0 ? 64 : o->lds_batch, st));
@@ -439,6 +446,7 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     bb.grad_LE = grad_LE; bb.pair_grad = (float*)c->pair_grad.p; bb.stamp = (const uint32_t*)c->counters.p + 4;
     const bool persist = (o->flags & GSR_PERSISTENT) != 0;
     bb.queues = persist ? (uint32_t*)c->queues.p + kQueues * kQueueStride : nullptr;
+    bb.tile_order = persist ? nullptr : (const uint32_t*)c->tile_order.p;
     if (persist) HIP_TRY(c, launch_fill_u32(bb.queues, 0u, kQueues * kQueueStride, st));
     HIP_TRY(c, launch_blend_bwd(bb, o->lds_batch == 0 ? 64 : o->lds_batch, st));
     tb.stop();
@@ -583,7 +591,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     drop_graphs(c);
     Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->tt_s, &c->rect_s, &c->radius,
                    &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
-                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->queues, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->reg_tmp, &c->ssim_tmp,
+                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->tile_order, &c->queues, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->reg_tmp, &c->ssim_tmp,
                    &c->l1_tmp };
     for (Dev* d : all) free_dev(*d);
     for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }

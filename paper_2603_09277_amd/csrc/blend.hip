@@ -256,7 +256,19 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
     __shared__ int32_t s_pos[kWavesPerGroup][B]; // position in the tile list
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
     WaveQueue wq;
-    uint32_t item = PERSIST ? next_item_wave(wq, a.queues, a.n_blocks, lane) : blockIdx.x * kWavesPerGroup + wid;
+    uint32_t item;
+    if (PERSIST) {
+        item = next_item_wave(wq, a.queues, a.n_blocks, lane);
+    } else if (a.tile_order) {                   // hardware dispatch, longest tiles first
+        if (a.spt == 4) {
+            item = a.tile_order[blockIdx.x] * kWavesPerGroup + wid;  // one tile per workgroup
+        } else {
+            const uint32_t i = blockIdx.x * kWavesPerGroup + wid;    // one tile per wavefront
+            item = i < a.n_blocks ? a.tile_order[i] : a.n_blocks;
+        }
+    } else {
+        item = blockIdx.x * kWavesPerGroup + wid;
+    }
     for (; item < a.n_blocks; item = PERSIST ? next_item_wave(wq, a.queues, a.n_blocks, lane) : a.n_blocks) {
     const uint32_t wb = item;
     const BlockGeom g = block_geom(a.cams, a.n_views, wb, lane, a.tile_shift_x, a.tile_shift_y, a.spt);
@@ -487,7 +499,10 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     };
     uint32_t item;
     if (PERSIST) item = next();
-    else item = SHARED ? blockIdx.x : blockIdx.x * kWavesPerGroup + wid;
+    else if (a.tile_order) {                     // hardware dispatch, longest tiles first
+        const uint32_t i = SHARED ? blockIdx.x : blockIdx.x * kWavesPerGroup + wid;
+        item = i < n_items ? a.tile_order[i] : n_items;
+    } else item = SHARED ? blockIdx.x : blockIdx.x * kWavesPerGroup + wid;
     for (; item < n_items; item = next()) {
     const uint32_t tile_id = item;
     const uint32_t wb = SHARED ? tile_id * kWavesPerGroup + wid : tile_id;

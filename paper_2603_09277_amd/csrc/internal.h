@@ -109,6 +109,7 @@ struct BlendFwdArgs {
     uint4* block_cnt;                     // [n_blocks] (alpha evaluations, sum of n_contrib, blended, 0)
     uint32_t* queues;                     // persistent mode: kQueues heads kQueueStride words apart, zeroed; or null
     int32_t render_only;                  // 1: colour only (no entropy, no saved state)
+    const uint32_t* tile_order;           // [n_tiles] tiles, longest list first (hardware dispatch); or null
 };
 
 struct BlendBwdArgs {
@@ -128,6 +129,7 @@ struct BlendBwdArgs {
     float* pair_grad;                     // [P][10] per-pair gradient rows, emission order
     const uint32_t* stamp;                // this backward's row stamp
     uint32_t* queues;                     // persistent mode: kQueues heads kQueueStride words apart, zeroed; or null
+    const uint32_t* tile_order;           // [n_tiles] tiles, longest list first (hardware dispatch); or null
 };
 
 // ---- launchers (return hipError_t of the launch) ----
@@ -168,6 +170,10 @@ hipError_t launch_bump_u32(uint32_t* p, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 // p[i] = i
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
+// order[n_tiles]: the tiles by decreasing list length (16 classes per octave);
+// hist: 512 words, zeroed (bucket counts, then bucket fill counters)
+constexpr uint32_t kTileHistWords = 512;
+hipError_t launch_tile_order(const uint2* ranges, uint32_t n_tiles, uint32_t* hist, uint32_t* order, hipStream_t s);
 // per-tile [start, end) of the sorted pairs
 hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges, hipStream_t s);
 

@@ -696,6 +696,77 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Tile order for the blend kernels: longest list first.  Tile list lengths are
+// very uneven (the 99th percentile is several times the mean), and with the
+// tiles in spatial order a few long tiles dispatched late decide the end of the
+// grid.  A counting sort over 256 length classes (16 per octave of the length)
+// gives the hardware dispatcher the long tiles first and leaves the short ones
+// to fill the end.  Only the scheduling changes: a tile's results do not depend
+// on the workgroup that handles it, so the order inside a class (set by
+// atomics) is immaterial.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t tile_bucket(uint2 r)
+{
+    const float c = 16.f * __builtin_amdgcn_logf((float)(r.y - r.x) + 1.f);   // 16 log2(len + 1)
+    return 255u - (c < 255.f ? (uint32_t)c : 255u);                            // bucket 0: longest
+}
+
+__global__ __launch_bounds__(kThreads) void tile_hist_kernel(const uint2* ranges, uint32_t n_tiles, uint32_t* hist)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < n_tiles; t += gridDim.x * kThreads)
+        atomicAdd(&h[tile_bucket(ranges[t])], 1u);
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(kThreads) void tile_order_kernel(const uint2* ranges, uint32_t n_tiles,
+                                                              const uint32_t* hist, uint32_t* fill, uint32_t* order)
+{
+    __shared__ uint32_t s_start[256], s_cnt[256], s_base[256];
+    // exclusive prefix of the class counts (the same in every workgroup)
+    const uint32_t mine = hist[threadIdx.x];
+    s_start[threadIdx.x] = mine;
+    __syncthreads();
+    for (uint32_t o = 1; o < 256; o <<= 1) {
+        const uint32_t v = threadIdx.x >= o ? s_start[threadIdx.x - o] : 0u;
+        __syncthreads();
+        s_start[threadIdx.x] += v;
+        __syncthreads();
+    }
+    s_start[threadIdx.x] -= mine;
+    const uint32_t nchunk = (n_tiles + kThreads - 1) / kThreads;
+    for (uint32_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        s_cnt[threadIdx.x] = 0u;
+        __syncthreads();
+        const uint32_t t = ch * kThreads + threadIdx.x;
+        uint32_t b = 0, local = 0;
+        if (t < n_tiles) {
+            b = tile_bucket(ranges[t]);
+            local = atomicAdd(&s_cnt[b], 1u);
+        }
+        __syncthreads();
+        if (s_cnt[threadIdx.x]) s_base[threadIdx.x] = atomicAdd(&fill[threadIdx.x], s_cnt[threadIdx.x]);
+        __syncthreads();
+        if (t < n_tiles) order[s_start[b] + s_base[b] + local] = t;
+        __syncthreads();
+    }
+}
+
+hipError_t launch_tile_order(const uint2* ranges, uint32_t n_tiles, uint32_t* hist, uint32_t* order, hipStream_t s)
+{
+    if (n_tiles == 0) return hipSuccess;
+    uint32_t grid = (n_tiles + kThreads - 1) / kThreads;
+    if (grid > 1024) grid = 1024;
+    hipLaunchKernelGGL(tile_hist_kernel, dim3(grid), dim3(kThreads), 0, s, ranges, n_tiles, hist);
+    hipLaunchKernelGGL(tile_order_kernel, dim3(grid), dim3(kThreads), 0, s, ranges, n_tiles, hist, hist + 256, order);
+    return hipGetLastError();
+}
+
 hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges, hipStream_t s)
 {
     if (cap == 0) return hipSuccess;

@@ -35,9 +35,11 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 # Algorithmic work of the blend kernels (the derivation is in the design notes).
-# Per pixel the method walks its list: every position visited costs the alpha
+# Per pixel the method walks its list: every position it tests costs the alpha
 # test; a position that is blended (alpha >= 1/255 before the ray stopped) costs
-# the blending (forward) or its gradient (backward) on top.
+# the blending (forward) or its gradient (backward) on top.  Positions whose
+# Gaussian the exact 8x8-block cull proves unreachable are not tested and not
+# counted: the counts are the kernels' own (tested_fwd, tested_bwd, blended).
 OPS_ALPHA_TEST = 11         # FP32 VALU ops: offset, exponent, exp2, opacity scale, clamp, skip test
 OPS_BLEND_FWD = 10          # per blended pair: transmittance, stop test, colour, entropy term
 OPS_BLEND_BWD = 49          # per blended pair: T recovery, dC/dalpha, Alg. 1, 9 gradient terms and their sums
@@ -48,8 +50,8 @@ OPS_ENTROPY = 2             # of OPS_BLEND_FWD: log2 and the entropy FMA (absent
 
 def blend_ops(kind, st, render=False):
     if kind == "blend_fwd":
-        return OPS_ALPHA_TEST * st["evals_fwd"] + (OPS_BLEND_FWD - (OPS_ENTROPY if render else 0)) * st["blended"]
-    return OPS_ALPHA_TEST * st["evals_bwd"] + OPS_BLEND_BWD * st["blended"]
+        return OPS_ALPHA_TEST * st["tested_fwd"] + (OPS_BLEND_FWD - (OPS_ENTROPY if render else 0)) * st["blended"]
+    return OPS_ALPHA_TEST * st["tested_bwd"] + OPS_BLEND_BWD * st["blended"]
 
 
 def parse():
@@ -303,14 +305,15 @@ def main():
         R.set_timing(False)
         stages = R.stage_times(reset=True)
     if args.per_view:      # statistics of every view: forward each once more, untimed
-        st = dict(pairs=0, evals_fwd=0, evals_bwd=0, blended=0, mean_len=0.0, p99_len=0, overflow=False)
+        st = dict(pairs=0, evals_fwd=0, evals_bwd=0, blended=0, tested_fwd=0, tested_bwd=0, mean_len=0.0, p99_len=0,
+                  overflow=False)
         n_t = 0
         for w in work:
             R.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], w["cams"], opts, out=w["out"])
             sv = R.stats(1)
             c = w["cams"][0]
             nt = ((c.width + tile[0] - 1) // tile[0]) * ((c.height + tile[1] - 1) // tile[1])
-            for k in ("pairs", "evals_fwd", "evals_bwd", "blended"):
+            for k in ("pairs", "evals_fwd", "evals_bwd", "blended", "tested_fwd", "tested_bwd"):
                 st[k] += sv[k]
             st["mean_len"] += sv["mean_len"] * nt
             n_t += nt
@@ -327,7 +330,7 @@ def main():
 
     # stage times are per launch sequence; in the per-view form one launch covers one view
     launches = len(work)
-    stl = {k: st[k] / launches for k in ("pairs", "evals_fwd", "evals_bwd", "blended")}
+    stl = {k: st[k] / launches for k in ("pairs", "evals_fwd", "evals_bwd", "blended", "tested_fwd", "tested_bwd")}
     stage_report = {}
     for name, (ms, cnt) in list(stages.items()) + list(hot_times.items()):   # the timed region's figures last
         if cnt == 0:
@@ -385,7 +388,7 @@ def main():
                    "loss": None if args.forward_only else "L1 + 0.015 L_E"},
         "pairs_per_s": round(st["pairs"] / sec, 1), "pairs": st["pairs"], "mean_list_len": round(st["mean_len"], 2),
         "p99_list_len": st["p99_len"], "evals_fwd": st["evals_fwd"], "evals_bwd": st["evals_bwd"],
-        "blended": st["blended"],
+        "blended": st["blended"], "tested_fwd": st["tested_fwd"], "tested_bwd": st["tested_bwd"],
         "overflow": st["overflow"], "stages": stage_report, "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -258,6 +258,11 @@ typedef struct {
                                   positions visited until the ray stopped or the list ended */
     int64_t evals_bwd;         /* list positions the backward walks: the sum of n_contrib */
     int64_t blended;           /* (pixel, Gaussian) pairs blended: alpha >= 1/255 before the ray stopped */
+    int64_t tested_fwd;        /* alpha tests the forward blend makes: of the positions counted in
+                                  evals_fwd, those whose Gaussian survives the exact 8x8-block cull
+                                  (the others cannot reach 1/255 at any pixel of the block) */
+    int64_t tested_bwd;        /* alpha tests the backward makes: surviving positions up to each
+                                  pixel's last contributor (a subset of evals_bwd) */
 } gsr_frame_stats;
 
 /* Fills `out` (host) and pairs_per_view [n_views] (host, may be NULL) for

@@ -310,7 +310,7 @@ gsr_status ensure_tiles(gsr_ctx* c, uint32_t tiles, uint32_t blocks)
     if ((s = grow(c, c->ranges, ((size_t)std::max<uint32_t>(tiles, 1) * 2 + kTileHistWords) * 4)) ||
         (s = grow(c, c->tile_order, (size_t)std::max<uint32_t>(tiles, 1) * 4)) ||
         (s = grow(c, c->block_H, (size_t)std::max<uint32_t>(blocks, 1) * 4)) ||
-        (s = grow(c, c->block_cnt, (size_t)std::max<uint32_t>(blocks, 1) * 16)) ||
+        (s = grow(c, c->block_cnt, (size_t)std::max<uint32_t>(blocks, 1) * 32)) ||
         (s = grow(c, c->hchunk, (size_t)(blocks / kRedChunk + 64) * 8)))
         return s;
     return GSR_OK;
@@ -798,12 +798,12 @@ gsr_status gsr_stats(gsr_ctx* c, void* stream, int64_t* pairs_per_view, gsr_fram
     HIP_TRY(c, hipSetDevice(c->device));
     const uint32_t nt = c->lay.n_tiles;
     std::vector<uint32_t> rg((size_t)nt * 2 + 2);
-    std::vector<uint32_t> cnt2((size_t)c->lay.n_blocks * 4 + 4);
+    std::vector<uint32_t> cnt2((size_t)c->lay.n_blocks * 8 + 8);
     uint32_t cnt[2];
     if (nt) HIP_TRY(c, hipMemcpyAsync(rg.data(), c->ranges.p, (size_t)nt * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(cnt, c->counters.p, 8, hipMemcpyDeviceToHost, st));
     if (c->lay.n_blocks)
-        HIP_TRY(c, hipMemcpyAsync(cnt2.data(), c->block_cnt.p, (size_t)c->lay.n_blocks * 16, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipMemcpyAsync(cnt2.data(), c->block_cnt.p, (size_t)c->lay.n_blocks * 32, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
     c->replay_pending = false;
     std::memset(out, 0, sizeof *out);
@@ -831,9 +831,11 @@ gsr_status gsr_stats(gsr_ctx* c, void* stream, int64_t* pairs_per_view, gsr_fram
         out->p99_len = (int32_t)len[k];
     }
     for (uint32_t b = 0; b < c->lay.n_blocks; ++b) {
-        out->evals_fwd += cnt2[4 * b];
-        out->evals_bwd += cnt2[4 * b + 1];
-        out->blended += cnt2[4 * b + 2];
+        out->evals_fwd += cnt2[8 * b];
+        out->evals_bwd += cnt2[8 * b + 1];
+        out->blended += cnt2[8 * b + 2];
+        out->tested_fwd += cnt2[8 * b + 4];
+        out->tested_bwd += cnt2[8 * b + 5];
     }
     c->pairs = cnt[0];
     return GSR_OK;

@@ -279,6 +279,9 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
     float T = 1.f, Cr = 0.f, Cg = 0.f, Cb = 0.f, H2 = 0.f;   // H2: entropy in log2 units
     int32_t last = 0, stop_pos = -1;
     uint32_t nbl = 0;                                        // entries blended
+    // alpha tests made (surviving entries visited): svm over the batches finished
+    // before the stop, sv_stop up to the stopping entry, sv_last up to the last blend
+    uint32_t svm = 0, sv_stop = 0, sv_last = 0;
     bool done = !g.inside;
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
         if (__ballot(!done) == 0ull) break;
@@ -317,6 +320,7 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
                 if (Tn < kTStop) {
                     done = true;
                     stop_pos = s_pos[wid][k];
+                    sv_stop = svm + k + 1u;
                 } else {
                     const float w = alpha * T;
                     Cr = fmaf(w, g1.z, Cr);
@@ -326,9 +330,11 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
                     T = Tn;
                     last = s_pos[wid][k] + 1;
                     ++nbl;
+                    sv_last = svm + k + 1u;
                 }
             }
         }
+        if (!done) svm += m;
         wave_lds_sync();
     }
     // background weight T_{N+1} (Eq. 9-10), then natural-log units
@@ -348,10 +354,16 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
     const uint32_t ne = (uint32_t)wave_sum_all_i(n_eval);
     const uint32_t nc = (uint32_t)wave_sum_all_i(last);
     const uint32_t nb = (uint32_t)wave_sum_all_i((int)nbl);
+    // alpha tests at list positions that survived the block cull: the ones this
+    // kernel made (until the ray stopped) and the ones the backward makes (up to
+    // the last contributor)
+    const uint32_t tf = (uint32_t)wave_sum_all_i((int)(stop_pos >= 0 ? sv_stop : svm));
+    const uint32_t tb = (uint32_t)wave_sum_all_i((int)sv_last);
     const float hs = RENDER ? 0.f : wave_sum_all(g.inside ? H : 0.f);
     if (lane == 0) {
         if (!RENDER) a.block_H[wb] = hs;
-        a.block_cnt[wb] = make_uint4(ne, nc, nb, 0u);
+        a.block_cnt[2 * wb] = make_uint4(ne, nc, nb, 0u);
+        a.block_cnt[2 * wb + 1] = make_uint4(tf, tb, 0u, 0u);
     }
     }
 }

@@ -106,7 +106,8 @@ struct BlendFwdArgs {
     float* out_T;
     int32_t* out_nc;
     float* block_H;                       // [n_blocks] sum of H over the block
-    uint4* block_cnt;                     // [n_blocks] (alpha evaluations, sum of n_contrib, blended, 0)
+    uint4* block_cnt;                     // [n_blocks][2]: (list positions visited, sum of n_contrib, blended, 0),
+                                          //   (alpha tests made, alpha tests the backward makes, 0, 0)
     uint32_t* queues;                     // persistent mode: kQueues heads kQueueStride words apart, zeroed; or null
     int32_t render_only;                  // 1: colour only (no entropy, no saved state)
     const uint32_t* tile_order;           // [n_tiles] tiles, longest list first (hardware dispatch); or null

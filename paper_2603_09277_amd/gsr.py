@@ -56,7 +56,7 @@ class FwdOut(ctypes.Structure):
 class FrameStats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("mean_len", ctypes.c_double), ("p99_len", ctypes.c_int32),
                 ("overflow", ctypes.c_int32), ("evals_fwd", ctypes.c_int64), ("evals_bwd", ctypes.c_int64),
-                ("blended", ctypes.c_int64)]
+                ("blended", ctypes.c_int64), ("tested_fwd", ctypes.c_int64), ("tested_bwd", ctypes.c_int64)]
 
 
 STAGES = ["project", "depth_sort", "scan", "duplicate", "tile_sort", "ranges", "blend_fwd", "entropy_mean",
@@ -349,7 +349,7 @@ class Rasterizer:
         _check(self._ctx, lib().gsr_stats(self._ctx, _stream(), ppv, ctypes.byref(fs)))
         return dict(pairs_per_view=list(ppv), pairs=fs.pairs, mean_len=fs.mean_len, p99_len=fs.p99_len,
                     overflow=bool(fs.overflow), evals_fwd=fs.evals_fwd, evals_bwd=fs.evals_bwd,
-                    blended=fs.blended)
+                    blended=fs.blended, tested_fwd=fs.tested_fwd, tested_bwd=fs.tested_bwd)
 
     def l1_loss(self, cams, rgb, target, grad_rgb=None, loss=None):
         """L1 per view and its gradient, on the GPU, for the latest forward's cameras."""

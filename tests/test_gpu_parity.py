@@ -558,6 +558,11 @@ def test_stats_match_lists(R, tiny):
     assert abs(st["blended"] - ref["n_blend"]) <= slack
     assert abs(st["evals_fwd"] - ref["n_eval"]) <= slack
     assert 0 < st["blended"] <= st["evals_bwd"] <= st["evals_fwd"]
+    # alpha tests the kernels make: positions that survive the block cull, a subset of the
+    # visited ones; every blended entry is tested, and the backward tests no further than the
+    # last contributor
+    assert st["blended"] <= st["tested_bwd"] <= st["tested_fwd"] <= st["evals_fwd"]
+    assert st["tested_bwd"] <= st["evals_bwd"]
 
 
 def _single_gaussian_scene(means, scales, opac, n_extra=0):

@@ -326,7 +326,10 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     const uint32_t n = (uint32_t)g->n, V = (uint32_t)L.cams.size(), vn = n * V;
     const CamDev* dc = (const CamDev*)c->cams.p;
     uint32_t* counters = (uint32_t*)c->counters.p;
-    HIP_TRY(c, launch_fill_u32(counters, 0u, 2, st));
+    // pair count and overflow cleared; a new stamp for the per-pair gradient rows of
+    // this frame's backward (every backward of one forward writes the same rows: the
+    // entries some pixel blended)
+    HIP_TRY(c, launch_frame_begin(counters, st));
 
     ProjectFwdArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
@@ -344,10 +347,9 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     uint32_t* od[2] = { (uint32_t*)c->ord0.p, (uint32_t*)c->ord1.p };
     {
         StageTimer tm(c, st, GSR_STAGE_DEPTH_SORT, !c->capturing);
-        HIP_TRY(c, launch_iota_u32(od[0], vn, st));
-        for (int pass = 0; pass < 4; ++pass)
-            HIP_TRY(c, launch_radix_pass(dk[pass & 1], od[pass & 1], dk[(pass + 1) & 1], od[(pass + 1) & 1], nullptr,
-                                         vn, 8 * pass, (uint32_t*)c->radix_tmp.p, st));
+        for (int pass = 0; pass < 4; ++pass)               // the first pass's values are the record indices
+            HIP_TRY(c, launch_radix_pass(dk[pass & 1], pass ? od[pass & 1] : nullptr, dk[(pass + 1) & 1],
+                                         od[(pass + 1) & 1], nullptr, vn, 8 * pass, (uint32_t*)c->radix_tmp.p, st));
     }
     // offsets of each record's pairs in depth order; total pair count
     {
@@ -434,8 +436,6 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     const uint32_t n = (uint32_t)g->n, V = (uint32_t)L.cams.size(), vn = n * V;
     const CamDev* dc = (const CamDev*)c->cams.p;
     StageTimer tb(c, st, GSR_STAGE_BLEND_BWD, !c->capturing);
-    // a new stamp for the per-pair rows this backward writes
-    HIP_TRY(c, launch_bump_u32((uint32_t*)c->counters.p + 4, st));
     uint32_t* pv[2] = { (uint32_t*)c->pv0.p, (uint32_t*)c->pv1.p };
     BlendBwdArgs bb;
     bb.rec = (const float4*)c->rec.p; bb.pair_vals = pv[c->sorted_buf];

@@ -590,7 +590,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
         if (SHARED) __syncthreads(); else wave_lds_sync();
         // store the rows of the window's blended entries (emission slots),
         // summing the wavefront slots in a fixed order, and clear the slots;
-        // entries no pixel blended keep no row (their stamp is not this backward's)
+        // entries no pixel blended keep no row (their stamp is not this frame's)
         for (int32_t j = tid; j < cnt; j += nthr) {
             if (!s_hit[slot][j]) continue;
             s_hit[slot][j] = 0u;

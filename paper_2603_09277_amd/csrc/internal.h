@@ -51,7 +51,8 @@ constexpr uint32_t kQueueStride = 32;
 //   dmean x, dmean y, dA, dB, dC, dopacity, dred, dgreen, dblue
 constexpr int kG2 = 9;
 // per-pair gradient row: the 9 components and a stamp (uint32 bits) naming the
-// backward that wrote it; rows with another stamp count as zero
+// frame whose backward wrote it; rows with another stamp count as zero (every
+// backward of one frame writes the same rows: the entries some pixel blended)
 constexpr int kRowF = 10;
 
 struct ProjectFwdArgs {
@@ -128,7 +129,7 @@ struct BlendBwdArgs {
     const float* grad_H;                  // may be null
     const float* grad_LE;                 // [V] may be null
     float* pair_grad;                     // [P][10] per-pair gradient rows, emission order
-    const uint32_t* stamp;                // this backward's row stamp
+    const uint32_t* stamp;                // this frame's row stamp
     uint32_t* queues;                     // persistent mode: kQueues heads kQueueStride words apart, zeroed; or null
     const uint32_t* tile_order;           // [n_tiles] tiles, longest list first (hardware dispatch); or null
 };
@@ -146,7 +147,8 @@ hipError_t launch_gather_scan(const uint32_t* vals, const uint2* rect, const uin
                               uint32_t* tmp, hipStream_t s);
 
 // one stable LSD radix pass of 8 bits at `shift` over (key, value) pairs; the
-// item count is min(*n_dev, n_max) read on the device (n_dev may be null: n_max).
+// item count is min(*n_dev, n_max) read on the device (n_dev may be null: n_max);
+// vals_in null: the values are the items' indices.
 size_t radix_tmp_words(uint32_t n_max);
 hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                              uint32_t* vals_out, const uint32_t* n_dev, uint32_t n_max, int shift,
@@ -166,8 +168,8 @@ size_t seg_carry_bytes(uint32_t cap);
 hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* stamp, const uint32_t* emit_vg, uint32_t vn,
                               const uint32_t* total, uint32_t cap, float* grad2d, void* carry, hipStream_t s);
 
-// *p += 1 (one thread)
-hipError_t launch_bump_u32(uint32_t* p, hipStream_t s);
+// a forward's counters: pair total and overflow flag cleared, row stamp (counters[4]) advanced
+hipError_t launch_frame_begin(uint32_t* counters, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 // p[i] = i
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
         const uint32_t li = wid * kPerWave + (uint32_t)r * 64u + lane;
         const bool ok = li < cnt;
         k_[r] = ok ? keys_in[base + li] : 0u;
-        v_[r] = ok ? vals_in[base + li] : 0u;
+        v_[r] = ok ? (vals_in ? vals_in[base + li] : (uint32_t)(base + li)) : 0u;   // null: the item's index
     }
     const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* ord
 
 // Per-Gaussian sum of the per-pair gradient rows.  Rows (9 floats and a stamp)
 // are stored in emission order, where all pairs of one (view, Gaussian) are
-// contiguous; a row whose stamp is not this backward's was not written by it
+// contiguous; a row whose stamp is not this frame's was not written by its backward
 // (no pixel blended that pair) and counts as zero.  One wavefront takes a
 // chunk of 256 consecutive rows (10 KB, staged through LDS with 16-byte
 // loads), 4 per lane: each lane sums its rows segment by segment, one
@@ -570,9 +570,13 @@ __global__ void iota_u32_kernel(uint32_t* p, uint32_t count)
     if (i < count) p[i] = i;
 }
 
-__global__ void bump_u32_kernel(uint32_t* p)
+__global__ void frame_begin_kernel(uint32_t* counters)
 {
-    if (threadIdx.x == 0) *p += 1u;
+    if (threadIdx.x == 0) {
+        counters[0] = 0u;
+        counters[1] = 0u;
+        atomicAdd(&counters[4], 1u);
+    }
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t value, size_t count)
@@ -681,11 +685,12 @@ hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s)
 }
 
 
-hipError_t launch_bump_u32(uint32_t* p, hipStream_t s)
+hipError_t launch_frame_begin(uint32_t* counters, hipStream_t s)
 {
-    hipLaunchKernelGGL(bump_u32_kernel, dim3(1), dim3(64), 0, s, p);
+    hipLaunchKernelGGL(frame_begin_kernel, dim3(1), dim3(64), 0, s, counters);
     return hipGetLastError();
 }
+
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s)
 {

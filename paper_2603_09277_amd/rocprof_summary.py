@@ -165,7 +165,7 @@ def main():
     a = ap.parse_args()
 
     if a.cmd == "stats":
-        lines = [f"# {a.title}", "", "Command (from the repository root's parent working directory /tmp):", "",
+        lines = [f"# {a.title}", "", "Command:", "",
                  "```", a.command, "```", ""]
         if a.note:
             lines += [a.note, ""]

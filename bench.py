@@ -80,6 +80,9 @@ def parse():
                     help="untimed steps after the timed region with every stage bracketed by events")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 launches), to scale HBM counters")
+    ap.add_argument("--aux", action="store_true",
+                    help="time the training-step and scheduler entry points (scale reset, opacity regulariser, "
+                         "Adam, D-SSIM, base loss, r_max selection) at the training workload's sizes")
     ap.add_argument("--train", action="store_true",
                     help="time a synthetic training run (loss of Eq. 6 + 12, Adam, scale reset, resolution scheduler)")
     ap.add_argument("--train-iters", type=int, default=30000,
@@ -105,9 +108,9 @@ def stage_bytes(stage, n, V, sh_bytes, pairs, n_tiles, npix, evals_fwd, evals_bw
         "ranges": pairs * 4 + n_tiles * 8,
         "blend_fwd": pairs * 52 + npix * 24,                # pair value + record; rgb, H, T, n_contrib
         "entropy_mean": 0,
-        "blend_bwd": pairs * 92 + npix * 24,                # pair value + record + gradient row; per-pixel state
+        "blend_bwd": pairs * 92 + npix * 24,                # pair value + record + gradient row and stamp; per-pixel state
         "project_bwd": n * (88 + 2 * sh_bytes) + vn * 40,   # params + SH in, grads out; 2D grads + tt per view
-        "grad_reduce": pairs * 44 + vn * 36,                # rows + owners in, 2D grads out
+        "grad_reduce": pairs * 8 + vn * 36,                 # stamps + owners in (rows only where written), 2D grads out
     }[stage]
 
 
@@ -201,6 +204,79 @@ def run_train(args, torch, dev):
     print(json.dumps(result), flush=True)
 
 
+METRIC_AUX = "auxiliary entry points: per-call time and HBM rate at 1 MI355X"
+
+
+def run_aux(args, torch, dev):
+    """Per-call time of the element-wise and image entry points around the rasterizer, at the
+    training workload's sizes, with their algorithmic HBM bytes (read and written once)."""
+    from paper_2603_09277_amd import gsr, scenes
+    n = args.train_gaussians
+    W, H = (int(x) for x in args.train_res.split("x"))
+    scene = scenes.gmm_scene(9, n)
+    t = {k: torch.from_numpy(np.ascontiguousarray(getattr(scene, k))).to(dev) for k in
+         ("means", "scales", "quats", "opacities", "sh")}
+    R = gsr.Rasterizer(max_views=1)
+    cam = scenes.orbit_cameras(np.random.default_rng(10), [(W, H)])[0]
+    opts = gsr.RasterOptions(tile=(16, 16), lds_batch=args.lds, sh_degree=3)
+    g = torch.Generator(device="cpu").manual_seed(11)
+    sc = t["scales"].clone()
+    lsc = torch.log(sc).contiguous()
+    grad_o = torch.zeros(n, device=dev)
+    loss1 = torch.zeros(1, device=dev)
+    P = W * H
+    img = torch.rand((P, 3), generator=g).to(dev)
+    tgt = torch.rand((P, 3), generator=g).to(dev)
+    grad_img = torch.zeros_like(img)
+    lv = torch.zeros(1, device=dev)
+    lv2 = torch.zeros(1, device=dev)
+    # Adam over the 59 floats of every Gaussian, kinds as in training
+    attrs = [(3, 0), (3, 1), (4, 0), (1, 2), (48, 0)]     # means, log-scales, quats, opacity logits, SH
+    ad = []
+    for width, kind in attrs:
+        raw = torch.randn((n * width,), generator=g).to(dev)
+        ad.append((raw, torch.zeros_like(raw), torch.zeros_like(raw), torch.empty_like(raw) if kind else None,
+                   (torch.randn((n * width,), generator=g) * 1e-3).to(dev), kind))
+    state = {"step": 0}
+
+    def adam_all():
+        state["step"] += 1
+        for raw, m, v, act, gr, kind in ad:
+            R.adam(raw, m, v, act, gr, kind, 1e-3, state["step"])
+
+    ops = {
+        "scale_reset": (lambda: R.scale_reset(sc, 1.0, lsc), n * 3 * 16),
+        "opacity_loss": (lambda: R.opacity_loss(t["opacities"], 3.0, grad_o, loss1), n * 12),
+        "adam": (adam_all, n * (59 * 28 + 4 * 4)),
+        "dssim": (lambda: R.dssim([cam], img, tgt, 0.2, grad_img, lv), P * 3 * 16),
+        "select_rmax": (lambda: R.select_rmax(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cam, opts),
+                        None),
+    }
+    res = {}
+    for name, (fn, nbytes) in ops.items():
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        r = {"ms": round(ms, 4)}
+        if nbytes:
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            r.update({"algorithmic_bytes": nbytes, "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)})
+        res[name] = r
+    R.close()
+    print(json.dumps({"metric": METRIC_AUX, "unit": "ms per call", "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": f"{n} Gaussians (Adam over 59 floats each), one {W}x{H} image",
+                                 "gaussians": n, "resolution": [W, H]},
+                      "ops": res}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -226,6 +302,9 @@ def main():
         return
     if args.train:
         run_train(args, torch, dev)
+        return
+    if args.aux:
+        run_aux(args, torch, dev)
         return
     tile = tuple(int(x) for x in args.tile.split("x"))
     scene, cams, meta = scenes.workload(args.workload)

@@ -53,7 +53,7 @@ struct gsr_ctx {
 
     // grow-only device buffers
     Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, tt_s, rect_s, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
-    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, seg_carry, ranges, tile_order, queues, block_H, block_cnt, hchunk, counters, l1_tmp, reg_tmp, ssim_tmp;
+    Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, pair_stamp, seg_carry, ranges, tile_order, queues, block_H, block_cnt, hchunk, counters, l1_tmp, reg_tmp, ssim_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
     uint64_t gen_fwd = 0, gen_bwd = 0;
@@ -292,6 +292,7 @@ gsr_status ensure_pairs(gsr_ctx* c, size_t p)
     gsr_status s;
     if ((s = grow(c, c->pk0, p * 4)) || (s = grow(c, c->pk1, p * 4)) || (s = grow(c, c->pv0, p * 4)) ||
         (s = grow(c, c->pv1, p * 4)) || (s = grow(c, c->emit_vg, p * 4)) || (s = grow(c, c->pair_grad, p * 4 * kRowF + 64, true)) ||
+        (s = grow(c, c->pair_stamp, p * 4 + 64, true)) ||
         (s = grow(c, c->seg_carry, seg_carry_bytes((uint32_t)p))))
         return s;
     c->pair_cap = p;
@@ -443,7 +444,8 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     bb.cams = dc; bb.n_views = (int32_t)V; bb.tile_shift_x = L.tsx; bb.tile_shift_y = L.tsy; bb.spt = L.spt;
     bb.n_blocks = L.n_blocks;
     bb.T_final = saved->t_final; bb.n_contrib = saved->n_contrib; bb.grad_rgb = grad_rgb; bb.grad_H = grad_H;
-    bb.grad_LE = grad_LE; bb.pair_grad = (float*)c->pair_grad.p; bb.stamp = (const uint32_t*)c->counters.p + 4;
+    bb.grad_LE = grad_LE; bb.pair_grad = (float*)c->pair_grad.p;
+    bb.pair_stamp = (uint32_t*)c->pair_stamp.p; bb.stamp = (const uint32_t*)c->counters.p + 4;
     const bool persist = (o->flags & GSR_PERSISTENT) != 0;
     bb.queues = persist ? (uint32_t*)c->queues.p + kQueues * kQueueStride : nullptr;
     bb.tile_order = persist ? nullptr : (const uint32_t*)c->tile_order.p;
@@ -452,7 +454,8 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     tb.stop();
     {
         StageTimer tr(c, st, GSR_STAGE_GRAD_REDUCE, !c->capturing);
-        HIP_TRY(c, launch_grad_reduce((const float*)c->pair_grad.p, (const uint32_t*)c->counters.p + 4,
+        HIP_TRY(c, launch_grad_reduce((const float*)c->pair_grad.p, (const uint32_t*)c->pair_stamp.p,
+                                      (const uint32_t*)c->counters.p + 4,
                                       (const uint32_t*)c->emit_vg.p,
                                       vn, (const uint32_t*)c->counters.p, (uint32_t)c->pair_cap_used,
                                       (float*)c->grad2d.p, c->seg_carry.p, st));
@@ -591,7 +594,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     drop_graphs(c);
     Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->tt_s, &c->rect_s, &c->radius,
                    &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
-                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->seg_carry, &c->ranges, &c->tile_order, &c->queues, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->reg_tmp, &c->ssim_tmp,
+                   &c->pv1, &c->emit_vg, &c->pair_grad, &c->pair_stamp, &c->seg_carry, &c->ranges, &c->tile_order, &c->queues, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->reg_tmp, &c->ssim_tmp,
                    &c->l1_tmp };
     for (Dev* d : all) free_dev(*d);
     for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }

@@ -495,7 +495,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     __shared__ uint32_t s_item;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
     const uint32_t slot = SHARED ? 0u : wid;
-    const float stamp = __uint_as_float(*a.stamp);
+    const uint32_t stamp = *a.stamp;
     // work items: tiles (SHARED: one per workgroup; else one per wavefront), claimed from the per-XCD queues
     const uint32_t n_items = SHARED ? a.n_blocks / kWavesPerGroup : a.n_blocks;
     WaveQueue wq;
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
             float* row = a.pair_grad + (size_t)kRowF * s_e[slot][j];
 #pragma unroll
             for (int k = 0; k < kG2; ++k) row[k] = G[k];
-            row[kG2] = stamp;
+            a.pair_stamp[s_e[slot][j]] = stamp;
         }
         if (SHARED) __syncthreads(); else wave_lds_sync();
     }

@@ -128,7 +128,8 @@ struct BlendBwdArgs {
     const float* grad_rgb;
     const float* grad_H;                  // may be null
     const float* grad_LE;                 // [V] may be null
-    float* pair_grad;                     // [P][10] per-pair gradient rows, emission order
+    float* pair_grad;                     // [P][10] per-pair gradient rows (9 values), emission order
+    uint32_t* pair_stamp;                 // [P] stamp of the frame whose backward wrote each row
     const uint32_t* stamp;                // this frame's row stamp
     uint32_t* queues;                     // persistent mode: kQueues heads kQueueStride words apart, zeroed; or null
     const uint32_t* tile_order;           // [n_tiles] tiles, longest list first (hardware dispatch); or null
@@ -161,11 +162,12 @@ hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, cons
                             const uint2* rect_s, const CamDev* cams, uint32_t n, uint32_t vn,
                             const uint32_t* total, uint32_t cap, uint32_t* keys, uint32_t* vals,
                             uint32_t* emit_vg, uint32_t* overflow, float4* rec, hipStream_t s);
-// grad2d[vg] = sum of the per-pair rows pair_grad[10 e .. 10 e + 8] stamped *stamp over the Gaussian's
+// grad2d[vg] = sum of the per-pair rows pair_grad[10 e .. 10 e + 8] with pair_stamp[e] == *stamp over the Gaussian's
 // emission range, for every (view, Gaussian) with pairs (others are left untouched)
 // (zero for Gaussians without pairs); carry holds seg_carry_bytes(cap) bytes
 size_t seg_carry_bytes(uint32_t cap);
-hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* stamp, const uint32_t* emit_vg, uint32_t vn,
+hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* pair_stamp, const uint32_t* stamp,
+                              const uint32_t* emit_vg, uint32_t vn,
                               const uint32_t* total, uint32_t cap, float* grad2d, void* carry, hipStream_t s);
 
 // a forward's counters: pair total and overflow flag cleared, row stamp (counters[4]) advanced

@@ -381,12 +381,13 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* ord
     }
 }
 
-// Per-Gaussian sum of the per-pair gradient rows.  Rows (9 floats and a stamp)
+// Per-Gaussian sum of the per-pair gradient rows.  Rows (9 floats, 10 apart)
 // are stored in emission order, where all pairs of one (view, Gaussian) are
-// contiguous; a row whose stamp is not this frame's was not written by its backward
-// (no pixel blended that pair) and counts as zero.  One wavefront takes a
-// chunk of 256 consecutive rows (10 KB, staged through LDS with 16-byte
-// loads), 4 per lane: each lane sums its rows segment by segment, one
+// contiguous; a row whose stamp (a separate array) is not this frame's was not
+// written by its backward (no pixel blended that pair) and counts as zero, and
+// is not read: on long lists most rows are stale, so the stamps (4 bytes a pair)
+// replace most of the row traffic (40 bytes a pair).  One wavefront takes a
+// chunk of 256 consecutive rows, 4 per lane: each lane sums its rows segment by segment, one
 // segmented scan over the 64 lanes (keyed by the Gaussian) joins segments
 // that span lanes, and every segment that starts and ends inside the chunk is
 // written; segments that cross chunk boundaries leave their partial sums in
@@ -402,7 +403,6 @@ struct SegCarry {
 
 constexpr uint32_t kRowsPerLane = 4;
 constexpr uint32_t kChunkRows = 64 * kRowsPerLane;           // 256
-constexpr uint32_t kLaneF4 = kRowsPerLane * kRowF / 4 + 1;   // 10 float4 of rows + 1 of padding per lane
 constexpr uint32_t kNoSeg = 0xffffffffu;
 
 __device__ __forceinline__ void add9(float* a, const float* b)
@@ -417,50 +417,60 @@ __device__ __forceinline__ void store9(float* dst, const float* v)
     for (int k = 0; k < kG2; ++k) dst[k] = v[k];
 }
 
-__global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_grad, const uint32_t* stamp,
-                                                              const uint32_t* emit_vg, const uint32_t* total,
-                                                              uint32_t cap, float* grad2d, SegCarry* carry)
+__global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_grad, const uint32_t* pair_stamp,
+                                                              const uint32_t* stamp, const uint32_t* emit_vg,
+                                                              const uint32_t* total, uint32_t cap, float* grad2d,
+                                                              SegCarry* carry)
 {
-    __shared__ float4 s_rows[kThreads / 64][64 * kLaneF4];
     const uint32_t P = *total < cap ? *total : cap;
     const uint32_t st = *stamp;
-    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    const uint32_t lane = lane_id();
     const uint32_t nchunk = (P + kChunkRows - 1) / kChunkRows;
-    const size_t fend = (size_t)P * kRowF;
     // chunks, grid-stride (the grid does not grow with the pair capacity)
     for (uint32_t c = (blockIdx.x * kThreads + threadIdx.x) >> 6; c < nchunk; c += (gridDim.x * kThreads) >> 6) {
         const uint32_t r0 = c * kChunkRows;
-        // stage the chunk: float4 f belongs to lane f / 10, part f % 10
-        for (uint32_t f = lane; f < 64u * (kLaneF4 - 1); f += 64u) {
-            const size_t fi = (size_t)r0 * kRowF + 4u * (size_t)f;
-            if (fi < fend)
-                s_rows[wid][(f / (kLaneF4 - 1)) * kLaneF4 + f % (kLaneF4 - 1)] =
-                    *reinterpret_cast<const float4*>(pair_grad + fi);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // this lane's rows and owners
+        // this lane's 4 rows: owners and stamps with one 16-byte load each; a row's 9
+        // values are read only if this frame's backward wrote it
         const uint32_t e0 = r0 + lane * kRowsPerLane;
-        float rw[kRowsPerLane * kRowF];
+        uint32_t sg[kRowsPerLane], sp[kRowsPerLane];
+        if (e0 + kRowsPerLane <= P) {
+            const uint4 o4 = *reinterpret_cast<const uint4*>(emit_vg + e0);
+            const uint4 p4 = *reinterpret_cast<const uint4*>(pair_stamp + e0);
+            sg[0] = o4.x; sg[1] = o4.y; sg[2] = o4.z; sg[3] = o4.w;
+            sp[0] = p4.x; sp[1] = p4.y; sp[2] = p4.z; sp[3] = p4.w;
+        } else {
 #pragma unroll
-        for (uint32_t q = 0; q < kLaneF4 - 1; ++q) {
-            const float4 x = s_rows[wid][lane * kLaneF4 + q];
-            rw[4 * q] = x.x; rw[4 * q + 1] = x.y; rw[4 * q + 2] = x.z; rw[4 * q + 3] = x.w;
+            for (uint32_t r = 0; r < kRowsPerLane; ++r) {
+                sg[r] = e0 + r < P ? emit_vg[e0 + r] : kNoSeg;
+                sp[r] = e0 + r < P ? pair_stamp[e0 + r] : 0u;
+            }
         }
-        uint32_t sg[kRowsPerLane];
+        float rw[kRowsPerLane * kG2];
 #pragma unroll
-        for (uint32_t r = 0; r < kRowsPerLane; ++r) sg[r] = e0 + r < P ? emit_vg[e0 + r] : kNoSeg;
+        for (uint32_t r = 0; r < kRowsPerLane; ++r) {
+            const bool live = sg[r] != kNoSeg && sp[r] == st;
+            const float2* row = reinterpret_cast<const float2*>(pair_grad + (size_t)kRowF * (e0 + r));
+            float2 x0 = make_float2(0.f, 0.f), x1 = x0, x2 = x0, x3 = x0;
+            float x4 = 0.f;
+            if (live) {
+                x0 = row[0]; x1 = row[1]; x2 = row[2]; x3 = row[3];
+                x4 = pair_grad[(size_t)kRowF * (e0 + r) + 8];
+            }
+            float* d = rw + r * kG2;
+            d[0] = x0.x; d[1] = x0.y; d[2] = x1.x; d[3] = x1.y; d[4] = x2.x; d[5] = x2.y;
+            d[6] = x3.x; d[7] = x3.y; d[8] = x4;
+        }
         // lane-local segments: A = first segment's partial, B = last segment's partial
+        // (rows not written by this frame's backward hold zeros in rw)
         float A[kG2], B[kG2];
         uint32_t s0 = sg[0], sl = sg[0], nseg = 1;
 #pragma unroll
-        for (int k = 0; k < kG2; ++k) B[k] = (sg[0] != kNoSeg && __float_as_uint(rw[kG2]) == st) ? rw[k] : 0.f;
+        for (int k = 0; k < kG2; ++k) B[k] = rw[k];
 #pragma unroll
         for (uint32_t r = 1; r < kRowsPerLane; ++r) {
             if (sg[r] == kNoSeg) break;
-            const float* row = rw + r * kRowF;
-            const bool live = __float_as_uint(row[kG2]) == st;
+            const float* row = rw + r * kG2;
+            const bool live = sp[r] == st;
             if (sg[r] != sl) {                                   // segment sl ends inside this lane
                 if (nseg == 1) {
 #pragma unroll
@@ -524,9 +534,6 @@ __global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_
             cr->last_seg = sl;
             cr->flags = (crosses_in ? 1u : 0u) | (crosses_out ? 2u : 0u);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // rows read before the next chunk lands
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -664,14 +671,15 @@ hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, cons
 
 size_t seg_carry_bytes(uint32_t cap) { return ((size_t)cap + kChunkRows - 1) / kChunkRows * sizeof(SegCarry) + sizeof(SegCarry); }
 
-hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* stamp, const uint32_t* emit_vg, uint32_t vn,
-                              const uint32_t* total, uint32_t cap, float* grad2d, void* carry, hipStream_t s)
+hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* pair_stamp, const uint32_t* stamp,
+                              const uint32_t* emit_vg, uint32_t vn, const uint32_t* total, uint32_t cap, float* grad2d,
+                              void* carry, hipStream_t s)
 {
     (void)vn;
     if (cap == 0) return hipSuccess;
     const uint32_t nw = (cap + kChunkRows - 1) / kChunkRows;
     hipLaunchKernelGGL(seg_reduce_kernel, dim3(grid_cap((nw * 64 + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
-                       pair_grad, stamp, emit_vg, total, cap, grad2d, reinterpret_cast<SegCarry*>(carry));
+                       pair_grad, pair_stamp, stamp, emit_vg, total, cap, grad2d, reinterpret_cast<SegCarry*>(carry));
     hipLaunchKernelGGL(seg_fixup_kernel, dim3(grid_cap((nw + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
                        reinterpret_cast<const SegCarry*>(carry), total, cap, grad2d);
     return hipGetLastError();

@@ -720,6 +720,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_
 // atomics) is immaterial.
 // ---------------------------------------------------------------------------
 
+namespace {
+
 __device__ __forceinline__ uint32_t tile_bucket(uint2 r)
 {
     const float c = 16.f * __builtin_amdgcn_logf((float)(r.y - r.x) + 1.f);   // 16 log2(len + 1)
@@ -769,6 +771,8 @@ __global__ __launch_bounds__(kThreads) void tile_order_kernel(const uint2* range
         __syncthreads();
     }
 }
+
+}  // namespace
 
 hipError_t launch_tile_order(const uint2* ranges, uint32_t n_tiles, uint32_t* hist, uint32_t* order, hipStream_t s)
 {

@@ -52,6 +52,7 @@ struct gsr_ctx {
     std::string err;
 
     // grow-only device buffers
+    // rect: per record (rectangle, tiles touched) as uint4
     Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, tt_s, rect_s, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
     Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, pair_stamp, seg_carry, ranges, tile_order, queues, block_H, block_cnt, hchunk, counters, l1_tmp, reg_tmp, ssim_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
@@ -274,7 +275,7 @@ gsr_status ensure_vn(gsr_ctx* c, uint32_t vn)
     v = std::max(v, c->vn_cap + c->vn_cap / 4);
     gsr_status s;
     if ((s = grow(c, c->rec, v * 48)) || (s = grow(c, c->dkey0, v * 4)) || (s = grow(c, c->dkey1, v * 4)) ||
-        (s = grow(c, c->ord0, v * 4)) || (s = grow(c, c->ord1, v * 4)) || (s = grow(c, c->rect, v * 8)) ||
+        (s = grow(c, c->ord0, v * 4)) || (s = grow(c, c->ord1, v * 4)) || (s = grow(c, c->rect, v * 16)) ||
         (s = grow(c, c->tt, v * 4)) || (s = grow(c, c->tt_s, v * 4)) || (s = grow(c, c->rect_s, v * 8)) ||
         (s = grow(c, c->radius, v * 4)) || (s = grow(c, c->depth, v * 4)) ||
         (s = grow(c, c->offsets, v * 4)) || (s = grow(c, c->grad2d, v * 4 * kG2)) ||
@@ -336,7 +337,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
     pa.n = n; pa.n_views = (int32_t)V; pa.flags = o->flags; pa.tile_shift_x = L.tsx; pa.tile_shift_y = L.tsy;
     pa.cams = dc;
-    pa.rec = (float4*)c->rec.p; pa.depth_key = (uint32_t*)c->dkey0.p; pa.rect = (uint2*)c->rect.p;
+    pa.rec = (float4*)c->rec.p; pa.depth_key = (uint32_t*)c->dkey0.p; pa.trect = (uint4*)c->rect.p;
     pa.tiles_touched = (uint32_t*)c->tt.p; pa.radius = (int32_t*)c->radius.p; pa.depth = (float*)c->depth.p;
     {
         StageTimer tm(c, st, GSR_STAGE_PROJECT, !c->capturing);
@@ -355,7 +356,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     // offsets of each record's pairs in depth order; total pair count
     {
         StageTimer tm(c, st, GSR_STAGE_SCAN, !c->capturing);
-        HIP_TRY(c, launch_gather_scan((const uint32_t*)c->tt.p, (const uint2*)c->rect.p, od[0], vn,
+        HIP_TRY(c, launch_gather_scan((const uint4*)c->rect.p, od[0], vn,
                                       (uint32_t*)c->offsets.p, (uint32_t*)c->tt_s.p, (uint2*)c->rect_s.p, counters,
                                       counters + 1, (uint32_t*)c->scan_tmp.p, st));
     }
@@ -930,16 +931,16 @@ static gsr_status count_pairs(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
     pa.n = n; pa.n_views = n_views; pa.flags = o->flags; pa.tile_shift_x = L.tsx; pa.tile_shift_y = L.tsy;
     pa.cams = (const CamDev*)c->cams.p;
-    pa.rec = (float4*)c->rec.p; pa.depth_key = (uint32_t*)c->dkey0.p; pa.rect = (uint2*)c->rect.p;
+    pa.rec = (float4*)c->rec.p; pa.depth_key = (uint32_t*)c->dkey0.p; pa.trect = (uint4*)c->rect.p;
     pa.tiles_touched = (uint32_t*)c->tt.p; pa.radius = (int32_t*)c->radius.p; pa.depth = (float*)c->depth.p;
     HIP_TRY(c, launch_project_fwd(pa, o->sh_degree, o->sh_dtype == 1, st));
     uint32_t* counters = (uint32_t*)c->counters.p;
     for (int v = 0; v < n_views; ++v) {             // one scan per view: its pair count
         HIP_TRY(c, launch_fill_u32(counters, 0u, 2, st));
         HIP_TRY(c, launch_iota_u32((uint32_t*)c->ord0.p, n, st));
-        HIP_TRY(c, launch_gather_scan((const uint32_t*)c->tt.p + (size_t)v * n, (const uint2*)c->rect.p + (size_t)v * n,
-                                      (const uint32_t*)c->ord0.p, n, (uint32_t*)c->offsets.p, (uint32_t*)c->tt_s.p,
-                                      (uint2*)c->rect_s.p, counters, counters + 1, (uint32_t*)c->scan_tmp.p, st));
+        HIP_TRY(c, launch_gather_scan((const uint4*)c->rect.p + (size_t)v * n, (const uint32_t*)c->ord0.p, n,
+                                      (uint32_t*)c->offsets.p, (uint32_t*)c->tt_s.p, (uint2*)c->rect_s.p, counters,
+                                      counters + 1, (uint32_t*)c->scan_tmp.p, st));
         HIP_TRY(c, hipMemcpyAsync(c->counters_host, counters, 8, hipMemcpyDeviceToHost, st));
         HIP_TRY(c, hipStreamSynchronize(st));
         if (c->counters_host[1]) return fail(c, GSR_ERR_CAPACITY, "pair count exceeds 2^32");

@@ -68,7 +68,8 @@ struct ProjectFwdArgs {
     const CamDev* cams;
     float4* rec;                          // [V*n][3]
     uint32_t* depth_key;                  // [V*n] float bits of camera z; culled = 0xffffffff
-    uint2* rect;                          // [V*n] (x0 | x1 << 16, y0 | y1 << 16)
+    uint4* trect;                         // [V*n] (x0 | x1 << 16, y0 | y1 << 16, tiles touched, 0): one
+                                          //   16-byte gather for the depth-ordered scan
     uint32_t* tiles_touched;              // [V*n]
     int32_t* radius;                      // [V*n]
     float* depth;                         // [V*n]
@@ -143,9 +144,9 @@ hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, bool sh_bf
 // *overflow |= 1 if the total does not fit in 32 bits; vals_s[i] = vals[order[i]] and
 // rect_s[i] = rect[order[i]].  tmp holds scan_tmp_words(n) words.
 size_t scan_tmp_words(uint32_t n);
-hipError_t launch_gather_scan(const uint32_t* vals, const uint2* rect, const uint32_t* order, uint32_t n,
-                              uint32_t* out, uint32_t* vals_s, uint2* rect_s, uint32_t* total, uint32_t* overflow,
-                              uint32_t* tmp, hipStream_t s);
+hipError_t launch_gather_scan(const uint4* trect, const uint32_t* order, uint32_t n, uint32_t* out,
+                              uint32_t* vals_s, uint2* rect_s, uint32_t* total, uint32_t* overflow, uint32_t* tmp,
+                              hipStream_t s);
 
 // one stable LSD radix pass of 8 bits at `shift` over (key, value) pairs; the
 // item count is min(*n_dev, n_max) read on the device (n_dev may be null: n_max);

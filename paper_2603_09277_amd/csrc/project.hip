@@ -285,7 +285,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectFwdArgs a)
         a.rec[3 * o + 2] = r2;
         a.depth_key[o] = P.ok ? __float_as_uint(P.tz) : 0xffffffffu;
         a.depth[o] = P.tz;
-        a.rect[o] = rc;
+        a.trect[o] = make_uint4(rc.x, rc.y, tt, 0u);
         a.tiles_touched[o] = tt;
         a.radius[o] = P.ok ? rad : 0;
     }

@@ -53,14 +53,14 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* total)
 }
 
 // ---------------------------------------------------------------------------
-// Device-wide exclusive scan (reduce, spine, downsweep) of vals[order[i]].
-// The reduce step also gathers vals and rect into depth order (vals_s,
-// rect_s), so the downsweep and the duplication read them coalesced.
+// Device-wide exclusive scan (reduce, spine, downsweep) of the tiles touched
+// taken in depth order.  The reduce step gathers each record's (rectangle,
+// tiles touched) with one 16-byte load into depth order (vals_s, rect_s), so
+// the downsweep and the duplication read them coalesced.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* vals, const uint2* rect,
-                                                               const uint32_t* order, uint32_t n, uint32_t* partial,
-                                                               uint32_t* vals_s, uint2* rect_s)
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint4* trect, const uint32_t* order, uint32_t n,
+                                                               uint32_t* partial, uint32_t* vals_s, uint2* rect_s)
 {
     size_t base = (size_t)blockIdx.x * kTileItems + threadIdx.x;
     uint32_t sum = 0;
@@ -68,11 +68,10 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* v
     for (int k = 0; k < kItems; ++k) {
         size_t idx = base + (size_t)k * kThreads;
         if (idx < n) {
-            const uint32_t o = order[idx];
-            const uint32_t v = vals[o];
-            vals_s[idx] = v;
-            rect_s[idx] = rect[o];
-            sum += v;
+            const uint4 t = trect[order[idx]];
+            vals_s[idx] = t.z;
+            rect_s[idx] = make_uint2(t.x, t.y);
+            sum += t.z;
         }
     }
     uint32_t tot;
@@ -613,14 +612,13 @@ static uint32_t grid_cap(uint32_t blocks) { return blocks < 16384u ? (blocks ? b
 
 size_t scan_tmp_words(uint32_t n) { return (size_t)(n + kTileItems - 1) / kTileItems + 1; }
 
-hipError_t launch_gather_scan(const uint32_t* vals, const uint2* rect, const uint32_t* order, uint32_t n,
-                              uint32_t* out, uint32_t* vals_s, uint2* rect_s, uint32_t* total, uint32_t* overflow,
-                              uint32_t* tmp, hipStream_t s)
+hipError_t launch_gather_scan(const uint4* trect, const uint32_t* order, uint32_t n, uint32_t* out,
+                              uint32_t* vals_s, uint2* rect_s, uint32_t* total, uint32_t* overflow, uint32_t* tmp,
+                              hipStream_t s)
 {
     uint32_t nb = (n + kTileItems - 1) / kTileItems;
     if (nb > 0)
-        hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kThreads), 0, s, vals, rect, order, n, tmp, vals_s,
-                           rect_s);
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kThreads), 0, s, trect, order, n, tmp, vals_s, rect_s);
     hipLaunchKernelGGL(scan_spine_kernel, dim3(1), dim3(kThreads), 0, s, tmp, nb, total, overflow);
     if (nb > 0) hipLaunchKernelGGL(scan_down_kernel, dim3(nb), dim3(kThreads), 0, s, vals_s, n, tmp, out);
     return hipGetLastError();

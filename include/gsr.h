@@ -313,12 +313,10 @@ gsr_status gsr_autotune(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, cons
  * (synchronises `stream`); for stage-by-stage testing.  *bytes receives the
  * size of the buffer; dst may be NULL to query it. */
 typedef enum {
-    GSR_BUF_RECORDS = 0,       /* float[V*n][12]: mean x, y, A', B', C', opacity, r, g, b, L, base, w with
+    GSR_BUF_RECORDS = 0,       /* float[V*n][12]: mean x, y, A', B', C', opacity, r, g, b, L, 0, 0 with
                                   the conic pre-scaled: A' = -A log2(e)/2, B' = -B log2(e), C' = -C log2(e)/2;
                                   L = log2(255 opacity) + 1e-4, the level the blend uses to skip Gaussians
-                                  that cannot reach alpha >= 1/255 anywhere in an 8x8 pixel block; base and w
-                                  (uint32 bits, set for Gaussians with pairs) place the pair of local tile
-                                  (tx, ty) at emission index base + ty w + tx */
+                                  that cannot reach alpha >= 1/255 anywhere in an 8x8 pixel block */
     GSR_BUF_RADIUS = 1,        /* int32[V*n], 0 = culled */
     GSR_BUF_DEPTH = 2,         /* float[V*n], camera z */
     GSR_BUF_TILES_TOUCHED = 3, /* int32[V*n] */

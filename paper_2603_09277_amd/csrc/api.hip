@@ -379,17 +379,17 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     {
         StageTimer tm(c, st, GSR_STAGE_DUPLICATE, !c->capturing);
         HIP_TRY(c, launch_duplicate(od[0], (const uint32_t*)c->offsets.p, (const uint32_t*)c->tt_s.p,
-                                    (const uint2*)c->rect_s.p, dc, n, vn, counters, cap, pk[0], pv[0],
-                                    (uint32_t*)c->emit_vg.p, counters + 1, (float4*)c->rec.p, st));
+                                    (const uint2*)c->rect_s.p, dc, n, vn, counters, cap, pk[0],
+                                    (uint32_t*)c->emit_vg.p, counters + 1, st));
     }
     // stable sort of the pairs by tile id
     int tile_bits = std::max(1, ilog2((int)std::max<uint32_t>(L.n_tiles, 2)));
     int passes = (tile_bits + 7) / 8;
     {
         StageTimer tm(c, st, GSR_STAGE_TILE_SORT, !c->capturing);
-        for (int pass = 0; pass < passes; ++pass)
-            HIP_TRY(c, launch_radix_pass(pk[pass & 1], pv[pass & 1], pk[(pass + 1) & 1], pv[(pass + 1) & 1], counters,
-                                         cap, 8 * pass, (uint32_t*)c->radix_tmp.p, st));
+        for (int pass = 0; pass < passes; ++pass)          // the first pass's values: the emission indices
+            HIP_TRY(c, launch_radix_pass(pk[pass & 1], pass ? pv[pass & 1] : nullptr, pk[(pass + 1) & 1],
+                                         pv[(pass + 1) & 1], counters, cap, 8 * pass, (uint32_t*)c->radix_tmp.p, st));
     }
     const int sb = passes & 1;
     const bool persist = (o->flags & GSR_PERSISTENT) != 0;
@@ -406,7 +406,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     }
 
     BlendFwdArgs ba;
-    ba.rec = (const float4*)c->rec.p; ba.pair_vals = pv[sb];
+    ba.rec = (const float4*)c->rec.p; ba.pair_vals = pv[sb]; ba.emit_vg = (const uint32_t*)c->emit_vg.p;
     ba.ranges = (const uint2*)c->ranges.p; ba.cams = dc;
     ba.n_views = (int32_t)V; ba.tile_shift_x = L.tsx; ba.tile_shift_y = L.tsy; ba.spt = L.spt; ba.n_blocks = L.n_blocks;
     ba.out_rgb = out->rgb; ba.out_H = out->entropy; ba.out_T = out->t_final; ba.out_nc = out->n_contrib;
@@ -415,6 +415,13 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     ba.queues = persist ? (uint32_t*)c->queues.p : nullptr;
     ba.render_only = render_only ? 1 : 0;
     ba.tile_order = persist ? nullptr : (const uint32_t*)c->tile_order.p;
+    // long lists: the 4 blocks of a tile share each staged batch; short lists: each
+    // block stages its own and leaves as soon as its pixels have stopped (a fixed
+    // capacity is 1.5x a frame's pairs, hence the estimate)
+    {
+        const double p_est = plain ? (double)cap : (double)cap / 1.5;
+        ba.shared_batches = (L.n_tiles > 0 && p_est >= kSharedBatchMeanLen * (double)L.n_tiles) ? 1 : 0;
+    }
     {
         StageTimer tm(c, st, GSR_STAGE_BLEND_FWD, !c->capturing);
         HIP_TRY(c, launch_blend_fwd(ba, o->lds_batch == 0 ? 64 : o->lds_batch, st));
@@ -441,6 +448,7 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     uint32_t* pv[2] = { (uint32_t*)c->pv0.p, (uint32_t*)c->pv1.p };
     BlendBwdArgs bb;
     bb.rec = (const float4*)c->rec.p; bb.pair_vals = pv[c->sorted_buf];
+    bb.emit_vg = (const uint32_t*)c->emit_vg.p;
     bb.ranges = (const uint2*)c->ranges.p;
     bb.cams = dc; bb.n_views = (int32_t)V; bb.tile_shift_x = L.tsx; bb.tile_shift_y = L.tsy; bb.spt = L.spt;
     bb.n_blocks = L.n_blocks;
@@ -841,7 +849,7 @@ gsr_status gsr_stats(gsr_ctx* c, void* stream, int64_t* pairs_per_view, gsr_fram
         out->tested_fwd += cnt2[8 * b + 4];
         out->tested_bwd += cnt2[8 * b + 5];
     }
-    c->pairs = cnt[0];
+    c->pairs = std::min<size_t>(cnt[0], c->pair_cap);     // pairs held (a fixed capacity may have overflowed)
     return GSR_OK;
 }
 
@@ -1084,7 +1092,21 @@ gsr_status gsr_inspect(gsr_ctx* c, void* stream, gsr_buffer which, void* dst, in
         case GSR_BUF_RADIUS: src = c->radius.p; sz = (size_t)c->vn * 4; break;
         case GSR_BUF_DEPTH: src = c->depth.p; sz = (size_t)c->vn * 4; break;
         case GSR_BUF_TILES_TOUCHED: src = c->tt.p; sz = (size_t)c->vn * 4; break;
-        case GSR_BUF_PAIR_VALUES: src = pv[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
+        case GSR_BUF_PAIR_VALUES: {    // the sorted emission indices, mapped to their records
+            sz = (size_t)c->pairs * 4;
+            *bytes = (int64_t)sz;
+            if (!dst) return GSR_OK;
+            if ((int64_t)sz > capacity_bytes) return fail(c, GSR_ERR_INVALID_ARG, "destination too small");
+            std::vector<uint32_t> ev(c->pairs);
+            if (sz) {
+                HIP_TRY(c, hipMemcpyAsync(dst, pv[c->sorted_buf], sz, hipMemcpyDeviceToHost, st));
+                HIP_TRY(c, hipMemcpyAsync(ev.data(), c->emit_vg.p, sz, hipMemcpyDeviceToHost, st));
+            }
+            HIP_TRY(c, hipStreamSynchronize(st));
+            uint32_t* out = (uint32_t*)dst;
+            for (size_t q = 0; q < c->pairs; ++q) out[q] = out[q] < c->pairs ? ev[out[q]] : 0xffffffffu;
+            return GSR_OK;
+        }
         case GSR_BUF_PAIR_TILES: src = pk[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
         case GSR_BUF_RANGES: src = c->ranges.p; sz = (size_t)c->lay.n_tiles * 8; break;
         case GSR_BUF_GRAD2D: {         // zero rows for (view, Gaussian)s without pairs

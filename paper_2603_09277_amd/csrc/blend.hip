@@ -246,7 +246,100 @@ __device__ __forceinline__ uint32_t next_item_wave(WaveQueue& q, uint32_t* queue
 }
 
 
-// RENDER: colour only (test-time rendering): no entropy, no per-pixel saved state
+// Per-lane state of the front-to-back walk of one pixel.
+struct FwdPix {
+    float T, Cr, Cg, Cb, H2;         // transmittance, colour, entropy in log2 units
+    int32_t last, stop_pos;          // n_contrib; list position of the stopping entry (-1: none)
+    uint32_t nbl;                    // entries blended
+    // alpha tests made (surviving entries visited): svm over the batches finished
+    // before the stop, sv_stop up to the stopping entry, sv_last up to the last blend
+    uint32_t svm, sv_stop, sv_last;
+    bool done;
+};
+
+__device__ __forceinline__ void fwd_init(FwdPix& q, bool inside)
+{
+    q.T = 1.f; q.Cr = q.Cg = q.Cb = q.H2 = 0.f;
+    q.last = 0; q.stop_pos = -1; q.nbl = 0;
+    q.svm = q.sv_stop = q.sv_last = 0;
+    q.done = !inside;
+}
+
+// One surviving list entry (the k-th of this batch's survivors, at list position
+// pos) for one pixel: alpha (Eq. 3), the transmittance stop, colour (Eq. 5) and
+// the entropy term -w log2 w (Eq. 10).
+template <bool RENDER>
+__device__ __forceinline__ void fwd_step(FwdPix& q, float4 g0, float4 g1, float b, float fpx, float fpy, int32_t pos,
+                                         uint32_t k)
+{
+    const float p = gauss_p2(g0.z, g0.w, g1.x, g0.x - fpx, g0.y - fpy);
+    const float alpha = fminf(kAlphaMax, g1.y * __builtin_amdgcn_exp2f(p));
+    const float Tn = q.T * (1.f - alpha);
+    const bool hit = !q.done && alpha >= kAlphaMin;
+    const bool stop = hit && Tn < kTStop;                    // this entry would take T below 1e-4
+    const bool blend = hit && !stop;
+    // the bookkeeping as selects (conditional stores to different members would
+    // be merged into one store through a selected address, which keeps q in memory)
+    const uint32_t sv = q.svm + k + 1u;
+    q.sv_stop = stop ? sv : q.sv_stop;
+    q.stop_pos = stop ? pos : q.stop_pos;
+    q.sv_last = blend ? sv : q.sv_last;
+    q.last = blend ? pos + 1 : q.last;
+    q.nbl += blend ? 1u : 0u;
+    q.done = q.done || stop;
+    if (blend) {
+        const float w = alpha * q.T;
+        q.Cr = fmaf(w, g1.z, q.Cr);
+        q.Cg = fmaf(w, g1.w, q.Cg);
+        q.Cb = fmaf(w, b, q.Cb);
+        if (!RENDER) q.H2 = fmaf(-w, __builtin_amdgcn_logf(w), q.H2);    // -w log2 w   (Eq. 10)
+        q.T = Tn;
+    }
+}
+
+// Outputs of one pixel and the work counts of its 8x8 block.
+template <bool RENDER>
+__device__ __forceinline__ void fwd_store(const BlendFwdArgs& a, const BlockGeom& g, const FwdPix& q, uint2 rg,
+                                          uint32_t wb, uint32_t lane)
+{
+    // background weight T_{N+1} (Eq. 9-10), then natural-log units
+    const float H = RENDER ? 0.f : kLn2 * fmaf(-q.T, __builtin_amdgcn_logf(q.T), q.H2);
+    if (g.inside) {
+        a.out_rgb[3 * g.pix + 0] = q.Cr;
+        a.out_rgb[3 * g.pix + 1] = q.Cg;
+        a.out_rgb[3 * g.pix + 2] = q.Cb;
+        if (!RENDER) {
+            a.out_H[g.pix] = H;
+            a.out_T[g.pix] = q.T;
+            a.out_nc[g.pix] = q.last;
+        }
+    }
+    // list positions this pixel visited (the stopping entry included), culled ones counted
+    const int32_t n_eval = !g.inside ? 0 : (q.stop_pos >= 0 ? q.stop_pos + 1 : (int32_t)(rg.y - rg.x));
+    const uint32_t ne = (uint32_t)wave_sum_all_i(n_eval);
+    const uint32_t nc = (uint32_t)wave_sum_all_i(q.last);
+    const uint32_t nb = (uint32_t)wave_sum_all_i((int)q.nbl);
+    // alpha tests at list positions that survived the block cull: the ones this
+    // kernel made (until the ray stopped) and the ones the backward makes (up to
+    // the last contributor)
+    // (both members read, then combined: a select between two members becomes a
+    // load through a selected address, which keeps q in memory)
+    const uint32_t tested = q.svm + (q.stop_pos >= 0 ? q.sv_stop - q.svm : 0u);
+    const uint32_t tf = (uint32_t)wave_sum_all_i((int)tested);
+    const uint32_t tb = (uint32_t)wave_sum_all_i((int)q.sv_last);
+    const float hs = RENDER ? 0.f : wave_sum_all(g.inside ? H : 0.f);
+    if (lane == 0) {
+        if (!RENDER) a.block_H[wb] = hs;
+        a.block_cnt[2 * wb] = make_uint4(ne, nc, nb, 0u);
+        a.block_cnt[2 * wb + 1] = make_uint4(tf, tb, 0u, 0u);
+    }
+}
+
+// One wavefront per 8x8 block with its own batches: a wavefront whose pixels
+// have all stopped leaves at once, which pays on short lists; on long ones the
+// four blocks of a tile restage the same entries (blend_fwd_shared_kernel
+// below stages them once).  RENDER: colour only (test-time rendering): no
+// entropy, no per-pixel saved state.
 template <int B, bool PERSIST, bool RENDER>
 __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
 {
@@ -275,16 +368,13 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
     const uint2 rg = a.ranges[g.tile];
     const float fpx = (float)g.px + 0.5f, fpy = (float)g.py + 0.5f;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-
-    float T = 1.f, Cr = 0.f, Cg = 0.f, Cb = 0.f, H2 = 0.f;   // H2: entropy in log2 units
-    int32_t last = 0, stop_pos = -1;
-    uint32_t nbl = 0;                                        // entries blended
-    // alpha tests made (surviving entries visited): svm over the batches finished
-    // before the stop, sv_stop up to the stopping entry, sv_last up to the last blend
-    uint32_t svm = 0, sv_stop = 0, sv_last = 0;
-    bool done = !g.inside;
+    FwdPix q;
+    fwd_init(q, g.inside);
+    // the record indices of a batch's first 64 entries (two dependent loads) are
+    // fetched one batch ahead
+    uint32_t pv = rg.x + lane < rg.y ? a.emit_vg[a.pair_vals[rg.x + lane]] : 0u;
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
-        if (__ballot(!done) == 0ull) break;
+        if (__ballot(!q.done) == 0ull) break;
         const uint32_t cnt = (rg.y - bs) < (uint32_t)B ? (rg.y - bs) : (uint32_t)B;
         // stage the batch, keeping (in list order) only Gaussians that can reach this block
         uint32_t m = 0;
@@ -293,7 +383,8 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
             bool keep = false;
             float4 r0, r1, r2;
             if (j < cnt) {
-                const float4* r = a.rec + (size_t)kRecF4 * a.pair_vals[bs + j];
+                const uint32_t vg = j0 == 0 ? pv : a.emit_vg[a.pair_vals[bs + j]];
+                const float4* r = a.rec + (size_t)kRecF4 * vg;
                 r0 = r[0];
                 r1 = r[1];
                 r2 = r[2];
@@ -309,62 +400,88 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
             }
             m += (uint32_t)__popcll(bal);
         }
+        if (bs + B + lane < rg.y) pv = a.emit_vg[a.pair_vals[bs + B + lane]];
         wave_lds_sync();
-        for (uint32_t k = 0; k < m; ++k) {
-            const float4 g0 = s_g0[wid][k];
-            const float4 g1 = s_g1[wid][k];
-            const float p = gauss_p2(g0.z, g0.w, g1.x, g0.x - fpx, g0.y - fpy);
-            const float alpha = fminf(kAlphaMax, g1.y * __builtin_amdgcn_exp2f(p));
-            if (!done && alpha >= kAlphaMin) {
-                const float Tn = T * (1.f - alpha);
-                if (Tn < kTStop) {
-                    done = true;
-                    stop_pos = s_pos[wid][k];
-                    sv_stop = svm + k + 1u;
-                } else {
-                    const float w = alpha * T;
-                    Cr = fmaf(w, g1.z, Cr);
-                    Cg = fmaf(w, g1.w, Cg);
-                    Cb = fmaf(w, s_b[wid][k], Cb);
-                    if (!RENDER) H2 = fmaf(-w, __builtin_amdgcn_logf(w), H2);    // -w log2 w   (Eq. 10)
-                    T = Tn;
-                    last = s_pos[wid][k] + 1;
-                    ++nbl;
-                    sv_last = svm + k + 1u;
-                }
+        for (uint32_t k = 0; k < m; ++k)
+            fwd_step<RENDER>(q, s_g0[wid][k], s_g1[wid][k], s_b[wid][k], fpx, fpy, s_pos[wid][k], k);
+        if (!q.done) q.svm += m;
+        wave_lds_sync();
+    }
+    fwd_store<RENDER>(a, g, q, rg, wb, lane);
+    }
+}
+
+// The 4 wavefronts of a workgroup are the 4 8x8 blocks of one 16x16 or 32x8
+// tile: each batch of the tile's list is staged once for all four (one entry per
+// thread), then every wavefront keeps the entries that can reach its block (the
+// exact cull, into its own index list) and blends them.  The batch loop ends when
+// no pixel of the tile is still open.
+template <int B, bool PERSIST, bool RENDER>
+__global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
+{
+    static_assert(B <= 256, "one staged entry per thread");
+    __shared__ float4 s_g0[B];                    // mean x, mean y, A', B'
+    __shared__ float4 s_g1[B];                    // C', opacity, red, green
+    __shared__ float s_b[B];                      // blue
+    __shared__ float s_cull[B];                   // L
+    __shared__ int32_t s_idx[kWavesPerGroup][B];  // each wavefront's surviving batch entries, in list order
+    __shared__ uint32_t s_item;
+    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, tid = threadIdx.x;
+    const uint32_t n_items = a.n_blocks / kWavesPerGroup;      // tiles
+    auto next = [&]() -> uint32_t {
+        if (!PERSIST) return n_items;
+        __syncthreads();
+        if (tid == 0) s_item = claim_items(a.queues, n_items, 1u).x;
+        __syncthreads();
+        return s_item;
+    };
+    uint32_t item;
+    if (PERSIST) item = next();
+    else item = a.tile_order ? a.tile_order[blockIdx.x] : blockIdx.x;   // longest tiles first
+    for (; item < n_items; item = next()) {
+    const uint32_t wb = item * kWavesPerGroup + wid;
+    const BlockGeom g = block_geom(a.cams, a.n_views, wb, lane, a.tile_shift_x, a.tile_shift_y, a.spt);
+    const uint2 rg = a.ranges[g.tile];
+    const float fpx = (float)g.px + 0.5f, fpy = (float)g.py + 0.5f;
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+    FwdPix q;
+    fwd_init(q, g.inside);
+    // each thread stages one entry of a batch; its record index (two dependent
+    // loads) is fetched one batch ahead
+    uint32_t pv = 0;
+    if (tid < (uint32_t)B && rg.x + tid < rg.y) pv = a.emit_vg[a.pair_vals[rg.x + tid]];
+    for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
+        if (!__syncthreads_or(q.done ? 0 : 1)) break;           // every pixel of the tile has stopped
+        const uint32_t cnt = (rg.y - bs) < (uint32_t)B ? (rg.y - bs) : (uint32_t)B;
+        if (tid < cnt) {
+            const float4* r = a.rec + (size_t)kRecF4 * pv;
+            const float4 r2 = r[2];
+            s_g0[tid] = r[0];
+            s_g1[tid] = r[1];
+            s_b[tid] = r2.x;
+            s_cull[tid] = r2.y;
+        }
+        __syncthreads();
+        if (tid < (uint32_t)B && bs + B + tid < rg.y) pv = a.emit_vg[a.pair_vals[bs + B + tid]];
+        uint32_t m = 0;
+        if (__ballot(!q.done) != 0ull) {                         // this block still has open pixels
+            for (uint32_t j0 = 0; j0 < cnt; j0 += kWave) {
+                const uint32_t j = j0 + lane;
+                const bool keep = j < cnt && !culled(g, s_g0[j], s_g1[j].x, s_cull[j]);
+                const uint64_t bal = __ballot(keep);
+                if (keep) s_idx[wid][m + (uint32_t)__popcll(bal & lt_mask)] = (int32_t)j;
+                m += (uint32_t)__popcll(bal);
             }
         }
-        if (!done) svm += m;
         wave_lds_sync();
-    }
-    // background weight T_{N+1} (Eq. 9-10), then natural-log units
-    const float H = RENDER ? 0.f : kLn2 * fmaf(-T, __builtin_amdgcn_logf(T), H2);
-    if (g.inside) {
-        a.out_rgb[3 * g.pix + 0] = Cr;
-        a.out_rgb[3 * g.pix + 1] = Cg;
-        a.out_rgb[3 * g.pix + 2] = Cb;
-        if (!RENDER) {
-            a.out_H[g.pix] = H;
-            a.out_T[g.pix] = T;
-            a.out_nc[g.pix] = last;
+        for (uint32_t k = 0; k < m; ++k) {
+            const int32_t j = s_idx[wid][k];
+            fwd_step<RENDER>(q, s_g0[j], s_g1[j], s_b[j], fpx, fpy, (int32_t)(bs - rg.x) + j, k);
         }
+        if (!q.done) q.svm += m;
+        __syncthreads();                                         // the batch arrays are restaged next
     }
-    // list positions this pixel visited (the stopping entry included), culled ones counted
-    const int32_t n_eval = !g.inside ? 0 : (stop_pos >= 0 ? stop_pos + 1 : (int32_t)(rg.y - rg.x));
-    const uint32_t ne = (uint32_t)wave_sum_all_i(n_eval);
-    const uint32_t nc = (uint32_t)wave_sum_all_i(last);
-    const uint32_t nb = (uint32_t)wave_sum_all_i((int)nbl);
-    // alpha tests at list positions that survived the block cull: the ones this
-    // kernel made (until the ray stopped) and the ones the backward makes (up to
-    // the last contributor)
-    const uint32_t tf = (uint32_t)wave_sum_all_i((int)(stop_pos >= 0 ? sv_stop : svm));
-    const uint32_t tb = (uint32_t)wave_sum_all_i((int)sv_last);
-    const float hs = RENDER ? 0.f : wave_sum_all(g.inside ? H : 0.f);
-    if (lane == 0) {
-        if (!RENDER) a.block_H[wb] = hs;
-        a.block_cnt[2 * wb] = make_uint4(ne, nc, nb, 0u);
-        a.block_cnt[2 * wb + 1] = make_uint4(tf, tb, 0u, 0u);
-    }
+    fwd_store<RENDER>(a, g, q, rg, wb, lane);
     }
 }
 
@@ -537,21 +654,45 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     const bool row_lead = (lane & 15u) == 0u;
     const int32_t rc = row_comp(lane >> 4);
 
+    // SHARED: each thread stages one entry of a window; its emission index and
+    // record index (two dependent loads) are fetched one window ahead
+    uint32_t pe = 0, pv = 0;
+    if (SHARED && maxn > 0) {
+        const int32_t lo0 = maxn - B > 0 ? maxn - B : 0;
+        if ((int32_t)tid < maxn - lo0) {
+            pe = a.pair_vals[rg.x + (uint32_t)(lo0 + (int32_t)tid)];
+            pv = a.emit_vg[pe];
+        }
+    }
     for (int32_t hi = maxn; hi > 0; hi -= B) {
         const int32_t lo = hi - B > 0 ? hi - B : 0;
         const int32_t cnt = hi - lo;
         // stage the window
         for (int32_t j = tid; j < cnt; j += nthr) {
-            const float4* r = a.rec + (size_t)kRecF4 * a.pair_vals[rg.x + (uint32_t)(lo + j)];
+            uint32_t e, vg;
+            if (SHARED) {                                                  // j == tid
+                e = pe;
+                vg = pv;
+            } else {
+                e = a.pair_vals[rg.x + (uint32_t)(lo + j)];                // the pair's emission index
+                vg = a.emit_vg[e];
+            }
+            const float4* r = a.rec + (size_t)kRecF4 * vg;
             const float4 r2 = r[2];
-            // emission slot of this (tile, Gaussian) pair
-            s_e[slot][j] = __float_as_uint(r2.z) + g.ty * __float_as_uint(r2.w) + g.tx;
+            s_e[slot][j] = e;
             s_g0[slot][j] = r[0];
             s_g1[slot][j] = r[1];
             s_b[slot][j] = r2.x;
             s_cull[slot][j] = r2.y;
         }
         if (SHARED) __syncthreads(); else wave_lds_sync();
+        if (SHARED && lo > 0) {                                            // the next window's indices
+            const int32_t lo2 = lo - B > 0 ? lo - B : 0;
+            if ((int32_t)tid < lo - lo2) {
+                pe = a.pair_vals[rg.x + (uint32_t)(lo2 + (int32_t)tid)];
+                pv = a.emit_vg[pe];
+            }
+        }
         // this wavefront's surviving entries of the window, in list order
         const int32_t jtop = (wave_n - lo) < cnt ? (wave_n - lo) : cnt;
         int32_t m = 0;
@@ -673,24 +814,31 @@ uint32_t resident_groups(K kernel, uint32_t want)
     return g < want ? g : want;
 }
 
+template <int B, bool RENDER>
+hipError_t fwd_launch(const BlendFwdArgs& a, hipStream_t s)
+{
+    const uint32_t groups = (a.n_blocks + kWavesPerGroup - 1) / kWavesPerGroup;
+    if (a.spt == 4 && a.shared_batches) {  // one tile per workgroup, batches shared by its 4 blocks
+        if (a.queues)
+            hipLaunchKernelGGL((blend_fwd_shared_kernel<B, true, RENDER>),
+                               dim3(resident_groups(blend_fwd_shared_kernel<B, true, RENDER>, groups)), dim3(256), 0,
+                               s, a);
+        else
+            hipLaunchKernelGGL((blend_fwd_shared_kernel<B, false, RENDER>), dim3(groups), dim3(256), 0, s, a);
+    } else {                               // one 8x8 block per wavefront, its own batches
+        if (a.queues)
+            hipLaunchKernelGGL((blend_fwd_kernel<B, true, RENDER>),
+                               dim3(resident_groups(blend_fwd_kernel<B, true, RENDER>, groups)), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((blend_fwd_kernel<B, false, RENDER>), dim3(groups), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 template <int B>
 hipError_t fwd_b(const BlendFwdArgs& a, hipStream_t s)
 {
-    const uint32_t groups = (a.n_blocks + kWavesPerGroup - 1) / kWavesPerGroup;
-    if (a.render_only) {
-        if (a.queues)
-            hipLaunchKernelGGL((blend_fwd_kernel<B, true, true>),
-                               dim3(resident_groups(blend_fwd_kernel<B, true, true>, groups)), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((blend_fwd_kernel<B, false, true>), dim3(groups), dim3(256), 0, s, a);
-    } else {
-        if (a.queues)
-            hipLaunchKernelGGL((blend_fwd_kernel<B, true, false>),
-                               dim3(resident_groups(blend_fwd_kernel<B, true, false>, groups)), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((blend_fwd_kernel<B, false, false>), dim3(groups), dim3(256), 0, s, a);
-    }
-    return hipGetLastError();
+    return a.render_only ? fwd_launch<B, true>(a, s) : fwd_launch<B, false>(a, s);
 }
 
 template <int B>

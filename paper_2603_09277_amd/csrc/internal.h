@@ -38,12 +38,16 @@ constexpr int kL1Block = 256;      // pixels per L1 block
 // Projected record of one (view, Gaussian): three float4
 //   r0 = (mean x, mean y, A', B')
 //   r1 = (C', opacity, red, green)
-//   r2 = (blue, L, base, w)  (L: cull level; base, w as uint32 bits: the pair of local
-//                             tile (tx, ty) has emission index base + ty w + tx)
+//   r2 = (blue, L, 0, 0)  (L: cull level)
 // with the conic pre-scaled to log2 units: A' = -A log2(e)/2, B' = -B log2(e),
 // C' = -C log2(e)/2, so that the exponent is A' dx^2 + B' dx dy + C' dy^2.
 constexpr double kLog2e = 1.4426950408889634;
 constexpr int kRecF4 = 3;
+// mean per-tile list length from which the forward stages each batch once per
+// 16x16 / 32x8 tile instead of once per 8x8 block (measured: 200k Gaussians at
+// 1296x840, mean 211, per block 0.105 vs shared 0.116 ms; 1M at 1600x1060, mean
+// 1025, 0.232 vs 0.184 ms; its half-scale variant, mean 495, per block 0.244 ms)
+constexpr double kSharedBatchMeanLen = 256.0;
 // persistent blend kernels: one work queue per XCD, heads 128 bytes apart
 constexpr uint32_t kQueues = 8;
 constexpr uint32_t kQueueStride = 32;
@@ -96,7 +100,8 @@ struct ProjectBwdArgs {
 
 struct BlendFwdArgs {
     const float4* rec;
-    const uint32_t* pair_vals;            // sorted pairs: view*n + Gaussian index
+    const uint32_t* pair_vals;            // sorted pairs: emission index e of each (tile, Gaussian) pair
+    const uint32_t* emit_vg;              // [P] record (view*n + Gaussian index) of emission index e
     const uint2* ranges;
     const CamDev* cams;
     int32_t n_views;
@@ -113,11 +118,13 @@ struct BlendFwdArgs {
     uint32_t* queues;                     // persistent mode: kQueues heads kQueueStride words apart, zeroed; or null
     int32_t render_only;                  // 1: colour only (no entropy, no saved state)
     const uint32_t* tile_order;           // [n_tiles] tiles, longest list first (hardware dispatch); or null
+    int32_t shared_batches;               // 16x16 / 32x8 tiles: stage each batch once for the 4 blocks
 };
 
 struct BlendBwdArgs {
     const float4* rec;
-    const uint32_t* pair_vals;
+    const uint32_t* pair_vals;            // sorted pairs: emission index e (the pair's gradient row)
+    const uint32_t* emit_vg;              // [P] record of emission index e
     const uint2* ranges;
     const CamDev* cams;
     int32_t n_views;
@@ -156,13 +163,14 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, u
                              uint32_t* vals_out, const uint32_t* n_dev, uint32_t n_max, int shift,
                              uint32_t* tmp, hipStream_t s);
 
-// write (tile id, view*n + Gaussian index) pairs of every Gaussian in depth order,
-// emit_vg[emission index] = view*n + Gaussian index, and into each record with
-// pairs its emission base and rectangle width (record words 10, 11)
+// write the tile id of every (tile, Gaussian) pair, Gaussians in depth order, at
+// its emission index (keys[e]), and emit_vg[e] = view*n + Gaussian index; the
+// pairs' sort values are their emission indices (the tile sort's first pass
+// takes them as the items' indices)
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const uint32_t* tt_s,
                             const uint2* rect_s, const CamDev* cams, uint32_t n, uint32_t vn,
-                            const uint32_t* total, uint32_t cap, uint32_t* keys, uint32_t* vals,
-                            uint32_t* emit_vg, uint32_t* overflow, float4* rec, hipStream_t s);
+                            const uint32_t* total, uint32_t cap, uint32_t* keys, uint32_t* emit_vg,
+                            uint32_t* overflow, hipStream_t s);
 // grad2d[vg] = sum of the per-pair rows pair_grad[10 e .. 10 e + 8] with pair_stamp[e] == *stamp over the Gaussian's
 // emission range, for every (view, Gaussian) with pairs (others are left untouched)
 // (zero for Gaussians without pairs); carry holds seg_carry_bytes(cap) bytes

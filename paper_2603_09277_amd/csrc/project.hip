@@ -275,8 +275,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectFwdArgs a)
             r0 = make_float4(P.mx, P.my, A2, B2);
             r1 = make_float4(C2, op, col[0], col[1]);
             // Cull level for the blend: alpha < 1/255 wherever the exponent is
-            // below -L, L = log2(255 opacity) + 1e-4.  (r2.z, r2.w) are filled by
-            // the pair duplication.
+            // below -L, L = log2(255 opacity) + 1e-4.
             const double Lc = op > 0.f ? log2(255.0 * (double)op) + 1e-4 : -HUGE_VAL;
             r2 = make_float4(col[2], (float)Lc, 0.f, 0.f);
         }

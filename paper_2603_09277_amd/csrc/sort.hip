@@ -301,13 +301,15 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
 
 // ---------------------------------------------------------------------------
 // Duplication: every (view, Gaussian) in depth order writes one pair per tile
-// of its rectangle, row-major, at its scanned offset.  The pair's value is the
-// (view, Gaussian) record index; emit_vg[emission index] holds it too.  All
-// pairs of one Gaussian are contiguous in emission order, which the backward
-// uses to reduce per-pair gradients without atomics: the pair of local tile
-// (tx, ty) has emission index base + ty w + tx (mod 2^32), with
-// base = offset - y0 w - x0 and w = x1 - x0 + 1 stored in the record's last
-// two words.
+// of its rectangle, row-major, at its scanned offset (the pair's emission
+// index e): its tile id, and its record index in emit_vg[e].  The pair's sort
+// value is e itself, so after the tile sort a list entry names both the pair's
+// gradient row (e) and, through emit_vg, its record.  All pairs of one Gaussian
+// are contiguous in emission order, which the backward uses to reduce
+// per-pair gradients without atomics.  (An earlier form sorted record indices
+// and wrote each Gaussian's emission base into its record: 8-byte writes to
+// records in depth order, scattered over the record array, which took 2/3 of
+// this kernel's time on the 8-view workload.)
 //
 // One wavefront takes 64 consecutive Gaussians in depth order; their pairs are
 // one contiguous output range, which its 64 lanes write together, 64
@@ -320,8 +322,7 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* ord
                                                              const uint32_t* tt_s, const uint2* rect_s,
                                                              const CamDev* cams, uint32_t n, uint32_t vn,
                                                              const uint32_t* total, uint32_t cap, uint32_t* keys,
-                                                             uint32_t* vals, uint32_t* emit_vg, uint32_t* overflow,
-                                                             float4* rec)
+                                                             uint32_t* emit_vg, uint32_t* overflow)
 {
     __shared__ uint32_t s_loc[kThreads / 64][64];
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
@@ -336,13 +337,6 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* ord
         tt = tt_s[s];
         off = offsets[s];
         rc = rect_s[s];
-    }
-    const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
-    const uint32_t w = x1 - x0 + 1u;
-    if (tt) {
-        float4* r2 = rec + (size_t)kRecF4 * vg + 2;
-        r2->z = __uint_as_float(off - y0 * w - x0);
-        r2->w = __uint_as_float(w);
     }
     // the wavefront's pairs: [off0, off0 + count)
     const uint32_t off0 = __shfl(off, 0, 64);
@@ -374,7 +368,6 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* ord
         const uint32_t p = off0 + q;
         if (q0 + lane < count && p < cap) {
             keys[p] = cams[v].tile_base + (ry0 + dy) * (uint32_t)cams[v].gx + rx0 + dx;
-            vals[p] = rvg;
             emit_vg[p] = rvg;
         }
     }
@@ -658,12 +651,11 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, u
 
 hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, const uint32_t* tt_s,
                             const uint2* rect_s, const CamDev* cams, uint32_t n, uint32_t vn, const uint32_t* total,
-                            uint32_t cap, uint32_t* keys, uint32_t* vals, uint32_t* emit_vg, uint32_t* overflow,
-                            float4* rec, hipStream_t s)
+                            uint32_t cap, uint32_t* keys, uint32_t* emit_vg, uint32_t* overflow, hipStream_t s)
 {
     if (vn == 0) return hipSuccess;
     hipLaunchKernelGGL(duplicate_kernel, dim3((vn + kThreads - 1) / kThreads), dim3(kThreads), 0, s, order, offsets,
-                       tt_s, rect_s, cams, n, vn, total, cap, keys, vals, emit_vg, overflow, rec);
+                       tt_s, rect_s, cams, n, vn, total, cap, keys, emit_vg, overflow);
     return hipGetLastError();
 }
 

@@ -233,6 +233,37 @@ def test_blend_backward_stagewise(R, tiny):
     assert rel_norm(g2g[:, 6:9], g2o["rgb"]) < GRAD_TOL
 
 
+@pytest.mark.parametrize("tile,lds", [((16, 16), 128), ((32, 8), 64), ((16, 16), 256)])
+def test_long_lists_shared_batches_vs_oracle(R, tile, lds):
+    """Mean list length above 512: the forward stages each batch once per tile for its four
+    8x8 blocks (the short-list tests cover the per-block staging).  Image, entropy and
+    transmittance stage-wise, and the blend backward, against the oracle."""
+    scene, cams = scenes.tiny_scene(41, 8000)
+    scene.scales = (scene.scales * np.float32(4.0)).astype(np.float32)
+    cam = cams[0]
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=tile, lds_batch=lds, sh_degree=0)
+    out = gpu_forward(R, t, cams, opts)
+    st = R.stats(1)
+    assert st["mean_len"] >= 512, st["mean_len"]
+    pg = gpu_records(R, scene.n, 1)[0]
+    img_o = oracle_stagewise(pg, cam, tile)
+    _cmp_image(out, img_o, cam)
+    g_rgb = l1_grad_torch(out["rgb"], scenes.target_image(43, cam.height, cam.width))
+    M = cam.width * cam.height
+    gpu_backward(R, t, cams, opts, out, g_rgb, None, torch.full((1,), GAMMA, device=DEV))
+    vals, ranges = orc.bin_lists(pg["mean2d"], pg["radius"], pg["depth32"], cam.width, cam.height, tile[0], tile[1])
+    g2o = orc.backward_render(cam.width, cam.height, tile[0], tile[1], pg["mean2d"], pg["conic"], pg["opacity"],
+                              pg["rgb"], ranges, vals,
+                              g_rgb.cpu().numpy().reshape(cam.height, cam.width, 3).astype(np.float64),
+                              np.full((cam.height, cam.width), GAMMA / M))
+    g2g = R.inspect(gsr.BUF_GRAD2D).reshape(scene.n, 9).astype(np.float64)
+    assert rel_norm(g2g[:, 0:2], g2o["mean2d"]) < GRAD_TOL
+    assert rel_norm(g2g[:, 2:5], g2o["conic"]) < GRAD_TOL
+    assert rel_norm(g2g[:, 5], g2o["opacity"]) < GRAD_TOL
+    assert rel_norm(g2g[:, 6:9], g2o["rgb"]) < GRAD_TOL
+
+
 def test_projection_backward_stagewise(R, tiny):
     scene, cams = tiny
     t, opts, out, target, g_rgb, grads = _tiny_backward(R, scene, cams)

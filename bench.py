@@ -103,12 +103,12 @@ def stage_bytes(stage, n, V, sh_bytes, pairs, n_tiles, npix, evals_fwd, evals_bw
         "project": n * (44 + sh_bytes) + vn * 64,          # params + SH once; record 48 + key 4 + rect 8 + tt 4
         "depth_sort": vn * 4 * 20,                          # 4 passes: key+value in/out, key histogram
         "scan": vn * 36,                                    # order, tt and rect gathered, depth-ordered copies, offsets
-        "duplicate": vn * 28 + pairs * 12,                  # order/tt/offset/rect + emission base; key, value, owner
+        "duplicate": vn * 20 + pairs * 8,                   # order/tt/offset/rect; tile id, owner
         "tile_sort": pairs * 20 * 2,                        # 2 passes
         "ranges": pairs * 4 + n_tiles * 8,
-        "blend_fwd": pairs * 52 + npix * 24,                # pair value + record; rgb, H, T, n_contrib
+        "blend_fwd": pairs * 56 + npix * 24,                # pair value + owner + record; rgb, H, T, n_contrib
         "entropy_mean": 0,
-        "blend_bwd": pairs * 92 + npix * 24,                # pair value + record + gradient row and stamp; per-pixel state
+        "blend_bwd": pairs * 96 + npix * 24,                # pair value + owner + record + row + stamp; per-pixel state
         "project_bwd": n * (88 + 2 * sh_bytes) + vn * 40,   # params + SH in, grads out; 2D grads + tt per view
         "grad_reduce": pairs * 8 + vn * 36,                 # stamps + owners in (rows only where written), 2D grads out
     }[stage]

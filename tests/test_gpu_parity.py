@@ -262,6 +262,17 @@ def test_long_lists_shared_batches_vs_oracle(R, tile, lds):
     assert rel_norm(g2g[:, 2:5], g2o["conic"]) < GRAD_TOL
     assert rel_norm(g2g[:, 5], g2o["opacity"]) < GRAD_TOL
     assert rel_norm(g2g[:, 6:9], g2o["rgb"]) < GRAD_TOL
+    # the persistent scheduling of the same kernels: bit-identical outputs and gradients
+    ref = {k: out[k].clone() for k in ("rgb", "entropy", "t_final", "n_contrib", "entropy_mean")}
+    gref = gpu_backward(R, t, cams, opts, gpu_forward(R, t, cams, opts), g_rgb, None,
+                        torch.full((1,), GAMMA, device=DEV))
+    popts = gsr.RasterOptions(tile=tile, lds_batch=lds, sh_degree=0, flags=gsr.GSR_DEFAULT_FLAGS | gsr.GSR_PERSISTENT)
+    pout = gpu_forward(R, t, cams, popts)
+    for k in ref:
+        assert torch.equal(pout[k], ref[k]), k
+    pg_ = gpu_backward(R, t, cams, popts, pout, g_rgb, None, torch.full((1,), GAMMA, device=DEV))
+    for k in KEYS:
+        assert np.array_equal(pg_[k], gref[k]), k
 
 
 def test_projection_backward_stagewise(R, tiny):

@@ -109,8 +109,8 @@ def stage_bytes(stage, n, V, sh_bytes, pairs, n_tiles, npix, evals_fwd, evals_bw
         "blend_fwd": pairs * 56 + npix * 24,                # pair value + owner + record; rgb, H, T, n_contrib
         "entropy_mean": 0,
         "blend_bwd": pairs * 96 + npix * 24,                # pair value + owner + record + row + stamp; per-pixel state
-        "project_bwd": n * (88 + 2 * sh_bytes) + vn * 40,   # params + SH in, grads out; 2D grads + tt per view
-        "grad_reduce": pairs * 8 + vn * 36,                 # stamps + owners in (rows only where written), 2D grads out
+        "project_bwd": n * (88 + 2 * sh_bytes) + vn * 44,   # params + SH in, grads out; 2D grads + tt + stamp per view
+        "grad_reduce": pairs * 8,                           # stamps + owners in (rows and 2D grads only where blended)
     }[stage]
 
 

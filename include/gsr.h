@@ -323,7 +323,9 @@ typedef enum {
     GSR_BUF_PAIR_VALUES = 4,   /* uint32[P]: view*n + Gaussian index, sorted by (tile, depth, index) */
     GSR_BUF_PAIR_TILES = 5,    /* uint32[P]: global tile id of each sorted pair */
     GSR_BUF_RANGES = 6,        /* uint32[n_tiles_total][2] = [start, end) */
-    GSR_BUF_GRAD2D = 7         /* float[V*n][9]: dL/d mean x, y, conic A, B, C, opacity, r, g, b */
+    GSR_BUF_GRAD2D = 7         /* float[V*n][9]: dL/d mean x, y, conic A, B, C, opacity, r, g, b of the
+                                  latest backward (zero rows for (view, Gaussian)s none of whose pairs
+                                  a pixel blended: the device keeps no row for them) */
 } gsr_buffer;
 
 gsr_status gsr_inspect(gsr_ctx* ctx, void* stream, gsr_buffer which, void* dst, int64_t capacity_bytes,

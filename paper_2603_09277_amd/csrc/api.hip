@@ -53,7 +53,7 @@ struct gsr_ctx {
 
     // grow-only device buffers
     // rect: per record (rectangle, tiles touched) as uint4
-    Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, tt_s, rect_s, radius, depth, offsets, grad2d, scan_tmp, radix_tmp;
+    Dev cams, rec, dkey0, dkey1, ord0, ord1, rect, tt, tt_s, rect_s, radius, depth, offsets, grad2d, rec_stamp, scan_tmp, radix_tmp;
     Dev pk0, pk1, pv0, pv1, emit_vg, pair_grad, pair_stamp, seg_carry, ranges, tile_order, queues, block_H, block_cnt, hchunk, counters, l1_tmp, reg_tmp, ssim_tmp;
     size_t vn_cap = 0, pair_cap = 0, tile_cap = 0, block_cap = 0;
     uint64_t gen = 0;                      // bumped on every reallocation; graphs hold raw pointers
@@ -278,7 +278,7 @@ gsr_status ensure_vn(gsr_ctx* c, uint32_t vn)
         (s = grow(c, c->ord0, v * 4)) || (s = grow(c, c->ord1, v * 4)) || (s = grow(c, c->rect, v * 16)) ||
         (s = grow(c, c->tt, v * 4)) || (s = grow(c, c->tt_s, v * 4)) || (s = grow(c, c->rect_s, v * 8)) ||
         (s = grow(c, c->radius, v * 4)) || (s = grow(c, c->depth, v * 4)) ||
-        (s = grow(c, c->offsets, v * 4)) || (s = grow(c, c->grad2d, v * 4 * kG2)) ||
+        (s = grow(c, c->offsets, v * 4)) || (s = grow(c, c->grad2d, v * 4 * kG2)) || (s = grow(c, c->rec_stamp, v * 4, true)) ||
         (s = grow(c, c->scan_tmp, scan_tmp_words((uint32_t)v) * 4)))
         return s;
     c->vn_cap = v;
@@ -330,8 +330,8 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     uint32_t* counters = (uint32_t*)c->counters.p;
     // pair count and overflow cleared; a new stamp for the per-pair gradient rows of
     // this frame's backward (every backward of one forward writes the same rows: the
-    // entries some pixel blended)
-    HIP_TRY(c, launch_frame_begin(counters, st));
+    // entries some pixel blended); the tile ranges and tile-order class counts cleared
+    HIP_TRY(c, launch_frame_begin(counters, (uint32_t*)c->ranges.p, L.n_tiles * 2u + kTileHistWords, st));
 
     ProjectFwdArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
@@ -395,7 +395,6 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     const bool persist = (o->flags & GSR_PERSISTENT) != 0;
     {
         StageTimer tm(c, st, GSR_STAGE_RANGES, !c->capturing);
-        HIP_TRY(c, launch_fill_u32((uint32_t*)c->ranges.p, 0u, (size_t)L.n_tiles * 2 + kTileHistWords, st));
         HIP_TRY(c, launch_ranges(pk[sb], counters, cap, (uint2*)c->ranges.p, st));
         // hardware dispatch visits the tiles longest list first (persistent kernels keep their queues)
         if (!persist)
@@ -467,13 +466,14 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
                                       (const uint32_t*)c->counters.p + 4,
                                       (const uint32_t*)c->emit_vg.p,
                                       vn, (const uint32_t*)c->counters.p, (uint32_t)c->pair_cap_used,
-                                      (float*)c->grad2d.p, c->seg_carry.p, st));
+                                      (float*)c->grad2d.p, (uint32_t*)c->rec_stamp.p, c->seg_carry.p, st));
     }
     StageTimer tp(c, st, GSR_STAGE_PROJECT_BWD, !c->capturing);
     ProjectBwdArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
     pa.n = n; pa.n_views = (int32_t)V; pa.flags = o->flags; pa.cams = dc; pa.grad2d = (const float*)c->grad2d.p;
     pa.tiles_touched = (const uint32_t*)c->tt.p;
+    pa.rec_stamp = (const uint32_t*)c->rec_stamp.p; pa.stamp = (const uint32_t*)c->counters.p + 4;
     pa.g_means = gr->means; pa.g_scales = gr->scales; pa.g_quats = gr->quats; pa.g_opac = gr->opacities;
     pa.g_sh = gr->sh;
     HIP_TRY(c, launch_project_bwd(pa, o->sh_degree, o->sh_dtype == 1, st));
@@ -602,7 +602,7 @@ gsr_status gsr_destroy(gsr_ctx* c)
     (void)hipDeviceSynchronize();
     drop_graphs(c);
     Dev* all[] = { &c->cams, &c->rec, &c->dkey0, &c->dkey1, &c->ord0, &c->ord1, &c->rect, &c->tt, &c->tt_s, &c->rect_s, &c->radius,
-                   &c->depth, &c->offsets, &c->grad2d, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
+                   &c->depth, &c->offsets, &c->grad2d, &c->rec_stamp, &c->scan_tmp, &c->radix_tmp, &c->pk0, &c->pk1, &c->pv0,
                    &c->pv1, &c->emit_vg, &c->pair_grad, &c->pair_stamp, &c->seg_carry, &c->ranges, &c->tile_order, &c->queues, &c->block_H, &c->block_cnt, &c->hchunk, &c->counters, &c->reg_tmp, &c->ssim_tmp,
                    &c->l1_tmp };
     for (Dev* d : all) free_dev(*d);
@@ -1109,20 +1109,23 @@ gsr_status gsr_inspect(gsr_ctx* c, void* stream, gsr_buffer which, void* dst, in
         }
         case GSR_BUF_PAIR_TILES: src = pk[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
         case GSR_BUF_RANGES: src = c->ranges.p; sz = (size_t)c->lay.n_tiles * 8; break;
-        case GSR_BUF_GRAD2D: {         // zero rows for (view, Gaussian)s without pairs
+        case GSR_BUF_GRAD2D: {         // zero rows for (view, Gaussian)s without a blended pair
             sz = (size_t)c->vn * 4 * kG2;
             *bytes = (int64_t)sz;
             if (!dst) return GSR_OK;
             if ((int64_t)sz > capacity_bytes) return fail(c, GSR_ERR_INVALID_ARG, "destination too small");
-            std::vector<uint32_t> tt(c->vn);
+            std::vector<uint32_t> tt(c->vn), rs(c->vn);
+            uint32_t cnt[5] = {0, 0, 0, 0, 0};
             if (sz) {
                 HIP_TRY(c, hipMemcpyAsync(dst, c->grad2d.p, sz, hipMemcpyDeviceToHost, st));
                 HIP_TRY(c, hipMemcpyAsync(tt.data(), c->tt.p, (size_t)c->vn * 4, hipMemcpyDeviceToHost, st));
+                HIP_TRY(c, hipMemcpyAsync(rs.data(), c->rec_stamp.p, (size_t)c->vn * 4, hipMemcpyDeviceToHost, st));
+                HIP_TRY(c, hipMemcpyAsync(cnt, c->counters.p, sizeof(cnt), hipMemcpyDeviceToHost, st));
             }
             HIP_TRY(c, hipStreamSynchronize(st));
             float* out = (float*)dst;
             for (uint32_t i = 0; i < c->vn; ++i)
-                if (!tt[i]) std::memset(out + (size_t)kG2 * i, 0, sizeof(float) * kG2);
+                if (!tt[i] || rs[i] != cnt[4]) std::memset(out + (size_t)kG2 * i, 0, sizeof(float) * kG2);
             return GSR_OK;
         }
         default: return fail(c, GSR_ERR_INVALID_ARG, "unknown buffer");

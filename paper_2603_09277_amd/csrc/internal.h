@@ -89,7 +89,9 @@ struct ProjectBwdArgs {
     int32_t n_views;
     uint32_t flags;
     const CamDev* cams;
-    const float* grad2d;                  // [V*n][9], valid where tiles_touched > 0
+    const float* grad2d;                  // [V*n][9], valid where rec_stamp == *stamp (else zero)
+    const uint32_t* rec_stamp;            // [V*n]
+    const uint32_t* stamp;                // the frame's stamp (device)
     const uint32_t* tiles_touched;        // [V*n]
     float* g_means;
     float* g_scales;
@@ -172,15 +174,18 @@ hipError_t launch_duplicate(const uint32_t* order, const uint32_t* offsets, cons
                             const uint32_t* total, uint32_t cap, uint32_t* keys, uint32_t* emit_vg,
                             uint32_t* overflow, hipStream_t s);
 // grad2d[vg] = sum of the per-pair rows pair_grad[10 e .. 10 e + 8] with pair_stamp[e] == *stamp over the Gaussian's
-// emission range, for every (view, Gaussian) with pairs (others are left untouched)
-// (zero for Gaussians without pairs); carry holds seg_carry_bytes(cap) bytes
+// emission range, written, with rec_stamp[vg] = *stamp, for every (view, Gaussian) with at least one such
+// row; every other grad2d row is zero by definition and left untouched, with its old stamp;
+// carry holds seg_carry_bytes(cap) bytes
 size_t seg_carry_bytes(uint32_t cap);
 hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* pair_stamp, const uint32_t* stamp,
                               const uint32_t* emit_vg, uint32_t vn,
-                              const uint32_t* total, uint32_t cap, float* grad2d, void* carry, hipStream_t s);
+                              const uint32_t* total, uint32_t cap, float* grad2d, uint32_t* rec_stamp, void* carry,
+                              hipStream_t s);
 
-// a forward's counters: pair total and overflow flag cleared, row stamp (counters[4]) advanced
-hipError_t launch_frame_begin(uint32_t* counters, hipStream_t s);
+// a forward's counters: pair total and overflow flag cleared, row stamp (counters[4]) advanced;
+// ranges[0 .. n_words) cleared
+hipError_t launch_frame_begin(uint32_t* counters, uint32_t* ranges, uint32_t n_words, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 // p[i] = i
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);

@@ -312,12 +312,30 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a)
 #pragma unroll
     for (int k = 0; k < K * 3; ++k) gsh[k] = 0.f;
 
+    // this view's tiles-touched count, row stamp and 2D gradient row, loaded one view ahead;
+    // a row whose stamp is not this frame's is zero (no pixel blended any of its pairs)
+    const uint32_t st = *a.stamp;
+    uint32_t tt_n = a.n_views > 0 ? a.tiles_touched[i] : 0u;
+    uint32_t rs_n = a.n_views > 0 ? a.rec_stamp[i] : 0u;
+    float g_n[kG2];
+#pragma unroll
+    for (int k = 0; k < kG2; ++k) g_n[k] = a.n_views > 0 ? a.grad2d[(size_t)kG2 * i + k] : 0.f;
     for (int v = 0; v < a.n_views; ++v) {
+        const uint32_t tt_v = tt_n, rs_v = rs_n;
+        float g[kG2];
+#pragma unroll
+        for (int k = 0; k < kG2; ++k) g[k] = g_n[k];
+        if (v + 1 < a.n_views) {
+            const size_t o = (size_t)(v + 1) * a.n + i;
+            tt_n = a.tiles_touched[o];
+            rs_n = a.rec_stamp[o];
+#pragma unroll
+            for (int k = 0; k < kG2; ++k) g_n[k] = a.grad2d[(size_t)kG2 * o + k];
+        }
         const CamDev& c = a.cams[v];
         ViewProj P;
         view_proj(c, mu, L, a.flags, P);
-        if (!P.ok || a.tiles_touched[(size_t)v * a.n + i] == 0) continue;   // no pairs: zero gradient
-        const float* g = a.grad2d + (size_t)kG2 * ((size_t)v * a.n + i);
+        if (!P.ok || tt_v == 0 || rs_v != st) continue;     // no pairs, or none blended: zero gradient
         float gmx = g[0], gmy = g[1], gA = g[2], gB = g[3], gC = g[4];
         gop += g[5];
         // ---- colour -> SH coefficients and viewing direction
@@ -430,8 +448,25 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a)
     a.g_opac[i] = any ? gop : 0.f;
     if constexpr (BF16) {
         uint16_t* p = reinterpret_cast<uint16_t*>(a.g_sh) + (size_t)i * (K * 3);
+        if constexpr ((K * 3) % 8 == 0) {                    // eight values a 16-byte store
+            uint32_t w[K * 3 / 2];
 #pragma unroll
-        for (int k = 0; k < K * 3; ++k) p[k] = f32_to_bf16_rne(any ? gsh[k] : 0.f);
+            for (int k = 0; k < K * 3; k += 2)
+                w[k / 2] = (uint32_t)f32_to_bf16_rne(any ? gsh[k] : 0.f) |
+                           ((uint32_t)f32_to_bf16_rne(any ? gsh[k + 1] : 0.f) << 16);
+            if ((reinterpret_cast<uintptr_t>(a.g_sh) & 15u) == 0u) {
+                uint4* p4 = reinterpret_cast<uint4*>(p);
+#pragma unroll
+                for (int k = 0; k < K * 3 / 8; ++k)
+                    p4[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < K * 3; ++k) p[k] = (uint16_t)(w[k / 2] >> (16 * (k & 1)));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K * 3; ++k) p[k] = f32_to_bf16_rne(any ? gsh[k] : 0.f);
+        }
     } else {
         float* p = reinterpret_cast<float*>(a.g_sh) + (size_t)i * (K * 3);
 #pragma unroll

@@ -129,8 +129,9 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* val
 // ---------------------------------------------------------------------------
 // Stable LSD radix pass, 8-bit digits, 256 threads x ITEMS items per block
 // (16 for large inputs, 8 below 2^21 items so that small sorts still fill the chip):
-//   upsweep   per-block digit histograms, digit-major  hist[d * nb + b]
-//   spine     one block per digit: exclusive scan of its row; row total
+//   upsweep   per-block digit histograms, block-major  hist[b * 256 + d] (one
+//             coalesced 1 KB store a block, and one 1 KB load in the downsweep)
+//   spine     one block per digit: exclusive scan of its column; column total
 //   downsweep each wavefront ranks its 64 x ITEMS consecutive items (ITEMS rounds
 //             of 64, peers found with 8 ballots, running per-digit counts in
 //             LDS); one block scan turns the (digit, wavefront) counts into
@@ -163,7 +164,7 @@ __device__ __forceinline__ void wave_lds_order()
 
 template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t* keys, const uint32_t* n_dev,
-                                                                 uint32_t n_max, int shift, uint32_t* hist, uint32_t nb)
+                                                                 uint32_t n_max, int shift, uint32_t* hist)
 {
     constexpr int kRadixTile = kThreads * ITEMS;
     __shared__ uint32_t s_h[kBins];
@@ -172,29 +173,56 @@ __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t*
     const uint32_t n = item_count(n_dev, n_max);
     size_t base = (size_t)blockIdx.x * kRadixTile;
     if (base < n) {
+        // a wavefront takes 64 consecutive keys a round; a run of equal digits in
+        // neighbouring lanes adds its length with one atomic, from its first lane
+        // (sorted tile keys come in long runs, which would otherwise serialise on
+        // one LDS address)
+        const uint32_t lane = lane_id();
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            size_t idx = base + (size_t)k * kThreads + threadIdx.x;
-            if (idx < n) atomicAdd(&s_h[(keys[idx] >> shift) & 0xffu], 1u);
+            const size_t idx = base + (size_t)k * kThreads + threadIdx.x;
+            const bool ok = idx < n;
+            const uint32_t d = ok ? (keys[idx] >> shift) & 0xffu : kBins;
+            const uint32_t prv = __shfl_up(d, 1, 64);
+            const bool lead = ok && (lane == 0u || prv != d);
+            const uint64_t leaders = __ballot(lead);
+            const uint32_t nvalid = (uint32_t)__popcll(__ballot(ok));    // valid lanes are a prefix
+            if (lead) {
+                const uint64_t later = lane == 63u ? 0ull : leaders & ~((2ull << lane) - 1ull);
+                const uint32_t end = later ? (uint32_t)__builtin_ctzll(later) : nvalid;
+                atomicAdd(&s_h[d], end - lane);
+            }
         }
     }
     __syncthreads();
-    hist[(size_t)threadIdx.x * nb + blockIdx.x] = s_h[threadIdx.x];
+    hist[(size_t)blockIdx.x * kBins + threadIdx.x] = s_h[threadIdx.x];
 }
 
+template <uint32_t kSpineItems>
 __global__ __launch_bounds__(kThreads) void radix_spine_kernel(uint32_t* hist, uint32_t nb, uint32_t* digit_total)
 {
     __shared__ unsigned int s_carry;
-    uint32_t* row = hist + (size_t)blockIdx.x * nb;
+    uint32_t* col = hist + blockIdx.x;                       // digit blockIdx.x of every block, kBins apart
     if (threadIdx.x == 0) s_carry = 0u;
     __syncthreads();
-    for (uint32_t start = 0; start < nb; start += kThreads) {
-        uint32_t idx = start + threadIdx.x;
-        uint32_t v = idx < nb ? row[idx] : 0u;
+    // kSpineItems consecutive counts a thread: one block scan per kThreads * kSpineItems
+    for (uint32_t start = 0; start < nb; start += kThreads * kSpineItems) {
+        const uint32_t i0 = start + threadIdx.x * kSpineItems;
+        uint32_t v[kSpineItems], sum = 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < kSpineItems; ++j) {
+            v[j] = i0 + j < nb ? col[(size_t)(i0 + j) * kBins] : 0u;
+            sum += v[j];
+        }
         uint32_t tot;
-        uint32_t ex = block_excl_scan(v, &tot);
-        uint32_t carry = s_carry;
-        if (idx < nb) row[idx] = carry + ex;
+        const uint32_t ex = block_excl_scan(sum, &tot);
+        const uint32_t carry = s_carry;
+        uint32_t run = carry + ex;
+#pragma unroll
+        for (uint32_t j = 0; j < kSpineItems; ++j) {
+            if (i0 + j < nb) col[(size_t)(i0 + j) * kBins] = run;
+            run += v[j];
+        }
         __syncthreads();
         if (threadIdx.x == 0) s_carry = carry + tot;
         __syncthreads();
@@ -206,7 +234,7 @@ template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_t* keys_in, const uint32_t* vals_in,
                                                                    uint32_t* keys_out, uint32_t* vals_out,
                                                                    const uint32_t* n_dev, uint32_t n_max, int shift,
-                                                                   const uint32_t* hist, uint32_t nb,
+                                                                   const uint32_t* hist,
                                                                    const uint32_t* digit_total)
 {
     constexpr int kRadixItems = ITEMS;
@@ -226,7 +254,7 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
     // global offsets: exclusive prefix of the digit totals + this block's row offset
     uint32_t tot;
     const uint32_t dbase = block_excl_scan(digit_total[tid], &tot);
-    s_gofs[tid] = dbase + hist[(size_t)tid * nb + blockIdx.x];
+    s_gofs[tid] = dbase + hist[(size_t)blockIdx.x * kBins + tid];
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s_wh[w][tid] = 0u;
     __syncthreads();
@@ -389,13 +417,15 @@ struct SegCarry {
     float head[kG2];         // first segment's sum over this chunk, if it started earlier and ends here
     float tail[kG2];         // last segment's sum over this chunk, if it continues past it
     uint32_t first_seg, last_seg;
-    uint32_t flags;          // 1: first segment started earlier; 2: last segment continues
-    uint32_t pad;
+    uint32_t flags;          // 1: first segment started earlier; 2: last segment continues; 4: tail has a live row
+    uint32_t head_live;      // live rows in head
 };
 
 constexpr uint32_t kRowsPerLane = 4;
 constexpr uint32_t kChunkRows = 64 * kRowsPerLane;           // 256
 constexpr uint32_t kNoSeg = 0xffffffffu;
+constexpr uint32_t kChunkWords = kChunkRows * kRowF / 4;     // 16-byte words of a chunk's rows
+static_assert(kChunkWords % 64u == 0u && (kRowsPerLane * kRowF) % 4u == 0u, "chunk rows in whole 16-byte words");
 
 __device__ __forceinline__ void add9(float* a, const float* b)
 {
@@ -409,81 +439,132 @@ __device__ __forceinline__ void store9(float* dst, const float* v)
     for (int k = 0; k < kG2; ++k) dst[k] = v[k];
 }
 
-__global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_grad, const uint32_t* pair_stamp,
-                                                              const uint32_t* stamp, const uint32_t* emit_vg,
-                                                              const uint32_t* total, uint32_t cap, float* grad2d,
-                                                              SegCarry* carry)
+// one chunk's owners and stamps (4 rows a lane) and the owners of the rows just
+// before and just after it
+struct ChunkMeta {
+    uint32_t sg[kRowsPerLane], sp[kRowsPerLane];
+    uint32_t before, after;
+};
+
+__device__ __forceinline__ void load_meta(const uint32_t* emit_vg, const uint32_t* pair_stamp, uint32_t P,
+                                          uint32_t c, uint32_t lane, ChunkMeta& m)
 {
-    const uint32_t P = *total < cap ? *total : cap;
-    const uint32_t st = *stamp;
-    const uint32_t lane = lane_id();
-    const uint32_t nchunk = (P + kChunkRows - 1) / kChunkRows;
-    // chunks, grid-stride (the grid does not grow with the pair capacity)
-    for (uint32_t c = (blockIdx.x * kThreads + threadIdx.x) >> 6; c < nchunk; c += (gridDim.x * kThreads) >> 6) {
-        const uint32_t r0 = c * kChunkRows;
-        // this lane's 4 rows: owners and stamps with one 16-byte load each; a row's 9
-        // values are read only if this frame's backward wrote it
-        const uint32_t e0 = r0 + lane * kRowsPerLane;
-        uint32_t sg[kRowsPerLane], sp[kRowsPerLane];
-        if (e0 + kRowsPerLane <= P) {
-            const uint4 o4 = *reinterpret_cast<const uint4*>(emit_vg + e0);
-            const uint4 p4 = *reinterpret_cast<const uint4*>(pair_stamp + e0);
-            sg[0] = o4.x; sg[1] = o4.y; sg[2] = o4.z; sg[3] = o4.w;
-            sp[0] = p4.x; sp[1] = p4.y; sp[2] = p4.z; sp[3] = p4.w;
-        } else {
-#pragma unroll
-            for (uint32_t r = 0; r < kRowsPerLane; ++r) {
-                sg[r] = e0 + r < P ? emit_vg[e0 + r] : kNoSeg;
-                sp[r] = e0 + r < P ? pair_stamp[e0 + r] : 0u;
-            }
-        }
-        float rw[kRowsPerLane * kG2];
+    const uint32_t r0 = c * kChunkRows, e0 = r0 + lane * kRowsPerLane;
+    if (e0 + kRowsPerLane <= P) {
+        const uint4 o4 = *reinterpret_cast<const uint4*>(emit_vg + e0);
+        const uint4 p4 = *reinterpret_cast<const uint4*>(pair_stamp + e0);
+        m.sg[0] = o4.x; m.sg[1] = o4.y; m.sg[2] = o4.z; m.sg[3] = o4.w;
+        m.sp[0] = p4.x; m.sp[1] = p4.y; m.sp[2] = p4.z; m.sp[3] = p4.w;
+    } else {
 #pragma unroll
         for (uint32_t r = 0; r < kRowsPerLane; ++r) {
-            const bool live = sg[r] != kNoSeg && sp[r] == st;
-            const float2* row = reinterpret_cast<const float2*>(pair_grad + (size_t)kRowF * (e0 + r));
-            float2 x0 = make_float2(0.f, 0.f), x1 = x0, x2 = x0, x3 = x0;
-            float x4 = 0.f;
-            if (live) {
-                x0 = row[0]; x1 = row[1]; x2 = row[2]; x3 = row[3];
-                x4 = pair_grad[(size_t)kRowF * (e0 + r) + 8];
-            }
-            float* d = rw + r * kG2;
-            d[0] = x0.x; d[1] = x0.y; d[2] = x1.x; d[3] = x1.y; d[4] = x2.x; d[5] = x2.y;
-            d[6] = x3.x; d[7] = x3.y; d[8] = x4;
+            m.sg[r] = e0 + r < P ? emit_vg[e0 + r] : kNoSeg;
+            m.sp[r] = e0 + r < P ? pair_stamp[e0 + r] : 0u;
         }
-        // lane-local segments: A = first segment's partial, B = last segment's partial
-        // (rows not written by this frame's backward hold zeros in rw)
-        float A[kG2], B[kG2];
-        uint32_t s0 = sg[0], sl = sg[0], nseg = 1;
+    }
+    m.before = r0 > 0 ? emit_vg[r0 - 1] : kNoSeg;
+    m.after = r0 + kChunkRows < P ? emit_vg[r0 + kChunkRows] : kNoSeg;
+}
+
+__global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pair_grad, const uint32_t* pair_stamp,
+                                                              const uint32_t* stamp, const uint32_t* emit_vg,
+                                                              const uint32_t* total, uint32_t cap, float* grad2d,
+                                                              uint32_t* rec_stamp, SegCarry* carry)
+{
+    __shared__ uint4 s_rows[kWaves][kChunkWords];
+    const uint32_t P = *total < cap ? *total : cap;
+    const uint32_t st = *stamp;
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    const uint32_t nchunk = (P + kChunkRows - 1) / kChunkRows;
+    // chunks, grid-stride (the grid does not grow with the pair capacity); each
+    // chunk's owners and stamps are loaded while the previous chunk's rows are in
+    // flight, so a chunk waits on one round trip to memory, not three
+    const uint32_t stride = (gridDim.x * kThreads) >> 6;
+    uint32_t c = (blockIdx.x * kThreads + threadIdx.x) >> 6;
+    ChunkMeta nx;
+    if (c < nchunk) load_meta(emit_vg, pair_stamp, P, c, lane, nx);
+    for (; c < nchunk; c += stride) {
+        const ChunkMeta m = nx;
+        const uint32_t r0 = c * kChunkRows;
+        const uint32_t* sg = m.sg;
+        const uint32_t* sp = m.sp;
+        // the chunk's rows are one contiguous 10 KB span: the wavefront reads it with
+        // coalesced 16-byte loads into LDS (a 16-byte word only if a row it overlaps is
+        // live; a row is live if this frame's backward wrote it) and each lane then
+        // takes its own 4 rows from there
+        bool lv[kRowsPerLane];
+        uint64_t lbal[kRowsPerLane];                             // bit l: row 4 l + r of the chunk is live
 #pragma unroll
-        for (int k = 0; k < kG2; ++k) B[k] = rw[k];
+        for (uint32_t r = 0; r < kRowsPerLane; ++r) {
+            lv[r] = sg[r] != kNoSeg && sp[r] == st;
+            lbal[r] = __ballot(lv[r]);
+        }
+        const uint4* src = reinterpret_cast<const uint4*>(pair_grad + (size_t)kRowF * r0);
+        uint4* srow = s_rows[wid];
+        uint4 words[kChunkWords / 64u];
+#pragma unroll
+        for (uint32_t i = 0; i < kChunkWords / 64u; ++i) {
+            const uint32_t q = i * 64u + lane;
+            const uint32_t ra = (4u * q) / (uint32_t)kRowF, rb = (4u * q + 3u) / (uint32_t)kRowF;
+            const bool need = ((lbal[ra & 3u] >> (ra >> 2)) & 1ull) | ((lbal[rb & 3u] >> (rb >> 2)) & 1ull);
+            words[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (need) words[i] = src[q];
+        }
+        if (c + stride < nchunk) load_meta(emit_vg, pair_stamp, P, c + stride, lane, nx);
+#pragma unroll
+        for (uint32_t i = 0; i < kChunkWords / 64u; ++i) srow[i * 64u + lane] = words[i];
+        wave_lds_order();
+        // this lane's row r, from LDS (rows not written by this frame's backward read as zeros)
+        const float* mine = reinterpret_cast<const float*>(srow) + lane * (kRowsPerLane * kRowF);
+        auto load_row = [&](uint32_t r, float* row) {
+            const float2* x = reinterpret_cast<const float2*>(mine + r * kRowF);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float2 y = x[k];
+                row[2 * k] = lv[r] ? y.x : 0.f;
+                row[2 * k + 1] = lv[r] ? y.y : 0.f;
+            }
+            row[8] = lv[r] ? mine[r * kRowF + 8] : 0.f;
+        };
+        // lane-local segments: A = first segment's partial, B = last segment's partial,
+        // la / lb their numbers of live rows (a segment without one is not written)
+        float A[kG2], B[kG2];
+        uint32_t s0 = sg[0], sl = sg[0], nseg = 1, la = 0, lb = lv[0] ? 1u : 0u;
+        load_row(0, B);
 #pragma unroll
         for (uint32_t r = 1; r < kRowsPerLane; ++r) {
             if (sg[r] == kNoSeg) break;
-            const float* row = rw + r * kG2;
-            const bool live = sp[r] == st;
+            float row[kG2];
+            load_row(r, row);
+            const bool live = lv[r];
             if (sg[r] != sl) {                                   // segment sl ends inside this lane
                 if (nseg == 1) {
 #pragma unroll
                     for (int k = 0; k < kG2; ++k) A[k] = B[k];
-                } else {
-                    store9(grad2d + (size_t)kG2 * sl, B);        // started and ended in this lane
+                    la = lb;
+                } else if (lb) {                                 // started and ended in this lane
+                    store9(grad2d + (size_t)kG2 * sl, B);
+                    rec_stamp[sl] = st;
                 }
                 sl = sg[r];
                 ++nseg;
 #pragma unroll
                 for (int k = 0; k < kG2; ++k) B[k] = live ? row[k] : 0.f;
+                lb = live ? 1u : 0u;
             } else if (live) {
                 add9(B, row);
+                ++lb;
             }
         }
+        wave_lds_order();                                        // the next chunk overwrites srow
         if (nseg == 1) {
 #pragma unroll
             for (int k = 0; k < kG2; ++k) A[k] = B[k];
+            la = lb;
         }
-        // C = segmented inclusive sum of B over lanes, keyed by the last segment
+        // C = segmented inclusive sum of B over lanes, keyed by the last segment (Cl: of lb)
         float C[kG2];
+        uint32_t Cl = lb;
 #pragma unroll
         for (int k = 0; k < kG2; ++k) C[k] = B[k];
 #pragma unroll
@@ -495,27 +576,43 @@ __global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_
                 const float y = __shfl_up(C[k], d, 64);
                 C[k] += same ? y : 0.f;
             }
+            const uint32_t yl = __shfl_up(Cl, d, 64);
+            Cl += same ? yl : 0u;
         }
         // the chunk's neighbours: the row before it and the row after it
         const uint32_t sfirst = __shfl(s0, 0, 64);
-        const bool crosses_in = r0 > 0 && emit_vg[r0 - 1] == sfirst;
-        const uint32_t after = r0 + kChunkRows < P ? emit_vg[r0 + kChunkRows] : kNoSeg;
+        const bool crosses_in = r0 > 0 && m.before == sfirst;
+        const uint32_t after = m.after;
         uint32_t nxt = __shfl_down(s0, 1, 64);
         if (lane == 63) nxt = after;
         const uint32_t prv_sl = __shfl_up(sl, 1, 64);
         float prvC[kG2];
 #pragma unroll
         for (int k = 0; k < kG2; ++k) prvC[k] = __shfl_up(C[k], 1, 64);
+        const uint32_t prvCl = __shfl_up(Cl, 1, 64);
         const bool valid = s0 != kNoSeg;
         SegCarry* cr = carry + c;
         if (valid && nseg >= 2) {                                // first segment ends in this lane
-            if (lane > 0 && prv_sl == s0) add9(A, prvC);          // ... and began in an earlier lane
-            if (crosses_in && s0 == sfirst) store9(cr->head, A);
-            else store9(grad2d + (size_t)kG2 * s0, A);
+            if (lane > 0 && prv_sl == s0) {                      // ... and began in an earlier lane
+                add9(A, prvC);
+                la += prvCl;
+            }
+            if (crosses_in && s0 == sfirst) {
+                store9(cr->head, A);
+                cr->head_live = la;
+            } else if (la) {
+                store9(grad2d + (size_t)kG2 * s0, A);
+                rec_stamp[s0] = st;
+            }
         }
         if (valid && nxt != sl) {                                // last segment ends in this lane
-            if (crosses_in && sl == sfirst) store9(cr->head, C);
-            else store9(grad2d + (size_t)kG2 * sl, C);
+            if (crosses_in && sl == sfirst) {
+                store9(cr->head, C);
+                cr->head_live = Cl;
+            } else if (Cl) {
+                store9(grad2d + (size_t)kG2 * sl, C);
+                rec_stamp[sl] = st;
+            }
         }
         // the chunk's last valid lane (the next lane holds no rows, or lane 63) records the chunk
         if (valid && (lane == 63 || nxt == kNoSeg)) {
@@ -524,7 +621,7 @@ __global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_
             for (int k = 0; k < kG2; ++k) cr->tail[k] = crosses_out ? C[k] : 0.f;
             cr->first_seg = sfirst;
             cr->last_seg = sl;
-            cr->flags = (crosses_in ? 1u : 0u) | (crosses_out ? 2u : 0u);
+            cr->flags = (crosses_in ? 1u : 0u) | (crosses_out ? 2u : 0u) | (crosses_out && Cl ? 4u : 0u);
         }
     }
 }
@@ -532,7 +629,8 @@ __global__ __launch_bounds__(kThreads) void seg_reduce_kernel(const float* pair_
 // one thread per chunk: a segment that starts in chunk w and continues past it
 // is summed here over the following chunks, in order
 __global__ __launch_bounds__(kThreads) void seg_fixup_kernel(const SegCarry* carry, const uint32_t* total,
-                                                             uint32_t cap, float* grad2d)
+                                                             uint32_t cap, const uint32_t* stamp, float* grad2d,
+                                                             uint32_t* rec_stamp)
 {
     const uint32_t P = *total < cap ? *total : cap;
     const uint32_t nw = (P + kChunkRows - 1) / kChunkRows;
@@ -542,6 +640,7 @@ __global__ __launch_bounds__(kThreads) void seg_fixup_kernel(const SegCarry* car
     if ((c.flags & 1u) && c.first_seg == c.last_seg) continue;   // w is inside a segment begun earlier
     const uint32_t s = c.last_seg;
     float acc[kG2];
+    bool live = (c.flags & 4u) != 0u;
 #pragma unroll
     for (int k = 0; k < kG2; ++k) acc[k] = c.tail[k];
     for (uint32_t u = w + 1; u < nw; ++u) {
@@ -550,15 +649,19 @@ __global__ __launch_bounds__(kThreads) void seg_fixup_kernel(const SegCarry* car
         if (whole) {
 #pragma unroll
             for (int k = 0; k < kG2; ++k) acc[k] += d.tail[k];
+            live = live || (d.flags & 4u) != 0u;
             continue;
         }
 #pragma unroll
         for (int k = 0; k < kG2; ++k) acc[k] += d.head[k];
+        live = live || d.head_live != 0u;
         break;
     }
+    if (!live) continue;                                         // no row of the segment was written
     float* dst = grad2d + (size_t)kG2 * s;
 #pragma unroll
     for (int k = 0; k < kG2; ++k) dst[k] = acc[k];
+    rec_stamp[s] = *stamp;
     }
 }
 
@@ -569,13 +672,16 @@ __global__ void iota_u32_kernel(uint32_t* p, uint32_t count)
     if (i < count) p[i] = i;
 }
 
-__global__ void frame_begin_kernel(uint32_t* counters)
+// a frame's first kernel: pair count and overflow cleared, the row stamp advanced,
+// and the tile ranges (plus the tile-order class counts behind them) cleared
+__global__ void frame_begin_kernel(uint32_t* counters, uint32_t* ranges, uint32_t n_words)
 {
-    if (threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         counters[0] = 0u;
         counters[1] = 0u;
         atomicAdd(&counters[4], 1u);
     }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += gridDim.x * blockDim.x) ranges[i] = 0u;
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t value, size_t count)
@@ -589,10 +695,27 @@ __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* tiles,
                                                           uint2* ranges)
 {
     const uint32_t P = *total < cap ? *total : cap;
-    for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < P; i += gridDim.x * kThreads) {
-        const uint32_t t = tiles[i];
-        if (i == 0 || tiles[i - 1] != t) ranges[t].x = i;
-        if (i == P - 1 || tiles[i + 1] != t) ranges[t].y = i + 1;
+    // four keys a thread, one 16-byte load (the key buffer is 16-byte aligned)
+    for (uint32_t q = blockIdx.x * kThreads + threadIdx.x; q < (P + 3u) / 4u; q += gridDim.x * kThreads) {
+        const uint32_t i0 = 4u * q;
+        uint32_t k[4];
+        if (i0 + 4u <= P) {
+            const uint4 v = reinterpret_cast<const uint4*>(tiles)[q];
+            k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < 4u; ++j) k[j] = i0 + j < P ? tiles[i0 + j] : 0u;
+        }
+        const uint32_t before = i0 > 0u ? tiles[i0 - 1u] : 0u;
+        const uint32_t after = i0 + 4u < P ? tiles[i0 + 4u] : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < 4u; ++j) {
+            const uint32_t i = i0 + j;
+            if (i >= P) break;
+            const uint32_t prv = j > 0u ? k[j - 1u] : before, nxt = j < 3u ? k[j + 1u] : after;
+            if (i == 0u || prv != k[j]) ranges[k[j]].x = i;
+            if (i == P - 1u || nxt != k[j]) ranges[k[j]].y = i + 1u;
+        }
     }
 }
 
@@ -635,17 +758,24 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, u
     uint32_t* digit_total = tmp + (size_t)kBins * nb;
     if (items == kRadixLargeItems)
         hipLaunchKernelGGL(radix_upsweep_kernel<kRadixLargeItems>, dim3(nb), dim3(kThreads), 0, s, keys_in, n_dev,
-                           n_max, shift, hist, nb);
+                           n_max, shift, hist);
     else
         hipLaunchKernelGGL(radix_upsweep_kernel<kRadixSmallItems>, dim3(nb), dim3(kThreads), 0, s, keys_in, n_dev,
-                           n_max, shift, hist, nb);
-    hipLaunchKernelGGL(radix_spine_kernel, dim3(kBins), dim3(kThreads), 0, s, hist, nb, digit_total);
+                           n_max, shift, hist);
+    // counts a thread: enough that a long column takes few block scans, few enough
+    // that a short one is spread over the workgroup
+    if (nb > 8u * kThreads)
+        hipLaunchKernelGGL(radix_spine_kernel<32>, dim3(kBins), dim3(kThreads), 0, s, hist, nb, digit_total);
+    else if (nb > kThreads)
+        hipLaunchKernelGGL(radix_spine_kernel<8>, dim3(kBins), dim3(kThreads), 0, s, hist, nb, digit_total);
+    else
+        hipLaunchKernelGGL(radix_spine_kernel<1>, dim3(kBins), dim3(kThreads), 0, s, hist, nb, digit_total);
     if (items == kRadixLargeItems)
         hipLaunchKernelGGL(radix_downsweep_kernel<kRadixLargeItems>, dim3(nb), dim3(kThreads), 0, s, keys_in,
-                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
+                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, digit_total);
     else
         hipLaunchKernelGGL(radix_downsweep_kernel<kRadixSmallItems>, dim3(nb), dim3(kThreads), 0, s, keys_in,
-                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
+                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, digit_total);
     return hipGetLastError();
 }
 
@@ -663,15 +793,16 @@ size_t seg_carry_bytes(uint32_t cap) { return ((size_t)cap + kChunkRows - 1) / k
 
 hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* pair_stamp, const uint32_t* stamp,
                               const uint32_t* emit_vg, uint32_t vn, const uint32_t* total, uint32_t cap, float* grad2d,
-                              void* carry, hipStream_t s)
+                              uint32_t* rec_stamp, void* carry, hipStream_t s)
 {
     (void)vn;
     if (cap == 0) return hipSuccess;
     const uint32_t nw = (cap + kChunkRows - 1) / kChunkRows;
     hipLaunchKernelGGL(seg_reduce_kernel, dim3(grid_cap((nw * 64 + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
-                       pair_grad, pair_stamp, stamp, emit_vg, total, cap, grad2d, reinterpret_cast<SegCarry*>(carry));
+                       pair_grad, pair_stamp, stamp, emit_vg, total, cap, grad2d, rec_stamp,
+                       reinterpret_cast<SegCarry*>(carry));
     hipLaunchKernelGGL(seg_fixup_kernel, dim3(grid_cap((nw + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
-                       reinterpret_cast<const SegCarry*>(carry), total, cap, grad2d);
+                       reinterpret_cast<const SegCarry*>(carry), total, cap, stamp, grad2d, rec_stamp);
     return hipGetLastError();
 }
 
@@ -683,9 +814,11 @@ hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s)
 }
 
 
-hipError_t launch_frame_begin(uint32_t* counters, hipStream_t s)
+hipError_t launch_frame_begin(uint32_t* counters, uint32_t* ranges, uint32_t n_words, hipStream_t s)
 {
-    hipLaunchKernelGGL(frame_begin_kernel, dim3(1), dim3(64), 0, s, counters);
+    uint32_t blocks = (n_words + 255u) / 256u;
+    blocks = blocks < 1u ? 1u : (blocks > 1024u ? 1024u : blocks);
+    hipLaunchKernelGGL(frame_begin_kernel, dim3(blocks), dim3(256), 0, s, counters, ranges, n_words);
     return hipGetLastError();
 }
 
@@ -777,9 +910,9 @@ hipError_t launch_tile_order(const uint2* ranges, uint32_t n_tiles, uint32_t* hi
 hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges, hipStream_t s)
 {
     if (cap == 0) return hipSuccess;
-    hipLaunchKernelGGL(ranges_kernel, dim3(grid_cap((cap + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, tiles,
-                       total, cap,
-                       ranges);
+    const uint32_t quads = (cap + 3u) / 4u;
+    hipLaunchKernelGGL(ranges_kernel, dim3(grid_cap((quads + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, tiles,
+                       total, cap, ranges);
     return hipGetLastError();
 }
 

@@ -132,6 +132,8 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* val
 //   upsweep   per-block digit histograms, block-major  hist[b * 256 + d] (one
 //             coalesced 1 KB store a block, and one 1 KB load in the downsweep)
 //   spine     one block per digit: exclusive scan of its column; column total
+//             (a pass of at most kSelfSpineBlocks blocks has no spine: each
+//             downsweep block sums the counts of the blocks before it itself)
 //   downsweep each wavefront ranks its 64 x ITEMS consecutive items (ITEMS rounds
 //             of 64, peers found with 8 ballots, running per-digit counts in
 //             LDS); one block scan turns the (digit, wavefront) counts into
@@ -142,6 +144,7 @@ constexpr int kRadixSmallItems = 8;
 constexpr int kRadixLargeItems = 16;
 constexpr uint32_t kRadixLargeFrom = 1u << 21;
 constexpr int kWaves = kThreads / 64;
+constexpr uint32_t kSelfSpineBlocks = 128;
 
 __host__ __device__ constexpr uint32_t radix_items(uint32_t n_max)
 {
@@ -230,11 +233,13 @@ __global__ __launch_bounds__(kThreads) void radix_spine_kernel(uint32_t* hist, u
     if (threadIdx.x == 0) digit_total[blockIdx.x] = s_carry;
 }
 
-template <int ITEMS>
+// SELF: few blocks (nb <= kSelfSpineBlocks); every block sums the raw per-block
+// counts itself and no spine kernel runs
+template <int ITEMS, bool SELF>
 __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_t* keys_in, const uint32_t* vals_in,
                                                                    uint32_t* keys_out, uint32_t* vals_out,
                                                                    const uint32_t* n_dev, uint32_t n_max, int shift,
-                                                                   const uint32_t* hist,
+                                                                   const uint32_t* hist, uint32_t nb,
                                                                    const uint32_t* digit_total)
 {
     constexpr int kRadixItems = ITEMS;
@@ -253,8 +258,19 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
 
     // global offsets: exclusive prefix of the digit totals + this block's row offset
     uint32_t tot;
-    const uint32_t dbase = block_excl_scan(digit_total[tid], &tot);
-    s_gofs[tid] = dbase + hist[(size_t)blockIdx.x * kBins + tid];
+    if (SELF) {                               // digit tid: its count in all blocks and in the blocks before this one
+        uint32_t all = 0u, before = 0u;
+#pragma unroll 8
+        for (uint32_t b = 0; b < nb; ++b) {
+            const uint32_t v = hist[(size_t)b * kBins + tid];
+            all += v;
+            before += b < blockIdx.x ? v : 0u;
+        }
+        s_gofs[tid] = block_excl_scan(all, &tot) + before;
+    } else {
+        const uint32_t dbase = block_excl_scan(digit_total[tid], &tot);
+        s_gofs[tid] = dbase + hist[(size_t)blockIdx.x * kBins + tid];
+    }
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s_wh[w][tid] = 0u;
     __syncthreads();
@@ -762,6 +778,15 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, u
     else
         hipLaunchKernelGGL(radix_upsweep_kernel<kRadixSmallItems>, dim3(nb), dim3(kThreads), 0, s, keys_in, n_dev,
                            n_max, shift, hist);
+    if (nb <= kSelfSpineBlocks) {             // the downsweep blocks find their offsets themselves
+        if (items == kRadixLargeItems)
+            hipLaunchKernelGGL((radix_downsweep_kernel<kRadixLargeItems, true>), dim3(nb), dim3(kThreads), 0, s,
+                               keys_in, vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
+        else
+            hipLaunchKernelGGL((radix_downsweep_kernel<kRadixSmallItems, true>), dim3(nb), dim3(kThreads), 0, s,
+                               keys_in, vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
+        return hipGetLastError();
+    }
     // counts a thread: enough that a long column takes few block scans, few enough
     // that a short one is spread over the workgroup
     if (nb > 8u * kThreads)
@@ -771,11 +796,11 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, u
     else
         hipLaunchKernelGGL(radix_spine_kernel<1>, dim3(kBins), dim3(kThreads), 0, s, hist, nb, digit_total);
     if (items == kRadixLargeItems)
-        hipLaunchKernelGGL(radix_downsweep_kernel<kRadixLargeItems>, dim3(nb), dim3(kThreads), 0, s, keys_in,
-                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, digit_total);
+        hipLaunchKernelGGL((radix_downsweep_kernel<kRadixLargeItems, false>), dim3(nb), dim3(kThreads), 0, s, keys_in,
+                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
     else
-        hipLaunchKernelGGL(radix_downsweep_kernel<kRadixSmallItems>, dim3(nb), dim3(kThreads), 0, s, keys_in,
-                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, digit_total);
+        hipLaunchKernelGGL((radix_downsweep_kernel<kRadixSmallItems, false>), dim3(nb), dim3(kThreads), 0, s, keys_in,
+                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
     return hipGetLastError();
 }
 

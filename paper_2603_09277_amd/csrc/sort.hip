@@ -205,7 +205,10 @@ template <uint32_t kSpineItems>
 __global__ __launch_bounds__(kThreads) void radix_spine_kernel(uint32_t* hist, uint32_t nb, uint32_t* digit_total)
 {
     __shared__ unsigned int s_carry;
-    uint32_t* col = hist + blockIdx.x;                       // digit blockIdx.x of every block, kBins apart
+    // workgroups are dealt to the 8 XCDs round-robin: XCD x takes digits [32 x, 32 x + 32),
+    // so the 32 workgroups reading one 128-byte line of a count row share that XCD's L2
+    const uint32_t d = (blockIdx.x & 7u) * (uint32_t)(kBins / 8) + (blockIdx.x >> 3);
+    uint32_t* col = hist + d;                                // digit d of every block, kBins apart
     if (threadIdx.x == 0) s_carry = 0u;
     __syncthreads();
     // kSpineItems consecutive counts a thread: one block scan per kThreads * kSpineItems
@@ -230,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void radix_spine_kernel(uint32_t* hist, u
         if (threadIdx.x == 0) s_carry = carry + tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) digit_total[blockIdx.x] = s_carry;
+    if (threadIdx.x == 0) digit_total[d] = s_carry;
 }
 
 // SELF: few blocks (nb <= kSelfSpineBlocks); every block sums the raw per-block

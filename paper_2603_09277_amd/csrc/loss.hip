@@ -41,11 +41,14 @@ __global__ __launch_bounds__(kL1Block) void l1_kernel(const float* rgb, const fl
     if (q < M) {
         const int64_t p = c.pix_base + q;
         const float inv = weight / (3.0f * (float)M);
+        float d[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) d[ch] = rgb[3 * p + ch] - target[3 * p + ch];   // all loads before any store
+#pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            const float d = rgb[3 * p + ch] - target[3 * p + ch];
-            const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+            const float sg = d[ch] > 0.f ? 1.f : (d[ch] < 0.f ? -1.f : 0.f);
             if (grad) grad[3 * p + ch] = sg * inv;
-            acc += (double)fabsf(d);
+            acc += (double)fabsf(d[ch]);
         }
     }
     const double tot = block_sum_f64(acc);

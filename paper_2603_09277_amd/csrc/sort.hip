@@ -64,14 +64,24 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint4* trec
 {
     size_t base = (size_t)blockIdx.x * kTileItems + threadIdx.x;
     uint32_t sum = 0;
+    // the kItems order loads, then the kItems gathers, each batch in flight together
+    // (a clamped index instead of a branch; items past the end are not stored or summed)
+    uint32_t o[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        size_t idx = base + (size_t)k * kThreads;
+        const size_t idx = base + (size_t)k * kThreads;
+        o[k] = order[idx < n ? idx : (size_t)n - 1];
+    }
+    uint4 t[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) t[k] = trect[o[k]];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const size_t idx = base + (size_t)k * kThreads;
         if (idx < n) {
-            const uint4 t = trect[order[idx]];
-            vals_s[idx] = t.z;
-            rect_s[idx] = make_uint2(t.x, t.y);
-            sum += t.z;
+            vals_s[idx] = t[k].z;
+            rect_s[idx] = make_uint2(t[k].x, t[k].y);
+            sum += t[k].z;
         }
     }
     uint32_t tot;
@@ -112,8 +122,9 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* val
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        size_t idx = base + k;
-        v[k] = idx < n ? vals_s[idx] : 0u;
+        const size_t idx = base + k;
+        const uint32_t x = vals_s[idx < n ? idx : (size_t)n - 1];
+        v[k] = idx < n ? x : 0u;
         sum += v[k];
     }
     uint32_t tot;
@@ -181,11 +192,19 @@ __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t*
         // (sorted tile keys come in long runs, which would otherwise serialise on
         // one LDS address)
         const uint32_t lane = lane_id();
+        // all ITEMS loads first (a clamped index instead of a branch, so they are in
+        // flight together), then the counting rounds
+        uint32_t kv[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const size_t idx = base + (size_t)k * kThreads + threadIdx.x;
+            kv[k] = keys[idx < n ? idx : (size_t)n - 1];
+        }
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const size_t idx = base + (size_t)k * kThreads + threadIdx.x;
             const bool ok = idx < n;
-            const uint32_t d = ok ? (keys[idx] >> shift) & 0xffu : kBins;
+            const uint32_t d = ok ? (kv[k] >> shift) & 0xffu : kBins;
             const uint32_t prv = __shfl_up(d, 1, 64);
             const bool lead = ok && (lane == 0u || prv != d);
             const uint64_t leaders = __ballot(lead);
@@ -279,13 +298,23 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
     __syncthreads();
 
     // wavefront wid owns items [wid * kPerWave, (wid + 1) * kPerWave): round r, lane l -> + r * 64 + l
+    // every load issued before any is used: a clamped index instead of a branch (items
+    // past the end are never ranked into place or written)
     uint32_t k_[kRadixItems], v_[kRadixItems], rk[kRadixItems];
 #pragma unroll
     for (int r = 0; r < kRadixItems; ++r) {
         const uint32_t li = wid * kPerWave + (uint32_t)r * 64u + lane;
-        const bool ok = li < cnt;
-        k_[r] = ok ? keys_in[base + li] : 0u;
-        v_[r] = ok ? (vals_in ? vals_in[base + li] : (uint32_t)(base + li)) : 0u;   // null: the item's index
+        k_[r] = keys_in[base + (li < cnt ? li : cnt - 1u)];
+    }
+    if (vals_in) {
+#pragma unroll
+        for (int r = 0; r < kRadixItems; ++r) {
+            const uint32_t li = wid * kPerWave + (uint32_t)r * 64u + lane;
+            v_[r] = vals_in[base + (li < cnt ? li : cnt - 1u)];
+        }
+    } else {                                  // null: the item's index
+#pragma unroll
+        for (int r = 0; r < kRadixItems; ++r) v_[r] = (uint32_t)(base + wid * kPerWave + (uint32_t)r * 64u + lane);
     }
     const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
@@ -377,13 +406,16 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* ord
     if (s == 0 && *total > cap) *overflow = 1u;
     if (s - lane >= vn) return;                               // whole wavefront
     const bool valid = s < vn;
-    uint32_t vg = 0, tt = 0, off = 0;
+    uint32_t vg = 0, tt = 0, off = 0, tb = 0, gx = 0;
     uint2 rc = make_uint2(0u, 0u);
     if (valid) {
         vg = order[s];
         tt = tt_s[s];
         off = offsets[s];
         rc = rect_s[s];
+        const CamDev& c = cams[vg / n];                       // the record's view: its tile numbering
+        tb = c.tile_base;
+        gx = (uint32_t)c.gx;
     }
     // the wavefront's pairs: [off0, off0 + count)
     const uint32_t off0 = __shfl(off, 0, 64);
@@ -408,13 +440,14 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(const uint32_t* ord
         const uint32_t rvg = (uint32_t)__shfl((int)vg, (int)r, 64);
         const uint32_t rx = (uint32_t)__shfl((int)rc.x, (int)r, 64);
         const uint32_t ry = (uint32_t)__shfl((int)rc.y, (int)r, 64);
+        const uint32_t rtb = (uint32_t)__shfl((int)tb, (int)r, 64);
+        const uint32_t rgx = (uint32_t)__shfl((int)gx, (int)r, 64);
         const uint32_t k = q - s_loc[wid][r];
         const uint32_t rx0 = rx & 0xffffu, rw = (rx >> 16) - rx0 + 1u, ry0 = ry & 0xffffu;
         const uint32_t dy = k / rw, dx = k - dy * rw;
-        const uint32_t v = rvg / n;
         const uint32_t p = off0 + q;
         if (q0 + lane < count && p < cap) {
-            keys[p] = cams[v].tile_base + (ry0 + dy) * (uint32_t)cams[v].gx + rx0 + dx;
+            keys[p] = rtb + (ry0 + dy) * rgx + rx0 + dx;
             emit_vg[p] = rvg;
         }
     }

@@ -370,21 +370,31 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     FwdPix q;
     fwd_init(q, g.inside);
-    // the record indices of a batch's first 64 entries (two dependent loads) are
-    // fetched one batch ahead
-    uint32_t pv = rg.x + lane < rg.y ? a.emit_vg[a.pair_vals[rg.x + lane]] : 0u;
+    // the record indices of a batch's entries (two dependent loads) are fetched one
+    // batch ahead, 64 a register
+    constexpr int NH = (B + kWave - 1) / kWave;
+    uint32_t pv[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        const uint32_t e = rg.x + (uint32_t)h * kWave + lane;
+        pv[h] = (uint32_t)h * kWave + lane < (uint32_t)B && e < rg.y ? a.emit_vg[a.pair_vals[e]] : 0u;
+    }
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
         if (__ballot(!q.done) == 0ull) break;
         const uint32_t cnt = (rg.y - bs) < (uint32_t)B ? (rg.y - bs) : (uint32_t)B;
         // stage the batch, keeping (in list order) only Gaussians that can reach this block
         uint32_t m = 0;
-        for (uint32_t j0 = 0; j0 < cnt; j0 += kWave) {
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const uint32_t j0 = (uint32_t)h * kWave;
+            if (j0 >= cnt) continue;                           // (uniform; no break, so pv[h] stays in registers)
             const uint32_t j = j0 + lane;
             bool keep = false;
-            float4 r0, r1, r2;
+            // defined on every path: with undefined values on the j >= cnt path the
+            // register allocator spilled r1 to scratch around the cull
+            float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
             if (j < cnt) {
-                const uint32_t vg = j0 == 0 ? pv : a.emit_vg[a.pair_vals[bs + j]];
-                const float4* r = a.rec + (size_t)kRecF4 * vg;
+                const float4* r = a.rec + (size_t)kRecF4 * pv[h];
                 r0 = r[0];
                 r1 = r[1];
                 r2 = r[2];
@@ -400,7 +410,11 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
             }
             m += (uint32_t)__popcll(bal);
         }
-        if (bs + B + lane < rg.y) pv = a.emit_vg[a.pair_vals[bs + B + lane]];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const uint32_t e = bs + B + (uint32_t)h * kWave + lane;
+            if ((uint32_t)h * kWave + lane < (uint32_t)B && e < rg.y) pv[h] = a.emit_vg[a.pair_vals[e]];
+        }
         wave_lds_sync();
         for (uint32_t k = 0; k < m; ++k)
             fwd_step<RENDER>(q, s_g0[wid][k], s_g1[wid][k], s_b[wid][k], fpx, fpy, s_pos[wid][k], k);

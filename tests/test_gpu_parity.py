@@ -347,6 +347,37 @@ def test_batched_equals_plain(R, tiny):
         assert rel_norm(gb[k], gsum[k]) < 1e-5, k
 
 
+def test_many_views_one_launch_equals_per_view(tiny):
+    """More views than the projection kernels stage in LDS at once (16): 20 views in one
+    launch give bit-identical images and the summed per-view gradients."""
+    from scipy.spatial.transform import Rotation
+    scene, _ = tiny
+    cams = []
+    for k in range(20):
+        w, h = (64, 48) if k % 2 else (48, 40)
+        Rm = Rotation.from_euler("y", -0.2 + 0.02 * k).as_matrix().astype(np.float32)
+        cams.append(scenes.Camera(w, h, 60.0, 60.0, w / 2.0, h / 2.0, Rm,
+                                  np.array([0.01 * k - 0.1, 0.0, 0.1], np.float32), 0.2))
+    G = gsr.Rasterizer(max_views=len(cams))
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=0)
+    ob = gpu_forward(G, t, cams, opts)
+    gb = gpu_backward(G, t, cams, opts, ob, torch.full_like(ob["rgb"], 1e-4), None,
+                      torch.full((len(cams),), GAMMA, device=DEV))
+    off = gsr.pixel_offsets(cams)
+    gsum = {k: np.zeros_like(v) for k, v in gb.items()}
+    for v, cam in enumerate(cams):
+        os_ = gpu_forward(G, t, [cam], opts)
+        for k in ("rgb", "entropy", "t_final", "n_contrib"):
+            assert torch.equal(ob[k][off[v]:off[v + 1]], os_[k]), (v, k)
+        gv = gpu_backward(G, t, [cam], opts, os_, torch.full_like(os_["rgb"], 1e-4), None,
+                          torch.full((1,), GAMMA, device=DEV))
+        for k in gsum:
+            gsum[k] += gv[k]
+    for k in gsum:
+        assert rel_norm(gb[k], gsum[k]) < 1e-5, k
+
+
 def test_batched_views_vs_oracle(R, tiny):
     scene, _ = tiny
     cams = _tiny_cams()

@@ -795,9 +795,19 @@ __global__ __launch_bounds__(256) void entropy_chunk_kernel(const float* block_H
     const CamDev& c = cams[v];
     const uint32_t nb = c.n_wblocks;
     const uint32_t b0 = (ch - c.hred_base) * kRedChunk;
+    // all loads first (clamped index), then the sum in the same order as a plain loop
+    constexpr int kPer = kRedChunk / 256;
+    static_assert(kRedChunk % 256 == 0, "whole rounds of 256");
+    float hv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const uint32_t b = b0 + threadIdx.x + 256u * (uint32_t)j;
+        hv[j] = block_H[c.block_base + (b < nb ? b : nb - 1u)];
+    }
     double acc = 0.0;
-    for (uint32_t k = threadIdx.x; k < (uint32_t)kRedChunk; k += 256)
-        if (b0 + k < nb) acc += (double)block_H[c.block_base + b0 + k];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+        if (b0 + threadIdx.x + 256u * (uint32_t)j < nb) acc += (double)hv[j];
     const double tot = block_sum_f64(acc);
     if (threadIdx.x == 0) chunk_sum[ch] = tot;
 }

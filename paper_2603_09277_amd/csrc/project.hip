@@ -212,9 +212,10 @@ __device__ __forceinline__ void view_proj(const CamDev& c, const float* mu, cons
     P.ok = true;
 }
 
-// The cameras of a launch are read from LDS, kCamChunk at a time: a per-view
-// camera read from global memory (the compiler makes it a vector load) would
-// wait, through the shared vector-memory counter, for the previous view's stores.
+// The forward reads the cameras of a launch from LDS, kCamChunk at a time: read
+// from global memory in its view loop, a camera became vector loads, whose wait
+// (the shared vector-memory counter) also waited for the previous view's stores.
+// The backward stores nothing in its view loop and reads them with scalar loads.
 constexpr int kCamChunk = 16;
 static_assert(sizeof(CamDev) % 4 == 0, "cameras are copied in 4-byte words");
 
@@ -318,10 +319,8 @@ template <int DEG, bool BF16>
 __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    __shared__ CamDev s_cam[kCamChunk];
-    const uint32_t i0 = blockIdx.x * 256u + threadIdx.x;
-    const bool active = i0 < a.n;
-    const uint32_t i = active ? i0 : a.n - 1u;               // past the end: only helps stage the cameras
+    uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= a.n) return;
     float mu[3] = { a.means[3 * (size_t)i], a.means[3 * (size_t)i + 1], a.means[3 * (size_t)i + 2] };
     float s[3] = { a.scales[3 * (size_t)i], a.scales[3 * (size_t)i + 1], a.scales[3 * (size_t)i + 2] };
     float q[4] = { a.quats[4 * (size_t)i], a.quats[4 * (size_t)i + 1], a.quats[4 * (size_t)i + 2], a.quats[4 * (size_t)i + 3] };
@@ -346,11 +345,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a)
     float g_n[kG2];
 #pragma unroll
     for (int k = 0; k < kG2; ++k) g_n[k] = a.n_views > 0 ? a.grad2d[(size_t)kG2 * i + k] : 0.f;
-    for (int v0 = 0; v0 < a.n_views; v0 += kCamChunk) {
-    const int nv = a.n_views - v0 < kCamChunk ? a.n_views - v0 : kCamChunk;
-    stage_cams(s_cam, a.cams, v0, nv);
-    if (!active) continue;
-    for (int v = v0; v < v0 + nv; ++v) {
+    for (int v = 0; v < a.n_views; ++v) {
         const uint32_t tt_v = tt_n, rs_v = rs_n;
         float g[kG2];
 #pragma unroll
@@ -362,7 +357,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a)
 #pragma unroll
             for (int k = 0; k < kG2; ++k) g_n[k] = a.grad2d[(size_t)kG2 * o + k];
         }
-        const CamDev& c = s_cam[v - v0];
+        const CamDev& c = a.cams[v];                        // scalar loads here (unlike the forward)
         ViewProj P;
         view_proj(c, mu, L, a.flags, P);
         if (!P.ok || tt_v == 0 || rs_v != st) continue;     // no pairs, or none blended: zero gradient
@@ -438,8 +433,6 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs a)
         gmu[1] += c.R[1] * gtx + c.R[4] * gty + c.R[7] * gtz;
         gmu[2] += c.R[2] * gtx + c.R[5] * gty + c.R[8] * gtz;
     }
-    }
-    if (!active) return;
 
     // ---- Sigma = M M^T with M = R diag(s):  dL/dM = 2 G M
     float G[9] = { gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5] };

@@ -114,9 +114,33 @@ __global__ __launch_bounds__(kThreads) void scan_spine_kernel(uint32_t* partial,
     }
 }
 
+// SELF (at most kThreads blocks): partial holds the raw block sums; each block adds
+// up those before it itself, and the last block writes the total (no spine kernel)
+template <bool SELF>
 __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* vals_s, uint32_t n,
-                                                             const uint32_t* partial, uint32_t* out)
+                                                             const uint32_t* partial, uint32_t nb, uint32_t* out,
+                                                             uint32_t* total, uint32_t* overflow)
 {
+    uint32_t bpre;
+    if (SELF) {
+        __shared__ unsigned long long s_w[kThreads / 64];
+        unsigned long long x = threadIdx.x < blockIdx.x ? (unsigned long long)partial[threadIdx.x] : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((threadIdx.x & 63u) == 0u) s_w[threadIdx.x >> 6] = x;
+        __syncthreads();
+        unsigned long long pre = 0ull;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) pre += s_w[w];
+        bpre = (uint32_t)pre;
+        if (blockIdx.x == nb - 1u && threadIdx.x == 0) {
+            const unsigned long long c = pre + partial[blockIdx.x];
+            *total = c > 0xffffffffull ? 0xffffffffu : (uint32_t)c;
+            if (c > 0xffffffffull) *overflow = 1u;
+        }
+    } else {
+        bpre = partial[blockIdx.x];
+    }
     size_t base = (size_t)blockIdx.x * kTileItems + (size_t)threadIdx.x * kItems;
     uint32_t v[kItems];
     uint32_t sum = 0;
@@ -128,7 +152,7 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* val
         sum += v[k];
     }
     uint32_t tot;
-    uint32_t run = block_excl_scan(sum, &tot) + partial[blockIdx.x];
+    uint32_t run = block_excl_scan(sum, &tot) + bpre;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         size_t idx = base + k;
@@ -787,8 +811,15 @@ hipError_t launch_gather_scan(const uint4* trect, const uint32_t* order, uint32_
     uint32_t nb = (n + kTileItems - 1) / kTileItems;
     if (nb > 0)
         hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kThreads), 0, s, trect, order, n, tmp, vals_s, rect_s);
+    if (nb > 0 && nb <= (uint32_t)kThreads) {          // few blocks: no spine
+        hipLaunchKernelGGL(scan_down_kernel<true>, dim3(nb), dim3(kThreads), 0, s, vals_s, n, tmp, nb, out, total,
+                           overflow);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(scan_spine_kernel, dim3(1), dim3(kThreads), 0, s, tmp, nb, total, overflow);
-    if (nb > 0) hipLaunchKernelGGL(scan_down_kernel, dim3(nb), dim3(kThreads), 0, s, vals_s, n, tmp, out);
+    if (nb > 0)
+        hipLaunchKernelGGL(scan_down_kernel<false>, dim3(nb), dim3(kThreads), 0, s, vals_s, n, tmp, nb, out, total,
+                           overflow);
     return hipGetLastError();
 }
 

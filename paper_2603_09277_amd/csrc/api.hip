@@ -254,7 +254,7 @@ Layout make_layout(const gsr_camera* cams, int32_t n_views, const gsr_opts* o)
         d.hred_base = hb;
         d.l1_base = lb;
         hb += (d.n_wblocks + kRedChunk - 1) / kRedChunk;
-        lb += (uint32_t)(((int64_t)k.width * k.height + kL1Block - 1) / kL1Block);
+        lb += (uint32_t)(((int64_t)k.width * k.height + kL1Pix - 1) / kL1Pix);
         tb += (uint32_t)(d.gx * d.gy);
         bb += d.n_wblocks;
         pb += (int64_t)k.width * k.height;

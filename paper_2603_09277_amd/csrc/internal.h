@@ -33,7 +33,8 @@ struct CamDev {
 };
 
 constexpr int kRedChunk = 1024;    // 8x8 blocks summed per entropy-reduction chunk
-constexpr int kL1Block = 256;      // pixels per L1 block
+constexpr int kL1Block = 256;      // threads per L1 block
+constexpr int kL1Pix = 4 * kL1Block;   // pixels per L1 block (4 a thread)
 
 // Projected record of one (view, Gaussian): three float4
 //   r0 = (mean x, mean y, A', B')

@@ -1,8 +1,8 @@
 // L1 photometric term of the base loss (Sec. 3, Eq. 6 with lambda = 0):
 //   L1_v = mean over the 3 M_v values of view v of |C - target|,
 //   dL1_v/dC = sign(C - target) / (3 M_v), with sign(0) = 0.
-// Every block covers pixels of a single view, so the per-view loss is a fixed
-// order FP64 sum of whole blocks: deterministic.
+// Every block covers kL1Pix pixels of a single view, so the per-view loss is a
+// fixed-order FP64 sum of whole blocks: deterministic.
 #include <cmath>
 
 #include "internal.h"
@@ -29,29 +29,53 @@ __device__ __forceinline__ double block_sum_f64(double x)
     return s[0];
 }
 
+// sum over the block in a fixed order: lanes by xor-shuffle, then the 4 wavefronts
+__device__ __forceinline__ double block_sum_f64_shfl(double x)
+{
+    __shared__ double s_w[kL1Block / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if ((threadIdx.x & 63u) == 0u) s_w[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kL1Block / 64; ++w) t += s_w[w];
+    return t;
+}
+
 __global__ __launch_bounds__(kL1Block) void l1_kernel(const float* rgb, const float* target, const CamDev* cams,
                                                       int n_views, float weight, float* grad, double* block_sum)
 {
+    constexpr int kPer = kL1Pix / kL1Block;
     const uint32_t b = blockIdx.x;
     const int v = view_of_l1_block(cams, n_views, b);
     const CamDev& c = cams[v];
     const int64_t M = (int64_t)c.W * c.H;
-    const int64_t q = (int64_t)(b - c.l1_base) * kL1Block + threadIdx.x;   // pixel within the view
-    double acc = 0.0;
-    if (q < M) {
-        const int64_t p = c.pix_base + q;
-        const float inv = weight / (3.0f * (float)M);
-        float d[3];
+    const int64_t q0 = (int64_t)(b - c.l1_base) * kL1Pix + threadIdx.x;   // pixels q0 + kL1Block k of the view
+    const float inv = weight / (3.0f * (float)M);
+    // every load before any store (a clamped index for pixels past the view's end)
+    float d[kPer][3];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) d[ch] = rgb[3 * p + ch] - target[3 * p + ch];   // all loads before any store
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t q = q0 + (int64_t)k * kL1Block;
+        const int64_t p = c.pix_base + (q < M ? q : M - 1);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) d[k][ch] = rgb[3 * p + ch] - target[3 * p + ch];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t q = q0 + (int64_t)k * kL1Block;
+        if (q >= M) continue;
+        const int64_t p = c.pix_base + q;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            const float sg = d[ch] > 0.f ? 1.f : (d[ch] < 0.f ? -1.f : 0.f);
+            const float sg = d[k][ch] > 0.f ? 1.f : (d[k][ch] < 0.f ? -1.f : 0.f);
             if (grad) grad[3 * p + ch] = sg * inv;
-            acc += (double)fabsf(d[ch]);
+            acc += (double)fabsf(d[k][ch]);
         }
     }
-    const double tot = block_sum_f64(acc);
+    const double tot = block_sum_f64_shfl(acc);
     if (threadIdx.x == 0) block_sum[b] = tot;
 }
 

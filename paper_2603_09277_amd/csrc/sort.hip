@@ -304,15 +304,38 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
 
     // global offsets: exclusive prefix of the digit totals + this block's row offset
     uint32_t tot;
-    if (SELF) {                               // digit tid: its count in all blocks and in the blocks before this one
-        uint32_t all = 0u, before = 0u;
-#pragma unroll 8
-        for (uint32_t b = 0; b < nb; ++b) {
-            const uint32_t v = hist[(size_t)b * kBins + tid];
-            all += v;
-            before += b < blockIdx.x ? v : 0u;
+    if (SELF) {
+        // every digit's count in all blocks and in the blocks before this one: wavefront
+        // w sums rows w, w + 4, ... (lane l: digits 4 l .. 4 l + 3, one 16-byte load a row,
+        // 8 rows in flight), then the 4 partial sums of digit tid are added
+        uint4 all = make_uint4(0u, 0u, 0u, 0u), bef = all;
+        for (uint32_t b0 = wid; b0 < nb; b0 += 8u * kWaves) {
+            uint4 v[8];
+#pragma unroll
+            for (uint32_t k = 0; k < 8u; ++k) {
+                const uint32_t b = b0 + k * kWaves;
+                v[k] = b < nb ? reinterpret_cast<const uint4*>(hist + (size_t)b * kBins)[lane] : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < 8u; ++k) {
+                const uint32_t b = b0 + k * kWaves;
+                all.x += v[k].x; all.y += v[k].y; all.z += v[k].z; all.w += v[k].w;
+                if (b < blockIdx.x) { bef.x += v[k].x; bef.y += v[k].y; bef.z += v[k].z; bef.w += v[k].w; }
+            }
         }
-        s_gofs[tid] = block_excl_scan(all, &tot) + before;
+        s_wh[wid][4u * lane + 0u] = all.x; s_wh[wid][4u * lane + 1u] = all.y;
+        s_wh[wid][4u * lane + 2u] = all.z; s_wh[wid][4u * lane + 3u] = all.w;
+        s_keys[wid * kBins + 4u * lane + 0u] = bef.x; s_keys[wid * kBins + 4u * lane + 1u] = bef.y;
+        s_keys[wid * kBins + 4u * lane + 2u] = bef.z; s_keys[wid * kBins + 4u * lane + 3u] = bef.w;
+        __syncthreads();
+        uint32_t a = 0u, before = 0u;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            a += s_wh[w][tid];
+            before += s_keys[w * kBins + tid];
+        }
+        __syncthreads();                      // s_wh and s_keys are reused below
+        s_gofs[tid] = block_excl_scan(a, &tot) + before;
     } else {
         const uint32_t dbase = block_excl_scan(digit_total[tid], &tot);
         s_gofs[tid] = dbase + hist[(size_t)blockIdx.x * kBins + tid];

@@ -111,6 +111,21 @@ def test_binning_sort_ranges_bit_exact(R, tiny, tile):
     assert np.array_equal(gr.astype(np.int64), ranges.astype(np.int64))
 
 
+def test_binning_bit_exact_mid_size_sort(R):
+    """A tile sort of 2.8e5-3.3e5 pairs: 129-256 radix blocks, the pass size whose spine
+    takes one count a thread (smaller passes have no spine, larger ones 8 or 32)."""
+    scene, cams = scenes.tiny_scene(41, 8000)
+    scene.scales = (scene.scales * np.float32(7.0)).astype(np.float32)
+    t = to_dev(scene)
+    gpu_forward(R, t, cams, gsr.RasterOptions(tile=(16, 16), sh_degree=0))
+    pg = gpu_records(R, scene.n, 1)[0]
+    cam = cams[0]
+    vals, ranges = orc.bin_lists(pg["mean2d"], pg["radius"], pg["depth32"], cam.width, cam.height, 16, 16)
+    assert 128 * 2048 < len(vals) <= 256 * 2048, len(vals)
+    assert np.array_equal(R.inspect(gsr.BUF_PAIR_VALUES).astype(np.int64), vals.astype(np.int64))
+    assert np.array_equal(R.inspect(gsr.BUF_RANGES).reshape(-1, 2).astype(np.int64), ranges.astype(np.int64))
+
+
 def test_binning_bit_exact_single_view_full(R):
     """The 200k-Gaussian 1296x840 workload: every one of ~1e6 pairs in order."""
     scene, cams, _ = scenes.workload("single")

@@ -230,7 +230,8 @@ __device__ __forceinline__ void stage_cams(CamDev* s_cam, const CamDev* cams, in
     __syncthreads();
 }
 
-template <int DEG, bool BF16>
+// ONE: a launch of one view (a constant view count; fewer registers)
+template <int DEG, bool BF16, bool ONE>
 __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectFwdArgs a)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -247,8 +248,9 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectFwdArgs a)
     Local L;
     local_state(mu, s, q, op, sh, K * 3, L);
     const int tsx = a.tile_shift_x, tsy = a.tile_shift_y;
-    for (int v0 = 0; v0 < a.n_views; v0 += kCamChunk) {
-    const int nv = a.n_views - v0 < kCamChunk ? a.n_views - v0 : kCamChunk;
+    const int n_views = ONE ? 1 : a.n_views;
+    for (int v0 = 0; v0 < n_views; v0 += kCamChunk) {
+    const int nv = n_views - v0 < kCamChunk ? n_views - v0 : kCamChunk;
     stage_cams(s_cam, a.cams, v0, nv);
     if (!active) continue;
     for (int v = v0; v < v0 + nv; ++v) {
@@ -507,7 +509,8 @@ template <int DEG, bool BF16>
 hipError_t fwd_dispatch(const ProjectFwdArgs& a, hipStream_t s)
 {
     dim3 grid((a.n + 255u) / 256u);
-    hipLaunchKernelGGL((project_fwd_kernel<DEG, BF16>), grid, dim3(256), 0, s, a);
+    if (a.n_views == 1) hipLaunchKernelGGL((project_fwd_kernel<DEG, BF16, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((project_fwd_kernel<DEG, BF16, false>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -76,8 +76,12 @@ typedef struct {
 #define GSR_DILATE          1u   /* +0.3 on the 2D covariance diagonal */
 #define GSR_JACOBIAN_CLAMP  2u   /* 1.3x field-of-view clamp inside the EWA Jacobian */
 #define GSR_COLOR_CLAMP     4u   /* clamp colour at 0 */
-#define GSR_GRAPH           8u   /* capture forward / backward into HIP graphs and replay them;
-                                    fixed pair capacity, no host synchronisation */
+#define GSR_GRAPH           8u   /* capture forward / backward into HIP graphs and replay them at a
+                                    fixed pair capacity: every capture first runs one plain forward and
+                                    sizes the capacity at 1.5x its pairs + 4096; a replay whose count came
+                                    within 10 % of the capacity (or past it) makes the next forward capture
+                                    again; gsr_backward waits for the replayed forward to finish and refuses
+                                    (GSR_ERR_CAPACITY) a frame whose pairs did not fit */
 #define GSR_PERSISTENT     16u   /* persistent blend kernels: resident workgroups pull tiles from 8 device
                                     queues (one per XCD) of spatially contiguous tiles, stealing from the
                                     others when their own is empty */
@@ -91,7 +95,9 @@ typedef struct {
 
 typedef struct {
     int32_t tile_w, tile_h;    /* {8,8}, {16,16} or {32,8} */
-    int32_t lds_batch;         /* Gaussians staged per LDS batch: 32, 64, 128, 256; 0 = 64 */
+    int32_t lds_batch;         /* Gaussians staged per LDS batch of the forward: 32, 64, 128, 256; 0 = 64.
+                                  The backward walks windows of min(lds_batch, 128) entries (its LDS
+                                  holds per-wavefront partial sums of every window entry) */
     int32_t sh_degree;         /* 0 .. 3; K = (sh_degree + 1)^2 coefficients per channel */
     int32_t sh_dtype;          /* 0 = float32, 1 = bfloat16 (SH storage and SH gradients) */
     uint32_t flags;            /* GSR_* flags */
@@ -248,7 +254,11 @@ gsr_status gsr_select_rmax(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, c
                            const gsr_opts* opts, int32_t r_cap, double max_mean_len, int32_t* r_out,
                            double* mean_len);
 
-/* Statistics of the latest forward. */
+/* Statistics of the latest forward: the per-tile Gaussian-list lengths whose
+ * shortening is the paper's subject (Sec. 5.4 Ablation Study, "Length of
+ * Gaussian Lists" and its list-length distribution figure; Sec. 4.1 Overview),
+ * and the work the blend did on them (list positions visited, alpha tests,
+ * blended pairs; Sec. 3 Background, Eq. 3-5). */
 typedef struct {
     int64_t pairs;             /* (tile, Gaussian) pairs over all views */
     double mean_len;           /* mean per-tile list length over all tiles */
@@ -299,7 +309,9 @@ typedef enum {
 gsr_status gsr_set_timing(gsr_ctx* ctx, int32_t enable);
 gsr_status gsr_stage_times(gsr_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);
 
-/* Time forward+backward for every tile shape in {8x8, 16x16, 32x8}, LDS
+/* Tile-size choice (Sec. 5.4 Ablation Study, "Effect of tile sizes" and its
+ * tile-size table: smaller tiles shorten the per-tile lists but add tiles).
+ * Time forward+backward for every tile shape in {8x8, 16x16, 32x8}, LDS
  * batch in {32, 64, 128, 256} and blend scheduling (hardware dispatch or
  * GSR_PERSISTENT) on the given inputs, and write the fastest into
  * inout->tile_w/tile_h/lds_batch and the GSR_PERSISTENT bit of inout->flags

@@ -84,6 +84,7 @@ struct gsr_ctx {
     bool capturing = false;                // a graph capture is recording (no stage events)
     bool nosync_ready = false;             // a GSR_NO_SYNC frame has sized the pair capacity
     bool replay_pending = false;
+    int64_t graph_frame = -1;              // frame id of the latest forward-graph replay
 
     // per-stage timing (eager launches; not under graph capture)
     uint32_t timing = 0;                   // bit s: stage s is timed
@@ -656,16 +657,23 @@ gsr_status gsr_forward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const g
         HIP_TRY(c, hipMemcpyAsync(c->cams.p, c->lay.cams.data(), sizeof(CamDev) * L.cams.size(), hipMemcpyHostToDevice, st));
         if ((s = enqueue_forward(c, st, g, o, out, true))) return s;
     } else {
-        // a pair capacity is needed before capture: measure once in plain mode
-        if (c->pair_cap <= 1) {
+        FrameKey k = make_key(g, cams, n_views, o, outs);
+        bool recapture = !c->gexec_fwd || !(k == c->key_fwd) || c->gen != c->gen_fwd;
+        // the previous frame was this graph's replay (wait_replay has run, so its pair count
+        // and overflow flag are in counters_host): a count within 10 % of the captured
+        // capacity, or past it, sends this frame through a new capture
+        if (!recapture && c->graph_frame == c->frame &&
+            (c->counters_host[1] != 0 || (size_t)c->counters_host[0] + c->counters_host[0] / 10 > c->pair_cap))
+            recapture = true;
+        if (recapture) {
+            // every capture starts from an exact count: one plain forward, then the
+            // fixed capacity at 1.5x its pairs + 4096 (the buffers only grow)
+            drop_graphs(c);
             HIP_TRY(c, hipMemcpyAsync(c->cams.p, c->lay.cams.data(), sizeof(CamDev) * L.cams.size(), hipMemcpyHostToDevice, st));
             if ((s = enqueue_forward(c, st, g, o, out, true))) return s;
             size_t want = (size_t)c->pairs + c->pairs / 2 + 4096;
             if ((s = ensure_pairs(c, want)) || (s = ensure_radix_tmp(c, std::max<size_t>(c->pair_cap, vn)))) return s;
-            drop_graphs(c);
         }
-        FrameKey k = make_key(g, cams, n_views, o, outs);
-        if (c->gexec_fwd && (!(k == c->key_fwd) || c->gen != c->gen_fwd)) drop_graphs(c);
         std::memcpy(c->cams_host, L.cams.data(), sizeof(CamDev) * L.cams.size());
         if (!c->gexec_fwd) {
             hipStream_t cs;
@@ -700,6 +708,7 @@ gsr_status gsr_forward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const g
         c->pairs = 0;
         int tile_bits = std::max(1, ilog2((int)std::max<uint32_t>(L.n_tiles, 2)));
         c->sorted_buf = ((tile_bits + 7) / 8) & 1;
+        c->graph_frame = c->frame + 1;
     }
     c->frame += 1;
     c->have_frame = true;
@@ -767,6 +776,14 @@ gsr_status gsr_backward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
     if (!(o->flags & GSR_GRAPH))
         return enqueue_backward(c, st, g, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, gr);
 
+    // a replayed forward ran at a fixed pair capacity: its pair count comes back with it,
+    // and a frame whose lists did not fit (truncated lists) gets no gradients
+    if (c->graph_frame == c->frame) {
+        if ((s = wait_replay(c))) return s;
+        if (c->counters_host[1] != 0 || c->counters_host[0] > c->pair_cap_used)
+            return fail(c, GSR_ERR_CAPACITY, "the forward's pairs exceeded the graph's fixed capacity (its lists are "
+                                             "truncated); the next forward captures again at a larger capacity");
+    }
     const void* outs[5] = { saved->rgb, saved->entropy, saved->t_final, saved->n_contrib, saved->entropy_mean };
     FrameKey k = make_key(g, cams, n_views, o, outs);
     void* gouts[5] = { gr->means, gr->scales, gr->quats, gr->opacities, gr->sh };
@@ -1190,7 +1207,14 @@ gsr_status gsr_autotune(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
     gsr_grads gg;
     gg.means = (float*)take(g->n * 12); gg.scales = (float*)take(g->n * 12); gg.quats = (float*)take(g->n * 16);
     gg.opacities = (float*)take(g->n * 4); gg.sh = take(shb);
-    HIP_TRY(c, hipMemsetAsync(grgb, 0, npix * 12, st));
+    // upstream gradients of the size an L1 term gives (every blended entry carries a colour
+    // gradient, as in training) and gamma = 0.015 on every view's mean entropy
+    {
+        const float gc = 1.0f / (3.0f * (float)std::max<int64_t>(npix, 1));
+        uint32_t bits;
+        std::memcpy(&bits, &gc, 4);
+        HIP_TRY(c, launch_fill_u32((uint32_t*)grgb, bits, (size_t)npix * 3, st));
+    }
     HIP_TRY(c, launch_fill_u32((uint32_t*)gle, 0x3c75c28fu /* 0.015f */, n_views, st));
     const int shapes[3][2] = { { 8, 8 }, { 16, 16 }, { 32, 8 } };
     const int batches[4] = { 32, 64, 128, 256 };

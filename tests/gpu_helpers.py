@@ -104,3 +104,40 @@ def oracle_grads(scene, cams, targets, gamma, tile, gpu_rgb=None, ambiguous=1e-5
         acc = orc.backward_project(scene, cam, g2, flags, acc)
         off += M
     return L, acc
+
+
+GRAD_TOL = 1e-3       # relative gradient tolerance
+GRAD_FLOOR = 1e-5     # element-wise floor, as a fraction of the tensor's largest |g*|
+
+
+def check_grad(g, ref, name="", tol=GRAD_TOL, floor=GRAD_FLOOR, mask=None):
+    """The gradient tolerance for FP32 gradients, per tensor and per element:
+    ||g - g*||_2 <= tol ||g*||_2 and |g - g*| <= tol |g*| + floor max|g*| for every
+    element (of the rows selected by `mask`, a boolean over the first axis, when given;
+    the L2 check always covers the whole tensor)."""
+    g = np.asarray(g, np.float64)
+    ref = np.asarray(ref, np.float64)
+    assert g.shape == ref.shape, (name, g.shape, ref.shape)
+    rn = rel_norm(g, ref)
+    assert rn <= tol, (name, "relative L2 error", rn)
+    if ref.size == 0:
+        return rn
+    scale = float(np.abs(ref).max())
+    gs, rs = (g, ref) if mask is None else (g[mask], ref[mask])
+    err = np.abs(gs - rs)
+    bound = tol * np.abs(rs) + floor * scale
+    bad = np.flatnonzero((err > bound).reshape(-1))
+    if bad.size:
+        worst = bad[np.argsort(-(err.reshape(-1)[bad] / np.maximum(bound.reshape(-1)[bad], 1e-300)))[:5]]
+        raise AssertionError((name, f"{bad.size} of {err.size} elements beyond tol |g*| + floor max|g*|",
+                              [(int(i), float(gs.reshape(-1)[i]), float(rs.reshape(-1)[i])) for i in worst]))
+    return rn
+
+
+def check_grad2d(g2g, g2o, tol=GRAD_TOL, floor=GRAD_FLOOR):
+    """The blend backward's per-Gaussian 2D gradients (BUF_GRAD2D rows) against the
+    oracle's, component group by component group."""
+    check_grad(g2g[:, 0:2], g2o["mean2d"], "mean2d", tol, floor)
+    check_grad(g2g[:, 2:5], g2o["conic"], "conic", tol, floor)
+    check_grad(g2g[:, 5], g2o["opacity"], "opacity", tol, floor)
+    check_grad(g2g[:, 6:9], g2o["rgb"], "rgb", tol, floor)

@@ -401,10 +401,10 @@ def _loss_sig(orc, scene, cam, target, gamma, tile):
     return L, sig
 
 
-def _fd_check(orc, scene, cam, target, gamma, tile, grads, params, rng, n_gauss, rtol, atol_frac):
+def _fd_check(orc, scene, cam, target, gamma, tile, grads, params, rng, n_gauss, rtol, atol_frac, gauss=None):
     checked = 0
     redrawn = 0
-    for g in rng.choice(scene.n, n_gauss, replace=False):
+    for g in (rng.choice(scene.n, n_gauss, replace=False) if gauss is None else gauss):
         for name in params:
             arr = getattr(scene, name)
             flat = arr.reshape(scene.n, -1)
@@ -439,6 +439,83 @@ def test_full_backward_matches_central_fd(orc):
     checked, redrawn = _fd_check(orc, scene, cam, target, gamma, tile, grads,
                                  ["means", "scales", "quats", "opacities", "sh"], rng, 24, 1e-4, 1e-6)
     assert checked > 300 and redrawn < checked // 4
+
+
+def _camera_space_scene(rng, cam, cam_xyz, log_scale, opac, n_fill, deg=1):
+    """Gaussians placed by camera-space position (x/z, y/z, z), then mapped to the
+    world with the camera's pose; `n_fill` ordinary Gaussians fill the view."""
+    R = np.asarray(cam.R, np.float64)
+    t0 = np.asarray(cam.t, np.float64)
+    fill = np.stack([rng.uniform(-0.4, 0.4, n_fill), rng.uniform(-0.3, 0.3, n_fill), rng.uniform(3.0, 5.0, n_fill)], 1)
+    xyz = np.concatenate([np.asarray(cam_xyz, np.float64), fill])
+    tc = np.stack([xyz[:, 0] * xyz[:, 2], xyz[:, 1] * xyz[:, 2], xyz[:, 2]], 1)
+    means = (tc - t0) @ R                                   # R^T (t_cam - t)
+    n = len(xyz)
+    scales = np.exp(np.concatenate([np.full((len(cam_xyz), 3), log_scale), rng.normal(-2.3, 0.4, (n_fill, 3))])
+                    + rng.normal(0.0, 0.15, (n, 3)))
+    quats = rng.standard_normal((n, 4))
+    op = np.concatenate([np.full(len(cam_xyz), opac), 1 / (1 + np.exp(-rng.normal(0.0, 1.0, n_fill)))])
+    K = (deg + 1) ** 2
+    sh = rng.normal(0.0, 0.3, (n, K, 3))
+    sh[:, 0, :] = rng.uniform(-1.0, 1.0, (n, 3))
+    return make_scene(means, scales, quats, op, sh, deg)
+
+
+def test_backward_fd_in_jacobian_clamp_branch(orc):
+    """Gaussians whose x/z or y/z lies beyond 1.3x the half field of view, large enough to
+    reach into the image: the EWA Jacobian is taken at the clamped position, whose
+    derivative with respect to the camera-space position has only the depth term
+    (reading R12).  Central differences through the whole chain, clamped Gaussians only."""
+    R = Rotation.from_euler("xyz", [0.04, -0.06, 0.02]).as_matrix()
+    cam = scenes.Camera(40, 32, 36.0, 38.0, 20.7, 15.6, R.astype(np.float32), np.array([0.1, -0.05, 0.2], np.float32),
+                        0.2)
+    limx, limy = 1.3 * 20.0 / 36.0, 1.3 * 16.0 / 38.0
+    rng = np.random.default_rng(21)
+    clamped = [(0.80, 0.10, 3.5), (-0.82, -0.20, 3.8), (0.20, 0.60, 3.3), (-0.10, -0.62, 3.6), (0.79, -0.59, 4.0),
+               (-0.78, 0.58, 3.4)]
+    assert all(abs(x) > limx or abs(y) > limy for x, y, _ in clamped)
+    scene = _camera_space_scene(rng, cam, clamped, np.log(0.55), 0.8, 24)
+    pr = orc.project(scene, cam)
+    nc = len(clamped)
+    jmask = (pr["mask"][:nc] & (8 | 16)) != 0
+    assert jmask.all() and pr["radius"][:nc].min() > 0
+    target = rng.uniform(0, 1, (cam.height, cam.width, 3))
+    gamma, tile = 0.5, (8, 8)
+    L, grads, _ = orc.loss_and_grads(scene, [cam], [target], gamma, tile)
+    # the clamped Gaussians reach the image: their gradients are not negligible
+    for name in ("means", "scales", "quats"):
+        assert (np.abs(grads[name][:nc]).max(axis=-1) > 1e-3 * np.abs(grads[name]).max()).sum() >= nc - 1, name
+    checked, redrawn = _fd_check(orc, scene, cam, target, gamma, tile, grads,
+                                 ["means", "scales", "quats", "opacities", "sh"], rng, 0, 1e-4, 1e-6,
+                                 gauss=range(nc))
+    assert checked >= 0.8 * nc * 15 and redrawn < checked // 4, (checked, redrawn)
+
+
+def test_backward_fd_in_alpha_clamp_branch(orc):
+    """Front Gaussians with opacity 0.999 and a 2D spread of several pixels: near their
+    centres opacity * g exceeds 0.99, alpha = 0.99 there and its derivative is exactly 0
+    (reading R2).  Central differences of the whole loss on those Gaussians."""
+    cam = ident_cam(40, 32, 36.0)
+    rng = np.random.default_rng(23)
+    front = [(0.05, 0.02, 2.2), (-0.25, -0.15, 2.4), (0.3, 0.2, 2.6)]
+    scene = _camera_space_scene(rng, cam, front, np.log(0.8), 0.9995, 24)
+    pr = orc.project(scene, cam)
+    nf = len(front)
+    # pixel centres where opacity * g > 0.99, per front Gaussian (coverage of the branch)
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width] + 0.5
+    n_clamped = 0
+    for i in range(nf):
+        dx, dy = pr["mean2d"][i, 0] - xs, pr["mean2d"][i, 1] - ys
+        A, B, C = pr["conic"][i]
+        g = np.exp(-0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy)
+        n_clamped += int((scene.opacities[i] * g > 0.99).sum())
+    assert n_clamped >= 3 * nf, n_clamped
+    target = rng.uniform(0, 1, (cam.height, cam.width, 3))
+    gamma, tile = 0.5, (16, 16)
+    L, grads, _ = orc.loss_and_grads(scene, [cam], [target], gamma, tile)
+    checked, redrawn = _fd_check(orc, scene, cam, target, gamma, tile, grads,
+                                 ["means", "scales", "quats", "opacities"], rng, 0, 1e-4, 1e-6, gauss=range(nf))
+    assert checked >= 0.8 * nf * 11 and redrawn < checked // 4, (checked, redrawn)
 
 
 def test_entropy_only_backward_matches_fd(orc):

@@ -97,7 +97,8 @@ typedef struct {
     int32_t tile_w, tile_h;    /* {8,8}, {16,16} or {32,8} */
     int32_t lds_batch;         /* Gaussians staged per LDS batch of the forward: 32, 64, 128, 256; 0 = 64.
                                   The backward walks windows of min(lds_batch, 128) entries (its LDS
-                                  holds per-wavefront partial sums of every window entry) */
+                                  holds per-wavefront partial sums of every window entry), or of
+                                  min(lds_batch, 64) when the frame's mean list length is 256 or more */
     int32_t sh_degree;         /* 0 .. 3; K = (sh_degree + 1)^2 coefficients per channel */
     int32_t sh_dtype;          /* 0 = float32, 1 = bfloat16 (SH storage and SH gradients) */
     uint32_t flags;            /* GSR_* flags */

@@ -42,6 +42,7 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTStop = 1e-4f;
 constexpr float kLn2 = 0.6931471805599453f;
 constexpr int kWavesPerGroup = 4;
+constexpr int kAccF = 10;            // floats per backward accumulator row: 9 sums and a hit flag
 
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -64,24 +65,21 @@ __device__ __forceinline__ float dpp_f(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
 }
 
-// sum over each row of 16 lanes in a fixed order; every lane of the row
-// receives its row's sum
-__device__ __forceinline__ float row_sum16(float x)
-{
-    x += dpp_f<0xb1, 0xf>(x);    // quad_perm [1,0,3,2]
-    x += dpp_f<0x4e, 0xf>(x);    // quad_perm [2,3,0,1]
-    x += dpp_f<0x141, 0xf>(x);   // row_half_mirror
-    x += dpp_f<0x140, 0xf>(x);   // row_mirror
-    return x;
-}
-
-// Wavefront sums of 9 values by a reduce-scatter: the gfx950 lane swaps
-// between the two 32-lane halves and between neighbouring 16-lane rows pair
-// values up so that one add serves two of them, then a 16-lane DPP row sum
-// finishes each register.  On return every lane of row r holds, in v0, the
-// wavefront total of o[row_comp(r)], in v1 that of o[4 + row_comp(r)], and in
-// v2 that of o[8].  Fixed order: bit-reproducible.
+// Wavefront sums of the 9 per-pixel gradient terms of one list entry, by
+// folding registers in pairs so that one add serves two values: the gfx950
+// lane swaps between the two 32-lane halves and between neighbouring 16-lane
+// rows, then inside each row a rotation by 8 lanes, a half-row mirror and a
+// quad sum.  Fixed order: bit-reproducible.  The total of o[c] ends in lane
+// tot_lane(c): lanes 16 r and 16 r + 8 hold o[row_comp(r)] and
+// o[4 + row_comp(r)], lane 4 holds o[8] (see wave_sum9).
 __device__ __forceinline__ int row_comp(uint32_t r) { return (int)(((r & 1u) << 1) | (r >> 1)); }
+
+// the component whose wavefront total wave_sum9 leaves in this lane, or -1
+__device__ __forceinline__ int tot_comp(uint32_t lane)
+{
+    const uint32_t q = lane & 15u;
+    return q == 0u ? row_comp(lane >> 4) : (q == 8u ? 4 + row_comp(lane >> 4) : (lane == 4u ? 8 : -1));
+}
 
 // lanes 0-31: x[l] + x[l + 32]; lanes 32-63: y[l - 32] + y[l]
 __device__ __forceinline__ float fold_halves(float x, float y)
@@ -97,14 +95,28 @@ __device__ __forceinline__ float fold_rows(float x, float y)
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-__device__ __forceinline__ void wave_sum9(const float* o, float& v0, float& v1, float& v2)
+__device__ __forceinline__ float wave_sum9(const float* o, uint32_t lane)
 {
     const float u0 = fold_halves(o[0], o[1]), u1 = fold_halves(o[2], o[3]);
     const float u2 = fold_halves(o[4], o[5]), u3 = fold_halves(o[6], o[7]);
-    const float u4 = fold_halves(o[8], o[8]);
-    v0 = row_sum16(fold_rows(u0, u1));
-    v1 = row_sum16(fold_rows(u2, u3));
-    v2 = row_sum16(fold_rows(u4, u4));
+    // o[8] has no partner: its own halves and rows are added through the LDS
+    // crossbar (ds_bpermute), which needs no register copy
+    const float u4 = o[8] + __shfl_xor(o[8], 32, 64);
+    // row r: x0 holds 16 partial sums of o[row_comp(r)], x1 of o[4 + row_comp(r)], x2 of o[8]
+    const float x0 = fold_rows(u0, u1), x1 = fold_rows(u2, u3);
+    const float x2 = u4 + __shfl_xor(u4, 16, 64);
+    // row_ror:8 adds lane l ^ 8: 8 partials in each half row
+    const float a0 = x0 + dpp_f<0x128, 0xf>(x0);
+    const float a1 = x1 + dpp_f<0x128, 0xf>(x1);
+    const float a2 = x2 + dpp_f<0x128, 0xf>(x2);
+    const float y0 = (lane & 8u) ? a1 : a0;         // lanes 0-7: o[rc], lanes 8-15: o[4 + rc]
+    // row_half_mirror adds lane 7 - l of the same half row: 4 partials
+    const float b0 = y0 + dpp_f<0x141, 0xf>(y0);
+    const float b2 = a2 + dpp_f<0x141, 0xf>(a2);
+    const float z = (lane & 4u) ? b2 : b0;          // quads: o[rc], o[8], o[4 + rc], o[8]
+    float t = z + dpp_f<0xb1, 0xf>(z);              // quad_perm [1,0,3,2]
+    t += dpp_f<0x4e, 0xf>(t);                       // quad_perm [2,3,0,1]
+    return t;
 }
 
 __device__ __forceinline__ int wave_max_i32(int x)
@@ -499,22 +511,29 @@ __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
     }
 }
 
-// Per-lane state of the backward walk of one pixel.
+// Per-lane state of the backward walk of one pixel.  The per-pixel sums the
+// backward needs, S_{i+1} = sum_{k>i} w_k c_k (colour, Eq. 13-14) and Alg. 1's
+// R_{i+1} = sum_{k>i} (ln w_k + 1) w_k + (ln T + 1) T (entropy, Eq. 15), only
+// ever enter dL/dalpha_i through Q_{i+1} = gh R_{i+1} - dL/dC . S_{i+1}, so one
+// running scalar carries both:
+//   dL/dalpha_i = T_i D_i + Q_{i+1} / (1 - alpha_i),
+//   D_i = dL/dC . c_i - gh (ln w_i + 1),   Q_i = Q_{i+1} - w_i D_i,
+// with gh = dL/dH of the pixel and Q_{N+1} = gh (ln T_final + 1) T_final.
 struct BwdPix {
     int32_t n;                       // list positions to walk (n_contrib)
     float T;                         // T_{i+1} while walking back; starts at T_final
-    float gCr, gCg, gCb, gh;         // dL/dC, dL/dH of this pixel
-    float Sr, Sg, Sb;                // S_{i+1} = sum_{k>i} w_k c_k
-    float Rs;                        // R_{i+1} of Alg. 1
+    float gCr, gCg, gCb;             // dL/dC of this pixel
+    float gh, ghl;                   // dL/dH of this pixel, and gh ln 2 (weights' logs are in log2 units)
+    float Q;                         // Q_{i+1}
     float fpx, fpy;
 };
 
-// Backward of list entry `pos` for one pixel.  Branch-free per lane: every
-// lane evaluates the entry and a lane whose pixel did not blend it (position
-// past its last contributor, or alpha < 1/255) contributes zero and keeps its
-// state.  bwd_alpha evaluates alpha; bwd_grad, run only if some lane of the
-// wavefront blended the entry, updates the walk state and returns the 9 per-pixel
-// terms whose sums over pixels give the entry's gradient:
+// Backward of one list entry for one pixel.  Branch-free per lane: every lane
+// evaluates the entry and a lane whose pixel did not blend it (position past its
+// last contributor, or alpha < 1/255) contributes zero and keeps its state.
+// bwd_alpha evaluates alpha; bwd_grad, run only if some lane of the wavefront
+// blended the entry, updates the walk state and returns the 9 per-pixel terms
+// whose sums over pixels give the entry's gradient:
 //   o[0] = e2 dg          (-> opacity; e2 = 2^p, dg = dL/dalpha in the unclamped branch)
 //   o[1] = o[0] dx,  o[2] = o[0] dy                     (-> mean, with the conic)
 //   o[3] = o[1] dx,  o[4] = o[1] dy,  o[5] = o[2] dy     (-> conic A, B, C)
@@ -526,7 +545,9 @@ struct BwdAlpha {
     bool act;
 };
 
-__device__ __forceinline__ BwdAlpha bwd_alpha(const BwdPix& q, int32_t pos, float4 g0, float4 g1)
+// j: the entry's index in the window, nrel = n - (the window's first list position),
+// both scaled by the same positive factor
+__device__ __forceinline__ BwdAlpha bwd_alpha(const BwdPix& q, int32_t j, int32_t nrel, float4 g0, float4 g1)
 {
     BwdAlpha r;
     r.dx = g0.x - q.fpx;
@@ -534,21 +555,19 @@ __device__ __forceinline__ BwdAlpha bwd_alpha(const BwdPix& q, int32_t pos, floa
     r.e2 = __builtin_amdgcn_exp2f(gauss_p2(g0.z, g0.w, g1.x, r.dx, r.dy));
     r.a_raw = g1.y * r.e2;
     r.alpha = fminf(kAlphaMax, r.a_raw);
-    r.act = (pos < q.n) & (r.alpha >= kAlphaMin);
+    r.act = (j < nrel) & (r.alpha >= kAlphaMin);
     return r;
 }
 
 __device__ __forceinline__ void bwd_grad(BwdPix& q, const BwdAlpha& r, float4 g1, float cb, float* o)
 {
     const bool act = r.act;
-    const float alpha = r.alpha;
-    const float rom = __builtin_amdgcn_rcpf(1.f - alpha);
+    const float rom = __builtin_amdgcn_rcpf(1.f - r.alpha);
     const float Ti = q.T * rom;                              // T_i = T_{i+1} / (1 - alpha_i)
-    const float w = alpha * Ti;
-    const float lw = kLn2 * __builtin_amdgcn_logf(act ? w : 1.f);   // ln w_i
-    // dC/dalpha_i = T_i c_i - S_{i+1} / (1 - alpha_i);  dH/dalpha_i by Eq. 15
-    float dal = q.gCr * (Ti * g1.z - q.Sr * rom) + q.gCg * (Ti * g1.w - q.Sg * rom) + q.gCb * (Ti * cb - q.Sb * rom);
-    dal += q.gh * ((-lw - 1.f) * Ti + q.Rs * rom);
+    const float w = r.alpha * Ti;
+    const float lw2 = __builtin_amdgcn_logf(act ? w : 1.f);  // log2 w_i
+    const float D = fmaf(-q.ghl, lw2, fmaf(q.gCr, g1.z, fmaf(q.gCg, g1.w, fmaf(q.gCb, cb, -q.gh))));
+    const float dal = rom * fmaf(q.T, D, q.Q);              // (T_{i+1} D_i + Q_{i+1}) / (1 - alpha_i)
     const float wa = act ? w : 0.f;
     const float dg = (act & (r.a_raw <= kAlphaMax)) ? dal : 0.f;   // zero in the clamped branch
     o[0] = r.e2 * dg;
@@ -560,10 +579,7 @@ __device__ __forceinline__ void bwd_grad(BwdPix& q, const BwdAlpha& r, float4 g1
     o[6] = wa * q.gCr;
     o[7] = wa * q.gCg;
     o[8] = wa * q.gCb;
-    q.Sr = fmaf(wa, g1.z, q.Sr);
-    q.Sg = fmaf(wa, g1.w, q.Sg);
-    q.Sb = fmaf(wa, cb, q.Sb);
-    q.Rs = fmaf(lw + 1.f, wa, q.Rs);                         // R_i = (log w_i + 1) w_i + R_{i+1}
+    q.Q = fmaf(-wa, D, q.Q);                                 // Q_i = Q_{i+1} - w_i D_i
     q.T = act ? Ti : q.T;
 }
 
@@ -602,8 +618,8 @@ __device__ __forceinline__ void bwd_init(const BlendBwdArgs& a, const BlockGeom&
             q.gh += a.grad_LE[g.view] / (float)((int64_t)c.W * c.H);
         }
     }
-    q.Sr = q.Sg = q.Sb = 0.f;
-    q.Rs = (logf(q.T) + 1.f) * q.T;                          // Alg. 1: R_{N+1} = (log T_final + 1) T_final
+    q.ghl = q.gh * kLn2;
+    q.Q = q.gh * ((logf(q.T) + 1.f) * q.T);                 // gh R_{N+1}, Alg. 1's initialisation
     q.fpx = (float)g.px + 0.5f;
     q.fpy = (float)g.py + 0.5f;
 }
@@ -614,19 +630,21 @@ template <int B, bool SHARED, bool PERSIST>
 __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
 {
     constexpr int NS = SHARED ? 1 : kWavesPerGroup;          // LDS slots
-    __shared__ float4 s_g0[NS][B];
-    __shared__ float4 s_g1[NS][B];
-    __shared__ float s_b[NS][B];
-    __shared__ float s_cull[NS][B];                     // L
+    // a window entry's record (3 float4, as in global memory) and, per wavefront, its
+    // accumulator row (the 9 wavefront sums, then 1 where the wavefront blended it)
+    __shared__ float4 s_rec[NS][B * kRecF4];
     __shared__ uint32_t s_e[NS][B];
-    __shared__ float s_acc[kWavesPerGroup][B * kG2];     // per-wavefront sums of each window entry
-    __shared__ uint32_t s_hit[NS][B];                   // some wavefront blended the entry
-    __shared__ int32_t s_idx[kWavesPerGroup][B];        // surviving window entries of each wavefront
+    __shared__ float s_acc[kWavesPerGroup][B * kAccF];   // per-wavefront sums of each window entry
+    // surviving window entries of each wavefront, as the offsets of their record
+    // (float4 index) and of their accumulator row (float index)
+    __shared__ int32_t s_idx[kWavesPerGroup][B];
+    __shared__ int32_t s_aidx[kWavesPerGroup][B];
     __shared__ int32_t s_max[kWavesPerGroup];
     __shared__ uint32_t s_item;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
     const uint32_t slot = SHARED ? 0u : wid;
     const uint32_t stamp = *a.stamp;
+    const int tcomp = tot_comp(lane);
     // work items: tiles (SHARED: one per workgroup; else one per wavefront), claimed from the per-XCD queues
     const uint32_t n_items = SHARED ? a.n_blocks / kWavesPerGroup : a.n_blocks;
     WaveQueue wq;
@@ -654,19 +672,17 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     const int32_t len = (int32_t)(rg.y - rg.x);
     BwdPix q;
     bwd_init(a, g, len, q);
-    const int32_t wave_n = wave_max_i32(q.n);
+    // wavefront-uniform loop bounds live in scalar registers
+    const int32_t wave_n = __builtin_amdgcn_readfirstlane(wave_max_i32(q.n));
     int32_t maxn = wave_n;
     if (SHARED) {
         if (lane == 0) s_max[wid] = wave_n;
         __syncthreads();
-        maxn = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+        maxn = __builtin_amdgcn_readfirstlane(max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3])));
     }
     const int32_t nthr = SHARED ? 256 : 64;
     const int32_t tid = SHARED ? (int32_t)threadIdx.x : (int32_t)lane;
-    for (int32_t i = (int32_t)lane; i < B * kG2; i += kWave) s_acc[wid][i] = 0.f;
-    for (int32_t i = tid; i < B; i += nthr) s_hit[slot][i] = 0u;
-    const bool row_lead = (lane & 15u) == 0u;
-    const int32_t rc = row_comp(lane >> 4);
+    for (int32_t i = (int32_t)lane; i < B * kAccF; i += kWave) s_acc[wid][i] = 0.f;
 
     // SHARED: each thread stages one entry of a window; its emission index and
     // record index (two dependent loads) are fetched one window ahead
@@ -692,12 +708,10 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
                 vg = a.emit_vg[e];
             }
             const float4* r = a.rec + (size_t)kRecF4 * vg;
-            const float4 r2 = r[2];
             s_e[slot][j] = e;
-            s_g0[slot][j] = r[0];
-            s_g1[slot][j] = r[1];
-            s_b[slot][j] = r2.x;
-            s_cull[slot][j] = r2.y;
+            s_rec[slot][kRecF4 * j + 0] = r[0];
+            s_rec[slot][kRecF4 * j + 1] = r[1];
+            s_rec[slot][kRecF4 * j + 2] = r[2];
         }
         if (SHARED) __syncthreads(); else wave_lds_sync();
         if (SHARED && lo > 0) {                                            // the next window's indices
@@ -714,31 +728,35 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
             const int32_t j = j0 + (int32_t)lane;
             bool keep = false;
             if (j < jtop) {
-                keep = !culled(g, s_g0[slot][j], s_g1[slot][j].x, s_cull[slot][j]);
+                const float4* r = &s_rec[slot][kRecF4 * j];
+                keep = !culled(g, r[0], r[1].x, r[2].y);
             }
             const uint64_t bal = __ballot(keep);
-            if (keep) s_idx[wid][m + (int32_t)__popcll(bal & ((1ull << lane) - 1ull))] = j;
+            if (keep) {
+                const int32_t k = m + (int32_t)__popcll(bal & ((1ull << lane) - 1ull));
+                s_idx[wid][k] = kRecF4 * j;
+                s_aidx[wid][k] = kAccF * j;
+            }
             m += (int32_t)__popcll(bal);
         }
         wave_lds_sync();
+        // window entries j < nrel lie in this pixel's list (compared as kRecF4 j, the
+        // entry's first float4 in s_rec)
+        const int32_t nrel = kRecF4 * (q.n - lo);
         // walk them back to front; per Gaussian, the wavefront sums go to this wavefront's slot
         for (int32_t kk = m - 1; kk >= 0; --kk) {
-            const int32_t j = s_idx[wid][kk];
-            const float4 g1 = s_g1[slot][j];
-            const BwdAlpha al = bwd_alpha(q, lo + j, s_g0[slot][j], g1);
+            const int32_t j3 = s_idx[wid][kk];
+            const float4* r = &s_rec[slot][j3];
+            const float4 g1 = r[1];
+            const BwdAlpha al = bwd_alpha(q, j3, nrel, r[0], g1);
             if (__ballot(al.act) != 0ull) {                  // else no lane of this wavefront blended it
                 float o[kG2];
-                bwd_grad(q, al, g1, s_b[slot][j], o);
-                float v0, v1, v2;
-                wave_sum9(o, v0, v1, v2);
-                if (row_lead) {
-                    float* dst = s_acc[wid] + j * kG2;
-                    dst[rc] = v0;
-                    dst[4 + rc] = v1;
-                    if (lane == 0u) {
-                        dst[8] = v2;
-                        s_hit[slot][j] = 1u;
-                    }
+                bwd_grad(q, al, g1, r[2].x, o);
+                const float tot = wave_sum9(o, lane);
+                if (tcomp >= 0) {
+                    float* acc = &s_acc[wid][s_aidx[wid][kk]];
+                    acc[tcomp] = tot;
+                    acc[kG2] = 1.f;                          // (every total's lane writes the same flag)
                 }
             }
         }
@@ -747,22 +765,24 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
         // summing the wavefront slots in a fixed order, and clear the slots;
         // entries no pixel blended keep no row (their stamp is not this frame's)
         for (int32_t j = tid; j < cnt; j += nthr) {
-            if (!s_hit[slot][j]) continue;
-            s_hit[slot][j] = 0u;
             constexpr int32_t nsl = SHARED ? kWavesPerGroup : 1;
             const int32_t s0 = SHARED ? 0 : (int32_t)wid;
+            bool hit = false;
+#pragma unroll
+            for (int32_t r = 0; r < nsl; ++r) hit |= s_acc[s0 + r][kAccF * j + kG2] != 0.f;
+            if (!hit) continue;
             float S[kG2], G[kG2];
 #pragma unroll
-            for (int k = 0; k < kG2; ++k) {
+            for (int k = 0; k < kG2 + 1; ++k) {
                 float v = 0.f;
 #pragma unroll
                 for (int32_t r = 0; r < nsl; ++r) {
-                    v += s_acc[s0 + r][j * kG2 + k];
-                    s_acc[s0 + r][j * kG2 + k] = 0.f;
+                    if (k < kG2) v += s_acc[s0 + r][kAccF * j + k];
+                    s_acc[s0 + r][kAccF * j + k] = 0.f;
                 }
-                S[k] = v;
+                if (k < kG2) S[k] = v;
             }
-            finish_row(S, s_g0[slot][j], s_g1[slot][j], G);
+            finish_row(S, s_rec[slot][kRecF4 * j], s_rec[slot][kRecF4 * j + 1], G);
             float* row = a.pair_grad + (size_t)kRowF * s_e[slot][j];
 #pragma unroll
             for (int k = 0; k < kG2; ++k) row[k] = G[k];
@@ -904,8 +924,7 @@ hipError_t launch_blend_bwd(const BlendBwdArgs& a, int lds_batch, hipStream_t s)
     switch (lds_batch) {
         case 32: return bwd_b<32>(a, s);
         case 64: return bwd_b<64>(a, s);
-        case 128:
-        case 256: return bwd_b<128>(a, s);      // the backward window is capped at 128 entries (LDS)
+        case 128: return bwd_b<128>(a, s);
     }
     return hipErrorInvalidValue;
 }

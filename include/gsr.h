@@ -195,6 +195,20 @@ gsr_status gsr_backward(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, cons
 gsr_status gsr_l1_loss(gsr_ctx* ctx, void* stream, const gsr_camera* cams, int32_t n_views, const float* rgb,
                        const float* target, float* grad_rgb, float* loss);
 
+/* gsr_l1_loss for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, the same kernels and bit-identical outputs, with the
+ * per-block partial sums in a static 1 MiB device array instead of memory the
+ * context allocates.  It calls no hipMalloc / hipFree; the array's device
+ * address is looked up once per device by gsr_create.  Limit: 131,071 L1
+ * blocks of 1,024 pixels over the views of the latest forward (each view's
+ * pixel count rounded up to whole blocks; 134,216,704 pixels in one view), else
+ * GSR_ERR_CAPACITY with nothing launched.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (different streams or threads)
+ * race, and must be serialised by the caller. */
+gsr_status gsr_l1_loss_noalloc(gsr_ctx* ctx, void* stream, const gsr_camera* cams, int32_t n_views, const float* rgb,
+                               const float* target, float* grad_rgb, float* loss);
+
 /* Opacity regulariser, the comparator of the entropy constraint in the
  * ablation of Sec. 4 (opacity vs entropy constraint): with sigma the
  * activated opacities (device, n floats),

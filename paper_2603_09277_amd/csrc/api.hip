@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,35 @@
 #include "internal.h"
 
 using namespace gsr;
+
+// Device memory of the allocation-free entry point (gsr_l1_loss_noalloc): the
+// per-block partial sums of the L1 kernels.  Each GPU the library runs on holds
+// its own copy for the life of the process; host code reaches it only through
+// the per-device address hipGetSymbolAddress returns (the array's name is a
+// host-side stand-in, not a device address).
+static constexpr size_t kScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's address of `scratch`, looked up once per device
+hipError_t scratch_address(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -60,6 +90,7 @@ struct gsr_ctx {
     uint64_t gen_fwd = 0, gen_bwd = 0;
     bool pair_cap_fixed = false;
 
+    void* scratch = nullptr;               // this device's static scratch array (gsr_l1_loss_noalloc)
     uint32_t* counters_host = nullptr;     // pinned: [0] total pairs, [1] overflow
     CamDev* cams_host = nullptr;           // pinned staging for graph replays
 
@@ -585,6 +616,11 @@ gsr_status gsr_create(gsr_ctx** out, int32_t max_views, int64_t pair_capacity)
     c->max_views = max_views;
     gsr_status s = GSR_OK;
     if (hipGetDevice(&c->device) != hipSuccess) s = GSR_ERR_HIP;
+    if (!s) {                                       // once per device: the address of its scratch array
+        void* p = nullptr;
+        if (scratch_address(c->device, &p) != hipSuccess) s = GSR_ERR_HIP;
+        c->scratch = p;
+    }
     if (!s) s = grow(c, c->cams, sizeof(CamDev) * (size_t)max_views);
     if (!s) s = grow(c, c->queues, 2 * kQueues * kQueueStride * 4);
     if (!s) s = grow(c, c->counters, 64, true);     // [4]: backward row stamp
@@ -1039,6 +1075,32 @@ gsr_status gsr_l1_loss(gsr_ctx* c, void* stream, const gsr_camera* cams, int32_t
     if (s) return s;
     HIP_TRY(c, launch_l1(rgb, target, (const CamDev*)c->cams.p, n_views, c->lay.n_l1, 1.0f, grad_rgb, loss,
                          (double*)c->l1_tmp.p, st));
+    return GSR_OK;
+}
+
+gsr_status gsr_l1_loss_noalloc(gsr_ctx* c, void* stream, const gsr_camera* cams, int32_t n_views, const float* rgb,
+                               const float* target, float* grad_rgb, float* loss)
+{
+    if (!c) return GSR_ERR_INVALID_ARG;
+    if (!cams || !rgb || !target) return fail(c, GSR_ERR_INVALID_ARG, "null l1 argument");
+    if (!c->have_frame || n_views != c->n_views) return fail(c, GSR_ERR_INVALID_ARG, "l1 views differ from the latest forward");
+    for (int v = 0; v < n_views; ++v)
+        if (cams[v].width != c->lay.cams[v].W || cams[v].height != c->lay.cams[v].H)
+            return fail(c, GSR_ERR_INVALID_ARG, "l1 camera sizes differ from the latest forward");
+    const size_t need = ((size_t)c->lay.n_l1 + 1) * sizeof(double);
+    if (need > kScratchBytes)
+        return fail(c, GSR_ERR_CAPACITY, "gsr_l1_loss_noalloc: " + std::to_string(c->lay.n_pix) + " pixels need " +
+                                             std::to_string(need) + " bytes of partial sums, more than its " +
+                                             std::to_string(kScratchBytes) + "-byte static scratch (" +
+                                             std::to_string((kScratchBytes / sizeof(double) - 1) * kL1Pix) +
+                                             " pixels at most); use gsr_l1_loss");
+    if (!c->scratch) return fail(c, GSR_ERR_HIP, "no static scratch address on this device");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    // every block overwrites its own partial sum before the per-view reduction reads it:
+    // nothing in the scratch needs clearing
+    HIP_TRY(c, launch_l1(rgb, target, (const CamDev*)c->cams.p, n_views, c->lay.n_l1, 1.0f, grad_rgb, loss,
+                         (double*)c->scratch, st));
     return GSR_OK;
 }
 

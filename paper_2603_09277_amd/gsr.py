@@ -72,7 +72,7 @@ EXPORTED = ["gsr_status_string", "gsr_last_error", "gsr_create", "gsr_destroy", 
             "gsr_forward", "gsr_render", "gsr_backward", "gsr_stats", "gsr_autotune", "gsr_inspect", "gsr_set_timing",
             "gsr_opacity_loss", "gsr_scale_reset", "gsr_pair_counts", "gsr_scaled_camera", "gsr_select_rmax",
             "gsr_dssim", "gsr_adam", "gsr_base_loss",
-            "gsr_stage_times", "gsr_l1_loss"]
+            "gsr_stage_times", "gsr_l1_loss", "gsr_l1_loss_noalloc"]
 
 _lib = None
 
@@ -101,6 +101,7 @@ def lib():
         L.gsr_stats.argtypes = [P, P, P, ctypes.POINTER(FrameStats)]
         L.gsr_set_timing.argtypes = [P, i32]
         L.gsr_l1_loss.argtypes = [P, P, P, i32, P, P, P, P]
+        L.gsr_l1_loss_noalloc.argtypes = [P, P, P, i32, P, P, P, P]
         L.gsr_stage_times.argtypes = [P, P, P, i32]
         L.gsr_autotune.argtypes = [P, P, ctypes.POINTER(Gaussians), P, i32, ctypes.POINTER(Opts), ctypes.c_char_p]
         L.gsr_inspect.argtypes = [P, P, ctypes.c_int, P, i64, ctypes.POINTER(i64)]
@@ -363,6 +364,17 @@ class Rasterizer:
         carr = make_cameras(cams)
         _check(self._ctx, lib().gsr_l1_loss(self._ctx, _stream(), carr, len(cams), _ptr(rgb), _ptr(target),
                                             _ptr(grad_rgb), _ptr(loss)))
+        return grad_rgb, loss
+
+    def l1_loss_noalloc(self, cams, rgb, target, grad_rgb: torch.Tensor, loss: torch.Tensor):
+        """gsr_l1_loss_noalloc: the L1 term into caller-provided grad_rgb [P, 3] and loss [V],
+        with the library allocating nothing (its partial sums live in a static device array)."""
+        for name, t in (("rgb", rgb), ("target", target), ("grad_rgb", grad_rgb), ("loss", loss)):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+        carr = make_cameras(cams)
+        _check(self._ctx, lib().gsr_l1_loss_noalloc(self._ctx, _stream(), carr, len(cams), _ptr(rgb), _ptr(target),
+                                                    _ptr(grad_rgb), _ptr(loss)))
         return grad_rgb, loss
 
     def set_timing(self, enable: bool, stages: Optional[Sequence[str]] = None):

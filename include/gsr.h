@@ -7,9 +7,9 @@
  *     (Sec. 3, Eq. 1-2),
  *   - tile-based front-to-back alpha blending (Sec. 3, Eq. 3-5),
  *   - the per-pixel entropy of the blending weights, background included,
- *     and its per-view mean (Sec. 3.3, Eq. 8-11),
+ *     and its per-view mean (Sec. 4.3, Eq. 8-11),
  *   - the gradient of L = L_base + gamma L_E with respect to every Gaussian
- *     attribute (Sec. 3.4, Eq. 12-15, Alg. 1, Suppl. B-C).
+ *     attribute (Sec. 4.4, Eq. 12-15, Alg. 1, Suppl. B-C).
  * L_base and gamma stay with the caller: the backward takes dL/dC per pixel,
  * dL/dH per pixel and dL/dL_E per view.
  *
@@ -177,7 +177,7 @@ gsr_status gsr_forward(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const
 gsr_status gsr_render(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
                       int32_t n_views, const gsr_opts* opts, float* rgb);
 
-/* Gradients of a loss of the forward outputs (Sec. 3.4, Eq. 13-15, Alg. 1,
+/* Gradients of a loss of the forward outputs (Sec. 4.4, Eq. 13-15, Alg. 1,
  * Suppl. C): grad_rgb [P][3] = dL/dC, grad_entropy [P] = dL/dH_j (may be
  * NULL), grad_entropy_mean [n_views] = dL/dL_E,v (device, may be NULL).
  * `saved` must be the gsr_fwd_out of the latest gsr_forward on this context
@@ -210,7 +210,7 @@ gsr_status gsr_l1_loss_noalloc(gsr_ctx* ctx, void* stream, const gsr_camera* cam
                                const float* target, float* grad_rgb, float* loss);
 
 /* Opacity regulariser, the comparator of the entropy constraint in the
- * ablation of Sec. 4 (opacity vs entropy constraint): with sigma the
+ * ablation of Sec. 5.4 (opacity vs entropy constraint): with sigma the
  * activated opacities (device, n floats),
  *   L_O = weight / n * sum_i exp(-(sigma_i - 0.5)^2 / 0.05),
  * grad_opacities[i] += dL_O/dsigma_i (device, accumulated, may be NULL) and
@@ -244,7 +244,7 @@ gsr_status gsr_base_loss(gsr_ctx* ctx, void* stream, const gsr_camera* cams, int
 gsr_status gsr_adam(gsr_ctx* ctx, void* stream, float* raw, float* m, float* v, float* act, const float* grad_act,
                     int64_t n, int32_t kind, float lr, float beta1, float beta2, float eps, int64_t step);
 
-/* Scale reset (Sec. 3.2, Eq. 7): scales[i][k] <- zeta * scales[i][k] in place
+/* Scale reset (Sec. 4.2, Eq. 7): scales[i][k] <- zeta * scales[i][k] in place
  * (device, n x 3 floats, zeta > 0); an optimiser's log-scales (device, n x 3,
  * may be NULL) get + log(zeta).  Asynchronous. */
 gsr_status gsr_scale_reset(gsr_ctx* ctx, void* stream, float* scales, float* log_scales, int64_t n, float zeta);
@@ -255,12 +255,12 @@ gsr_status gsr_scale_reset(gsr_ctx* ctx, void* stream, float* scales, float* log
 gsr_status gsr_pair_counts(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
                            int32_t n_views, const gsr_opts* opts, int64_t* pairs_per_view);
 
-/* The camera at downsampling factor r >= 1 (resolution scheduler, Sec. 4
+/* The camera at downsampling factor r >= 1 (resolution scheduler, Sec. 5.2
  * Implementation Details): width / r and height / r rounded down (at least 1),
  * fx, fy, cx, cy divided by r; pose and near plane unchanged. */
 gsr_camera gsr_scaled_camera(const gsr_camera* cam, int32_t r);
 
-/* r_max of the resolution scheduler (Sec. 4 Implementation Details): the
+/* r_max of the resolution scheduler (Sec. 5.2 Implementation Details): the
  * largest r in [1, r_cap] whose scaled camera keeps the mean per-tile list
  * length (pairs / tiles) at or below max_mean_len (the paper: about 150, with
  * r capped at 4); 1 if none does.  mean_len (host, r_cap doubles, may be NULL)

@@ -12,15 +12,15 @@
  *   - 3D density and covariance Sigma = R S S^T R^T          (Sec. 3, Eq. 1)
  *   - EWA projection to a 2D mean and covariance              (Sec. 3, Eq. 2)
  *   - alpha = opacity * g, transmittance, blended colour      (Sec. 3, Eq. 3-5)
- *   - blending weights, their sum with the background is one  (Sec. 3.3, Eq. 8-9;
+ *   - blending weights, their sum with the background is one  (Sec. 4.3, Eq. 8-9;
  *                                                              Suppl. A)
- *   - per-pixel entropy and its mean over pixels              (Sec. 3.3, Eq. 10-12)
- *   - dH/dalpha via the suffix variable R                     (Sec. 3.4, Eq. 13-15,
+ *   - per-pixel entropy and its mean over pixels              (Sec. 4.3, Eq. 10-12)
+ *   - dH/dalpha via the suffix variable R                     (Sec. 4.4, Eq. 13-15,
  *                                                              Alg. 1; Suppl. B)
  *   - attribute chain opacity / exponent / conic / 2D mean    (Suppl. C)
- *   - scale reset s <- zeta s                                 (Sec. 3.2, Eq. 7)
+ *   - scale reset s <- zeta s                                 (Sec. 4.2, Eq. 7)
  *   - the opacity regulariser compared against the entropy
- *     constraint, exp(-(sigma - 0.5)^2 / 0.05) per Gaussian   (Sec. 4, ablation)
+ *     constraint, exp(-(sigma - 0.5)^2 / 0.05) per Gaussian   (Sec. 5.4, ablation)
  *   - D-SSIM of the base loss and one Adam step               (Sec. 3, Eq. 6)
  * Conventions the paper leaves open (dilation 0.3, Jacobian clamp 1.3,
  * near plane, alpha clamp 0.99, 1/255 skip, 1e-4 transmittance stop, SH
@@ -752,7 +752,7 @@ int orc_backward_project(int64_t n, const float* means, const float* scales, con
     return 0;
 }
 
-/* Opacity regulariser of the ablation in Sec. 4: L_O = w / n * sum_i
+/* Opacity regulariser of the ablation in Sec. 5.4: L_O = w / n * sum_i
  * exp(-(sigma_i - 0.5)^2 / 0.05).  Adds dL_O/dsigma_i to grad (may be NULL)
  * and returns L_O. */
 double orc_opacity_loss(int64_t n, const float* opac, double w, double* grad)
@@ -768,7 +768,7 @@ double orc_opacity_loss(int64_t n, const float* opac, double w, double* grad)
     return w * sum / (double)n;
 }
 
-/* Scale reset (Sec. 3.2, Eq. 7): every scale multiplied by zeta, the product
+/* Scale reset (Sec. 4.2, Eq. 7): every scale multiplied by zeta, the product
  * rounded once to float32. */
 void orc_scale_reset(int64_t n, float* scales, double zeta)
 {

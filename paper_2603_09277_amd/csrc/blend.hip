@@ -1,6 +1,6 @@
 // Front-to-back alpha blending with the entropy of the blending weights
-// (Sec. 3, Eq. 3-5; Sec. 3.3, Eq. 8-11) and the back-to-front backward with
-// the O(N) entropy gradient of Alg. 1 (Sec. 3.4, Eq. 13-15; Suppl. C).
+// (Sec. 3, Eq. 3-5; Sec. 4.3, Eq. 8-11) and the back-to-front backward with
+// the O(N) entropy gradient of Alg. 1 (Sec. 4.4, Eq. 13-15; Suppl. C).
 //
 // Work decomposition.  Every 64-lane wavefront owns one 8x8 pixel block (one
 // pixel per lane) and walks the Gaussian list of the tile that contains it.

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kL1Block) void l1_reduce_kernel(const double* block
     if (threadIdx.x == 0) loss[v] = (float)((double)weight * tot / (3.0 * (double)((int64_t)c.W * c.H)));
 }
 
-// Opacity regulariser of the comparison in Sec. 4 (ablation, opacity vs entropy
+// Opacity regulariser of the comparison in Sec. 5.4 (ablation, opacity vs entropy
 // constraint): L_O = w / n * sum_i exp(-(sigma_i - 0.5)^2 / 0.05), pushing
 // opacities toward 0 or 1.  dL_O/dsigma_i = w / n * e_i * (-2 (sigma_i - 0.5) / 0.05)
 // is added to grad[i].  Block partial sums in FP64, summed in a fixed order.
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kL1Block) void opacity_reg_reduce_kernel(const doub
     if (threadIdx.x == 0) *loss = (float)((double)w * tot / (double)n);
 }
 
-// Scale reset (Sec. 3.2, Eq. 7): s <- zeta * s for every scale component, and
+// Scale reset (Sec. 4.2, Eq. 7): s <- zeta * s for every scale component, and
 // log s <- log s + log zeta for an optimiser's log-scales (may be null).
 __global__ void scale_reset_kernel(float* s, float* log_s, int64_t count, float zeta, float log_zeta)
 {

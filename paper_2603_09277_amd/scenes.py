@@ -6,7 +6,7 @@ oracle consume what it returns, so the two sides always see identical bits.
 
 Workload recipe (the paper measures on Mip-NeRF 360 / Tanks & Temples / Deep
 Blending, which are not available; these seeded scenes stand in for them with
-the Gaussian counts the paper trains at, Sec. 4 and Tab. 1, 0.4M-3.3M):
+the Gaussian counts the paper trains at, Sec. 5.3 and Tab. 1, 0.4M-3.3M):
 
 * ``tiny``      2,000 Gaussians in front of one 128x128 pinhole camera, SH
                 degree 0 with colours uniform in [0, 1].

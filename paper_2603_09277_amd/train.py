@@ -10,11 +10,11 @@ This module only orders those calls and keeps the optimiser state.
 
 Loss (Sec. 3, Eq. 6 and 12):  L = (1 - lambda) L1 + lambda L_D-SSIM + gamma L_E,
 with the entropy term on every other epoch of each scale-reset period and the
-scale reset s <- zeta s every `reset_every` epochs (Sec. 3.2, Eq. 7; Sec. 4,
+scale reset s <- zeta s every `reset_every` epochs (Sec. 4.2, Eq. 7; Sec. 5.2,
 Implementation Details).  The resolution scheduler trains coarse to fine:
 the downsampling factor falls linearly from r_max to 1 over the first
 `coarse_frac` of the iterations, r_max being the largest r <= 4 that keeps the
-mean per-tile list length under `max_list_len` (Sec. 4).  No densification:
+mean per-tile list length under `max_list_len` (Sec. 5.2).  No densification:
 the Gaussian count is fixed, as in the paper's fixed-budget comparisons.
 
 The held-out "teacher" scene is drawn with the bench generator; the student
@@ -43,14 +43,14 @@ class TrainConfig:
     width: int = 648
     height: int = 432
     iterations: int = 600
-    epochs: int = 150              # the schedule is laid out in epochs (Sec. 4: 150 epochs)
+    epochs: int = 150              # the schedule is laid out in epochs (Sec. 5.2: 150 epochs)
     epoch_views: int = 0           # images per epoch, sampled with replacement; 0: iterations // epochs
     lam: float = 0.2               # D-SSIM weight, Eq. 6
     gamma: float = 0.015           # entropy weight, Eq. 12
-    regulariser: str = "entropy"   # "entropy" (Eq. 12), "opacity" (the Sec. 4 comparator) or "none"
-    opacity_weight: float = 3.0    # weight of the opacity regulariser in the Sec. 4 comparison
+    regulariser: str = "entropy"   # "entropy" (Eq. 12), "opacity" (the Sec. 5.4 comparator) or "none"
+    opacity_weight: float = 3.0    # weight of the opacity regulariser in the Sec. 5.4 comparison
     zeta: float = 0.2              # scale-reset factor, Eq. 7
-    reset_every: int = 20          # epochs between scale resets (Sec. 4)
+    reset_every: int = 20          # epochs between scale resets (Sec. 5.2)
     r_cap: int = 4
     max_list_len: float = 150.0
     coarse_frac: float = 0.3

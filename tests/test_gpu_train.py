@@ -205,7 +205,7 @@ def test_training_run_learns_and_is_deterministic():
 
 
 def test_training_with_opacity_regulariser_adds_its_gradient():
-    """The comparator of the Sec. 4 ablation: on an epoch where the regulariser is on, the
+    """The comparator of the Sec. 5.4 ablation: on an epoch where the regulariser is on, the
     opacity gradient of the step is the image and entropy-free gradient plus dL_O/dsigma
     (weight 3.0, mean over Gaussians) at the step's opacities."""
     if not torch.cuda.is_available():
@@ -239,7 +239,7 @@ def test_training_with_opacity_regulariser_adds_its_gradient():
 
 @pytest.mark.parametrize("reg", ["opacity", "none"])
 def test_training_run_with_other_regularisers(reg):
-    """The comparator runs of the Sec. 4 ablation: the opacity regulariser in place of the
+    """The comparator runs of the Sec. 5.4 ablation: the opacity regulariser in place of the
     entropy term (its gradient is added to the opacity gradient), or no regulariser."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

@@ -91,6 +91,10 @@ typedef struct {
                                     frame grows the capacity when a count came within 10 % of it (a frame
                                     past it is flagged as an overflow, see gsr_stats); stage timing works;
                                     ignored with GSR_GRAPH, which never synchronises either */
+#define GSR_DEBUG_INVARIANTS 64u /* after each forward, check Eq. 9 (Sec. 4.3; Suppl. A) per pixel: the weights
+                                    of the blended Gaussians plus T_final sum to one, by an independent walk of
+                                    every pixel's list (debug speed); gsr_stats reports the largest error and
+                                    the pixels past the FP32 bound 4u (n_contrib + 1), u = 2^-24 */
 #define GSR_DEFAULT_FLAGS  (GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP)
 
 typedef struct {
@@ -186,6 +190,18 @@ gsr_status gsr_backward(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, cons
                         int32_t n_views, const gsr_opts* opts, const gsr_fwd_out* saved,
                         const float* grad_rgb, const float* grad_entropy, const float* grad_entropy_mean,
                         gsr_grads* grads);
+
+/* gsr_backward with the opacity regulariser of the Sec. 5.4 ablation (the
+ * comparator of the entropy constraint) fused into the projection backward:
+ * grads->opacities also receives dL_O/dsigma_i of
+ *   L_O = opacity_weight / n * sum_i exp(-(sigma_i - 0.5)^2 / 0.05)
+ * (bit-identical to gsr_backward followed by gsr_opacity_loss with the same
+ * weight), and *opacity_loss (device float, may be NULL) receives L_O, summed
+ * in a fixed order.  opacity_weight = 0 and opacity_loss = NULL is gsr_backward. */
+gsr_status gsr_backward_opacity_reg(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
+                                    int32_t n_views, const gsr_opts* opts, const gsr_fwd_out* saved,
+                                    const float* grad_rgb, const float* grad_entropy, const float* grad_entropy_mean,
+                                    float opacity_weight, float* opacity_loss, gsr_grads* grads);
 
 /* L1 term of the base loss (Sec. 3, Eq. 6 with lambda = 0) on the packed
  * images of the latest forward's cameras (cams must have the same sizes):
@@ -288,6 +304,9 @@ typedef struct {
                                   (the others cannot reach 1/255 at any pixel of the block) */
     int64_t tested_bwd;        /* alpha tests the backward makes: surviving positions up to each
                                   pixel's last contributor (a subset of evals_bwd) */
+    double invariant_max_err;  /* GSR_DEBUG_INVARIANTS: max over pixels of |sum w + T_final - 1| (Eq. 9);
+                                  -1 if the forward did not check */
+    int64_t invariant_violations; /* pixels whose error exceeds 4u (n_contrib + 1); -1 if not checked */
 } gsr_frame_stats;
 
 /* Fills `out` (host) and pairs_per_view [n_views] (host, may be NULL) for

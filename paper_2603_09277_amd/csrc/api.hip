@@ -110,6 +110,8 @@ struct gsr_ctx {
     FrameKey key_fwd, key_bwd;
     const float* key_bwd_grads[3] = {};
     void* key_bwd_outs[5] = {};
+    float key_bwd_reg_w = 0.f;
+    float* key_bwd_reg_loss = nullptr;
     hipEvent_t ev_replay = nullptr;
     bool nosync_count = false;             // counters_host holds the latest GSR_NO_SYNC frame's pair count
     bool capturing = false;                // a graph capture is recording (no stage events)
@@ -234,7 +236,8 @@ gsr_status validate(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cams, 
     if (!tile_ok(o->tile_w, o->tile_h)) return fail(c, GSR_ERR_UNSUPPORTED, "tile shape must be 8x8, 16x16 or 32x8");
     int lb = o->lds_batch == 0 ? 64 : o->lds_batch;
     if (lb != 32 && lb != 64 && lb != 128 && lb != 256) return fail(c, GSR_ERR_UNSUPPORTED, "lds_batch must be 32, 64, 128 or 256");
-    if (o->flags & ~(uint32_t)(GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP | GSR_GRAPH | GSR_PERSISTENT | GSR_NO_SYNC))
+    if (o->flags & ~(uint32_t)(GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP | GSR_GRAPH | GSR_PERSISTENT | GSR_NO_SYNC |
+                               GSR_DEBUG_INVARIANTS))
         return fail(c, GSR_ERR_INVALID_ARG, "unknown flag bits");
     uint64_t tiles = 0;
     for (int v = 0; v < n_views; ++v) {
@@ -464,6 +467,16 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
         HIP_TRY(c, launch_entropy_mean((const float*)c->block_H.p, dc, (int)V, L.n_hchunks, (double*)c->hchunk.p,
                                        out->entropy_mean, st));
     }
+    if (!render_only && (o->flags & GSR_DEBUG_INVARIANTS)) {    // Eq. 9 per pixel, reported by gsr_stats
+        HIP_TRY(c, launch_fill_u32(counters + 6, 0u, 2, st));
+        HIP_TRY(c, launch_fill_u32(counters + 8, 1u, 1, st));
+        InvArgs ia;
+        ia.rec = (const float4*)c->rec.p; ia.pair_vals = pv[sb]; ia.emit_vg = (const uint32_t*)c->emit_vg.p;
+        ia.ranges = (const uint2*)c->ranges.p; ia.cams = dc; ia.n_views = (int32_t)V;
+        ia.tile_shift_x = L.tsx; ia.tile_shift_y = L.tsy; ia.n_pix = L.n_pix;
+        ia.T_final = out->t_final; ia.n_contrib = out->n_contrib; ia.counters = counters;
+        HIP_TRY(c, launch_invariants(ia, st));
+    }
     c->sorted_buf = sb;
     c->pairs = plain ? cap : 0;
     c->pair_cap_used = cap;
@@ -472,7 +485,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
 
 gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, const gsr_opts* o,
                             const gsr_fwd_out* saved, const float* grad_rgb, const float* grad_H, const float* grad_LE,
-                            gsr_grads* gr)
+                            gsr_grads* gr, float reg_w = 0.f, float* reg_loss = nullptr)
 {
     const Layout& L = c->lay;
     const uint32_t n = (uint32_t)g->n, V = (uint32_t)L.cams.size(), vn = n * V;
@@ -516,7 +529,11 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     pa.rec_stamp = (const uint32_t*)c->rec_stamp.p; pa.stamp = (const uint32_t*)c->counters.p + 4;
     pa.g_means = gr->means; pa.g_scales = gr->scales; pa.g_quats = gr->quats; pa.g_opac = gr->opacities;
     pa.g_sh = gr->sh;
+    pa.reg_w = reg_w;
+    pa.reg_partial = (reg_loss && n > 0) ? (double*)c->reg_tmp.p : nullptr;
     HIP_TRY(c, launch_project_bwd(pa, o->sh_degree, o->sh_dtype == 1, st));
+    if (pa.reg_partial)
+        HIP_TRY(c, launch_opacity_reg_reduce(pa.reg_partial, 4u * ((n + 255u) / 256u), n, reg_w, reg_loss, st));
     return GSR_OK;
 }
 
@@ -797,12 +814,15 @@ gsr_status gsr_render(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gs
     return GSR_OK;
 }
 
-gsr_status gsr_backward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gsr_camera* cams, int32_t n_views,
-                        const gsr_opts* o, const gsr_fwd_out* saved, const float* grad_rgb, const float* grad_entropy,
-                        const float* grad_entropy_mean, gsr_grads* gr)
+static gsr_status backward_impl(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
+                                int32_t n_views, const gsr_opts* o, const gsr_fwd_out* saved, const float* grad_rgb,
+                                const float* grad_entropy, const float* grad_entropy_mean, float reg_w, float* reg_loss,
+                                gsr_grads* gr)
 {
     gsr_status s = validate(c, g, cams, n_views, o);
     if (s) return s;
+    if (!std::isfinite(reg_w)) return fail(c, GSR_ERR_INVALID_ARG, "opacity regulariser weight not finite");
+    if (reg_loss && g->n > 0 && (s = grow(c, c->reg_tmp, (size_t)((g->n + 255) / 256) * 4 * sizeof(double)))) return s;
     if (!saved || !saved->t_final || !saved->n_contrib || !grad_rgb || !gr)
         return fail(c, GSR_ERR_INVALID_ARG, "null backward argument");
     if (g->n > 0 && (!gr->means || !gr->scales || !gr->quats || !gr->opacities || !gr->sh))
@@ -818,7 +838,7 @@ gsr_status gsr_backward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
     if (!(o->flags & GSR_GRAPH))
-        return enqueue_backward(c, st, g, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, gr);
+        return enqueue_backward(c, st, g, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, gr, reg_w, reg_loss);
 
     // a replayed forward ran at a fixed pair capacity: its pair count comes back with it,
     // and a frame whose lists did not fit (truncated lists) gets no gradients
@@ -833,7 +853,8 @@ gsr_status gsr_backward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
     void* gouts[5] = { gr->means, gr->scales, gr->quats, gr->opacities, gr->sh };
     bool same = c->gexec_bwd && k == c->key_bwd && c->gen == c->gen_bwd && c->key_bwd_grads[0] == grad_rgb &&
                 c->key_bwd_grads[1] == grad_entropy && c->key_bwd_grads[2] == grad_entropy_mean &&
-                std::memcmp(gouts, c->key_bwd_outs, sizeof gouts) == 0;
+                std::memcmp(gouts, c->key_bwd_outs, sizeof gouts) == 0 && c->key_bwd_reg_w == reg_w &&
+                c->key_bwd_reg_loss == reg_loss;
     if (!same) {
         if (c->gexec_bwd) { (void)hipGraphExecDestroy(c->gexec_bwd); c->gexec_bwd = nullptr; }
         hipStream_t cs;
@@ -842,7 +863,8 @@ gsr_status gsr_backward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             c->capturing = true;
-            gsr_status bs = enqueue_backward(c, cs, g, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, gr);
+            gsr_status bs = enqueue_backward(c, cs, g, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, gr, reg_w,
+                                             reg_loss);
             c->capturing = false;
             hipError_t e2 = hipStreamEndCapture(cs, &graph_);
             e = bs != GSR_OK ? hipErrorUnknown : e2;
@@ -858,9 +880,28 @@ gsr_status gsr_backward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
         c->gen_bwd = c->gen;
         c->key_bwd_grads[0] = grad_rgb; c->key_bwd_grads[1] = grad_entropy; c->key_bwd_grads[2] = grad_entropy_mean;
         std::memcpy(c->key_bwd_outs, gouts, sizeof gouts);
+        c->key_bwd_reg_w = reg_w;
+        c->key_bwd_reg_loss = reg_loss;
     }
     HIP_TRY(c, hipGraphLaunch(c->gexec_bwd, st));
     return GSR_OK;
+}
+
+gsr_status gsr_backward(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gsr_camera* cams, int32_t n_views,
+                        const gsr_opts* o, const gsr_fwd_out* saved, const float* grad_rgb, const float* grad_entropy,
+                        const float* grad_entropy_mean, gsr_grads* gr)
+{
+    return backward_impl(c, stream, g, cams, n_views, o, saved, grad_rgb, grad_entropy, grad_entropy_mean, 0.f, nullptr,
+                         gr);
+}
+
+gsr_status gsr_backward_opacity_reg(gsr_ctx* c, void* stream, const gsr_gaussians* g, const gsr_camera* cams,
+                                    int32_t n_views, const gsr_opts* o, const gsr_fwd_out* saved, const float* grad_rgb,
+                                    const float* grad_entropy, const float* grad_entropy_mean, float opacity_weight,
+                                    float* opacity_loss, gsr_grads* gr)
+{
+    return backward_impl(c, stream, g, cams, n_views, o, saved, grad_rgb, grad_entropy, grad_entropy_mean,
+                         opacity_weight, opacity_loss, gr);
 }
 
 gsr_status gsr_stats(gsr_ctx* c, void* stream, int64_t* pairs_per_view, gsr_frame_stats* out)
@@ -872,9 +913,9 @@ gsr_status gsr_stats(gsr_ctx* c, void* stream, int64_t* pairs_per_view, gsr_fram
     const uint32_t nt = c->lay.n_tiles;
     std::vector<uint32_t> rg((size_t)nt * 2 + 2);
     std::vector<uint32_t> cnt2((size_t)c->lay.n_blocks * 8 + 8);
-    uint32_t cnt[2];
+    uint32_t cnt[16];
     if (nt) HIP_TRY(c, hipMemcpyAsync(rg.data(), c->ranges.p, (size_t)nt * 8, hipMemcpyDeviceToHost, st));
-    HIP_TRY(c, hipMemcpyAsync(cnt, c->counters.p, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(cnt, c->counters.p, sizeof cnt, hipMemcpyDeviceToHost, st));
     if (c->lay.n_blocks)
         HIP_TRY(c, hipMemcpyAsync(cnt2.data(), c->block_cnt.p, (size_t)c->lay.n_blocks * 32, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
@@ -911,6 +952,15 @@ gsr_status gsr_stats(gsr_ctx* c, void* stream, int64_t* pairs_per_view, gsr_fram
         out->tested_bwd += cnt2[8 * b + 5];
     }
     c->pairs = std::min<size_t>(cnt[0], c->pair_cap);     // pairs held (a fixed capacity may have overflowed)
+    if (cnt[8]) {
+        float e;
+        std::memcpy(&e, &cnt[6], 4);
+        out->invariant_max_err = (double)e;
+        out->invariant_violations = (int64_t)cnt[7];
+    } else {
+        out->invariant_max_err = -1.0;
+        out->invariant_violations = -1;
+    }
     return GSR_OK;
 }
 

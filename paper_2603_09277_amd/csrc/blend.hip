@@ -793,6 +793,53 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     }
 }
 
+// Debug check of Eq. 9 (GSR_DEBUG_INVARIANTS): the weights of the blended Gaussians and
+// the background weight T_final sum to one.  An independent per-pixel walk: one thread
+// per pixel re-evaluates its tile's list from the front, with the forward's alpha
+// arithmetic, sums the weights of the entries it blends up to the forward's n_contrib,
+// and compares sum w + T_final (the forward's) with 1.  Each blended step rounds w and T
+// within 2u T_i and the running sum within u per add, so |sum w + T - 1| <= 3u n_contrib;
+// the check counts pixels beyond 4u (n_contrib + 1).  Debug speed: uncoalesced walks.
+__global__ __launch_bounds__(256) void invariant_kernel(InvArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;   // packed pixel index
+    float err = 0.f;
+    bool bad = false;
+    if (p < a.n_pix) {
+        int v = 0;
+        while (v + 1 < a.n_views && a.cams[v + 1].pix_base <= p) ++v;
+        const CamDev& c = a.cams[v];
+        const int64_t q = p - c.pix_base;
+        const int px = (int)(q % c.W), py = (int)(q / c.W);
+        const uint32_t tile = c.tile_base + (uint32_t)((py >> a.tile_shift_y) * c.gx + (px >> a.tile_shift_x));
+        const uint2 rg = a.ranges[tile];
+        int32_t n = a.n_contrib[p];
+        n = n < 0 ? 0 : (n > (int32_t)(rg.y - rg.x) ? (int32_t)(rg.y - rg.x) : n);
+        const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+        float T = 1.f, S = 0.f;
+        for (int32_t i = 0; i < n; ++i) {
+            const float4* r = a.rec + (size_t)kRecF4 * a.emit_vg[a.pair_vals[rg.x + (uint32_t)i]];
+            const float4 g0 = r[0], g1 = r[1];
+            const float alpha =
+                fminf(kAlphaMax, g1.y * __builtin_amdgcn_exp2f(gauss_p2(g0.z, g0.w, g1.x, g0.x - fpx, g0.y - fpy)));
+            if (alpha < kAlphaMin) continue;
+            S = fmaf(alpha, T, S);
+            T *= 1.f - alpha;
+        }
+        err = fabsf(S + a.T_final[p] - 1.f);
+        bad = !(err <= 4.f * 5.9604645e-8f * (float)(n + 1));     // NaN counts as a violation
+        if (!(err == err)) err = __uint_as_float(0x7f800000u);      // reported as +inf
+    }
+    const uint32_t nbad = (uint32_t)__popcll(__ballot(bad));
+    float m = err;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63u) == 0u) {
+        if (nbad) atomicAdd(&a.counters[7], nbad);
+        atomicMax(&a.counters[6], __float_as_uint(m));           // non-negative floats order as their bits
+    }
+}
+
 __device__ __forceinline__ double block_sum_f64(double x)
 {
     __shared__ double s[256];
@@ -927,6 +974,14 @@ hipError_t launch_blend_bwd(const BlendBwdArgs& a, int lds_batch, hipStream_t s)
         case 128: return bwd_b<128>(a, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_invariants(const InvArgs& a, hipStream_t s)
+{
+    if (a.n_pix <= 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)((a.n_pix + 255) / 256);
+    hipLaunchKernelGGL(invariant_kernel, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_entropy_mean(const float* block_H, const CamDev* cams, int n_views, uint32_t n_chunks,

@@ -99,6 +99,12 @@ struct ProjectBwdArgs {
     float* g_quats;
     float* g_opac;
     void* g_sh;
+    // opacity regulariser fused into the projection backward (0 / null: none): g_opac also
+    // gets dL_O/dsigma of L_O = reg_w / n sum exp(-(sigma - 0.5)^2 / 0.05), and, if reg_partial
+    // is set, every wavefront writes the sum of its Gaussians' exp terms (FP64) to
+    // reg_partial[4 * block + wavefront]
+    float reg_w;
+    double* reg_partial;
 };
 
 struct BlendFwdArgs {
@@ -144,6 +150,22 @@ struct BlendBwdArgs {
     const uint32_t* stamp;                // this frame's row stamp
     uint32_t* queues;                     // persistent mode: kQueues heads kQueueStride words apart, zeroed; or null
     const uint32_t* tile_order;           // [n_tiles] tiles, longest list first (hardware dispatch); or null
+};
+
+// Debug check of Eq. 9 after a forward (GSR_DEBUG_INVARIANTS): per pixel, the sum of
+// the blending weights plus the final transmittance equals one.
+struct InvArgs {
+    const float4* rec;
+    const uint32_t* pair_vals;
+    const uint32_t* emit_vg;
+    const uint2* ranges;
+    const CamDev* cams;
+    int32_t n_views;
+    int32_t tile_shift_x, tile_shift_y;
+    int64_t n_pix;
+    const float* T_final;
+    const int32_t* n_contrib;
+    uint32_t* counters;                   // [6] max |sum w + T - 1| (float bits), [7] pixels past the bound
 };
 
 // ---- launchers (return hipError_t of the launch) ----
@@ -200,12 +222,16 @@ hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t 
 
 hipError_t launch_blend_fwd(const BlendFwdArgs& a, int lds_batch, hipStream_t s);
 hipError_t launch_blend_bwd(const BlendBwdArgs& a, int lds_batch, hipStream_t s);
+hipError_t launch_invariants(const InvArgs& a, hipStream_t s);
 // n_l1_blocks = sum over views of ceil(W H / kL1Block); tmp holds n_l1_blocks doubles
 // L_O = w / n * sum exp(-(sigma - 0.5)^2 / 0.05); grad[i] += dL_O/dsigma_i (grad may be null);
 // *loss (device, may be null); tmp holds opacity_reg_tmp_words(n) doubles
 size_t opacity_reg_tmp_words(int64_t n);
 hipError_t launch_opacity_reg(const float* opac, int64_t n, float w, float* grad, float* loss, double* tmp,
                               hipStream_t s);
+// L_O = w / n * sum of the n_partial FP64 partial sums, in a fixed order -> *loss
+hipError_t launch_opacity_reg_reduce(const double* partial, uint32_t n_partial, int64_t n, float w, float* loss,
+                                     hipStream_t s);
 // D-SSIM of one view: loss (device, may be null) = weight (1 - SSIM(x, y)); grad (may be null)
 // += dloss/dx; x, y, grad [W*H][3]; tmp holds ssim_tmp_bytes(W*H) bytes
 size_t ssim_tmp_bytes(int64_t M);

@@ -145,6 +145,14 @@ hipError_t launch_opacity_reg(const float* opac, int64_t n, float w, float* grad
     return hipGetLastError();
 }
 
+hipError_t launch_opacity_reg_reduce(const double* partial, uint32_t n_partial, int64_t n, float w, float* loss,
+                                     hipStream_t s)
+{
+    if (n <= 0 || !loss) return hipSuccess;
+    hipLaunchKernelGGL(opacity_reg_reduce_kernel, dim3(1), dim3(kL1Block), 0, s, partial, n_partial, n, w, loss);
+    return hipGetLastError();
+}
+
 hipError_t launch_scale_reset(float* scales, float* log_scales, int64_t count, float zeta, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;

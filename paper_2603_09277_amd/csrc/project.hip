@@ -325,6 +325,18 @@ __global__ __launch_bounds__(256, ONE ? 3 : 1) void project_bwd_kernel(ProjectBw
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
     uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (a.reg_partial) {
+        // the opacity regulariser's loss (Sec. 5.4 ablation): per-wavefront FP64 sums of
+        // exp(-(sigma - 0.5)^2 / 0.05), in a fixed order, for a fixed-order final sum
+        double e = 0.0;
+        if (i < a.n) {
+            const float d = a.opac[i] - 0.5f;
+            e = (double)expf(-(d * d) * 20.0f);              // 1 / 0.05 = 20
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+        if ((threadIdx.x & 63u) == 0u) a.reg_partial[4u * blockIdx.x + (threadIdx.x >> 6)] = e;
+    }
     if (i >= a.n) return;
     float mu[3] = { a.means[3 * (size_t)i], a.means[3 * (size_t)i + 1], a.means[3 * (size_t)i + 2] };
     float s[3] = { a.scales[3 * (size_t)i], a.scales[3 * (size_t)i + 1], a.scales[3 * (size_t)i + 2] };
@@ -476,7 +488,15 @@ __global__ __launch_bounds__(256, ONE ? 3 : 1) void project_bwd_kernel(ProjectBw
     a.g_quats[4 * (size_t)i + 1] = any ? (gx - x * qd) * iq : 0.f;
     a.g_quats[4 * (size_t)i + 2] = any ? (gy - y * qd) * iq : 0.f;
     a.g_quats[4 * (size_t)i + 3] = any ? (gz - z * qd) * iq : 0.f;
-    a.g_opac[i] = any ? gop : 0.f;
+    {
+        float go = any ? gop : 0.f;
+        if (a.reg_w != 0.f) {                                // + dL_O/dsigma, as a separate pass would add it
+            const float d = op - 0.5f;
+            const float e = expf(-(d * d) * 20.0f);
+            go += (a.reg_w / (float)a.n) * e * (-40.0f * d);
+        }
+        a.g_opac[i] = go;
+    }
     if constexpr (BF16) {
         uint16_t* p = reinterpret_cast<uint16_t*>(a.g_sh) + (size_t)i * (K * 3);
         if constexpr ((K * 3) % 8 == 0) {                    // eight values a 16-byte store

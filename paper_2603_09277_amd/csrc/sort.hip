@@ -778,6 +778,7 @@ __global__ void frame_begin_kernel(uint32_t* counters, uint32_t* ranges, uint32_
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         counters[0] = 0u;
         counters[1] = 0u;
+        counters[8] = 0u;                     // set when this frame's invariants are checked
         atomicAdd(&counters[4], 1u);
     }
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += gridDim.x * blockDim.x) ranges[i] = 0u;

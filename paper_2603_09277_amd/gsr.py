@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsr.so")
 
 GSR_DILATE, GSR_JACOBIAN_CLAMP, GSR_COLOR_CLAMP, GSR_GRAPH, GSR_PERSISTENT, GSR_NO_SYNC = 1, 2, 4, 8, 16, 32
+GSR_DEBUG_INVARIANTS = 64
 GSR_DEFAULT_FLAGS = GSR_DILATE | GSR_JACOBIAN_CLAMP | GSR_COLOR_CLAMP
 
 BUF_RECORDS, BUF_RADIUS, BUF_DEPTH, BUF_TILES_TOUCHED, BUF_PAIR_VALUES, BUF_PAIR_TILES, BUF_RANGES, BUF_GRAD2D = range(8)
@@ -56,7 +57,8 @@ class FwdOut(ctypes.Structure):
 class FrameStats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("mean_len", ctypes.c_double), ("p99_len", ctypes.c_int32),
                 ("overflow", ctypes.c_int32), ("evals_fwd", ctypes.c_int64), ("evals_bwd", ctypes.c_int64),
-                ("blended", ctypes.c_int64), ("tested_fwd", ctypes.c_int64), ("tested_bwd", ctypes.c_int64)]
+                ("blended", ctypes.c_int64), ("tested_fwd", ctypes.c_int64), ("tested_bwd", ctypes.c_int64),
+                ("invariant_max_err", ctypes.c_double), ("invariant_violations", ctypes.c_int64)]
 
 
 STAGES = ["project", "depth_sort", "scan", "duplicate", "tile_sort", "ranges", "blend_fwd", "entropy_mean",
@@ -72,7 +74,7 @@ EXPORTED = ["gsr_status_string", "gsr_last_error", "gsr_create", "gsr_destroy", 
             "gsr_forward", "gsr_render", "gsr_backward", "gsr_stats", "gsr_autotune", "gsr_inspect", "gsr_set_timing",
             "gsr_opacity_loss", "gsr_scale_reset", "gsr_pair_counts", "gsr_scaled_camera", "gsr_select_rmax",
             "gsr_dssim", "gsr_adam", "gsr_base_loss",
-            "gsr_stage_times", "gsr_l1_loss", "gsr_l1_loss_noalloc"]
+            "gsr_stage_times", "gsr_l1_loss", "gsr_l1_loss_noalloc", "gsr_backward_opacity_reg"]
 
 _lib = None
 
@@ -99,6 +101,9 @@ def lib():
         L.gsr_backward.argtypes = [P, P, ctypes.POINTER(Gaussians), P, i32, ctypes.POINTER(Opts),
                                    ctypes.POINTER(FwdOut), P, P, P, ctypes.POINTER(Grads)]
         L.gsr_stats.argtypes = [P, P, P, ctypes.POINTER(FrameStats)]
+        L.gsr_backward_opacity_reg.argtypes = [P, P, ctypes.POINTER(Gaussians), P, i32, ctypes.POINTER(Opts),
+                                               ctypes.POINTER(FwdOut), P, P, P, ctypes.c_float, P,
+                                               ctypes.POINTER(Grads)]
         L.gsr_set_timing.argtypes = [P, i32]
         L.gsr_l1_loss.argtypes = [P, P, P, i32, P, P, P, P]
         L.gsr_l1_loss_noalloc.argtypes = [P, P, P, i32, P, P, P, P]
@@ -324,7 +329,10 @@ class Rasterizer:
         return int(r.value), list(ml)
 
     def backward(self, means, scales, quats, opacities, sh, cams, opts: RasterOptions, saved: dict,
-                 grad_rgb, grad_entropy=None, grad_entropy_mean=None, grads: Optional[dict] = None):
+                 grad_rgb, grad_entropy=None, grad_entropy_mean=None, grads: Optional[dict] = None,
+                 opacity_weight: float = 0.0, opacity_loss: Optional[torch.Tensor] = None):
+        """gsr_backward; with opacity_weight or opacity_loss, gsr_backward_opacity_reg (the opacity
+        regulariser fused into the projection backward, its loss into the 1-element opacity_loss)."""
         g = _gaussians(means, scales, quats, opacities, sh, opts)
         carr = make_cameras(cams)
         if grads is None:
@@ -339,9 +347,18 @@ class Rasterizer:
             if t is not None and (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()):
                 raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
         o = opts.c()
-        _check(self._ctx, lib().gsr_backward(self._ctx, _stream(), ctypes.byref(g), carr, len(cams), ctypes.byref(o),
-                                             ctypes.byref(fo), _ptr(grad_rgb), _ptr(grad_entropy),
-                                             _ptr(grad_entropy_mean), ctypes.byref(gr)))
+        if opacity_weight == 0.0 and opacity_loss is None:
+            _check(self._ctx, lib().gsr_backward(self._ctx, _stream(), ctypes.byref(g), carr, len(cams),
+                                                 ctypes.byref(o), ctypes.byref(fo), _ptr(grad_rgb), _ptr(grad_entropy),
+                                                 _ptr(grad_entropy_mean), ctypes.byref(gr)))
+        else:
+            if opacity_loss is not None and (opacity_loss.dtype != torch.float32 or not opacity_loss.is_cuda):
+                raise ValueError("opacity_loss must be a float32 CUDA tensor")
+            _check(self._ctx, lib().gsr_backward_opacity_reg(self._ctx, _stream(), ctypes.byref(g), carr, len(cams),
+                                                             ctypes.byref(o), ctypes.byref(fo), _ptr(grad_rgb),
+                                                             _ptr(grad_entropy), _ptr(grad_entropy_mean),
+                                                             float(opacity_weight), _ptr(opacity_loss),
+                                                             ctypes.byref(gr)))
         return grads
 
     def stats(self, n_views: int):
@@ -350,7 +367,8 @@ class Rasterizer:
         _check(self._ctx, lib().gsr_stats(self._ctx, _stream(), ppv, ctypes.byref(fs)))
         return dict(pairs_per_view=list(ppv), pairs=fs.pairs, mean_len=fs.mean_len, p99_len=fs.p99_len,
                     overflow=bool(fs.overflow), evals_fwd=fs.evals_fwd, evals_bwd=fs.evals_bwd,
-                    blended=fs.blended, tested_fwd=fs.tested_fwd, tested_bwd=fs.tested_bwd)
+                    blended=fs.blended, tested_fwd=fs.tested_fwd, tested_bwd=fs.tested_bwd,
+                    invariant_max_err=fs.invariant_max_err, invariant_violations=fs.invariant_violations)
 
     def l1_loss(self, cams, rgb, target, grad_rgb=None, loss=None):
         """L1 per view and its gradient, on the GPU, for the latest forward's cameras."""

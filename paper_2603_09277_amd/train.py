@@ -174,10 +174,11 @@ class Trainer:
         ep = self.epoch(it)
         reg_on = (ep % cfg.reset_every) % 2 == 1              # every other epoch of a reset period
         entropy_on = reg_on and cfg.regulariser == "entropy"
+        opacity_on = reg_on and cfg.regulariser == "opacity"   # dL_O/dsigma fused into the projection backward
         g = self.R.backward(a["means"], a["scales"], a["quats"], a["opacities"], a["sh"], [cam], self.opts, out,
-                            g_rgb, None, self._g_le if entropy_on else self._g_le0, self.grads)
-        if reg_on and cfg.regulariser == "opacity":            # dL_O/dsigma added to the opacity gradient
-            self.R.opacity_loss(a["opacities"], cfg.opacity_weight, g["opacities"], self._loss_o)
+                            g_rgb, None, self._g_le if entropy_on else self._g_le0, self.grads,
+                            opacity_weight=cfg.opacity_weight if opacity_on else 0.0,
+                            opacity_loss=self._loss_o if opacity_on else None)
         self.step_no += 1
         for k in self.raw:
             act = None if self.kind[k] == 0 else self.act[k]

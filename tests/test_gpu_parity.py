@@ -937,6 +937,56 @@ def test_opacity_loss_vs_oracle(R):
     assert rel_norm(got, g_o) < 1e-5
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_opacity_regulariser_fused_into_projection_backward(R, tiny, graph):
+    """gsr_backward_opacity_reg: the opacity gradient equals gsr_backward's followed by
+    gsr_opacity_loss bit for bit, the other gradients equal gsr_backward's, and L_O matches
+    the separate pass and the oracle."""
+    scene, cams = tiny
+    t = to_dev(scene)
+    flags = gsr.GSR_DEFAULT_FLAGS | (gsr.GSR_GRAPH if graph else 0)
+    opts = gsr.RasterOptions(tile=(16, 16), sh_degree=0, flags=flags)
+    out = R.forward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts)
+    g_rgb = l1_grad_torch(out["rgb"], scenes.target_image(101, 128, 128))
+    g_le = torch.full((1,), GAMMA, device=DEV)
+    ref = R.backward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, out, g_rgb, None, g_le)
+    ref = {k: v.clone() for k, v in ref.items()}
+    loss_sep = R.opacity_loss(t["opacities"], 3.0, ref["opacities"])
+    loss_f = torch.zeros(1, device=DEV)
+    fused = {k: torch.empty_like(v) for k, v in t.items()}
+    for _ in range(2 if graph else 1):                 # capture, then a replay
+        R.backward(t["means"], t["scales"], t["quats"], t["opacities"], t["sh"], cams, opts, out, g_rgb, None, g_le,
+                   fused, opacity_weight=3.0, opacity_loss=loss_f)
+        torch.cuda.synchronize()
+        for k in KEYS:
+            assert torch.equal(fused[k], ref[k]), k
+        L_want, _ = orc.opacity_loss(scene.opacities, 3.0)
+        assert abs(float(loss_f[0]) - float(loss_sep[0])) <= 1e-6 * float(loss_sep[0])
+        assert abs(float(loss_f[0]) - L_want) <= 1e-6 * L_want
+
+
+@pytest.mark.parametrize("name,tile", [("tiny", (16, 16)), ("single", (16, 16)), ("single", (8, 8)),
+                                       ("sweep_half", (32, 8))])
+def test_debug_invariants_weights_sum_to_one(R, name, tile):
+    """GSR_DEBUG_INVARIANTS: every pixel's blending weights plus T_final sum to one (Eq. 9)
+    within the FP32 bound of its walk; the images are those of an unchecked forward."""
+    scene, cams, _ = scenes.workload(name)
+    t = to_dev(scene)
+    opts = gsr.RasterOptions(tile=tile, lds_batch=128, sh_degree=scene.sh_degree)
+    chk = gsr.RasterOptions(tile=tile, lds_batch=128, sh_degree=scene.sh_degree,
+                            flags=gsr.GSR_DEFAULT_FLAGS | gsr.GSR_DEBUG_INVARIANTS)
+    ref = gpu_forward(R, t, cams, opts)
+    ref = {k: ref[k].clone() for k in ("rgb", "entropy", "t_final", "n_contrib")}
+    assert R.stats(1)["invariant_violations"] == -1            # not checked
+    out = gpu_forward(R, t, cams, chk)
+    st = R.stats(1)
+    nmax = int(out["n_contrib"].max())
+    assert st["invariant_violations"] == 0, st
+    assert 0.0 <= st["invariant_max_err"] <= 4 * 2.0 ** -24 * (nmax + 1), (st["invariant_max_err"], nmax)
+    for k in ref:
+        assert torch.equal(out[k], ref[k]), k
+
+
 def test_scale_reset_bit_exact(R):
     scene = scenes.gmm_scene(32, 50_000)
     s = torch.from_numpy(scene.scales.copy()).to(DEV)

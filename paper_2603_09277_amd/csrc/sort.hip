@@ -567,6 +567,30 @@ __device__ __forceinline__ void load_meta(const uint32_t* emit_vg, const uint32_
     m.after = r0 + kChunkRows < P ? emit_vg[r0 + kChunkRows] : kNoSeg;
 }
 
+// DPP move: lane i takes `x` of the lane CTRL names; lanes without one (outside the
+// row, or in a row ROW_MASK leaves out) take `old`
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, ROW_MASK, 0xf, false);
+}
+
+// one step of the segmented lane scan: add the sums of the lane CTRL names if it
+// holds the same segment
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_scan_step(float (&C)[kG2], uint32_t& Cl, uint32_t sl)
+{
+    const uint32_t su = dpp_u32<CTRL, ROW_MASK>(kNoSeg, sl);
+    const bool same = su == sl && sl != kNoSeg;
+#pragma unroll
+    for (int k = 0; k < kG2; ++k) {
+        const float y = __uint_as_float(dpp_u32<CTRL, ROW_MASK>(0u, __float_as_uint(C[k])));
+        C[k] += same ? y : 0.f;
+    }
+    const uint32_t yl = dpp_u32<CTRL, ROW_MASK>(0u, Cl);
+    Cl += same ? yl : 0u;
+}
+
 __global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pair_grad, const uint32_t* pair_stamp,
                                                               const uint32_t* stamp, const uint32_t* emit_vg,
                                                               const uint32_t* total, uint32_t cap, float* grad2d,
@@ -615,17 +639,24 @@ __global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pa
 #pragma unroll
         for (uint32_t i = 0; i < kChunkWords / 64u; ++i) srow[i * 64u + lane] = words[i];
         wave_lds_order();
-        // this lane's row r, from LDS (rows not written by this frame's backward read as zeros)
-        const float* mine = reinterpret_cast<const float*>(srow) + lane * (kRowsPerLane * kRowF);
-        auto load_row = [&](uint32_t r, float* row) {
-            const float2* x = reinterpret_cast<const float2*>(mine + r * kRowF);
+        // this lane's 4 rows: 160 contiguous bytes of LDS, ten 16-byte reads (rows not
+        // written by this frame's backward read as zeros)
+        float mine[kRowsPerLane * kRowF];
+        {
+            const uint4* m4 = srow + lane * (kRowsPerLane * kRowF / 4u);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float2 y = x[k];
-                row[2 * k] = lv[r] ? y.x : 0.f;
-                row[2 * k + 1] = lv[r] ? y.y : 0.f;
+            for (uint32_t i = 0; i < kRowsPerLane * kRowF / 4u; ++i) {
+                const uint4 w = m4[i];
+                mine[4 * i + 0] = __uint_as_float(w.x);
+                mine[4 * i + 1] = __uint_as_float(w.y);
+                mine[4 * i + 2] = __uint_as_float(w.z);
+                mine[4 * i + 3] = __uint_as_float(w.w);
             }
-            row[8] = lv[r] ? mine[r * kRowF + 8] : 0.f;
+        }
+        wave_lds_order();                                        // the next chunk overwrites srow
+        auto load_row = [&](uint32_t r, float* row) {
+#pragma unroll
+            for (int k = 0; k < kG2; ++k) row[k] = lv[r] ? mine[r * kRowF + k] : 0.f;
         };
         // lane-local segments: A = first segment's partial, B = last segment's partial,
         // la / lb their numbers of live rows (a segment without one is not written)
@@ -657,40 +688,37 @@ __global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pa
                 ++lb;
             }
         }
-        wave_lds_order();                                        // the next chunk overwrites srow
         if (nseg == 1) {
 #pragma unroll
             for (int k = 0; k < kG2; ++k) A[k] = B[k];
             la = lb;
         }
-        // C = segmented inclusive sum of B over lanes, keyed by the last segment (Cl: of lb)
+        // C = segmented inclusive sum of B over lanes, keyed by the last segment (Cl: of lb):
+        // shifts by 1, 2, 4 and 8 lanes inside each row of 16, then the last lane of each
+        // row into the next row and of the lower half into the upper half, all as DPP
+        // moves (segments are contiguous, so an equal key two lanes apart means one
+        // segment between them)
         float C[kG2];
         uint32_t Cl = lb;
 #pragma unroll
         for (int k = 0; k < kG2; ++k) C[k] = B[k];
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t su = __shfl_up(sl, d, 64);
-            const bool same = lane >= (uint32_t)d && su == sl && sl != kNoSeg;   // segments are contiguous
-#pragma unroll
-            for (int k = 0; k < kG2; ++k) {
-                const float y = __shfl_up(C[k], d, 64);
-                C[k] += same ? y : 0.f;
-            }
-            const uint32_t yl = __shfl_up(Cl, d, 64);
-            Cl += same ? yl : 0u;
-        }
-        // the chunk's neighbours: the row before it and the row after it
-        const uint32_t sfirst = __shfl(s0, 0, 64);
+        seg_scan_step<0x111, 0xf>(C, Cl, sl);                   // row_shr:1
+        seg_scan_step<0x112, 0xf>(C, Cl, sl);                   // row_shr:2
+        seg_scan_step<0x114, 0xf>(C, Cl, sl);                   // row_shr:4
+        seg_scan_step<0x118, 0xf>(C, Cl, sl);                   // row_shr:8
+        seg_scan_step<0x142, 0xa>(C, Cl, sl);                   // row_bcast:15 into rows 1 and 3
+        seg_scan_step<0x143, 0xc>(C, Cl, sl);                   // row_bcast:31 into rows 2 and 3
+        // the chunk's neighbours: the row before it and the row after it; the previous
+        // lane's last segment and sums, the next lane's first segment (wave_shr:1, wave_shl:1)
+        const uint32_t sfirst = (uint32_t)__builtin_amdgcn_readlane((int)s0, 0);
         const bool crosses_in = r0 > 0 && m.before == sfirst;
         const uint32_t after = m.after;
-        uint32_t nxt = __shfl_down(s0, 1, 64);
-        if (lane == 63) nxt = after;
-        const uint32_t prv_sl = __shfl_up(sl, 1, 64);
+        const uint32_t nxt = dpp_u32<0x130, 0xf>(after, s0);
+        const uint32_t prv_sl = dpp_u32<0x138, 0xf>(kNoSeg, sl);
         float prvC[kG2];
 #pragma unroll
-        for (int k = 0; k < kG2; ++k) prvC[k] = __shfl_up(C[k], 1, 64);
-        const uint32_t prvCl = __shfl_up(Cl, 1, 64);
+        for (int k = 0; k < kG2; ++k) prvC[k] = __uint_as_float(dpp_u32<0x138, 0xf>(0u, __float_as_uint(C[k])));
+        const uint32_t prvCl = dpp_u32<0x138, 0xf>(0u, Cl);
         const bool valid = s0 != kNoSeg;
         SegCarry* cr = carry + c;
         if (valid && nseg >= 2) {                                // first segment ends in this lane

@@ -303,7 +303,8 @@ typedef struct {
                                   evals_fwd, those whose Gaussian survives the exact 8x8-block cull
                                   (the others cannot reach 1/255 at any pixel of the block) */
     int64_t tested_bwd;        /* alpha tests the backward makes: surviving positions up to each
-                                  pixel's last contributor (a subset of evals_bwd) */
+                                  pixel's last contributor (a subset of evals_bwd); counted by the
+                                  backward, 0 until a backward of this frame has run */
     double invariant_max_err;  /* GSR_DEBUG_INVARIANTS: max over pixels of |sum w + T_final - 1| (Eq. 9);
                                   -1 if the forward did not check */
     int64_t invariant_violations; /* pixels whose error exceeds 4u (n_contrib + 1); -1 if not checked */

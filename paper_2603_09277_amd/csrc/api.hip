@@ -504,6 +504,7 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     const bool persist = (o->flags & GSR_PERSISTENT) != 0;
     bb.queues = persist ? (uint32_t*)c->queues.p + kQueues * kQueueStride : nullptr;
     bb.tile_order = persist ? nullptr : (const uint32_t*)c->tile_order.p;
+    bb.block_cnt = (uint4*)c->block_cnt.p;
     if (persist) HIP_TRY(c, launch_fill_u32(bb.queues, 0u, kQueues * kQueueStride, st));
     // backward window: at most 128 entries; on long lists 64, whose smaller per-window LDS
     // (records and per-wavefront sums) lets more wavefronts stay resident (the walk of a long

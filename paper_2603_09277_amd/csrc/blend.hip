@@ -261,44 +261,44 @@ __device__ __forceinline__ uint32_t next_item_wave(WaveQueue& q, uint32_t* queue
 // Per-lane state of the front-to-back walk of one pixel.
 struct FwdPix {
     float T, Cr, Cg, Cb, H2;         // transmittance, colour, entropy in log2 units
-    int32_t last, stop_pos;          // n_contrib; list position of the stopping entry (-1: none)
+    int32_t last;                    // n_contrib
+    int32_t stop_pos;                // list position of the stopping entry; -1 while the
+                                     // pixel is open (0 from the start outside the image)
     uint32_t nbl;                    // entries blended
-    // alpha tests made (surviving entries visited): svm over the batches finished
-    // before the stop, sv_stop up to the stopping entry, sv_last up to the last blend
-    uint32_t svm, sv_stop, sv_last;
-    bool done;
+};
+
+// Alpha tests one wavefront made (a surviving entry visited by a pixel still
+// open), wavefront-uniform.
+struct FwdCount {
+    uint32_t tested;
 };
 
 __device__ __forceinline__ void fwd_init(FwdPix& q, bool inside)
 {
     q.T = 1.f; q.Cr = q.Cg = q.Cb = q.H2 = 0.f;
-    q.last = 0; q.stop_pos = -1; q.nbl = 0;
-    q.svm = q.sv_stop = q.sv_last = 0;
-    q.done = !inside;
+    q.last = 0; q.stop_pos = inside ? -1 : 0; q.nbl = 0;
 }
 
-// One surviving list entry (the k-th of this batch's survivors, at list position
-// pos) for one pixel: alpha (Eq. 3), the transmittance stop, colour (Eq. 5) and
-// the entropy term -w log2 w (Eq. 10).
+__device__ __forceinline__ bool fwd_open(const FwdPix& q) { return q.stop_pos < 0; }
+
+// One surviving list entry for one pixel: alpha (Eq. 3), the transmittance stop,
+// colour (Eq. 5) and the entropy term -w log2 w (Eq. 10).  pos1: the entry's list
+// position + 1.  The ray stops once per pixel, so its bookkeeping sits in a branch
+// the wavefront almost always skips; the test count is a wavefront sum of a lane
+// mask (scalar work).
 template <bool RENDER>
-__device__ __forceinline__ void fwd_step(FwdPix& q, float4 g0, float4 g1, float b, float fpx, float fpy, int32_t pos,
-                                         uint32_t k)
+__device__ __forceinline__ void fwd_step(FwdPix& q, FwdCount& wc, float4 g0, float4 g1, float b, float fpx, float fpy,
+                                         int32_t pos1)
 {
     const float p = gauss_p2(g0.z, g0.w, g1.x, g0.x - fpx, g0.y - fpy);
     const float alpha = fminf(kAlphaMax, g1.y * __builtin_amdgcn_exp2f(p));
     const float Tn = q.T * (1.f - alpha);
-    const bool hit = !q.done && alpha >= kAlphaMin;
+    const bool open = fwd_open(q);
+    const bool hit = open && alpha >= kAlphaMin;
     const bool stop = hit && Tn < kTStop;                    // this entry would take T below 1e-4
     const bool blend = hit && !stop;
-    // the bookkeeping as selects (conditional stores to different members would
-    // be merged into one store through a selected address, which keeps q in memory)
-    const uint32_t sv = q.svm + k + 1u;
-    q.sv_stop = stop ? sv : q.sv_stop;
-    q.stop_pos = stop ? pos : q.stop_pos;
-    q.sv_last = blend ? sv : q.sv_last;
-    q.last = blend ? pos + 1 : q.last;
-    q.nbl += blend ? 1u : 0u;
-    q.done = q.done || stop;
+    wc.tested += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(open));
+    if (__builtin_expect(stop, 0)) q.stop_pos = pos1 - 1;
     if (blend) {
         const float w = alpha * q.T;
         q.Cr = fmaf(w, g1.z, q.Cr);
@@ -306,13 +306,15 @@ __device__ __forceinline__ void fwd_step(FwdPix& q, float4 g0, float4 g1, float 
         q.Cb = fmaf(w, b, q.Cb);
         if (!RENDER) q.H2 = fmaf(-w, __builtin_amdgcn_logf(w), q.H2);    // -w log2 w   (Eq. 10)
         q.T = Tn;
+        q.last = pos1;
+        ++q.nbl;
     }
 }
 
 // Outputs of one pixel and the work counts of its 8x8 block.
 template <bool RENDER>
-__device__ __forceinline__ void fwd_store(const BlendFwdArgs& a, const BlockGeom& g, const FwdPix& q, uint2 rg,
-                                          uint32_t wb, uint32_t lane)
+__device__ __forceinline__ void fwd_store(const BlendFwdArgs& a, const BlockGeom& g, const FwdPix& q,
+                                          const FwdCount& wc, uint2 rg, uint32_t wb, uint32_t lane)
 {
     // background weight T_{N+1} (Eq. 9-10), then natural-log units
     const float H = RENDER ? 0.f : kLn2 * fmaf(-q.T, __builtin_amdgcn_logf(q.T), q.H2);
@@ -327,23 +329,19 @@ __device__ __forceinline__ void fwd_store(const BlendFwdArgs& a, const BlockGeom
         }
     }
     // list positions this pixel visited (the stopping entry included), culled ones counted
-    const int32_t n_eval = !g.inside ? 0 : (q.stop_pos >= 0 ? q.stop_pos + 1 : (int32_t)(rg.y - rg.x));
+    const int32_t n_eval = !g.inside ? 0 : (!fwd_open(q) ? q.stop_pos + 1 : (int32_t)(rg.y - rg.x));
     const uint32_t ne = (uint32_t)wave_sum_all_i(n_eval);
     const uint32_t nc = (uint32_t)wave_sum_all_i(q.last);
     const uint32_t nb = (uint32_t)wave_sum_all_i((int)q.nbl);
-    // alpha tests at list positions that survived the block cull: the ones this
-    // kernel made (until the ray stopped) and the ones the backward makes (up to
-    // the last contributor)
-    // (both members read, then combined: a select between two members becomes a
-    // load through a selected address, which keeps q in memory)
-    const uint32_t tested = q.svm + (q.stop_pos >= 0 ? q.sv_stop - q.svm : 0u);
-    const uint32_t tf = (uint32_t)wave_sum_all_i((int)tested);
-    const uint32_t tb = (uint32_t)wave_sum_all_i((int)q.sv_last);
+    // alpha tests at list positions that survived the block cull that this kernel
+    // made (until the ray stopped); the backward adds its own count (up to the last
+    // contributor) in the next word
+    const uint32_t tf = wc.tested;
     const float hs = RENDER ? 0.f : wave_sum_all(g.inside ? H : 0.f);
     if (lane == 0) {
         if (!RENDER) a.block_H[wb] = hs;
         a.block_cnt[2 * wb] = make_uint4(ne, nc, nb, 0u);
-        a.block_cnt[2 * wb + 1] = make_uint4(tf, tb, 0u, 0u);
+        a.block_cnt[2 * wb + 1] = make_uint4(tf, 0u, 0u, 0u);
     }
 }
 
@@ -357,8 +355,7 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
 {
     __shared__ float4 s_g0[kWavesPerGroup][B];   // mean x, mean y, A', B'
     __shared__ float4 s_g1[kWavesPerGroup][B];   // C', opacity, red, green
-    __shared__ float s_b[kWavesPerGroup][B];     // blue
-    __shared__ int32_t s_pos[kWavesPerGroup][B]; // position in the tile list
+    __shared__ float2 s_bp[kWavesPerGroup][B];   // blue, position in the tile list + 1 (int bits)
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
     WaveQueue wq;
     uint32_t item;
@@ -382,6 +379,7 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     FwdPix q;
     fwd_init(q, g.inside);
+    FwdCount wc = { 0u };
     // the record indices of a batch's entries (two dependent loads) are fetched one
     // batch ahead, 64 a register
     constexpr int NH = (B + kWave - 1) / kWave;
@@ -392,7 +390,7 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
         pv[h] = (uint32_t)h * kWave + lane < (uint32_t)B && e < rg.y ? a.emit_vg[a.pair_vals[e]] : 0u;
     }
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
-        if (__ballot(!q.done) == 0ull) break;
+        if (__ballot(fwd_open(q)) == 0ull) break;
         const uint32_t cnt = (rg.y - bs) < (uint32_t)B ? (rg.y - bs) : (uint32_t)B;
         // stage the batch, keeping (in list order) only Gaussians that can reach this block
         uint32_t m = 0;
@@ -417,8 +415,7 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
                 const uint32_t k = m + (uint32_t)__popcll(bal & lt_mask);
                 s_g0[wid][k] = r0;
                 s_g1[wid][k] = r1;
-                s_b[wid][k] = r2.x;
-                s_pos[wid][k] = (int32_t)(bs + j - rg.x);
+                s_bp[wid][k] = make_float2(r2.x, __int_as_float((int32_t)(bs + j - rg.x) + 1));
             }
             m += (uint32_t)__popcll(bal);
         }
@@ -428,12 +425,14 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
             if ((uint32_t)h * kWave + lane < (uint32_t)B && e < rg.y) pv[h] = a.emit_vg[a.pair_vals[e]];
         }
         wave_lds_sync();
-        for (uint32_t k = 0; k < m; ++k)
-            fwd_step<RENDER>(q, s_g0[wid][k], s_g1[wid][k], s_b[wid][k], fpx, fpy, s_pos[wid][k], k);
-        if (!q.done) q.svm += m;
+        m = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);   // wavefront-uniform: a scalar loop
+        for (uint32_t k = 0; k < m; ++k) {
+            const float2 bp = s_bp[wid][k];
+            fwd_step<RENDER>(q, wc, s_g0[wid][k], s_g1[wid][k], bp.x, fpx, fpy, __float_as_int(bp.y));
+        }
         wave_lds_sync();
     }
-    fwd_store<RENDER>(a, g, q, rg, wb, lane);
+    fwd_store<RENDER>(a, g, q, wc, rg, wb, lane);
     }
 }
 
@@ -446,11 +445,10 @@ template <int B, bool PERSIST, bool RENDER>
 __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
 {
     static_assert(B <= 256, "one staged entry per thread");
-    __shared__ float4 s_g0[B];                    // mean x, mean y, A', B'
-    __shared__ float4 s_g1[B];                    // C', opacity, red, green
-    __shared__ float s_b[B];                      // blue
-    __shared__ float s_cull[B];                   // L
-    __shared__ int32_t s_idx[kWavesPerGroup][B];  // each wavefront's surviving batch entries, in list order
+    // a batch entry: (mean x, mean y, A', B'), (C', opacity, red, green),
+    // (blue, L, list position + 1 as int bits, 0)
+    __shared__ float4 s_rec[kRecF4 * B];
+    __shared__ int32_t s_idx[kWavesPerGroup][B];  // each wavefront's surviving batch entries (byte offsets), in list order
     __shared__ uint32_t s_item;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, tid = threadIdx.x;
     const uint32_t n_items = a.n_blocks / kWavesPerGroup;      // tiles
@@ -472,42 +470,46 @@ __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     FwdPix q;
     fwd_init(q, g.inside);
+    FwdCount wc = { 0u };
     // each thread stages one entry of a batch; its record index (two dependent
     // loads) is fetched one batch ahead
     uint32_t pv = 0;
     if (tid < (uint32_t)B && rg.x + tid < rg.y) pv = a.emit_vg[a.pair_vals[rg.x + tid]];
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
-        if (!__syncthreads_or(q.done ? 0 : 1)) break;           // every pixel of the tile has stopped
+        if (!__syncthreads_or(fwd_open(q) ? 1 : 0)) break;      // every pixel of the tile has stopped
         const uint32_t cnt = (rg.y - bs) < (uint32_t)B ? (rg.y - bs) : (uint32_t)B;
         if (tid < cnt) {
             const float4* r = a.rec + (size_t)kRecF4 * pv;
             const float4 r2 = r[2];
-            s_g0[tid] = r[0];
-            s_g1[tid] = r[1];
-            s_b[tid] = r2.x;
-            s_cull[tid] = r2.y;
+            s_rec[kRecF4 * tid + 0] = r[0];
+            s_rec[kRecF4 * tid + 1] = r[1];
+            s_rec[kRecF4 * tid + 2] = make_float4(r2.x, r2.y, __int_as_float((int32_t)(bs - rg.x + tid) + 1), 0.f);
         }
         __syncthreads();
         if (tid < (uint32_t)B && bs + B + tid < rg.y) pv = a.emit_vg[a.pair_vals[bs + B + tid]];
         uint32_t m = 0;
-        if (__ballot(!q.done) != 0ull) {                         // this block still has open pixels
+        if (__ballot(fwd_open(q)) != 0ull) {                     // this block still has open pixels
             for (uint32_t j0 = 0; j0 < cnt; j0 += kWave) {
                 const uint32_t j = j0 + lane;
-                const bool keep = j < cnt && !culled(g, s_g0[j], s_g1[j].x, s_cull[j]);
+                const bool keep = j < cnt && !culled(g, s_rec[kRecF4 * j], s_rec[kRecF4 * j + 1].x, s_rec[kRecF4 * j + 2].y);
                 const uint64_t bal = __ballot(keep);
-                if (keep) s_idx[wid][m + (uint32_t)__popcll(bal & lt_mask)] = (int32_t)j;
+                if (keep) s_idx[wid][m + (uint32_t)__popcll(bal & lt_mask)] = (int32_t)(sizeof(float4) * kRecF4 * j);
                 m += (uint32_t)__popcll(bal);
             }
         }
         wave_lds_sync();
+        m = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);   // wavefront-uniform: a scalar loop
+        // the next entry's offset is read one step ahead (its LDS latency off the chain)
+        int32_t off = m > 0 ? s_idx[wid][0] : 0;
         for (uint32_t k = 0; k < m; ++k) {
-            const int32_t j = s_idx[wid][k];
-            fwd_step<RENDER>(q, s_g0[j], s_g1[j], s_b[j], fpx, fpy, (int32_t)(bs - rg.x) + j, k);
+            const float4* r = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_rec) + off);
+            if (k + 1 < m) off = s_idx[wid][k + 1];
+            const float4 r2 = r[2];
+            fwd_step<RENDER>(q, wc, r[0], r[1], r2.x, fpx, fpy, __float_as_int(r2.z));
         }
-        if (!q.done) q.svm += m;
         __syncthreads();                                         // the batch arrays are restaged next
     }
-    fwd_store<RENDER>(a, g, q, rg, wb, lane);
+    fwd_store<RENDER>(a, g, q, wc, rg, wb, lane);
     }
 }
 
@@ -546,7 +548,7 @@ struct BwdAlpha {
 };
 
 // j: the entry's index in the window, nrel = n - (the window's first list position),
-// both scaled by the same positive factor
+// both scaled by the same positive factor (the record's byte size)
 __device__ __forceinline__ BwdAlpha bwd_alpha(const BwdPix& q, int32_t j, int32_t nrel, float4 g0, float4 g1)
 {
     BwdAlpha r;
@@ -683,6 +685,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     const int32_t nthr = SHARED ? 256 : 64;
     const int32_t tid = SHARED ? (int32_t)threadIdx.x : (int32_t)lane;
     for (int32_t i = (int32_t)lane; i < B * kAccF; i += kWave) s_acc[wid][i] = 0.f;
+    uint32_t tested = 0;                     // alpha tests (list positions before a pixel's n_contrib)
 
     // SHARED: each thread stages one entry of a window; its emission index and
     // record index (two dependent loads) are fetched one window ahead
@@ -734,22 +737,26 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
             const uint64_t bal = __ballot(keep);
             if (keep) {
                 const int32_t k = m + (int32_t)__popcll(bal & ((1ull << lane) - 1ull));
-                s_idx[wid][k] = kRecF4 * j;
+                s_idx[wid][k] = (int32_t)sizeof(float4) * kRecF4 * j;
                 s_aidx[wid][k] = kAccF * j;
             }
             m += (int32_t)__popcll(bal);
         }
         wave_lds_sync();
-        // window entries j < nrel lie in this pixel's list (compared as kRecF4 j, the
-        // entry's first float4 in s_rec)
-        const int32_t nrel = kRecF4 * (q.n - lo);
-        // walk them back to front; per Gaussian, the wavefront sums go to this wavefront's slot
+        // window entries j < nrel lie in this pixel's list (compared as the byte offset
+        // of the entry's record in s_rec)
+        const int32_t nrel = (int32_t)sizeof(float4) * kRecF4 * (q.n - lo);
+        // walk them back to front; per Gaussian, the wavefront sums go to this wavefront's slot;
+        // the next entry's offset is read one step ahead
+        int32_t off = m > 0 ? s_idx[wid][m - 1] : 0;
         for (int32_t kk = m - 1; kk >= 0; --kk) {
-            const int32_t j3 = s_idx[wid][kk];
-            const float4* r = &s_rec[slot][j3];
+            const int32_t j3 = off;
+            const float4* r = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(&s_rec[slot][0]) + j3);
+            if (kk > 0) off = s_idx[wid][kk - 1];
             const float4 g1 = r[1];
             const BwdAlpha al = bwd_alpha(q, j3, nrel, r[0], g1);
-            if (__ballot(al.act) != 0ull) {                  // else no lane of this wavefront blended it
+            tested += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(j3 < nrel));
+            if (__builtin_amdgcn_ballot_w64(al.act) != 0ull) {   // else no lane of this wavefront blended it
                 float o[kG2];
                 bwd_grad(q, al, g1, r[2].x, o);
                 const float tot = wave_sum9(o, lane);
@@ -790,6 +797,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
         }
         if (SHARED) __syncthreads(); else wave_lds_sync();
     }
+    if (lane == 0) reinterpret_cast<uint32_t*>(a.block_cnt + 2 * wb + 1)[1] = tested;
     }
 }
 

@@ -123,7 +123,7 @@ struct BlendFwdArgs {
     int32_t* out_nc;
     float* block_H;                       // [n_blocks] sum of H over the block
     uint4* block_cnt;                     // [n_blocks][2]: (list positions visited, sum of n_contrib, blended, 0),
-                                          //   (alpha tests made, alpha tests the backward makes, 0, 0)
+                                          //   (alpha tests made, 0: the backward writes its alpha tests, 0, 0)
     uint32_t* queues;                     // persistent mode: kQueues heads kQueueStride words apart, zeroed; or null
     int32_t render_only;                  // 1: colour only (no entropy, no saved state)
     const uint32_t* tile_order;           // [n_tiles] tiles, longest list first (hardware dispatch); or null
@@ -150,6 +150,8 @@ struct BlendBwdArgs {
     const uint32_t* stamp;                // this frame's row stamp
     uint32_t* queues;                     // persistent mode: kQueues heads kQueueStride words apart, zeroed; or null
     const uint32_t* tile_order;           // [n_tiles] tiles, longest list first (hardware dispatch); or null
+    uint4* block_cnt;                     // the forward's block counts: word 1 of [2 wb + 1] gets the
+                                          //   backward's alpha tests of block wb
 };
 
 // Debug check of Eq. 9 after a forward (GSR_DEBUG_INVARIANTS): per pixel, the sum of

@@ -617,7 +617,11 @@ def test_single_view_full_size_sampled(R, bench_cfg):
 def test_stats_match_lists(R, tiny):
     scene, cams = tiny
     t = to_dev(scene)
-    gpu_forward(R, t, cams, gsr.RasterOptions(tile=(8, 8), sh_degree=0))
+    opts = gsr.RasterOptions(tile=(8, 8), sh_degree=0)
+    out = gpu_forward(R, t, cams, opts)
+    assert R.stats(1)["tested_bwd"] == 0                    # counted by the backward, which has not run
+    g = torch.ones_like(out["rgb"]) / out["rgb"].numel()
+    gpu_backward(R, t, cams, opts, out, g, torch.full_like(out["entropy"], 1e-3))
     st = R.stats(1)
     rg = R.inspect(gsr.BUF_RANGES).reshape(-1, 2).astype(np.int64)
     lens = np.sort(rg[:, 1] - rg[:, 0])

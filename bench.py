@@ -165,6 +165,56 @@ def percentiles(xs):
             "p90_ms": round(float(np.percentile(a, 90)), 4)}
 
 
+def _pixel_sample(cam, frac, seed, v):
+    """The seeded pixel sample of view v: sorted packed indices (shared by every oracle timing)."""
+    M = cam.width * cam.height
+    rng = np.random.default_rng(seed + v)
+    return np.sort(rng.choice(M, max(1, int(round(frac * M))), replace=False))
+
+
+def _oracle_view(orc, scene, cam, target, tile, forward_only, sel):
+    """One view through the oracle: projection and binning (and the projection backward)
+    in full, the blend (and entropy and blend backward) on the packed pixels `sel`.
+    Returns (seconds of the per-view part, seconds of the per-pixel part, oracle image)."""
+    tw, th = tile
+    W, H = cam.width, cam.height
+    M = W * H
+    pix = np.zeros(M, np.uint8)
+    pix[sel] = 1
+    pix = pix.reshape(H, W)
+    t0 = time.perf_counter()
+    pr = orc.project(scene, cam)
+    vals, ranges = orc.bin_lists(pr["mean2d"], pr["radius"], pr["depth32"], W, H, tw, th)
+    t1 = time.perf_counter()
+    img = orc.render(W, H, tw, th, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"], ranges, vals, pix)
+    t2 = t3 = t4 = time.perf_counter()
+    if not forward_only:
+        gC = np.sign(img["rgb"] - target) / (3.0 * M)
+        gH = np.full((H, W), GAMMA / M)
+        t2 = time.perf_counter()
+        g2 = orc.backward_render(W, H, tw, th, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"], ranges, vals,
+                                 gC, gH, pix)
+        t3 = time.perf_counter()
+        orc.backward_project(scene, cam, g2)
+        t4 = time.perf_counter()
+    return (t1 - t0) + (t4 - t3), (t2 - t1) + (t3 - t2), img
+
+
+def _per_iteration(cams, per_view):
+    """Seconds per iteration over all views: each unsampled view is charged the time of
+    the sampled view of its resolution."""
+    total = 0.0
+    for v, cam in enumerate(cams):
+        if v in per_view:
+            total += per_view[v]
+        else:
+            same = [u for u in per_view if (cams[u].width, cams[u].height) == (cam.width, cam.height)]
+            if not same:
+                raise ValueError(f"no sampled view of resolution {cam.width}x{cam.height}")
+            total += per_view[same[0]]
+    return total
+
+
 def cpu_baseline(scene, cams, tile, targets, forward_only=False, views=None, frac=0.5, seed=77):
     """The FP64 oracle (single-threaded) on a bounded sample of the same workload.
 
@@ -175,50 +225,19 @@ def cpu_baseline(scene, cams, tile, targets, forward_only=False, views=None, fra
     time of the sampled view of its resolution.  Returns the record and the
     oracle's images of the sampled pixels (for the image-error check)."""
     from oracle import oracle as orc
-    tw, th = tile
     views = list(range(len(cams))) if views is None else list(views)
     per_view = {}
     measured = 0.0
     sampled_px = {}
     for v in views:
-        cam, target = cams[v], targets[v]
-        W, H = cam.width, cam.height
-        M = W * H
-        rng = np.random.default_rng(seed + v)
-        sel = np.sort(rng.choice(M, max(1, int(round(frac * M))), replace=False))
-        pix = np.zeros(M, np.uint8)
-        pix[sel] = 1
-        pix = pix.reshape(H, W)
-        t0 = time.perf_counter()
-        pr = orc.project(scene, cam)
-        vals, ranges = orc.bin_lists(pr["mean2d"], pr["radius"], pr["depth32"], W, H, tw, th)
-        t1 = time.perf_counter()
-        img = orc.render(W, H, tw, th, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"], ranges, vals, pix)
-        t2 = t3 = t4 = time.perf_counter()
-        if not forward_only:
-            gC = np.sign(img["rgb"] - target) / (3.0 * M)
-            gH = np.full((H, W), GAMMA / M)
-            t2 = time.perf_counter()
-            g2 = orc.backward_render(W, H, tw, th, pr["mean2d"], pr["conic"], pr["opacity"], pr["rgb"], ranges, vals,
-                                     gC, gH, pix)
-            t3 = time.perf_counter()
-            orc.backward_project(scene, cam, g2)
-            t4 = time.perf_counter()
-        fixed = (t1 - t0) + (t4 - t3)
-        pixel = (t2 - t1) + (t3 - t2)
+        cam = cams[v]
+        M = cam.width * cam.height
+        sel = _pixel_sample(cam, frac, seed, v)
+        fixed, pixel, img = _oracle_view(orc, scene, cam, targets[v], tile, forward_only, sel)
         per_view[v] = fixed + pixel * M / len(sel)
         measured += fixed + pixel
         sampled_px[v] = (sel, img["rgb"].reshape(-1, 3)[sel], img["flags"].reshape(-1)[sel])
-    # unsampled views: the sampled view of the same resolution
-    total = 0.0
-    for v, cam in enumerate(cams):
-        if v in per_view:
-            total += per_view[v]
-        else:
-            same = [u for u in per_view if (cams[u].width, cams[u].height) == (cam.width, cam.height)]
-            if not same:
-                raise ValueError(f"no sampled view of resolution {cam.width}x{cam.height}")
-            total += per_view[same[0]]
+    total = _per_iteration(cams, per_view)
     n_sel = sum(len(s[0]) for s in sampled_px.values())
     res = [f"{cams[v].width}x{cams[v].height}" for v in views]
     rec = {"value": len(cams) / total, "unit": "views/s" if forward_only else "iters/s", "cores": 1,
@@ -230,6 +249,51 @@ def cpu_baseline(scene, cams, tile, targets, forward_only=False, views=None, fra
                       f"the unsampled views, per resolution; {measured:.1f} s measured, {total:.1f} s per "
                       f"{len(cams)}-view iteration")}
     return rec, sampled_px
+
+
+def _stripe_worker(job):
+    """One of P oracle processes: the workload drawn again from its seed, and on each
+    sampled view every P-th pixel of the seeded sample (a disjoint stripe)."""
+    name, sh_f32, tile, forward_only, views, frac, seed, i, P = job
+    from oracle import oracle as orc
+    from paper_2603_09277_amd import scenes
+    scene, cams, _ = scenes.workload(name, sh_f32=sh_f32)
+    out = {}
+    for v in views:
+        cam = cams[v]
+        target = scenes.target_image(1000 + v, cam.height, cam.width)
+        sel = _pixel_sample(cam, frac, seed, v)
+        fixed, pixel, _ = _oracle_view(orc, scene, cam, target, tile, forward_only, sel[i::P])
+        out[v] = (fixed, pixel, len(sel))
+    return out
+
+
+def cpu_baseline_processes(name, sh_f32, cams, tile, forward_only=False, views=None, frac=0.01, seed=77, procs=None):
+    """The same oracle sample as P independent processes (P = the host's CPUs available
+    to this process, at most 16), each taking a disjoint stripe of every sampled view's
+    pixels and repeating the view's projection and binning.  A view's time is the
+    slowest stripe, its pixel part extrapolated to a 1/P share of the view."""
+    import multiprocessing as mp
+    views = list(range(len(cams))) if views is None else list(views)
+    P = procs or max(1, min(16, len(os.sched_getaffinity(0))))
+    jobs = [(name, sh_f32, tile, forward_only, views, frac, seed, i, P) for i in range(P)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(P) as pool:
+        res = pool.map(_stripe_worker, jobs)
+    wall = time.perf_counter() - t0
+    per_view = {}
+    for v in views:
+        M = cams[v].width * cams[v].height
+        per_view[v] = max(r[v][0] + r[v][1] * M / r[v][2] for r in res)
+    total = _per_iteration(cams, per_view)
+    res_s = [f"{cams[v].width}x{cams[v].height}" for v in views]
+    return {"value": len(cams) / total, "unit": "views/s" if forward_only else "iters/s", "cores": P,
+            "kind": "oracle",
+            "sample": (f"FP64 oracle in {P} processes, one thread each, on views {views} ({', '.join(res_s)}): each "
+                       f"process projects and bins the view in full and takes every {P}-th pixel of the same seeded "
+                       f"{frac:.0%} sample; a view costs its slowest process with that process's pixel time "
+                       f"extrapolated to 1/{P} of the view; {total:.1f} s per {len(cams)}-view iteration; "
+                       f"{wall:.1f} s wall including each process drawing the scene")}
 
 
 def run_train(args, torch, dev):
@@ -603,6 +667,7 @@ def run_compare(args, torch, dev, gsr, scenes):
     if not args.no_cpu_baseline:
         # one view of each resolution (views 0, 2, 5), at the forms' tile shape
         cb, sampled = cpu_baseline(scene, cams, ob.tile, targets, views=[0, 2, 5], frac=0.01)
+        cb["processes"] = cpu_baseline_processes("batched", True, cams, ob.tile, views=[0, 2, 5], frac=0.01)
         result["cpu_baseline"] = cb
         result["image_err_vs_oracle"] = dict(
             image_errors(sampled, cams, {"batched_bf16_sh": img_b, "plain_f32_sh": img_p}),
@@ -666,6 +731,8 @@ def run_one(args, torch, dev, gsr, scenes):
         frac = 0.5 if args.workload in ("tiny", "single") else 0.01
         result["cpu_baseline"], _ = cpu_baseline(scene, cams, tile, targets_np, args.forward_only, views=views,
                                                  frac=frac)
+        result["cpu_baseline"]["processes"] = cpu_baseline_processes(args.workload, False, cams, tile,
+                                                                     args.forward_only, views=views, frac=frac)
     print(json.dumps(result), flush=True)
 
 

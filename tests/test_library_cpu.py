@@ -82,3 +82,19 @@ def test_generators_are_seeded():
     # the camera looks at the origin: the world origin projects to the principal point
     t = cams[0].t.astype(np.float64)
     assert abs(t[0]) < 1e-5 and abs(t[1]) < 1e-5 and t[2] > 0
+
+
+def test_oracle_baseline_in_processes_matches_its_record():
+    """bench.py's P-process oracle timing: every process takes a disjoint stripe of the
+    same seeded pixel sample, and the record states the process count it used."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    scene, cams, _ = scenes.workload("tiny")
+    sel = bench._pixel_sample(cams[0], 0.5, 77, 0)
+    stripes = [sel[i::3] for i in range(3)]
+    assert sum(len(x) for x in stripes) == len(sel)
+    assert len(np.unique(np.concatenate(stripes))) == len(sel)
+    rec = bench.cpu_baseline_processes("tiny", False, cams, (16, 16), views=[0], frac=0.5, procs=2)
+    assert rec["cores"] == 2 and rec["kind"] == "oracle" and rec["unit"] == "iters/s"
+    assert rec["value"] > 0 and "2 processes" in rec["sample"]

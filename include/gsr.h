@@ -360,10 +360,12 @@ gsr_status gsr_autotune(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, cons
  * (synchronises `stream`); for stage-by-stage testing.  *bytes receives the
  * size of the buffer; dst may be NULL to query it. */
 typedef enum {
-    GSR_BUF_RECORDS = 0,       /* float[V*n][12]: mean x, y, A', B', C', opacity, r, g, b, L, 0, 0 with
+    GSR_BUF_RECORDS = 0,       /* float[V*n][12]: mean x, y, A', B', C', opacity, r, g, b, L, kr, kc with
                                   the conic pre-scaled: A' = -A log2(e)/2, B' = -B log2(e), C' = -C log2(e)/2;
                                   L = log2(255 opacity) + 1e-4, the level the blend uses to skip Gaussians
-                                  that cannot reach alpha >= 1/255 anywhere in an 8x8 pixel block */
+                                  that cannot reach alpha >= 1/255 anywhere in an 8x8 pixel block, and
+                                  kr = -B'/(2C'), kc = -B'/(2A'), the slopes on which the exponent's
+                                  maximum along a pixel row / column lies (used by that test) */
     GSR_BUF_RADIUS = 1,        /* int32[V*n], 0 = culled */
     GSR_BUF_DEPTH = 2,         /* float[V*n], camera z */
     GSR_BUF_TILES_TOUCHED = 3, /* int32[V*n] */

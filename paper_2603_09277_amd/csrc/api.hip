@@ -311,7 +311,7 @@ gsr_status ensure_vn(gsr_ctx* c, uint32_t vn)
     v = std::max(v, c->vn_cap + c->vn_cap / 4);
     gsr_status s;
     if ((s = grow(c, c->rec, v * 48)) || (s = grow(c, c->dkey0, v * 4)) || (s = grow(c, c->dkey1, v * 4)) ||
-        (s = grow(c, c->ord0, v * 4)) || (s = grow(c, c->ord1, v * 4)) || (s = grow(c, c->rect, v * 16)) ||
+        (s = grow(c, c->ord0, v * 4)) || (s = grow(c, c->ord1, v * 4)) || (s = grow(c, c->rect, v * 8)) ||
         (s = grow(c, c->tt, v * 4)) || (s = grow(c, c->tt_s, v * 4)) || (s = grow(c, c->rect_s, v * 8)) ||
         (s = grow(c, c->radius, v * 4)) || (s = grow(c, c->depth, v * 4)) ||
         (s = grow(c, c->offsets, v * 4)) || (s = grow(c, c->grad2d, v * 4 * kG2)) || (s = grow(c, c->rec_stamp, v * 4, true)) ||
@@ -373,7 +373,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
     pa.n = n; pa.n_views = (int32_t)V; pa.flags = o->flags; pa.tile_shift_x = L.tsx; pa.tile_shift_y = L.tsy;
     pa.cams = dc;
-    pa.rec = (float4*)c->rec.p; pa.depth_key = (uint32_t*)c->dkey0.p; pa.trect = (uint4*)c->rect.p;
+    pa.rec = (float4*)c->rec.p; pa.depth_key = (uint32_t*)c->dkey0.p; pa.trect = (uint2*)c->rect.p;
     pa.tiles_touched = (uint32_t*)c->tt.p; pa.radius = (int32_t*)c->radius.p; pa.depth = (float*)c->depth.p;
     {
         StageTimer tm(c, st, GSR_STAGE_PROJECT, !c->capturing);
@@ -392,7 +392,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     // offsets of each record's pairs in depth order; total pair count
     {
         StageTimer tm(c, st, GSR_STAGE_SCAN, !c->capturing);
-        HIP_TRY(c, launch_gather_scan((const uint4*)c->rect.p, od[0], vn,
+        HIP_TRY(c, launch_gather_scan((const uint2*)c->rect.p, od[0], vn,
                                       (uint32_t*)c->offsets.p, (uint32_t*)c->tt_s.p, (uint2*)c->rect_s.p, counters,
                                       counters + 1, (uint32_t*)c->scan_tmp.p, st));
     }
@@ -1051,14 +1051,14 @@ static gsr_status count_pairs(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
     pa.n = n; pa.n_views = n_views; pa.flags = o->flags; pa.tile_shift_x = L.tsx; pa.tile_shift_y = L.tsy;
     pa.cams = (const CamDev*)c->cams.p;
-    pa.rec = (float4*)c->rec.p; pa.depth_key = (uint32_t*)c->dkey0.p; pa.trect = (uint4*)c->rect.p;
+    pa.rec = (float4*)c->rec.p; pa.depth_key = (uint32_t*)c->dkey0.p; pa.trect = (uint2*)c->rect.p;
     pa.tiles_touched = (uint32_t*)c->tt.p; pa.radius = (int32_t*)c->radius.p; pa.depth = (float*)c->depth.p;
     HIP_TRY(c, launch_project_fwd(pa, o->sh_degree, o->sh_dtype == 1, st));
     uint32_t* counters = (uint32_t*)c->counters.p;
     for (int v = 0; v < n_views; ++v) {             // one scan per view: its pair count
         HIP_TRY(c, launch_fill_u32(counters, 0u, 2, st));
         HIP_TRY(c, launch_iota_u32((uint32_t*)c->ord0.p, n, st));
-        HIP_TRY(c, launch_gather_scan((const uint4*)c->rect.p + (size_t)v * n, (const uint32_t*)c->ord0.p, n,
+        HIP_TRY(c, launch_gather_scan((const uint2*)c->rect.p + (size_t)v * n, (const uint32_t*)c->ord0.p, n,
                                       (uint32_t*)c->offsets.p, (uint32_t*)c->tt_s.p, (uint2*)c->rect_s.p, counters,
                                       counters + 1, (uint32_t*)c->scan_tmp.p, st));
         HIP_TRY(c, hipMemcpyAsync(c->counters_host, counters, 8, hipMemcpyDeviceToHost, st));

@@ -43,6 +43,7 @@ constexpr float kTStop = 1e-4f;
 constexpr float kLn2 = 0.6931471805599453f;
 constexpr int kWavesPerGroup = 4;
 constexpr int kAccF = 10;            // floats per backward accumulator row: 9 sums and a hit flag
+constexpr int kFwdRecF4 = kRecF4 + 1; // a staged forward entry: the record and its list position
 
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -153,36 +154,37 @@ struct BlockGeom {
     float cx0, cx1, cy0, cy1;        // pixel-centre rectangle of the block's in-image pixels
 };
 
-// max over v in [v0, v1] of the concave f(v) = a u^2 + b u v + c v^2 (c < 0)
-__device__ __forceinline__ float edge_max(float a, float b, float c, float u, float v0, float v1, float hc)
+// max over v in [v0, v1] of the concave f(v) = a u^2 + b u v + c v^2 (c < 0), whose
+// stationary point is v = k u with k = -b / (2 c)
+__device__ __forceinline__ float edge_max(float a, float b, float c, float u, float v0, float v1, float k)
 {
-    const float v = fminf(fmaxf(-b * u * hc, v0), v1);     // hc = 1 / (2c)
+    const float v = fminf(fmaxf(k * u, v0), v1);
     return fmaf(u, fmaf(a, u, b * v), (c * v) * v);
 }
 
 // true if the Gaussian cannot reach alpha >= 1/255 at any pixel centre of the
-// block: r0 = (mean, A', B'), c2 = C', L = log2(255 opacity) + 1e-4.  The blend
+// block: r0 = (mean, A', B'), c2 = C', r2 = (blue, L, -B'/(2C'), -B'/(2A')) with
+// L = log2(255 opacity) + 1e-4.  The exponent is concave with its maximum 0 at the
+// mean; over a rectangle that does not contain the mean its maximum lies on a side
+// that faces the mean (the mean is outside that side's half-plane), and at most one
+// side per axis faces it.  So two edge maxima give the exact maximum: the facing
+// side of each axis, or, for an axis whose range holds the mean, any side of it
+// (a value inside the rectangle, which cannot exceed the maximum).  The blend
 // evaluates the exponent in FP32 with an error below 1e-6 (|A'|+|B'|+|C'|) |d|^2;
-// the test adds twice that bound (and 1.5 % more) to the exact maximum of the
-// exponent over the block's pixel-centre rectangle.
-__device__ __forceinline__ bool culled(const BlockGeom& g, float4 r0, float c2, float L)
+// the test adds twice that bound (and 1.5 % more) to the maximum.
+__device__ __forceinline__ bool culled(const BlockGeom& g, float4 r0, float c2, float4 r2)
 {
-    const float eps = 2.03e-6f * (fabsf(r0.z) + fabsf(r0.w) + fabsf(c2));
+    const float a = r0.z, b = r0.w, c = c2;
+    const float eps = 2.03e-6f * (fabsf(a) + fabsf(b) + fabsf(c));
     const float u0 = g.cx0 - r0.x, u1 = g.cx1 - r0.x;       // pixel - mean
     const float v0 = g.cy0 - r0.y, v1 = g.cy1 - r0.y;
-    const float a = r0.z, b = r0.w, c = c2;
-    float qmax;
-    if (u0 <= 0.f && u1 >= 0.f && v0 <= 0.f && v1 >= 0.f) {
-        qmax = 0.f;                                          // the mean lies over the block
-    } else {
-        // the hardware reciprocal (1 ulp) only moves the maximiser along the edge: at the
-        // stationary point that lowers the maximum by |c| dv^2 ~ 1e-14 |c| d^2, far inside eps
-        const float hc = 0.5f * __builtin_amdgcn_rcpf(c), ha = 0.5f * __builtin_amdgcn_rcpf(a);
-        qmax = fmaxf(fmaxf(edge_max(a, b, c, u0, v0, v1, hc), edge_max(a, b, c, u1, v0, v1, hc)),
-                     fmaxf(edge_max(c, b, a, v0, u0, u1, ha), edge_max(c, b, a, v1, u0, u1, ha)));
-    }
-    const float dmax2 = fmaxf(u0 * u0, u1 * u1) + fmaxf(v0 * v0, v1 * v1);
-    return qmax + eps * dmax2 < -L;
+    const float uf = u0 > 0.f ? u0 : u1;                    // the side facing the mean (if any)
+    const float vf = v0 > 0.f ? v0 : v1;
+    float qmax = fmaxf(edge_max(a, b, c, uf, v0, v1, r2.z), edge_max(c, b, a, vf, u0, u1, r2.w));
+    if (u0 <= 0.f && u1 >= 0.f && v0 <= 0.f && v1 >= 0.f) qmax = 0.f;    // the mean lies over the block
+    const float um = fmaxf(fabsf(u0), fabsf(u1)), vm = fmaxf(fabsf(v0), fabsf(v1));
+    const float dmax2 = fmaf(um, um, vm * vm);
+    return qmax + eps * dmax2 < -r2.y;
 }
 
 // wave block id -> view, tile, pixel of this lane (tile-major numbering,
@@ -380,14 +382,26 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
     FwdPix q;
     fwd_init(q, g.inside);
     FwdCount wc = { 0u };
-    // the record indices of a batch's entries (two dependent loads) are fetched one
-    // batch ahead, 64 a register
+    // a batch's records are loaded into registers one batch ahead (in flight while the
+    // previous batch blends), their record indices (two dependent loads) two batches
+    // ahead, 64 entries a register
     constexpr int NH = (B + kWave - 1) / kWave;
     uint32_t pv[NH];
+    float4 c0[NH], c1[NH], c2[NH];
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
-        const uint32_t e = rg.x + (uint32_t)h * kWave + lane;
-        pv[h] = (uint32_t)h * kWave + lane < (uint32_t)B && e < rg.y ? a.emit_vg[a.pair_vals[e]] : 0u;
+        const uint32_t jh = (uint32_t)h * kWave + lane;
+        const uint32_t e = rg.x + jh;
+        pv[h] = jh < (uint32_t)B && e < rg.y ? a.emit_vg[a.pair_vals[e]] : 0u;
+        c0[h] = c1[h] = c2[h] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (jh < (uint32_t)B && e < rg.y) {
+            const float4* r = a.rec + (size_t)kRecF4 * pv[h];
+            c0[h] = r[0];
+            c1[h] = r[1];
+            c2[h] = r[2];
+        }
+        const uint32_t e2 = rg.x + B + jh;
+        if (jh < (uint32_t)B && e2 < rg.y) pv[h] = a.emit_vg[a.pair_vals[e2]];
     }
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
         if (__ballot(fwd_open(q)) == 0ull) break;
@@ -397,32 +411,29 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
             const uint32_t j0 = (uint32_t)h * kWave;
-            if (j0 >= cnt) continue;                           // (uniform; no break, so pv[h] stays in registers)
+            if (j0 >= cnt) continue;                           // (uniform; no break, so the registers stay)
             const uint32_t j = j0 + lane;
-            bool keep = false;
-            // defined on every path: with undefined values on the j >= cnt path the
-            // register allocator spilled r1 to scratch around the cull
-            float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-            if (j < cnt) {
-                const float4* r = a.rec + (size_t)kRecF4 * pv[h];
-                r0 = r[0];
-                r1 = r[1];
-                r2 = r[2];
-                keep = !culled(g, r0, r1.x, r2.y);
-            }
+            const bool keep = j < cnt && !culled(g, c0[h], c1[h].x, c2[h]);
             const uint64_t bal = __ballot(keep);
             if (keep) {
                 const uint32_t k = m + (uint32_t)__popcll(bal & lt_mask);
-                s_g0[wid][k] = r0;
-                s_g1[wid][k] = r1;
-                s_bp[wid][k] = make_float2(r2.x, __int_as_float((int32_t)(bs + j - rg.x) + 1));
+                s_g0[wid][k] = c0[h];
+                s_g1[wid][k] = c1[h];
+                s_bp[wid][k] = make_float2(c2[h].x, __int_as_float((int32_t)(bs + j - rg.x) + 1));
             }
             m += (uint32_t)__popcll(bal);
         }
+        // the next batch's records, the record indices of the one after
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
-            const uint32_t e = bs + B + (uint32_t)h * kWave + lane;
-            if ((uint32_t)h * kWave + lane < (uint32_t)B && e < rg.y) pv[h] = a.emit_vg[a.pair_vals[e]];
+            const uint32_t jh = (uint32_t)h * kWave + lane;
+            if (jh < (uint32_t)B && bs + B + jh < rg.y) {
+                const float4* r = a.rec + (size_t)kRecF4 * pv[h];
+                c0[h] = r[0];
+                c1[h] = r[1];
+                c2[h] = r[2];
+            }
+            if (jh < (uint32_t)B && bs + 2 * B + jh < rg.y) pv[h] = a.emit_vg[a.pair_vals[bs + 2 * B + jh]];
         }
         wave_lds_sync();
         m = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);   // wavefront-uniform: a scalar loop
@@ -445,9 +456,12 @@ template <int B, bool PERSIST, bool RENDER>
 __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
 {
     static_assert(B <= 256, "one staged entry per thread");
-    // a batch entry: (mean x, mean y, A', B'), (C', opacity, red, green),
-    // (blue, L, list position + 1 as int bits, 0)
-    __shared__ float4 s_rec[kRecF4 * B];
+    // a batch entry j: s_rec[0][j] = (mean x, mean y, A', B'), s_rec[1][j] = (C', opacity,
+    // red, green), s_rec[2][j] = (blue, L, -B'/(2C'), -B'/(2A')), s_rec[3][j].x = list
+    // position + 1 (int bits); one array per part, so that the lanes of the cull, one
+    // entry each, read 16-byte strides (no bank conflicts), and the blend loop reads all
+    // four parts of entry j at one offset, 16 j
+    __shared__ float4 s_rec[kFwdRecF4][B];
     __shared__ int32_t s_idx[kWavesPerGroup][B];  // each wavefront's surviving batch entries (byte offsets), in list order
     __shared__ uint32_t s_item;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, tid = threadIdx.x;
@@ -471,29 +485,44 @@ __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
     FwdPix q;
     fwd_init(q, g.inside);
     FwdCount wc = { 0u };
-    // each thread stages one entry of a batch; its record index (two dependent
-    // loads) is fetched one batch ahead
+    // each thread stages one entry of a batch: its record is loaded into registers one
+    // batch ahead (in flight while the previous batch blends), its record index (two
+    // dependent loads) two batches ahead
     uint32_t pv = 0;
-    if (tid < (uint32_t)B && rg.x + tid < rg.y) pv = a.emit_vg[a.pair_vals[rg.x + tid]];
+    float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
+    if (tid < (uint32_t)B && rg.x + tid < rg.y) {
+        pv = a.emit_vg[a.pair_vals[rg.x + tid]];
+        const float4* r = a.rec + (size_t)kRecF4 * pv;
+        n0 = r[0];
+        n1 = r[1];
+        n2 = r[2];
+    }
+    if (tid < (uint32_t)B && rg.x + B + tid < rg.y) pv = a.emit_vg[a.pair_vals[rg.x + B + tid]];
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
+        // (also orders this batch's staging after every wavefront's reads of the last one)
         if (!__syncthreads_or(fwd_open(q) ? 1 : 0)) break;      // every pixel of the tile has stopped
         const uint32_t cnt = (rg.y - bs) < (uint32_t)B ? (rg.y - bs) : (uint32_t)B;
         if (tid < cnt) {
-            const float4* r = a.rec + (size_t)kRecF4 * pv;
-            const float4 r2 = r[2];
-            s_rec[kRecF4 * tid + 0] = r[0];
-            s_rec[kRecF4 * tid + 1] = r[1];
-            s_rec[kRecF4 * tid + 2] = make_float4(r2.x, r2.y, __int_as_float((int32_t)(bs - rg.x + tid) + 1), 0.f);
+            s_rec[0][tid] = n0;
+            s_rec[1][tid] = n1;
+            s_rec[2][tid] = n2;
+            s_rec[3][tid] = make_float4(__int_as_float((int32_t)(bs - rg.x + tid) + 1), 0.f, 0.f, 0.f);
         }
         __syncthreads();
-        if (tid < (uint32_t)B && bs + B + tid < rg.y) pv = a.emit_vg[a.pair_vals[bs + B + tid]];
+        if (tid < (uint32_t)B && bs + B + tid < rg.y) {
+            const float4* r = a.rec + (size_t)kRecF4 * pv;
+            n0 = r[0];
+            n1 = r[1];
+            n2 = r[2];
+        }
+        if (tid < (uint32_t)B && bs + 2 * B + tid < rg.y) pv = a.emit_vg[a.pair_vals[bs + 2 * B + tid]];
         uint32_t m = 0;
         if (__ballot(fwd_open(q)) != 0ull) {                     // this block still has open pixels
             for (uint32_t j0 = 0; j0 < cnt; j0 += kWave) {
                 const uint32_t j = j0 + lane;
-                const bool keep = j < cnt && !culled(g, s_rec[kRecF4 * j], s_rec[kRecF4 * j + 1].x, s_rec[kRecF4 * j + 2].y);
+                const bool keep = j < cnt && !culled(g, s_rec[0][j], s_rec[1][j].x, s_rec[2][j]);
                 const uint64_t bal = __ballot(keep);
-                if (keep) s_idx[wid][m + (uint32_t)__popcll(bal & lt_mask)] = (int32_t)(sizeof(float4) * kRecF4 * j);
+                if (keep) s_idx[wid][m + (uint32_t)__popcll(bal & lt_mask)] = (int32_t)(sizeof(float4) * j);
                 m += (uint32_t)__popcll(bal);
             }
         }
@@ -502,12 +531,10 @@ __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
         // the next entry's offset is read one step ahead (its LDS latency off the chain)
         int32_t off = m > 0 ? s_idx[wid][0] : 0;
         for (uint32_t k = 0; k < m; ++k) {
-            const float4* r = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_rec) + off);
+            const float4* r = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(&s_rec[0][0]) + off);
             if (k + 1 < m) off = s_idx[wid][k + 1];
-            const float4 r2 = r[2];
-            fwd_step<RENDER>(q, wc, r[0], r[1], r2.x, fpx, fpy, __float_as_int(r2.z));
+            fwd_step<RENDER>(q, wc, r[0], r[B], r[2 * B].x, fpx, fpy, __float_as_int(r[3 * B].x));
         }
-        __syncthreads();                                         // the batch arrays are restaged next
     }
     fwd_store<RENDER>(a, g, q, wc, rg, wb, lane);
     }
@@ -687,41 +714,45 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     for (int32_t i = (int32_t)lane; i < B * kAccF; i += kWave) s_acc[wid][i] = 0.f;
     uint32_t tested = 0;                     // alpha tests (list positions before a pixel's n_contrib)
 
-    // SHARED: each thread stages one entry of a window; its emission index and
-    // record index (two dependent loads) are fetched one window ahead
-    uint32_t pe = 0, pv = 0;
-    if (SHARED && maxn > 0) {
+    // each thread stages entries tid, tid + nthr, ... of a window (SHARED: one); their
+    // emission and record indices (two dependent loads) are fetched one window ahead
+    constexpr int NW = SHARED ? 1 : (B + kWave - 1) / kWave;
+    uint32_t pe[NW], pv[NW];
+#pragma unroll
+    for (int h = 0; h < NW; ++h) {
+        pe[h] = pv[h] = 0u;
         const int32_t lo0 = maxn - B > 0 ? maxn - B : 0;
-        if ((int32_t)tid < maxn - lo0) {
-            pe = a.pair_vals[rg.x + (uint32_t)(lo0 + (int32_t)tid)];
-            pv = a.emit_vg[pe];
+        const int32_t j = tid + h * nthr;
+        if (j < maxn - lo0) {
+            pe[h] = a.pair_vals[rg.x + (uint32_t)(lo0 + j)];
+            pv[h] = a.emit_vg[pe[h]];
         }
     }
     for (int32_t hi = maxn; hi > 0; hi -= B) {
         const int32_t lo = hi - B > 0 ? hi - B : 0;
         const int32_t cnt = hi - lo;
         // stage the window
-        for (int32_t j = tid; j < cnt; j += nthr) {
-            uint32_t e, vg;
-            if (SHARED) {                                                  // j == tid
-                e = pe;
-                vg = pv;
-            } else {
-                e = a.pair_vals[rg.x + (uint32_t)(lo + j)];                // the pair's emission index
-                vg = a.emit_vg[e];
+#pragma unroll
+        for (int h = 0; h < NW; ++h) {
+            const int32_t j = tid + h * nthr;
+            if (j < cnt) {
+                const float4* r = a.rec + (size_t)kRecF4 * pv[h];
+                s_e[slot][j] = pe[h];
+                s_rec[slot][kRecF4 * j + 0] = r[0];
+                s_rec[slot][kRecF4 * j + 1] = r[1];
+                s_rec[slot][kRecF4 * j + 2] = r[2];
             }
-            const float4* r = a.rec + (size_t)kRecF4 * vg;
-            s_e[slot][j] = e;
-            s_rec[slot][kRecF4 * j + 0] = r[0];
-            s_rec[slot][kRecF4 * j + 1] = r[1];
-            s_rec[slot][kRecF4 * j + 2] = r[2];
         }
         if (SHARED) __syncthreads(); else wave_lds_sync();
-        if (SHARED && lo > 0) {                                            // the next window's indices
+        if (lo > 0) {                                                      // the next window's indices
             const int32_t lo2 = lo - B > 0 ? lo - B : 0;
-            if ((int32_t)tid < lo - lo2) {
-                pe = a.pair_vals[rg.x + (uint32_t)(lo2 + (int32_t)tid)];
-                pv = a.emit_vg[pe];
+#pragma unroll
+            for (int h = 0; h < NW; ++h) {
+                const int32_t j = tid + h * nthr;
+                if (j < lo - lo2) {
+                    pe[h] = a.pair_vals[rg.x + (uint32_t)(lo2 + j)];
+                    pv[h] = a.emit_vg[pe[h]];
+                }
             }
         }
         // this wavefront's surviving entries of the window, in list order
@@ -732,7 +763,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
             bool keep = false;
             if (j < jtop) {
                 const float4* r = &s_rec[slot][kRecF4 * j];
-                keep = !culled(g, r[0], r[1].x, r[2].y);
+                keep = !culled(g, r[0], r[1].x, r[2]);
             }
             const uint64_t bal = __ballot(keep);
             if (keep) {

@@ -39,7 +39,8 @@ constexpr int kL1Pix = 4 * kL1Block;   // pixels per L1 block (4 a thread)
 // Projected record of one (view, Gaussian): three float4
 //   r0 = (mean x, mean y, A', B')
 //   r1 = (C', opacity, red, green)
-//   r2 = (blue, L, 0, 0)  (L: cull level)
+//   r2 = (blue, L, kr, kc)  (L: cull level; kr = -B'/(2C'), kc = -B'/(2A'): where the
+//        exponent's maximum along a pixel row / column lies)
 // with the conic pre-scaled to log2 units: A' = -A log2(e)/2, B' = -B log2(e),
 // C' = -C log2(e)/2, so that the exponent is A' dx^2 + B' dx dy + C' dy^2.
 constexpr double kLog2e = 1.4426950408889634;
@@ -73,8 +74,9 @@ struct ProjectFwdArgs {
     const CamDev* cams;
     float4* rec;                          // [V*n][3]
     uint32_t* depth_key;                  // [V*n] float bits of camera z; culled = 0xffffffff
-    uint4* trect;                         // [V*n] (x0 | x1 << 16, y0 | y1 << 16, tiles touched, 0): one
-                                          //   16-byte gather for the depth-ordered scan
+    uint2* trect;                         // [V*n] (x0 | x1 << 16, y0 | y1 << 16), inclusive tile bounds
+                                          //   (empty: x1 < x0): one 8-byte gather for the depth-ordered
+                                          //   scan, which takes the tile count from the bounds
     uint32_t* tiles_touched;              // [V*n]
     int32_t* radius;                      // [V*n]
     float* depth;                         // [V*n]
@@ -178,7 +180,7 @@ hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, bool sh_bf
 // *overflow |= 1 if the total does not fit in 32 bits; vals_s[i] = vals[order[i]] and
 // rect_s[i] = rect[order[i]].  tmp holds scan_tmp_words(n) words.
 size_t scan_tmp_words(uint32_t n);
-hipError_t launch_gather_scan(const uint4* trect, const uint32_t* order, uint32_t n, uint32_t* out,
+hipError_t launch_gather_scan(const uint2* trect, const uint32_t* order, uint32_t n, uint32_t* out,
                               uint32_t* vals_s, uint2* rect_s, uint32_t* total, uint32_t* overflow, uint32_t* tmp,
                               hipStream_t s);
 

@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectFwdArgs a)
         view_proj(c, mu, L, a.flags, P);
         uint32_t tt = 0;
         int32_t rad = 0;
-        uint2 rc = make_uint2(0u, 0u);
+        uint2 rc = make_uint2(1u, 1u);                      // empty: x1 < x0 and y1 < y0
         float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
         if (P.ok) {
             double mid = 0.5 * (P.a + P.c);
@@ -301,16 +301,20 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectFwdArgs a)
             r0 = make_float4(P.mx, P.my, A2, B2);
             r1 = make_float4(C2, op, col[0], col[1]);
             // Cull level for the blend: alpha < 1/255 wherever the exponent is
-            // below -L, L = log2(255 opacity) + 1e-4.
+            // below -L, L = log2(255 opacity) + 1e-4; and the slopes of the exponent's
+            // ridge lines, where its maximum along a pixel row / column lies (dy = k dx
+            // with k = -B'/(2C'), dx = k' dy with k' = -B'/(2A')).
             const double Lc = op > 0.f ? log2(255.0 * (double)op) + 1e-4 : -HUGE_VAL;
-            r2 = make_float4(col[2], (float)Lc, 0.f, 0.f);
+            const float kr = (float)(-(double)B2 / (2.0 * (double)C2));
+            const float kc = (float)(-(double)B2 / (2.0 * (double)A2));
+            r2 = make_float4(col[2], (float)Lc, kr, kc);
         }
         a.rec[3 * o + 0] = r0;
         a.rec[3 * o + 1] = r1;
         a.rec[3 * o + 2] = r2;
         a.depth_key[o] = P.ok ? __float_as_uint(P.tz) : 0xffffffffu;
         a.depth[o] = P.tz;
-        a.trect[o] = make_uint4(rc.x, rc.y, tt, 0u);
+        a.trect[o] = rc;
         a.tiles_touched[o] = tt;
         a.radius[o] = P.ok ? rad : 0;
     }
@@ -321,23 +325,9 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(ProjectFwdArgs a)
 // kernel fits three wavefronts a SIMD (168 VGPRs; the compiler spills a few bytes)
 // instead of two.
 template <int DEG, bool BF16, bool ONE>
-__global__ __launch_bounds__(256, ONE ? 3 : 1) void project_bwd_kernel(ProjectBwdArgs a)
+__device__ __forceinline__ void project_bwd_one(const ProjectBwdArgs& a, uint32_t i)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    if (a.reg_partial) {
-        // the opacity regulariser's loss (Sec. 5.4 ablation): per-wavefront FP64 sums of
-        // exp(-(sigma - 0.5)^2 / 0.05), in a fixed order, for a fixed-order final sum
-        double e = 0.0;
-        if (i < a.n) {
-            const float d = a.opac[i] - 0.5f;
-            e = (double)expf(-(d * d) * 20.0f);              // 1 / 0.05 = 20
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
-        if ((threadIdx.x & 63u) == 0u) a.reg_partial[4u * blockIdx.x + (threadIdx.x >> 6)] = e;
-    }
-    if (i >= a.n) return;
     float mu[3] = { a.means[3 * (size_t)i], a.means[3 * (size_t)i + 1], a.means[3 * (size_t)i + 2] };
     float s[3] = { a.scales[3 * (size_t)i], a.scales[3 * (size_t)i + 1], a.scales[3 * (size_t)i + 2] };
     float q[4] = { a.quats[4 * (size_t)i], a.quats[4 * (size_t)i + 1], a.quats[4 * (size_t)i + 2], a.quats[4 * (size_t)i + 3] };
@@ -522,6 +512,27 @@ __global__ __launch_bounds__(256, ONE ? 3 : 1) void project_bwd_kernel(ProjectBw
         float* p = reinterpret_cast<float*>(a.g_sh) + (size_t)i * (K * 3);
 #pragma unroll
         for (int k = 0; k < K * 3; ++k) p[k] = any ? gsh[k] : 0.f;
+    }
+}
+
+template <int DEG, bool BF16, bool ONE>
+__global__ __launch_bounds__(256, ONE ? 3 : 1) void project_bwd_kernel(ProjectBwdArgs a)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    // the opacity regulariser's loss (Sec. 5.4 ablation): per-wavefront FP64 sums of
+    // exp(-(sigma - 0.5)^2 / 0.05), in a fixed order, for a fixed-order final sum; stored
+    // after the gradients (with a store ahead of the view loop, some camera fields in it
+    // became vector loads that waited on memory: 0.52 -> 0.62 ms on the 8-view workload)
+    double e = 0.0;
+    if (a.reg_partial && i < a.n) {
+        const float d = a.opac[i] - 0.5f;
+        e = (double)expf(-(d * d) * 20.0f);                  // 1 / 0.05 = 20
+    }
+    if (i < a.n) project_bwd_one<DEG, BF16, ONE>(a, i);
+    if (a.reg_partial) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+        if ((threadIdx.x & 63u) == 0u) a.reg_partial[4u * blockIdx.x + (threadIdx.x >> 6)] = e;
     }
 }
 

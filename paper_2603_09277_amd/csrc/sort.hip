@@ -54,12 +54,21 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* total)
 
 // ---------------------------------------------------------------------------
 // Device-wide exclusive scan (reduce, spine, downsweep) of the tiles touched
-// taken in depth order.  The reduce step gathers each record's (rectangle,
-// tiles touched) with one 16-byte load into depth order (vals_s, rect_s), so
-// the downsweep and the duplication read them coalesced.
+// taken in depth order.  The reduce step gathers each record's tile rectangle
+// with one 8-byte load into depth order (rect_s, and its tile count in vals_s),
+// so the downsweep and the duplication read them coalesced.  (With the count in
+// a 16-byte word the gathered array was 384 MB on the 8-view workload; at 8
+// bytes it is half that, within the chip's 256 MB last-level cache.)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint4* trect, const uint32_t* order, uint32_t n,
+// tiles in the inclusive tile rectangle (x0 | x1 << 16, y0 | y1 << 16); 0 when x1 < x0
+__device__ __forceinline__ uint32_t rect_tiles(uint2 r)
+{
+    const uint32_t w = (r.x >> 16) - (r.x & 0xffffu) + 1u, h = (r.y >> 16) - (r.y & 0xffffu) + 1u;
+    return w * h;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint2* trect, const uint32_t* order, uint32_t n,
                                                                uint32_t* partial, uint32_t* vals_s, uint2* rect_s)
 {
     size_t base = (size_t)blockIdx.x * kTileItems + threadIdx.x;
@@ -72,16 +81,17 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint4* trec
         const size_t idx = base + (size_t)k * kThreads;
         o[k] = order[idx < n ? idx : (size_t)n - 1];
     }
-    uint4 t[kItems];
+    uint2 t[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) t[k] = trect[o[k]];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const size_t idx = base + (size_t)k * kThreads;
         if (idx < n) {
-            vals_s[idx] = t[k].z;
-            rect_s[idx] = make_uint2(t[k].x, t[k].y);
-            sum += t[k].z;
+            const uint32_t tt = rect_tiles(t[k]);
+            vals_s[idx] = tt;
+            rect_s[idx] = t[k];
+            sum += tt;
         }
     }
     uint32_t tot;
@@ -858,7 +868,7 @@ static uint32_t grid_cap(uint32_t blocks) { return blocks < 16384u ? (blocks ? b
 
 size_t scan_tmp_words(uint32_t n) { return (size_t)(n + kTileItems - 1) / kTileItems + 1; }
 
-hipError_t launch_gather_scan(const uint4* trect, const uint32_t* order, uint32_t n, uint32_t* out,
+hipError_t launch_gather_scan(const uint2* trect, const uint32_t* order, uint32_t n, uint32_t* out,
                               uint32_t* vals_s, uint2* rect_s, uint32_t* total, uint32_t* overflow, uint32_t* tmp,
                               hipStream_t s)
 {

@@ -146,6 +146,8 @@ def stage_bytes(stage, n, V, sh_bytes, pairs, n_tiles, npix):
         "duplicate": vn * 20 + pairs * 8,                   # order/tt/offset/rect; tile id, owner
         "tile_sort": pairs * 20 * 2,                        # 2 passes
         "ranges": pairs * 4 + n_tiles * 8,
+        # blend stages: every pair of every list; the forward stops reading a tile's list
+        # once all its pixels have stopped, so this bounds what it reads from above
         "blend_fwd": pairs * 56 + npix * 24,                # pair value + owner + record; rgb, H, T, n_contrib
         "entropy_mean": 0,
         "blend_bwd": pairs * 96 + npix * 24,                # pair value + owner + record + row + stamp; per-pixel state
@@ -566,7 +568,9 @@ def roofline_of(res, rep, stl, traffic_key, render=False):
             "ops_per_launch": int(ops), "avg_launch_ms": rep[dom]["avg_ms"],
             "post_cull": {"achieved": round(pc, 3), "peak": round(VALU_ISSUE_TOPS, 2), "unit": "T VALU op/s",
                           "frac": round(pc / VALU_ISSUE_TOPS, 4)},
-            "hbm_GBs": rep[dom]["hbm_GBs"], "hbm_frac": round(rep[dom]["hbm_GBs"] / HBM_PEAK_GBS, 4)}
+            # measured HBM bytes (the traffic record) over this launch time, against 8 TB/s
+            "traffic_GBs": round(traffic / avg_s / 1e9, 1) if traffic else None,
+            "traffic_frac": round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None}
 
 
 def image_errors(sampled, cams, imgs):

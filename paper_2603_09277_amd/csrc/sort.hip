@@ -535,8 +535,7 @@ struct SegCarry {
 constexpr uint32_t kRowsPerLane = 4;
 constexpr uint32_t kChunkRows = 64 * kRowsPerLane;           // 256
 constexpr uint32_t kNoSeg = 0xffffffffu;
-constexpr uint32_t kChunkWords = kChunkRows * kRowF / 4;     // 16-byte words of a chunk's rows
-static_assert(kChunkWords % 64u == 0u && (kRowsPerLane * kRowF) % 4u == 0u, "chunk rows in whole 16-byte words");
+static_assert(kRowF % 2 == 0, "rows read as 8-byte pairs");
 
 __device__ __forceinline__ void add9(float* a, const float* b)
 {
@@ -585,20 +584,26 @@ __device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t x)
     return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, ROW_MASK, 0xf, false);
 }
 
-// one step of the segmented lane scan: add the sums of the lane CTRL names if it
-// holds the same segment
+// DPP move of a float: lanes without a source lane read 0
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ void seg_scan_step(float (&C)[kG2], uint32_t& Cl, uint32_t sl)
+__device__ __forceinline__ float dpp_f0(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, true));
+}
+
+// one step of the segmented lane scan: add the sums of the lane CTRL names if it
+// holds the same segment (Cl: live rows, exact as a float)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_scan_step(float (&C)[kG2], float& Cl, uint32_t sl)
 {
     const uint32_t su = dpp_u32<CTRL, ROW_MASK>(kNoSeg, sl);
-    const bool same = su == sl && sl != kNoSeg;
+    // the other lane's sums times 1 (same segment) or 0: one multiply-add a value, into
+    // which the compiler folds the DPP move (the sums are finite, and C + y * 1 rounds
+    // as C + y)
+    const float sf = (su == sl && sl != kNoSeg) ? 1.f : 0.f;
 #pragma unroll
-    for (int k = 0; k < kG2; ++k) {
-        const float y = __uint_as_float(dpp_u32<CTRL, ROW_MASK>(0u, __float_as_uint(C[k])));
-        C[k] += same ? y : 0.f;
-    }
-    const uint32_t yl = dpp_u32<CTRL, ROW_MASK>(0u, Cl);
-    Cl += same ? yl : 0u;
+    for (int k = 0; k < kG2; ++k) C[k] = fmaf(dpp_f0<CTRL, ROW_MASK>(C[k]), sf, C[k]);
+    Cl = fmaf(dpp_f0<CTRL, ROW_MASK>(Cl), sf, Cl);
 }
 
 __global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pair_grad, const uint32_t* pair_stamp,
@@ -606,7 +611,6 @@ __global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pa
                                                               const uint32_t* total, uint32_t cap, float* grad2d,
                                                               uint32_t* rec_stamp, SegCarry* carry)
 {
-    __shared__ uint4 s_rows[kWaves][kChunkWords];
     const uint32_t P = *total < cap ? *total : cap;
     const uint32_t st = *stamp;
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
@@ -623,50 +627,33 @@ __global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pa
         const uint32_t r0 = c * kChunkRows;
         const uint32_t* sg = m.sg;
         const uint32_t* sp = m.sp;
-        // the chunk's rows are one contiguous 10 KB span: the wavefront reads it with
-        // coalesced 16-byte loads into LDS (a 16-byte word only if a row it overlaps is
-        // live; a row is live if this frame's backward wrote it) and each lane then
-        // takes its own 4 rows from there
+        // each lane reads its own live rows (a row is live if this frame's backward wrote
+        // it), 40 bytes each as five 8-byte loads, all in flight before the first is used;
+        // stale rows are not read and count as zeros.  (Staging the chunk through LDS with
+        // coalesced 16-byte loads needed a per-word liveness lookup that held 40 VGPRs and
+        // a third of the kernel's VALU work; on long lists few rows are live, so the
+        // scattered loads of this form are few.)
         bool lv[kRowsPerLane];
-        uint64_t lbal[kRowsPerLane];                             // bit l: row 4 l + r of the chunk is live
+        float mine[kRowsPerLane * kRowF];
 #pragma unroll
         for (uint32_t r = 0; r < kRowsPerLane; ++r) {
             lv[r] = sg[r] != kNoSeg && sp[r] == st;
-            lbal[r] = __ballot(lv[r]);
-        }
-        const uint4* src = reinterpret_cast<const uint4*>(pair_grad + (size_t)kRowF * r0);
-        uint4* srow = s_rows[wid];
-        uint4 words[kChunkWords / 64u];
 #pragma unroll
-        for (uint32_t i = 0; i < kChunkWords / 64u; ++i) {
-            const uint32_t q = i * 64u + lane;
-            const uint32_t ra = (4u * q) / (uint32_t)kRowF, rb = (4u * q + 3u) / (uint32_t)kRowF;
-            const bool need = ((lbal[ra & 3u] >> (ra >> 2)) & 1ull) | ((lbal[rb & 3u] >> (rb >> 2)) & 1ull);
-            words[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (need) words[i] = src[q];
-        }
-        if (c + stride < nchunk) load_meta(emit_vg, pair_stamp, P, c + stride, lane, nx);
+            for (int k = 0; k < kRowF; ++k) mine[r * kRowF + k] = 0.f;
+            if (lv[r]) {
+                const float2* x = reinterpret_cast<const float2*>(pair_grad + (size_t)kRowF * (r0 + lane * kRowsPerLane + r));
 #pragma unroll
-        for (uint32_t i = 0; i < kChunkWords / 64u; ++i) srow[i * 64u + lane] = words[i];
-        wave_lds_order();
-        // this lane's 4 rows: 160 contiguous bytes of LDS, ten 16-byte reads (rows not
-        // written by this frame's backward read as zeros)
-        float mine[kRowsPerLane * kRowF];
-        {
-            const uint4* m4 = srow + lane * (kRowsPerLane * kRowF / 4u);
-#pragma unroll
-            for (uint32_t i = 0; i < kRowsPerLane * kRowF / 4u; ++i) {
-                const uint4 w = m4[i];
-                mine[4 * i + 0] = __uint_as_float(w.x);
-                mine[4 * i + 1] = __uint_as_float(w.y);
-                mine[4 * i + 2] = __uint_as_float(w.z);
-                mine[4 * i + 3] = __uint_as_float(w.w);
+                for (int k = 0; k < kRowF / 2; ++k) {
+                    const float2 y = x[k];
+                    mine[r * kRowF + 2 * k] = y.x;
+                    mine[r * kRowF + 2 * k + 1] = y.y;
+                }
             }
         }
-        wave_lds_order();                                        // the next chunk overwrites srow
+        if (c + stride < nchunk) load_meta(emit_vg, pair_stamp, P, c + stride, lane, nx);
         auto load_row = [&](uint32_t r, float* row) {
 #pragma unroll
-            for (int k = 0; k < kG2; ++k) row[k] = lv[r] ? mine[r * kRowF + k] : 0.f;
+            for (int k = 0; k < kG2; ++k) row[k] = mine[r * kRowF + k];
         };
         // lane-local segments: A = first segment's partial, B = last segment's partial,
         // la / lb their numbers of live rows (a segment without one is not written)
@@ -709,7 +696,7 @@ __global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pa
         // moves (segments are contiguous, so an equal key two lanes apart means one
         // segment between them)
         float C[kG2];
-        uint32_t Cl = lb;
+        float Cl = (float)lb;
 #pragma unroll
         for (int k = 0; k < kG2; ++k) C[k] = B[k];
         seg_scan_step<0x111, 0xf>(C, Cl, sl);                   // row_shr:1
@@ -728,7 +715,7 @@ __global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pa
         float prvC[kG2];
 #pragma unroll
         for (int k = 0; k < kG2; ++k) prvC[k] = __uint_as_float(dpp_u32<0x138, 0xf>(0u, __float_as_uint(C[k])));
-        const uint32_t prvCl = dpp_u32<0x138, 0xf>(0u, Cl);
+        const uint32_t prvCl = (uint32_t)__uint_as_float(dpp_u32<0x138, 0xf>(0u, __float_as_uint(Cl)));
         const bool valid = s0 != kNoSeg;
         SegCarry* cr = carry + c;
         if (valid && nseg >= 2) {                                // first segment ends in this lane
@@ -747,8 +734,8 @@ __global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pa
         if (valid && nxt != sl) {                                // last segment ends in this lane
             if (crosses_in && sl == sfirst) {
                 store9(cr->head, C);
-                cr->head_live = Cl;
-            } else if (Cl) {
+                cr->head_live = (uint32_t)Cl;
+            } else if (Cl != 0.f) {
                 store9(grad2d + (size_t)kG2 * sl, C);
                 rec_stamp[sl] = st;
             }
@@ -760,7 +747,7 @@ __global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pa
             for (int k = 0; k < kG2; ++k) cr->tail[k] = crosses_out ? C[k] : 0.f;
             cr->first_seg = sfirst;
             cr->last_seg = sl;
-            cr->flags = (crosses_in ? 1u : 0u) | (crosses_out ? 2u : 0u) | (crosses_out && Cl ? 4u : 0u);
+            cr->flags = (crosses_in ? 1u : 0u) | (crosses_out ? 2u : 0u) | (crosses_out && Cl != 0.f ? 4u : 0u);
         }
     }
 }

@@ -375,23 +375,30 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
 #pragma unroll
         for (int r = 0; r < kRadixItems; ++r) v_[r] = (uint32_t)(base + wid * kPerWave + (uint32_t)r * 64u + lane);
     }
-    const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
     for (int r = 0; r < kRadixItems; ++r) {
         const uint32_t li = wid * kPerWave + (uint32_t)r * 64u + lane;
         const bool ok = li < cnt;
         const uint32_t d = (k_[r] >> shift) & 0xffu;
-        // peers: lanes of this wavefront holding the same digit
-        uint64_t peers = __ballot(ok);
+        // peers: lanes of this wavefront holding the same digit.  Per digit bit b, m = 0 or
+        // ~0 (the bit, sign-extended), and the lanes that agree with this one on it are
+        // ~(ballot ^ m): one three-input bit operation per 32-lane half.  `below`: peers in
+        // lower lanes, by mbcnt.
+        const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
+        uint32_t plo = (uint32_t)okm, phi = (uint32_t)(okm >> 32);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            const uint64_t bal = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? bal : ~bal;
+            const uint32_t m = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(m != 0u);
+            plo &= ~((uint32_t)bal ^ m);
+            phi &= ~((uint32_t)(bal >> 32) ^ m);
         }
+        const uint64_t peers = ((uint64_t)phi << 32) | plo;
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
         const uint32_t before = s_wh[wid][d];                // this digit's items in earlier rounds
-        rk[r] = before + (uint32_t)__popcll(peers & lt_mask);
+        rk[r] = before + below;
         wave_lds_order();
-        if (ok && (peers & lt_mask) == 0ull) s_wh[wid][d] = before + (uint32_t)__popcll(peers);
+        if (ok && below == 0u) s_wh[wid][d] = before + (uint32_t)__popcll(peers);
         wave_lds_order();
     }
     __syncthreads();
@@ -403,6 +410,9 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
             td += cw[w];
         }
         uint32_t run = block_excl_scan(td, &tot);
+        // digit tid's block-local start is run: from here s_gofs[d] is the global
+        // position of the block's local slot 0 for digit d (local slot li -> s_gofs[d] + li)
+        s_gofs[tid] -= run;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
             s_wh[w][tid] = run;
@@ -410,26 +420,45 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
         }
     }
     __syncthreads();
+    // reorder through LDS, then a coalesced scatter of the locally sorted block.  A full
+    // block (all but the last) takes the unguarded form, so that the compiler can keep
+    // many items' LDS reads in flight instead of waiting on each item in turn.
+    if (cnt == (uint32_t)kRadixTile) {
 #pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) {
-        const uint32_t li = wid * kPerWave + (uint32_t)r * 64u + lane;
-        if (li < cnt) {
+        for (int r = 0; r < kRadixItems; ++r) {
             const uint32_t pos = s_wh[wid][(k_[r] >> shift) & 0xffu] + rk[r];
             s_keys[pos] = k_[r];
             s_vals[pos] = v_[r];
         }
-    }
-    __syncthreads();
-    // coalesced scatter of the locally sorted block; s_wh[0][d] is digit d's block-local start
+        __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) {
-        const uint32_t li = (uint32_t)r * kThreads + tid;
-        if (li < cnt) {
+        for (int r = 0; r < kRadixItems; ++r) {
+            const uint32_t li = (uint32_t)r * kThreads + tid;
             const uint32_t k = s_keys[li];
-            const uint32_t d = (k >> shift) & 0xffu;
-            const uint32_t o = s_gofs[d] + (li - s_wh[0][d]);
+            const uint32_t o = s_gofs[(k >> shift) & 0xffu] + li;
             keys_out[o] = k;
             vals_out[o] = s_vals[li];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kRadixItems; ++r) {
+            const uint32_t li = wid * kPerWave + (uint32_t)r * 64u + lane;
+            if (li < cnt) {
+                const uint32_t pos = s_wh[wid][(k_[r] >> shift) & 0xffu] + rk[r];
+                s_keys[pos] = k_[r];
+                s_vals[pos] = v_[r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRadixItems; ++r) {
+            const uint32_t li = (uint32_t)r * kThreads + tid;
+            if (li < cnt) {
+                const uint32_t k = s_keys[li];
+                const uint32_t o = s_gofs[(k >> shift) & 0xffu] + li;
+                keys_out[o] = k;
+                vals_out[o] = s_vals[li];
+            }
         }
     }
 }

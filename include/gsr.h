@@ -350,7 +350,8 @@ gsr_status gsr_stage_times(gsr_ctx* ctx, double* total_ms, int64_t* launches, in
  * batch in {32, 64, 128, 256} and blend scheduling (hardware dispatch or
  * GSR_PERSISTENT) on the given inputs, and write the fastest into
  * inout->tile_w/tile_h/lds_batch and the GSR_PERSISTENT bit of inout->flags
- * (the other flags are kept; the timing runs use plain mode).  If cache_path is not NULL the result
+ * (the other flags are kept; the timing runs use plain mode; a candidate's time is the
+ * fastest of five forward+backward iterations after one warm-up).  If cache_path is not NULL the result
  * is read from / appended to that text file, keyed by device and workload.
  * Synchronises `stream`.  Note the image depends on the tile shape. */
 gsr_status gsr_autotune(gsr_ctx* ctx, void* stream, const gsr_gaussians* g, const gsr_camera* cams,

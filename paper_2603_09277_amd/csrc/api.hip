@@ -1350,17 +1350,21 @@ gsr_status gsr_autotune(gsr_ctx* c, void* stream, const gsr_gaussians* g, const 
             gsr_opts o = *inout;
             o.tile_w = sh[0]; o.tile_h = sh[1]; o.lds_batch = lb;
             o.flags = (o.flags & ~(uint32_t)(GSR_GRAPH | GSR_PERSISTENT | GSR_NO_SYNC)) | (pe ? GSR_PERSISTENT : 0u);
-            double t = 0.0;
-            for (int it = 0; it < 4 && s == GSR_OK; ++it) {
-                if (it == 1) (void)hipEventRecord(e0, st);
+            // one warm-up iteration, then the fastest of five timed ones (the minimum is
+            // robust to interference; candidates often differ by a few per cent)
+            double t = 1e30;
+            for (int it = 0; it < 6 && s == GSR_OK; ++it) {
+                if (it > 0) (void)hipEventRecord(e0, st);
                 s = gsr_forward(c, st, g, cams, n_views, &o, &fo);
                 if (!s) s = gsr_backward(c, st, g, cams, n_views, &o, &fo, grgb, nullptr, gle, &gg);
+                if (!s && it > 0) {
+                    (void)hipEventRecord(e1, st);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    t = std::min(t, (double)ms);
+                }
             }
-            (void)hipEventRecord(e1, st);
-            (void)hipEventSynchronize(e1);
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            t = ms / 3.0;
             if (s) break;
             if (t < best) { best = t; bo = o; }
         }

@@ -597,7 +597,7 @@ def test_render_backward_matches_fd_on_records(orc):
 
 
 # --------------------------------------------------------------------------- #
-# the survey's next rows: opacity regulariser, scale reset, r_max policy
+# training-step functions: opacity regulariser, scale reset, r_max policy
 # --------------------------------------------------------------------------- #
 
 def test_opacity_loss_closed_forms_and_fd(orc):

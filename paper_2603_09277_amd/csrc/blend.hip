@@ -711,7 +711,8 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     }
     const int32_t nthr = SHARED ? 256 : 64;
     const int32_t tid = SHARED ? (int32_t)threadIdx.x : (int32_t)lane;
-    for (int32_t i = (int32_t)lane; i < B * kAccF; i += kWave) s_acc[wid][i] = 0.f;
+    // only the hit flags start at zero: a slot's sums are read only where its flag is set
+    for (int32_t i = (int32_t)lane; i < B; i += kWave) s_acc[wid][kAccF * i + kG2] = 0.f;
     uint32_t tested = 0;                     // alpha tests (list positions before a pixel's n_contrib)
 
     // each thread stages entries tid, tid + nthr, ... of a window (SHARED: one); their
@@ -800,25 +801,30 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
         }
         if (SHARED) __syncthreads(); else wave_lds_sync();
         // store the rows of the window's blended entries (emission slots),
-        // summing the wavefront slots in a fixed order, and clear the slots;
-        // entries no pixel blended keep no row (their stamp is not this frame's)
+        // summing the flagged wavefront slots in a fixed order and clearing their flags
+        // (a slot without its flag holds stale sums and adds nothing); entries no pixel
+        // blended keep no row (their stamp is not this frame's)
         for (int32_t j = tid; j < cnt; j += nthr) {
             constexpr int32_t nsl = SHARED ? kWavesPerGroup : 1;
             const int32_t s0 = SHARED ? 0 : (int32_t)wid;
+            bool f[nsl];
             bool hit = false;
 #pragma unroll
-            for (int32_t r = 0; r < nsl; ++r) hit |= s_acc[s0 + r][kAccF * j + kG2] != 0.f;
+            for (int32_t r = 0; r < nsl; ++r) {
+                f[r] = s_acc[s0 + r][kAccF * j + kG2] != 0.f;
+                hit |= f[r];
+            }
             if (!hit) continue;
             float S[kG2], G[kG2];
 #pragma unroll
-            for (int k = 0; k < kG2 + 1; ++k) {
-                float v = 0.f;
+            for (int k = 0; k < kG2; ++k) S[k] = 0.f;
 #pragma unroll
-                for (int32_t r = 0; r < nsl; ++r) {
-                    if (k < kG2) v += s_acc[s0 + r][kAccF * j + k];
-                    s_acc[s0 + r][kAccF * j + k] = 0.f;
-                }
-                if (k < kG2) S[k] = v;
+            for (int32_t r = 0; r < nsl; ++r) {
+                if (!f[r]) continue;
+                const float* src = &s_acc[s0 + r][kAccF * j];
+#pragma unroll
+                for (int k = 0; k < kG2; ++k) S[k] += src[k];
+                s_acc[s0 + r][kAccF * j + kG2] = 0.f;
             }
             finish_row(S, s_rec[slot][kRecF4 * j], s_rec[slot][kRecF4 * j + 1], G);
             float* row = a.pair_grad + (size_t)kRowF * s_e[slot][j];

@@ -96,16 +96,19 @@ __device__ __forceinline__ float fold_rows(float x, float y)
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// LDS_FOLD: o[8], which has no partner, has its halves and rows added through the LDS
+// crossbar (ds_bpermute, no register copy), else by lane swaps with a copy of itself
+// (two VALU operations more, one LDS round trip less: the per-block backward, which
+// runs at three wavefronts a SIMD, is faster so; the shared one, at eight, is not)
+template <bool LDS_FOLD>
 __device__ __forceinline__ float wave_sum9(const float* o, uint32_t lane)
 {
     const float u0 = fold_halves(o[0], o[1]), u1 = fold_halves(o[2], o[3]);
     const float u2 = fold_halves(o[4], o[5]), u3 = fold_halves(o[6], o[7]);
-    // o[8] has no partner: its own halves and rows are added through the LDS
-    // crossbar (ds_bpermute), which needs no register copy
-    const float u4 = o[8] + __shfl_xor(o[8], 32, 64);
+    const float u4 = LDS_FOLD ? o[8] + __shfl_xor(o[8], 32, 64) : fold_halves(o[8], o[8]);
     // row r: x0 holds 16 partial sums of o[row_comp(r)], x1 of o[4 + row_comp(r)], x2 of o[8]
     const float x0 = fold_rows(u0, u1), x1 = fold_rows(u2, u3);
-    const float x2 = u4 + __shfl_xor(u4, 16, 64);
+    const float x2 = LDS_FOLD ? u4 + __shfl_xor(u4, 16, 64) : fold_rows(u4, u4);
     // row_ror:8 adds lane l ^ 8: 8 partials in each half row
     const float a0 = x0 + dpp_f<0x128, 0xf>(x0);
     const float a1 = x1 + dpp_f<0x128, 0xf>(x1);
@@ -791,7 +794,7 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
             if (__builtin_amdgcn_ballot_w64(al.act) != 0ull) {   // else no lane of this wavefront blended it
                 float o[kG2];
                 bwd_grad(q, al, g1, r[2].x, o);
-                const float tot = wave_sum9(o, lane);
+                const float tot = wave_sum9<SHARED>(o, lane);
                 if (tcomp >= 0) {
                     float* acc = &s_acc[wid][s_aidx[wid][kk]];
                     acc[tcomp] = tot;

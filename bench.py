@@ -144,14 +144,18 @@ def stage_bytes(stage, n, V, sh_bytes, pairs, n_tiles, npix):
         "depth_sort": vn * 4 * 20,                          # 4 passes: key+value in/out, key histogram
         "scan": vn * 36,                                    # order, tt and rect gathered, depth-ordered copies, offsets
         "duplicate": vn * 20 + pairs * 8,                   # order/tt/offset/rect; tile id, owner
-        "tile_sort": pairs * 20 * 2,                        # 2 passes
-        "ranges": pairs * 4 + n_tiles * 8,
+        # 2 passes: keys read twice (histogram, ranking), key + value written; the first pass's
+        # values are the items' indices, the last pass writes no keys (it records the tile ranges)
+        "tile_sort": pairs * 16 * 2,
+        "ranges": n_tiles * 16,                             # empty tiles' bounds; the tile order reads them twice
         # blend stages: every pair of every list; the forward stops reading a tile's list
         # once all its pixels have stopped, so this bounds what it reads from above
         "blend_fwd": pairs * 56 + npix * 24,                # pair value + owner + record; rgb, H, T, n_contrib
         "entropy_mean": 0,
         "blend_bwd": pairs * 96 + npix * 24,                # pair value + owner + record + row + stamp; per-pixel state
-        "project_bwd": n * (88 + 2 * sh_bytes) + vn * 44,   # params + SH in, grads out; 2D grads + tt + stamp per view
+        # params + SH in, grads out; per view the row stamp and the 2D-gradient row (read only
+        # where the stamp is this frame's: every row counted, an upper bound)
+        "project_bwd": n * (88 + 2 * sh_bytes) + vn * 40,
         "grad_reduce": pairs * 8,                           # stamps + owners in (rows and 2D grads only where blended)
     }[stage]
 

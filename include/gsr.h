@@ -329,8 +329,9 @@ typedef enum {
     GSR_STAGE_DEPTH_SORT = 1,  /* LSD radix passes over the depth keys of all (view, Gaussian) */
     GSR_STAGE_SCAN = 2,        /* prefix sum of tiles touched, in depth order */
     GSR_STAGE_DUPLICATE = 3,   /* (tile, Gaussian) pair emission */
-    GSR_STAGE_TILE_SORT = 4,   /* stable LSD radix passes over the tile digits of the pairs */
-    GSR_STAGE_RANGES = 5,      /* per-tile [start, end) */
+    GSR_STAGE_TILE_SORT = 4,   /* stable LSD radix passes over the tile digits of the pairs; the
+                                  last pass also records each tile's [start, end) */
+    GSR_STAGE_RANGES = 5,      /* tiles without pairs set to [0, 0); the tile order */
     GSR_STAGE_BLEND_FWD = 6,   /* front-to-back blend with entropy */
     GSR_STAGE_ENTROPY_MEAN = 7,/* per-view mean entropy */
     GSR_STAGE_BLEND_BWD = 8,   /* back-to-front blend backward with Alg. 1, per-pair gradient rows */
@@ -371,7 +372,8 @@ typedef enum {
     GSR_BUF_DEPTH = 2,         /* float[V*n], camera z */
     GSR_BUF_TILES_TOUCHED = 3, /* int32[V*n] */
     GSR_BUF_PAIR_VALUES = 4,   /* uint32[P]: view*n + Gaussian index, sorted by (tile, depth, index) */
-    GSR_BUF_PAIR_TILES = 5,    /* uint32[P]: global tile id of each sorted pair */
+    GSR_BUF_PAIR_TILES = 5,    /* uint32[P]: global tile id of each sorted pair (rebuilt from the
+                                  tile ranges: the sort's last pass writes no keys) */
     GSR_BUF_RANGES = 6,        /* uint32[n_tiles_total][2] = [start, end) */
     GSR_BUF_GRAD2D = 7         /* float[V*n][9]: dL/d mean x, y, conic A, B, C, opacity, r, g, b of the
                                   latest backward (zero rows for (view, Gaussian)s none of whose pairs

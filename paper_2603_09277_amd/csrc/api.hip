@@ -367,7 +367,7 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     // pair count and overflow cleared; a new stamp for the per-pair gradient rows of
     // this frame's backward (every backward of one forward writes the same rows: the
     // entries some pixel blended); the tile ranges and tile-order class counts cleared
-    HIP_TRY(c, launch_frame_begin(counters, (uint32_t*)c->ranges.p, L.n_tiles * 2u + kTileHistWords, st));
+    HIP_TRY(c, launch_frame_begin(counters, (uint32_t*)c->ranges.p, L.n_tiles, L.n_tiles * 2u + kTileHistWords, st));
 
     ProjectFwdArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
@@ -423,15 +423,18 @@ gsr_status enqueue_forward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, c
     int passes = (tile_bits + 7) / 8;
     {
         StageTimer tm(c, st, GSR_STAGE_TILE_SORT, !c->capturing);
-        for (int pass = 0; pass < passes; ++pass)          // the first pass's values: the emission indices
+        // the first pass's values: the emission indices; the last pass records the tile
+        // ranges instead of writing the sorted keys
+        for (int pass = 0; pass < passes; ++pass)
             HIP_TRY(c, launch_radix_pass(pk[pass & 1], pass ? pv[pass & 1] : nullptr, pk[(pass + 1) & 1],
-                                         pv[(pass + 1) & 1], counters, cap, 8 * pass, (uint32_t*)c->radix_tmp.p, st));
+                                         pv[(pass + 1) & 1], counters, cap, 8 * pass, (uint32_t*)c->radix_tmp.p, st,
+                                         pass + 1 == passes ? (uint2*)c->ranges.p : nullptr));
     }
     const int sb = passes & 1;
     const bool persist = (o->flags & GSR_PERSISTENT) != 0;
     {
         StageTimer tm(c, st, GSR_STAGE_RANGES, !c->capturing);
-        HIP_TRY(c, launch_ranges(pk[sb], counters, cap, (uint2*)c->ranges.p, st));
+        HIP_TRY(c, launch_ranges_finish((uint2*)c->ranges.p, L.n_tiles, st));
         // hardware dispatch visits the tiles longest list first (persistent kernels keep their queues)
         if (!persist)
             HIP_TRY(c, launch_tile_order((const uint2*)c->ranges.p, L.n_tiles, (uint32_t*)c->ranges.p + 2 * (size_t)L.n_tiles,
@@ -526,7 +529,6 @@ gsr_status enqueue_backward(gsr_ctx* c, hipStream_t st, const gsr_gaussians* g, 
     ProjectBwdArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
     pa.n = n; pa.n_views = (int32_t)V; pa.flags = o->flags; pa.cams = dc; pa.grad2d = (const float*)c->grad2d.p;
-    pa.tiles_touched = (const uint32_t*)c->tt.p;
     pa.rec_stamp = (const uint32_t*)c->rec_stamp.p; pa.stamp = (const uint32_t*)c->counters.p + 4;
     pa.g_means = gr->means; pa.g_scales = gr->scales; pa.g_quats = gr->quats; pa.g_opac = gr->opacities;
     pa.g_sh = gr->sh;
@@ -1223,7 +1225,6 @@ gsr_status gsr_inspect(gsr_ctx* c, void* stream, gsr_buffer which, void* dst, in
     }
     const void* src = nullptr;
     size_t sz = 0;
-    uint32_t* pk[2] = { (uint32_t*)c->pk0.p, (uint32_t*)c->pk1.p };
     uint32_t* pv[2] = { (uint32_t*)c->pv0.p, (uint32_t*)c->pv1.p };
     switch (which) {
         case GSR_BUF_RECORDS: src = c->rec.p; sz = (size_t)c->vn * 48; break;
@@ -1245,7 +1246,21 @@ gsr_status gsr_inspect(gsr_ctx* c, void* stream, gsr_buffer which, void* dst, in
             for (size_t q = 0; q < c->pairs; ++q) out[q] = out[q] < c->pairs ? ev[out[q]] : 0xffffffffu;
             return GSR_OK;
         }
-        case GSR_BUF_PAIR_TILES: src = pk[c->sorted_buf]; sz = (size_t)c->pairs * 4; break;
+        case GSR_BUF_PAIR_TILES: {     // the sorted keys, from the tile ranges (the last sort pass writes no keys)
+            sz = (size_t)c->pairs * 4;
+            *bytes = (int64_t)sz;
+            if (!dst) return GSR_OK;
+            if ((int64_t)sz > capacity_bytes) return fail(c, GSR_ERR_INVALID_ARG, "destination too small");
+            const uint32_t nt = c->lay.n_tiles;
+            std::vector<uint32_t> rg((size_t)nt * 2);
+            if (nt) HIP_TRY(c, hipMemcpyAsync(rg.data(), c->ranges.p, (size_t)nt * 8, hipMemcpyDeviceToHost, st));
+            HIP_TRY(c, hipStreamSynchronize(st));
+            uint32_t* out = (uint32_t*)dst;
+            std::fill(out, out + c->pairs, 0xffffffffu);
+            for (uint32_t t = 0; t < nt; ++t)
+                for (uint32_t q = rg[2 * (size_t)t]; q < rg[2 * (size_t)t + 1] && q < c->pairs; ++q) out[q] = t;
+            return GSR_OK;
+        }
         case GSR_BUF_RANGES: src = c->ranges.p; sz = (size_t)c->lay.n_tiles * 8; break;
         case GSR_BUF_GRAD2D: {         // zero rows for (view, Gaussian)s without a blended pair
             sz = (size_t)c->vn * 4 * kG2;

@@ -95,7 +95,6 @@ struct ProjectBwdArgs {
     const float* grad2d;                  // [V*n][9], valid where rec_stamp == *stamp (else zero)
     const uint32_t* rec_stamp;            // [V*n]
     const uint32_t* stamp;                // the frame's stamp (device)
-    const uint32_t* tiles_touched;        // [V*n]
     float* g_means;
     float* g_scales;
     float* g_quats;
@@ -178,7 +177,8 @@ hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, bool sh_bf
 
 // exclusive scan of vals[order[i]] for i < n  ->  out[i]; total -> *total (uint32),
 // *overflow |= 1 if the total does not fit in 32 bits; vals_s[i] = vals[order[i]] and
-// rect_s[i] = rect[order[i]].  tmp holds scan_tmp_words(n) words.
+// rect_s[i] = rect[order[i]].  tmp holds scan_tmp_words(n) words; out and vals_s are
+// 16-byte aligned.
 size_t scan_tmp_words(uint32_t n);
 hipError_t launch_gather_scan(const uint2* trect, const uint32_t* order, uint32_t n, uint32_t* out,
                               uint32_t* vals_s, uint2* rect_s, uint32_t* total, uint32_t* overflow, uint32_t* tmp,
@@ -186,11 +186,15 @@ hipError_t launch_gather_scan(const uint2* trect, const uint32_t* order, uint32_
 
 // one stable LSD radix pass of 8 bits at `shift` over (key, value) pairs; the
 // item count is min(*n_dev, n_max) read on the device (n_dev may be null: n_max);
-// vals_in null: the values are the items' indices.
+// vals_in null: the values are the items' indices.  ranges non-null: the last pass
+// of the tile sort (the keys have no bits above this digit): keys_out is not written,
+// and each key k's [start, end) in the output is folded into ranges[k] by atomic
+// min / max (ranges initialised to (0xffffffff, 0), see launch_frame_begin; tiles
+// without items keep it until launch_ranges_finish).
 size_t radix_tmp_words(uint32_t n_max);
 hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                              uint32_t* vals_out, const uint32_t* n_dev, uint32_t n_max, int shift,
-                             uint32_t* tmp, hipStream_t s);
+                             uint32_t* tmp, hipStream_t s, uint2* ranges = nullptr);
 
 // write the tile id of every (tile, Gaussian) pair, Gaussians in depth order, at
 // its emission index (keys[e]), and emit_vg[e] = view*n + Gaussian index; the
@@ -211,8 +215,10 @@ hipError_t launch_grad_reduce(const float* pair_grad, const uint32_t* pair_stamp
                               hipStream_t s);
 
 // a forward's counters: pair total and overflow flag cleared, row stamp (counters[4]) advanced;
-// ranges[0 .. n_words) cleared
-hipError_t launch_frame_begin(uint32_t* counters, uint32_t* ranges, uint32_t n_words, hipStream_t s);
+// the n_tiles tile bounds in ranges set to (0xffffffff, 0), the words after them up to
+// ranges[n_words) cleared
+hipError_t launch_frame_begin(uint32_t* counters, uint32_t* ranges, uint32_t n_tiles, uint32_t n_words,
+                              hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 // p[i] = i
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
@@ -220,8 +226,8 @@ hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
 // hist: 512 words, zeroed (bucket counts, then bucket fill counters)
 constexpr uint32_t kTileHistWords = 512;
 hipError_t launch_tile_order(const uint2* ranges, uint32_t n_tiles, uint32_t* hist, uint32_t* order, hipStream_t s);
-// per-tile [start, end) of the sorted pairs
-hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges, hipStream_t s);
+// tiles that the last tile-sort pass gave no bounds (no pairs): [0, 0)
+hipError_t launch_ranges_finish(uint2* ranges, uint32_t n_tiles, hipStream_t s);
 
 
 hipError_t launch_blend_fwd(const BlendFwdArgs& a, int lds_batch, hipStream_t s);

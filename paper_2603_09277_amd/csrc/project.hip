@@ -344,31 +344,38 @@ __device__ __forceinline__ void project_bwd_one(const ProjectBwdArgs& a, uint32_
 #pragma unroll
     for (int k = 0; k < K * 3; ++k) gsh[k] = 0.f;
 
-    // this view's tiles-touched count, row stamp and 2D gradient row, loaded one view ahead;
-    // a row whose stamp is not this frame's is zero (no pixel blended any of its pairs)
+    // this view's row stamp and 2D gradient row: a row whose stamp is not this frame's
+    // is zero (no pixel blended any of its pairs, or the record has no pairs) and is not
+    // read.  Stamps are loaded two views ahead, so that the row of the next view is
+    // loaded (one view ahead) only where its stamp is this frame's.
     const uint32_t st = *a.stamp;
     const int n_views = ONE ? 1 : a.n_views;
-    uint32_t tt_n = n_views > 0 ? a.tiles_touched[i] : 0u;
     uint32_t rs_n = n_views > 0 ? a.rec_stamp[i] : 0u;
+    uint32_t rs_nn = n_views > 1 ? a.rec_stamp[(size_t)a.n + i] : 0u;
     float g_n[kG2];
 #pragma unroll
-    for (int k = 0; k < kG2; ++k) g_n[k] = n_views > 0 ? a.grad2d[(size_t)kG2 * i + k] : 0.f;
+    for (int k = 0; k < kG2; ++k) g_n[k] = 0.f;
+    if (rs_n == st) {
+#pragma unroll
+        for (int k = 0; k < kG2; ++k) g_n[k] = a.grad2d[(size_t)kG2 * i + k];
+    }
     for (int v = 0; v < n_views; ++v) {
-        const uint32_t tt_v = tt_n, rs_v = rs_n;
+        const uint32_t rs_v = rs_n;
         float g[kG2];
 #pragma unroll
         for (int k = 0; k < kG2; ++k) g[k] = g_n[k];
-        if (v + 1 < n_views) {
+        rs_n = rs_nn;
+        if (v + 1 < n_views && rs_n == st) {
             const size_t o = (size_t)(v + 1) * a.n + i;
-            tt_n = a.tiles_touched[o];
-            rs_n = a.rec_stamp[o];
 #pragma unroll
             for (int k = 0; k < kG2; ++k) g_n[k] = a.grad2d[(size_t)kG2 * o + k];
         }
+        if (v + 2 < n_views) rs_nn = a.rec_stamp[(size_t)(v + 2) * a.n + i];
+        if (rs_v != st) continue;                           // zero gradient from this view
         const CamDev& c = a.cams[v];                        // scalar loads here (unlike the forward)
         ViewProj P;
         view_proj(c, mu, L, a.flags, P);
-        if (!P.ok || tt_v == 0 || rs_v != st) continue;     // no pairs, or none blended: zero gradient
+        if (!P.ok) continue;
         float gmx = g[0], gmy = g[1], gA = g[2], gB = g[3], gC = g[4];
         gop += g[5];
         // ---- colour -> SH coefficients and viewing direction

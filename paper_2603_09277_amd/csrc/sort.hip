@@ -151,23 +151,38 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* val
     } else {
         bpre = partial[blockIdx.x];
     }
-    size_t base = (size_t)blockIdx.x * kTileItems + (size_t)threadIdx.x * kItems;
+    // kItems consecutive counts a thread, as two 16-byte words where all are in range
+    static_assert(kItems == 8, "two 16-byte words a thread");
+    const size_t base = (size_t)blockIdx.x * kTileItems + (size_t)threadIdx.x * kItems;
+    const bool whole = base + kItems <= n;
     uint32_t v[kItems];
     uint32_t sum = 0;
+    if (whole) {
+        const uint4 a = reinterpret_cast<const uint4*>(vals_s + base)[0];
+        const uint4 b = reinterpret_cast<const uint4*>(vals_s + base)[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const size_t idx = base + k;
-        const uint32_t x = vals_s[idx < n ? idx : (size_t)n - 1];
-        v[k] = idx < n ? x : 0u;
-        sum += v[k];
+        for (int k = 0; k < kItems; ++k) v[k] = base + k < n ? vals_s[base + k] : 0u;
     }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) sum += v[k];
     uint32_t tot;
     uint32_t run = block_excl_scan(sum, &tot) + bpre;
+    uint32_t o[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        size_t idx = base + k;
-        if (idx < n) out[idx] = run;
+        o[k] = run;
         run += v[k];
+    }
+    if (whole) {
+        reinterpret_cast<uint4*>(out + base)[0] = make_uint4(o[0], o[1], o[2], o[3]);
+        reinterpret_cast<uint4*>(out + base)[1] = make_uint4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k)
+            if (base + k < n) out[base + k] = o[k];
     }
 }
 
@@ -178,13 +193,15 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* val
 // on the 8-view workload the two tile passes take about 1.4 ms, 1.7 ms at 16 items):
 //   upsweep   per-block digit histograms, block-major  hist[b * 256 + d] (one
 //             coalesced 1 KB store a block, and one 1 KB load in the downsweep)
-//   spine     one block per digit: exclusive scan of its column; column total
-//             (a pass of at most kSelfSpineBlocks blocks has no spine: each
-//             downsweep block sums the counts of the blocks before it itself)
+//   spine     one block per 4 digits: exclusive scan of their columns over the
+//             blocks that hold items; column totals (a pass of at most
+//             kSelfSpineBlocks blocks has no spine: each downsweep block sums the
+//             counts of the blocks before it itself)
 //   downsweep each wavefront ranks its 64 x ITEMS consecutive items (ITEMS rounds
 //             of 64, peers found with 8 ballots, running per-digit counts in
 //             LDS); one block scan turns the (digit, wavefront) counts into
-//             block-local starts; reorder through LDS; coalesced scatter
+//             block-local starts; reorder through LDS; coalesced scatter; blocks
+//             take their data blocks in XCD-aware order (xcd_block)
 // ---------------------------------------------------------------------------
 
 constexpr int kRadixSmallItems = 8;
@@ -256,49 +273,119 @@ __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t*
     hist[(size_t)blockIdx.x * kBins + threadIdx.x] = s_h[threadIdx.x];
 }
 
-template <uint32_t kSpineItems>
-__global__ __launch_bounds__(kThreads) void radix_spine_kernel(uint32_t* hist, uint32_t nb, uint32_t* digit_total)
+// exclusive scan of four counts at once over the 256 threads of a block (the
+// per-component form of block_excl_scan); returns the block totals in *total
+__device__ __forceinline__ uint4 block_excl_scan4(uint4 x, uint4* total)
 {
-    __shared__ unsigned int s_carry;
-    // workgroups are dealt to the 8 XCDs round-robin: XCD x takes digits [32 x, 32 x + 32),
-    // so the 32 workgroups reading one 128-byte line of a count row share that XCD's L2
-    const uint32_t d = (blockIdx.x & 7u) * (uint32_t)(kBins / 8) + (blockIdx.x >> 3);
-    uint32_t* col = hist + d;                                // digit d of every block, kBins apart
-    if (threadIdx.x == 0) s_carry = 0u;
+    __shared__ uint4 s_wave4[kThreads / 64];
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    uint4 inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t yx = __shfl_up(inc.x, o, 64), yy = __shfl_up(inc.y, o, 64);
+        const uint32_t yz = __shfl_up(inc.z, o, 64), yw = __shfl_up(inc.w, o, 64);
+        if (lane >= (uint32_t)o) { inc.x += yx; inc.y += yy; inc.z += yz; inc.w += yw; }
+    }
+    if (lane == 63) s_wave4[wid] = inc;
     __syncthreads();
-    // kSpineItems consecutive counts a thread: one block scan per kThreads * kSpineItems
+    uint4 base = make_uint4(0u, 0u, 0u, 0u), tot = base;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        const uint4 v = s_wave4[w];
+        if (w < (int)wid) { base.x += v.x; base.y += v.y; base.z += v.z; base.w += v.w; }
+        tot.x += v.x; tot.y += v.y; tot.z += v.z; tot.w += v.w;
+    }
+    __syncthreads();
+    *total = tot;
+    return make_uint4(base.x + inc.x - x.x, base.y + inc.y - x.y, base.z + inc.z - x.z, base.w + inc.w - x.w);
+}
+
+// One workgroup per 4 digits: exclusive scan of their columns of the count rows
+// (one 16-byte word a row), column totals.  Only the rows of blocks that hold
+// items are scanned (a grid sized for a larger capacity leaves the others zero and
+// the downsweep does not read them).  Workgroups are dealt to the 8 XCDs
+// round-robin: XCD x takes digits [32 x, 32 x + 32), so the 8 workgroups reading
+// one 128-byte line of a count row share that XCD's L2.
+template <uint32_t kSpineItems>
+__global__ __launch_bounds__(kThreads) void radix_spine_kernel(uint32_t* hist, const uint32_t* n_dev, uint32_t n_max,
+                                                               uint32_t tile, uint32_t* digit_total)
+{
+    __shared__ uint4 s_carry;
+    const uint32_t g = (blockIdx.x & 7u) * (uint32_t)(kBins / 32) + (blockIdx.x >> 3);
+    uint4* col = reinterpret_cast<uint4*>(hist) + g;         // digits 4 g .. 4 g + 3 of row b: col[b * kBins / 4]
+    const uint32_t n = item_count(n_dev, n_max);
+    const uint32_t nb = (uint32_t)(((size_t)n + tile - 1) / tile);
+    if (threadIdx.x == 0) s_carry = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    // kSpineItems consecutive rows a thread: one block scan per kThreads * kSpineItems
     for (uint32_t start = 0; start < nb; start += kThreads * kSpineItems) {
         const uint32_t i0 = start + threadIdx.x * kSpineItems;
-        uint32_t v[kSpineItems], sum = 0u;
+        uint4 v[kSpineItems], sum = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
         for (uint32_t j = 0; j < kSpineItems; ++j) {
-            v[j] = i0 + j < nb ? col[(size_t)(i0 + j) * kBins] : 0u;
-            sum += v[j];
+            v[j] = i0 + j < nb ? col[(size_t)(i0 + j) * (kBins / 4)] : make_uint4(0u, 0u, 0u, 0u);
+            sum.x += v[j].x; sum.y += v[j].y; sum.z += v[j].z; sum.w += v[j].w;
         }
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(sum, &tot);
-        const uint32_t carry = s_carry;
-        uint32_t run = carry + ex;
+        uint4 tot;
+        const uint4 ex = block_excl_scan4(sum, &tot);
+        const uint4 carry = s_carry;
+        uint4 run = make_uint4(carry.x + ex.x, carry.y + ex.y, carry.z + ex.z, carry.w + ex.w);
 #pragma unroll
         for (uint32_t j = 0; j < kSpineItems; ++j) {
-            if (i0 + j < nb) col[(size_t)(i0 + j) * kBins] = run;
-            run += v[j];
+            if (i0 + j < nb) col[(size_t)(i0 + j) * (kBins / 4)] = run;
+            run.x += v[j].x; run.y += v[j].y; run.z += v[j].z; run.w += v[j].w;
         }
         __syncthreads();
-        if (threadIdx.x == 0) s_carry = carry + tot;
+        if (threadIdx.x == 0) s_carry = make_uint4(carry.x + tot.x, carry.y + tot.y, carry.z + tot.z, carry.w + tot.w);
         __syncthreads();
     }
-    if (threadIdx.x == 0) digit_total[d] = s_carry;
+    if (threadIdx.x == 0) reinterpret_cast<uint4*>(digit_total)[g] = s_carry;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b to XCD b % 8), and each
+// XCD has its own L2.  Block b of `nb` takes data block xcd_block(b, nb): XCD x serves
+// the x-th eighth of the data blocks in order, so the blocks resident on one XCD are
+// neighbours in the input.  Their runs for one digit are neighbours in the output too
+// (block k's run ends where block k + 1's begins), and a cache line that two such runs
+// share is completed in one L2 instead of being written back in part from two (the
+// runs average 128 bytes).  A bijection of [0, nb).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
+{
+    const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// The last pass of the tile sort writes no keys: it records each tile's [start, end)
+// instead.  The item in local slot li goes to output position o; its neighbours in the
+// block's local order (slots li - 1, li + 1) are its neighbours in the output only
+// inside one digit's group.  There a key change marks a tile's exact start or end; at
+// a group's first or last item the neighbour in the output belongs to another block and
+// is not known here, so the item offers itself as a candidate.  The start of a tile is
+// the smallest of its candidates and its exact start (the item at the exact start is
+// one of them), the end the largest: atomicMin / atomicMax on bounds initialised to
+// (0xffffffff, 0).  Keys of the last pass have no bits above its digit, so equal keys
+// are contiguous inside a group.
+__device__ __forceinline__ void tile_bounds(uint32_t k, uint32_t li, uint32_t o, uint32_t cnt, int shift,
+                                            const uint32_t* s_keys, uint32_t* ranges)
+{
+    const uint32_t d = k >> shift;
+    const uint32_t kp = li > 0u ? s_keys[li - 1u] : 0u;
+    const uint32_t kn = li + 1u < cnt ? s_keys[li + 1u] : 0u;
+    const bool in_p = li > 0u && (kp >> shift) == d;          // slot li - 1 is output position o - 1
+    const bool in_n = li + 1u < cnt && (kn >> shift) == d;    // slot li + 1 is output position o + 1
+    if (!in_p || kp != k) atomicMin(&ranges[2u * k], o);
+    if (!in_n || kn != k) atomicMax(&ranges[2u * k + 1u], o + 1u);
 }
 
 // SELF: few blocks (nb <= kSelfSpineBlocks); every block sums the raw per-block
-// counts itself and no spine kernel runs
-template <int ITEMS, bool SELF>
+// counts itself and no spine kernel runs.  RANGES: the last pass of the tile sort
+// (tile_bounds; keys_out is not written).
+template <int ITEMS, bool SELF, bool RANGES>
 __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_t* keys_in, const uint32_t* vals_in,
                                                                    uint32_t* keys_out, uint32_t* vals_out,
                                                                    const uint32_t* n_dev, uint32_t n_max, int shift,
                                                                    const uint32_t* hist, uint32_t nb,
-                                                                   const uint32_t* digit_total)
+                                                                   const uint32_t* digit_total, uint32_t* ranges)
 {
     constexpr int kRadixItems = ITEMS;
     constexpr int kRadixTile = kThreads * ITEMS;
@@ -309,8 +396,11 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
     __shared__ uint32_t s_gofs[kBins];        // global start of digit d for this block
 
     const uint32_t n = item_count(n_dev, n_max);
-    const size_t base = (size_t)blockIdx.x * kRadixTile;
-    if (base >= n) return;                    // whole block leaves together
+    // the blocks that hold items (the grid may be sized for a larger capacity)
+    const uint32_t nb_live = (uint32_t)(((size_t)n + kRadixTile - 1) / kRadixTile);
+    if (blockIdx.x >= nb_live) return;        // whole block leaves together
+    const uint32_t blk = xcd_block(blockIdx.x, nb_live);
+    const size_t base = (size_t)blk * kRadixTile;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
     const uint32_t cnt = (uint32_t)((n - base) < (size_t)kRadixTile ? (n - base) : (size_t)kRadixTile);
 
@@ -332,7 +422,7 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
             for (uint32_t k = 0; k < 8u; ++k) {
                 const uint32_t b = b0 + k * kWaves;
                 all.x += v[k].x; all.y += v[k].y; all.z += v[k].z; all.w += v[k].w;
-                if (b < blockIdx.x) { bef.x += v[k].x; bef.y += v[k].y; bef.z += v[k].z; bef.w += v[k].w; }
+                if (b < blk) { bef.x += v[k].x; bef.y += v[k].y; bef.z += v[k].z; bef.w += v[k].w; }
             }
         }
         s_wh[wid][4u * lane + 0u] = all.x; s_wh[wid][4u * lane + 1u] = all.y;
@@ -350,7 +440,7 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
         s_gofs[tid] = block_excl_scan(a, &tot) + before;
     } else {
         const uint32_t dbase = block_excl_scan(digit_total[tid], &tot);
-        s_gofs[tid] = dbase + hist[(size_t)blockIdx.x * kBins + tid];
+        s_gofs[tid] = dbase + hist[(size_t)blk * kBins + tid];
     }
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s_wh[w][tid] = 0u;
@@ -436,8 +526,9 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
             const uint32_t li = (uint32_t)r * kThreads + tid;
             const uint32_t k = s_keys[li];
             const uint32_t o = s_gofs[(k >> shift) & 0xffu] + li;
-            keys_out[o] = k;
+            if (!RANGES) keys_out[o] = k;
             vals_out[o] = s_vals[li];
+            if (RANGES) tile_bounds(k, li, o, cnt, shift, s_keys, ranges);
         }
     } else {
 #pragma unroll
@@ -456,8 +547,9 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(const uint32_
             if (li < cnt) {
                 const uint32_t k = s_keys[li];
                 const uint32_t o = s_gofs[(k >> shift) & 0xffu] + li;
-                keys_out[o] = k;
+                if (!RANGES) keys_out[o] = k;
                 vals_out[o] = s_vals[li];
+                if (RANGES) tile_bounds(k, li, o, cnt, shift, s_keys, ranges);
             }
         }
     }
@@ -626,9 +718,8 @@ template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ void seg_scan_step(float (&C)[kG2], float& Cl, uint32_t sl)
 {
     const uint32_t su = dpp_u32<CTRL, ROW_MASK>(kNoSeg, sl);
-    // the other lane's sums times 1 (same segment) or 0: one multiply-add a value, into
-    // which the compiler folds the DPP move (the sums are finite, and C + y * 1 rounds
-    // as C + y)
+    // the other lane's sums times 1 (same segment) or 0: a DPP move and a multiply-add
+    // a value (the sums are finite, and C + y * 1 rounds as C + y)
     const float sf = (su == sl && sl != kNoSeg) ? 1.f : 0.f;
 #pragma unroll
     for (int k = 0; k < kG2; ++k) C[k] = fmaf(dpp_f0<CTRL, ROW_MASK>(C[k]), sf, C[k]);
@@ -642,7 +733,7 @@ __global__ __launch_bounds__(kThreads, 3) void seg_reduce_kernel(const float* pa
 {
     const uint32_t P = *total < cap ? *total : cap;
     const uint32_t st = *stamp;
-    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    const uint32_t lane = lane_id();
     const uint32_t nchunk = (P + kChunkRows - 1) / kChunkRows;
     // chunks, grid-stride (the grid does not grow with the pair capacity); each
     // chunk's owners and stamps are loaded while the previous chunk's rows are in
@@ -829,7 +920,7 @@ __global__ void iota_u32_kernel(uint32_t* p, uint32_t count)
 
 // a frame's first kernel: pair count and overflow cleared, the row stamp advanced,
 // and the tile ranges (plus the tile-order class counts behind them) cleared
-__global__ void frame_begin_kernel(uint32_t* counters, uint32_t* ranges, uint32_t n_words)
+__global__ void frame_begin_kernel(uint32_t* counters, uint32_t* ranges, uint32_t n_tiles, uint32_t n_words)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         counters[0] = 0u;
@@ -837,7 +928,9 @@ __global__ void frame_begin_kernel(uint32_t* counters, uint32_t* ranges, uint32_
         counters[8] = 0u;                     // set when this frame's invariants are checked
         atomicAdd(&counters[4], 1u);
     }
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += gridDim.x * blockDim.x) ranges[i] = 0u;
+    // tile bounds (0xffffffff, 0), then the words after them zero
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += gridDim.x * blockDim.x)
+        ranges[i] = i < 2u * n_tiles && (i & 1u) == 0u ? 0xffffffffu : 0u;
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t value, size_t count)
@@ -847,32 +940,11 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t value, size_t count)
     for (; i < count; i += stride) p[i] = value;
 }
 
-__global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* tiles, const uint32_t* total, uint32_t cap,
-                                                          uint2* ranges)
+// tiles without pairs: bounds (0xffffffff, 0) from frame_begin -> [0, 0)
+__global__ __launch_bounds__(kThreads) void ranges_finish_kernel(uint2* ranges, uint32_t n_tiles)
 {
-    const uint32_t P = *total < cap ? *total : cap;
-    // four keys a thread, one 16-byte load (the key buffer is 16-byte aligned)
-    for (uint32_t q = blockIdx.x * kThreads + threadIdx.x; q < (P + 3u) / 4u; q += gridDim.x * kThreads) {
-        const uint32_t i0 = 4u * q;
-        uint32_t k[4];
-        if (i0 + 4u <= P) {
-            const uint4 v = reinterpret_cast<const uint4*>(tiles)[q];
-            k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
-        } else {
-#pragma unroll
-            for (uint32_t j = 0; j < 4u; ++j) k[j] = i0 + j < P ? tiles[i0 + j] : 0u;
-        }
-        const uint32_t before = i0 > 0u ? tiles[i0 - 1u] : 0u;
-        const uint32_t after = i0 + 4u < P ? tiles[i0 + 4u] : 0u;
-#pragma unroll
-        for (uint32_t j = 0; j < 4u; ++j) {
-            const uint32_t i = i0 + j;
-            if (i >= P) break;
-            const uint32_t prv = j > 0u ? k[j - 1u] : before, nxt = j < 3u ? k[j + 1u] : after;
-            if (i == 0u || prv != k[j]) ranges[k[j]].x = i;
-            if (i == P - 1u || nxt != k[j]) ranges[k[j]].y = i + 1u;
-        }
-    }
+    for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < n_tiles; t += gridDim.x * kThreads)
+        if (ranges[t].x == 0xffffffffu) ranges[t] = make_uint2(0u, 0u);
 }
 
 
@@ -911,8 +983,23 @@ size_t radix_tmp_words(uint32_t n_max)
     return (size_t)kBins * (nb > 0 ? nb : 1) + kBins;
 }
 
+template <int ITEMS, bool SELF>
+static void launch_downsweep(uint32_t nb, hipStream_t s, const uint32_t* keys_in, const uint32_t* vals_in,
+                             uint32_t* keys_out, uint32_t* vals_out, const uint32_t* n_dev, uint32_t n_max, int shift,
+                             const uint32_t* hist, const uint32_t* digit_total, uint2* ranges)
+{
+    if (ranges)
+        hipLaunchKernelGGL((radix_downsweep_kernel<ITEMS, SELF, true>), dim3(nb), dim3(kThreads), 0, s, keys_in,
+                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total,
+                           reinterpret_cast<uint32_t*>(ranges));
+    else
+        hipLaunchKernelGGL((radix_downsweep_kernel<ITEMS, SELF, false>), dim3(nb), dim3(kThreads), 0, s, keys_in,
+                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total, nullptr);
+}
+
 hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
-                             const uint32_t* n_dev, uint32_t n_max, int shift, uint32_t* tmp, hipStream_t s)
+                             const uint32_t* n_dev, uint32_t n_max, int shift, uint32_t* tmp, hipStream_t s,
+                             uint2* ranges)
 {
     const uint32_t items = radix_items(n_max), tile = kThreads * items;
     uint32_t nb = (n_max + tile - 1) / tile;
@@ -927,27 +1014,30 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, u
                            n_max, shift, hist);
     if (nb <= kSelfSpineBlocks) {             // the downsweep blocks find their offsets themselves
         if (items == kRadixLargeItems)
-            hipLaunchKernelGGL((radix_downsweep_kernel<kRadixLargeItems, true>), dim3(nb), dim3(kThreads), 0, s,
-                               keys_in, vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
+            launch_downsweep<kRadixLargeItems, true>(nb, s, keys_in, vals_in, keys_out, vals_out, n_dev, n_max, shift,
+                                                     hist, digit_total, ranges);
         else
-            hipLaunchKernelGGL((radix_downsweep_kernel<kRadixSmallItems, true>), dim3(nb), dim3(kThreads), 0, s,
-                               keys_in, vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
+            launch_downsweep<kRadixSmallItems, true>(nb, s, keys_in, vals_in, keys_out, vals_out, n_dev, n_max, shift,
+                                                     hist, digit_total, ranges);
         return hipGetLastError();
     }
     // counts a thread: enough that a long column takes few block scans, few enough
     // that a short one is spread over the workgroup
     if (nb > 8u * kThreads)
-        hipLaunchKernelGGL(radix_spine_kernel<32>, dim3(kBins), dim3(kThreads), 0, s, hist, nb, digit_total);
+        hipLaunchKernelGGL(radix_spine_kernel<16>, dim3(kBins / 4), dim3(kThreads), 0, s, hist, n_dev, n_max, tile,
+                           digit_total);
     else if (nb > kThreads)
-        hipLaunchKernelGGL(radix_spine_kernel<8>, dim3(kBins), dim3(kThreads), 0, s, hist, nb, digit_total);
+        hipLaunchKernelGGL(radix_spine_kernel<8>, dim3(kBins / 4), dim3(kThreads), 0, s, hist, n_dev, n_max, tile,
+                           digit_total);
     else
-        hipLaunchKernelGGL(radix_spine_kernel<1>, dim3(kBins), dim3(kThreads), 0, s, hist, nb, digit_total);
+        hipLaunchKernelGGL(radix_spine_kernel<1>, dim3(kBins / 4), dim3(kThreads), 0, s, hist, n_dev, n_max, tile,
+                           digit_total);
     if (items == kRadixLargeItems)
-        hipLaunchKernelGGL((radix_downsweep_kernel<kRadixLargeItems, false>), dim3(nb), dim3(kThreads), 0, s, keys_in,
-                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
+        launch_downsweep<kRadixLargeItems, false>(nb, s, keys_in, vals_in, keys_out, vals_out, n_dev, n_max, shift,
+                                                  hist, digit_total, ranges);
     else
-        hipLaunchKernelGGL((radix_downsweep_kernel<kRadixSmallItems, false>), dim3(nb), dim3(kThreads), 0, s, keys_in,
-                           vals_in, keys_out, vals_out, n_dev, n_max, shift, hist, nb, digit_total);
+        launch_downsweep<kRadixSmallItems, false>(nb, s, keys_in, vals_in, keys_out, vals_out, n_dev, n_max, shift,
+                                                  hist, digit_total, ranges);
     return hipGetLastError();
 }
 
@@ -986,11 +1076,11 @@ hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s)
 }
 
 
-hipError_t launch_frame_begin(uint32_t* counters, uint32_t* ranges, uint32_t n_words, hipStream_t s)
+hipError_t launch_frame_begin(uint32_t* counters, uint32_t* ranges, uint32_t n_tiles, uint32_t n_words, hipStream_t s)
 {
     uint32_t blocks = (n_words + 255u) / 256u;
     blocks = blocks < 1u ? 1u : (blocks > 1024u ? 1024u : blocks);
-    hipLaunchKernelGGL(frame_begin_kernel, dim3(blocks), dim3(256), 0, s, counters, ranges, n_words);
+    hipLaunchKernelGGL(frame_begin_kernel, dim3(blocks), dim3(256), 0, s, counters, ranges, n_tiles, n_words);
     return hipGetLastError();
 }
 
@@ -1079,12 +1169,11 @@ hipError_t launch_tile_order(const uint2* ranges, uint32_t n_tiles, uint32_t* hi
     return hipGetLastError();
 }
 
-hipError_t launch_ranges(const uint32_t* tiles, const uint32_t* total, uint32_t cap, uint2* ranges, hipStream_t s)
+hipError_t launch_ranges_finish(uint2* ranges, uint32_t n_tiles, hipStream_t s)
 {
-    if (cap == 0) return hipSuccess;
-    const uint32_t quads = (cap + 3u) / 4u;
-    hipLaunchKernelGGL(ranges_kernel, dim3(grid_cap((quads + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, tiles,
-                       total, cap, ranges);
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(ranges_finish_kernel, dim3(grid_cap((n_tiles + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                       ranges, n_tiles);
     return hipGetLastError();
 }
 

@@ -245,25 +245,34 @@ __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t*
         // (sorted tile keys come in long runs, which would otherwise serialise on
         // one LDS address)
         const uint32_t lane = lane_id();
-        // all ITEMS loads first (a clamped index instead of a branch, so they are in
-        // flight together), then the counting rounds
+        // all ITEMS loads first, then the counting rounds.  A full block (all but the
+        // last) loads without guards (one address, the rest immediate offsets); the last
+        // loads with a clamped index instead of a branch, so that its loads are in flight
+        // together too
+        const bool full = base + kRadixTile <= n;
+        const uint32_t cnt = full ? (uint32_t)kRadixTile : (uint32_t)(n - base);
         uint32_t kv[ITEMS];
+        if (full) {
 #pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-            const size_t idx = base + (size_t)k * kThreads + threadIdx.x;
-            kv[k] = keys[idx < n ? idx : (size_t)n - 1];
+            for (int k = 0; k < ITEMS; ++k) kv[k] = keys[base + (size_t)k * kThreads + threadIdx.x];
+        } else {
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const size_t idx = base + (size_t)k * kThreads + threadIdx.x;
+                kv[k] = keys[idx < n ? idx : (size_t)n - 1];
+            }
         }
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            const size_t idx = base + (size_t)k * kThreads + threadIdx.x;
-            const bool ok = idx < n;
+            const bool ok = (uint32_t)k * kThreads + threadIdx.x < cnt;
             const uint32_t d = ok ? (kv[k] >> shift) & 0xffu : kBins;
-            const uint32_t prv = __shfl_up(d, 1, 64);
-            const bool lead = ok && (lane == 0u || prv != d);
-            const uint64_t leaders = __ballot(lead);
-            const uint32_t nvalid = (uint32_t)__popcll(__ballot(ok));    // valid lanes are a prefix
+            // the previous lane's digit by a DPP wave shift (lane 0 takes a value no digit has)
+            const uint32_t prv = (uint32_t)__builtin_amdgcn_update_dpp((int)0xffffffffu, (int)d, 0x138, 0xf, 0xf, false);
+            const bool lead = ok && prv != d;
+            const uint64_t leaders = __builtin_amdgcn_ballot_w64(lead);
+            const uint32_t nvalid = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(ok));    // valid lanes are a prefix
             if (lead) {
-                const uint64_t later = lane == 63u ? 0ull : leaders & ~((2ull << lane) - 1ull);
+                const uint64_t later = leaders & ~((2ull << lane) - 1ull);    // leaders above this lane (none for lane 63)
                 const uint32_t end = later ? (uint32_t)__builtin_ctzll(later) : nvalid;
                 atomicAdd(&s_h[d], end - lane);
             }

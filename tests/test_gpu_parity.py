@@ -672,6 +672,7 @@ def test_edge_empty_scene(R):
     t, opts, out = _e2e(R, sc, cams)
     assert float(out["rgb"].abs().max()) == 0.0 and float(out["t_final"].min()) == 1.0
     assert float(out["entropy_mean"][0]) == 0.0
+    assert not np.any(R.inspect(gsr.BUF_RANGES))                      # every tile [0, 0)
     g = gpu_backward(R, t, cams, opts, out, torch.ones_like(out["rgb"]), None, torch.ones(1, device=DEV))
     assert all(v.size == 0 for v in g.values())
 
@@ -683,6 +684,14 @@ def test_edge_all_culled_and_nan(R):
     t, opts, out = _e2e(R, sc, cams)
     rad = R.inspect(gsr.BUF_RADIUS)
     assert list(rad[:3]) == [0, 0, 0] and rad[3] > 0
+    # the one visible Gaussian's tiles hold one pair each, in tile order; the others are [0, 0)
+    tt = int(R.inspect(gsr.BUF_TILES_TOUCHED)[3])
+    rg = R.inspect(gsr.BUF_RANGES).reshape(-1, 2).astype(np.int64)
+    hit = rg[:, 1] > rg[:, 0]
+    assert hit.sum() == tt and np.all(rg[~hit] == 0)
+    assert np.array_equal(rg[hit, 0], np.arange(tt)) and np.array_equal(rg[hit, 1], np.arange(1, tt + 1))
+    assert list(R.inspect(gsr.BUF_PAIR_VALUES)) == [3] * tt
+    assert np.array_equal(R.inspect(gsr.BUF_PAIR_TILES), np.nonzero(hit)[0])
     g = gpu_backward(R, t, cams, opts, out, torch.full_like(out["rgb"], 1e-3), None, torch.ones(1, device=DEV))
     assert np.all(g["means"][:3] == 0) and np.any(g["means"][3] != 0)
 

@@ -658,14 +658,43 @@ __device__ __forceinline__ void bwd_init(const BlendBwdArgs& a, const BlockGeom&
 
 // SHARED: the 4 wavefronts of the workgroup are the 4 blocks of one tile and
 // share each window; otherwise every wavefront has its own tile and window.
-template <int B, bool SHARED, bool PERSIST>
-__global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
+//
+// Window records in LDS.  SHARED: two buffers (the next window is loaded while this
+// one is walked), each as three arrays of one 16-byte part of every entry (part k of
+// entry j at s_rec[buffer][k B + j]), filled straight from global memory by direct
+// loads to LDS (global_load_lds_dwordx4: lane l's 16 bytes land at the wavefront's
+// LDS base + 16 l), so no register holds a record in flight.  Otherwise: per
+// wavefront slot, whole 48-byte entries (entry j at s_rec[slot][3 j]) staged through
+// registers.
+// 16 bytes per lane from global memory straight into LDS: lane l's land at lds + 16 l
+// (lds is the wavefront's base; a device function, so that only the device pass sees
+// the builtin)
+__device__ __forceinline__ void lds_direct_load16(const float4* src, float4* lds)
 {
+    __builtin_amdgcn_global_load_lds(src, lds, 16, 0, 0);
+}
+
+template <int B, bool SHARED>
+struct BwdRecLayout {
+    static constexpr int kBytes = SHARED ? (int)sizeof(float4) : (int)sizeof(float4) * kRecF4;  // per entry
+    static constexpr int kPart = SHARED ? B : 1;               // float4s between an entry's parts
+    __device__ static int idx(int j, int k) { return SHARED ? k * B + j : kRecF4 * j + k; }
+};
+
+template <int B, bool SHARED, bool PERSIST>
+__global__ __launch_bounds__(256, (SHARED && B <= 64 && !PERSIST) ? 8 : 1) void blend_bwd_kernel(BlendBwdArgs a)
+{
+    using RL = BwdRecLayout<B, SHARED>;
     constexpr int NS = SHARED ? 1 : kWavesPerGroup;          // LDS slots
-    // a window entry's record (3 float4, as in global memory) and, per wavefront, its
-    // accumulator row (the 9 wavefront sums, then 1 where the wavefront blended it)
+    // window entries' records (see above) and emission indices (SHARED: s_rec / s_e hold
+    // one buffer, s_rec2 / s_e2 the other; two arrays, so that the compiler sees that
+    // the direct loads into one never alias the reads of the other and makes those reads
+    // wait for nothing), and, per wavefront, each entry's accumulator row (the 9
+    // wavefront sums, then 1 where the wavefront blended it)
     __shared__ float4 s_rec[NS][B * kRecF4];
     __shared__ uint32_t s_e[NS][B];
+    __shared__ float4 s_rec2[SHARED ? B * kRecF4 : 1];
+    __shared__ uint32_t s_e2[SHARED ? B : 1];
     __shared__ float s_acc[kWavesPerGroup][B * kAccF];   // per-wavefront sums of each window entry
     // surviving window entries of each wavefront, as the offsets of their record
     // (float4 index) and of their accumulator row (float index)
@@ -674,7 +703,6 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     __shared__ int32_t s_max[kWavesPerGroup];
     __shared__ uint32_t s_item;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
-    const uint32_t slot = SHARED ? 0u : wid;
     const uint32_t stamp = *a.stamp;
     const int tcomp = tot_comp(lane);
     // work items: tiles (SHARED: one per workgroup; else one per wavefront), claimed from the per-XCD queues
@@ -718,46 +746,73 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
     for (int32_t i = (int32_t)lane; i < B; i += kWave) s_acc[wid][kAccF * i + kG2] = 0.f;
     uint32_t tested = 0;                     // alpha tests (list positions before a pixel's n_contrib)
 
-    // each thread stages entries tid, tid + nthr, ... of a window (SHARED: one); their
-    // emission and record indices (two dependent loads) are fetched one window ahead
+    // window x covers list positions [lo(x), lo(x) + cnt(x)), from the back
+    const int32_t nwin = (maxn + B - 1) / B;
+    auto win_lo = [&](int32_t x) { const int32_t l = maxn - (x + 1) * B; return l > 0 ? l : 0; };
+    auto win_cnt = [&](int32_t x) { const int32_t c = maxn - x * B; return c < B ? c : B; };
+    // per-block: each thread stages entries tid, tid + 64, ... of its wavefront's window
+    // through registers; their emission and record indices (two dependent loads) are
+    // fetched one window ahead
     constexpr int NW = SHARED ? 1 : (B + kWave - 1) / kWave;
     uint32_t pe[NW], pv[NW];
 #pragma unroll
-    for (int h = 0; h < NW; ++h) {
-        pe[h] = pv[h] = 0u;
-        const int32_t lo0 = maxn - B > 0 ? maxn - B : 0;
-        const int32_t j = tid + h * nthr;
-        if (j < maxn - lo0) {
-            pe[h] = a.pair_vals[rg.x + (uint32_t)(lo0 + j)];
-            pv[h] = a.emit_vg[pe[h]];
-        }
-    }
-    for (int32_t hi = maxn; hi > 0; hi -= B) {
-        const int32_t lo = hi - B > 0 ? hi - B : 0;
-        const int32_t cnt = hi - lo;
-        // stage the window
+    for (int h = 0; h < NW; ++h) pe[h] = pv[h] = 0u;
+    auto fetch_indices = [&](int32_t x) {
+        const int32_t lo_x = win_lo(x), cnt_x = win_cnt(x);
 #pragma unroll
         for (int h = 0; h < NW; ++h) {
             const int32_t j = tid + h * nthr;
-            if (j < cnt) {
-                const float4* r = a.rec + (size_t)kRecF4 * pv[h];
-                s_e[slot][j] = pe[h];
-                s_rec[slot][kRecF4 * j + 0] = r[0];
-                s_rec[slot][kRecF4 * j + 1] = r[1];
-                s_rec[slot][kRecF4 * j + 2] = r[2];
+            if (j < cnt_x) {
+                pe[h] = a.pair_vals[rg.x + (uint32_t)(lo_x + j)];
+                pv[h] = a.emit_vg[pe[h]];
             }
         }
-        if (SHARED) __syncthreads(); else wave_lds_sync();
-        if (lo > 0) {                                                      // the next window's indices
-            const int32_t lo2 = lo - B > 0 ? lo - B : 0;
+    };
+    // SHARED: thread tid < cnt(x) holds entry tid of window x.  A window's records are
+    // loaded into the other buffer while the one before it is walked, by direct loads
+    // (one instruction per 16-byte part for the wavefront's 64 entries); its record
+    // indices one window earlier, its emission indices one earlier again, so that every
+    // load waits only at the barrier that ends a window (the wait count of vector memory
+    // is in order: a dependent load issued after the direct loads would wait for them).
+    // e1, v1: emission and record index of the next window; e2: emission index of the
+    // one after.
+    uint32_t e1 = 0u, v1 = 0u, e2 = 0u;
+    auto load_window = [&](float4* rec_b, uint32_t* e_b, int32_t x) {
+        if (tid < win_cnt(x)) {
+            const float4* r = a.rec + (size_t)kRecF4 * v1;
+            const int w0 = tid & ~(kWave - 1);               // the wavefront's first entry
+#pragma unroll
+            for (int k = 0; k < kRecF4; ++k) lds_direct_load16(r + k, &rec_b[RL::idx(w0, k)]);
+            e_b[tid] = e1;
+        }
+    };
+    // one window: its records and emission indices in rec_w / e_w; SHARED: the next
+    // window's go to rec_n / e_n
+    auto window = [&](float4* rec_w, uint32_t* e_w, float4* rec_n, uint32_t* e_n, int32_t w) {
+        const int32_t lo = win_lo(w);
+        const int32_t cnt = win_cnt(w);
+        if (SHARED) {
+            // (the barrier that ended the last window also ended every read of rec_n)
+            if (w + 1 < nwin) load_window(rec_n, e_n, w + 1);
+            if (w + 2 < nwin && tid < win_cnt(w + 2)) {
+                v1 = a.emit_vg[e2];
+                e1 = e2;
+            }
+            if (w + 3 < nwin && tid < win_cnt(w + 3)) e2 = a.pair_vals[rg.x + (uint32_t)(win_lo(w + 3) + tid)];
+        } else {
 #pragma unroll
             for (int h = 0; h < NW; ++h) {
                 const int32_t j = tid + h * nthr;
-                if (j < lo - lo2) {
-                    pe[h] = a.pair_vals[rg.x + (uint32_t)(lo2 + j)];
-                    pv[h] = a.emit_vg[pe[h]];
+                if (j < cnt) {
+                    const float4* r = a.rec + (size_t)kRecF4 * pv[h];
+                    e_w[j] = pe[h];
+                    rec_w[kRecF4 * j + 0] = r[0];
+                    rec_w[kRecF4 * j + 1] = r[1];
+                    rec_w[kRecF4 * j + 2] = r[2];
                 }
             }
+            wave_lds_sync();
+            if (w + 1 < nwin) fetch_indices(w + 1);
         }
         // this wavefront's surviving entries of the window, in list order
         const int32_t jtop = (wave_n - lo) < cnt ? (wave_n - lo) : cnt;
@@ -765,14 +820,12 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
         for (int32_t j0 = 0; j0 < jtop; j0 += kWave) {
             const int32_t j = j0 + (int32_t)lane;
             bool keep = false;
-            if (j < jtop) {
-                const float4* r = &s_rec[slot][kRecF4 * j];
-                keep = !culled(g, r[0], r[1].x, r[2]);
-            }
+            if (j < jtop)
+                keep = !culled(g, rec_w[RL::idx(j, 0)], rec_w[RL::idx(j, 1)].x, rec_w[RL::idx(j, 2)]);
             const uint64_t bal = __ballot(keep);
             if (keep) {
                 const int32_t k = m + (int32_t)__popcll(bal & ((1ull << lane) - 1ull));
-                s_idx[wid][k] = (int32_t)sizeof(float4) * kRecF4 * j;
+                s_idx[wid][k] = RL::kBytes * j;
                 s_aidx[wid][k] = kAccF * j;
             }
             m += (int32_t)__popcll(bal);
@@ -780,20 +833,20 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
         wave_lds_sync();
         // window entries j < nrel lie in this pixel's list (compared as the byte offset
         // of the entry's record in s_rec)
-        const int32_t nrel = (int32_t)sizeof(float4) * kRecF4 * (q.n - lo);
+        const int32_t nrel = RL::kBytes * (q.n - lo);
         // walk them back to front; per Gaussian, the wavefront sums go to this wavefront's slot;
         // the next entry's offset is read one step ahead
         int32_t off = m > 0 ? s_idx[wid][m - 1] : 0;
         for (int32_t kk = m - 1; kk >= 0; --kk) {
             const int32_t j3 = off;
-            const float4* r = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(&s_rec[slot][0]) + j3);
+            const float4* r = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(rec_w) + j3);
             if (kk > 0) off = s_idx[wid][kk - 1];
-            const float4 g1 = r[1];
+            const float4 g1 = r[RL::kPart];
             const BwdAlpha al = bwd_alpha(q, j3, nrel, r[0], g1);
             tested += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(j3 < nrel));
             if (__builtin_amdgcn_ballot_w64(al.act) != 0ull) {   // else no lane of this wavefront blended it
                 float o[kG2];
-                bwd_grad(q, al, g1, r[2].x, o);
+                bwd_grad(q, al, g1, r[2 * RL::kPart].x, o);
                 const float tot = wave_sum9<SHARED>(o, lane);
                 if (tcomp >= 0) {
                     float* acc = &s_acc[wid][s_aidx[wid][kk]];
@@ -829,13 +882,42 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(BlendBwdArgs a)
                 for (int k = 0; k < kG2; ++k) S[k] += src[k];
                 s_acc[s0 + r][kAccF * j + kG2] = 0.f;
             }
-            finish_row(S, s_rec[slot][kRecF4 * j], s_rec[slot][kRecF4 * j + 1], G);
-            float* row = a.pair_grad + (size_t)kRowF * s_e[slot][j];
+            finish_row(S, rec_w[RL::idx(j, 0)], rec_w[RL::idx(j, 1)], G);
+            float* row = a.pair_grad + (size_t)kRowF * e_w[j];
 #pragma unroll
             for (int k = 0; k < kG2; ++k) row[k] = G[k];
-            a.pair_stamp[s_e[slot][j]] = stamp;
+            a.pair_stamp[e_w[j]] = stamp;
         }
-        if (SHARED) __syncthreads(); else wave_lds_sync();
+        if (SHARED) {
+            __builtin_amdgcn_s_waitcnt(0);                   // the next window's direct loads have landed
+            __syncthreads();
+        } else {
+            wave_lds_sync();
+        }
+    };
+    if (SHARED) {
+        if (nwin > 0) {
+            if (tid < win_cnt(0)) {
+                e1 = a.pair_vals[rg.x + (uint32_t)(win_lo(0) + tid)];
+                v1 = a.emit_vg[e1];
+            }
+            load_window(s_rec[0], s_e[0], 0);
+        }
+        if (nwin > 1 && tid < win_cnt(1)) {
+            e1 = a.pair_vals[rg.x + (uint32_t)(win_lo(1) + tid)];
+            v1 = a.emit_vg[e1];
+        }
+        if (nwin > 2 && tid < win_cnt(2)) e2 = a.pair_vals[rg.x + (uint32_t)(win_lo(2) + tid)];
+        __builtin_amdgcn_s_waitcnt(0);                       // this thread's direct loads have landed
+        __syncthreads();
+        // two windows an iteration, so that each buffer is one named array in each
+        for (int32_t w = 0; w < nwin; w += 2) {
+            window(s_rec[0], s_e[0], s_rec2, s_e2, w);
+            if (w + 1 < nwin) window(s_rec2, s_e2, s_rec[0], s_e[0], w + 1);
+        }
+    } else {
+        if (nwin > 0) fetch_indices(0);
+        for (int32_t w = 0; w < nwin; ++w) window(s_rec[wid], s_e[wid], nullptr, nullptr, w);
     }
     if (lane == 0) reinterpret_cast<uint32_t*>(a.block_cnt + 2 * wb + 1)[1] = tested;
     }

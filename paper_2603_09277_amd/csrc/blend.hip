@@ -269,42 +269,49 @@ struct FwdPix {
     int32_t last;                    // n_contrib
     int32_t stop_pos;                // list position of the stopping entry; -1 while the
                                      // pixel is open (0 from the start outside the image)
-    uint32_t nbl;                    // entries blended
 };
 
-// Alpha tests one wavefront made (a surviving entry visited by a pixel still
-// open), wavefront-uniform.
-struct FwdCount {
-    uint32_t tested;
+// Wavefront-uniform state of a block's walk (scalar registers): the mask of its
+// open pixels (lane l's bit set while stop_pos of lane l is -1), and the alpha
+// tests made (a surviving entry visited by a pixel still open) and the entries
+// blended, summed over the wavefront.
+struct FwdWave {
+    uint64_t open;
+    uint32_t tested, blended;
 };
 
-__device__ __forceinline__ void fwd_init(FwdPix& q, bool inside)
+__device__ __forceinline__ void fwd_init(FwdPix& q, FwdWave& wc, bool inside)
 {
     q.T = 1.f; q.Cr = q.Cg = q.Cb = q.H2 = 0.f;
-    q.last = 0; q.stop_pos = inside ? -1 : 0; q.nbl = 0;
+    q.last = 0; q.stop_pos = inside ? -1 : 0;
+    wc.open = __builtin_amdgcn_ballot_w64(inside);
+    wc.tested = wc.blended = 0u;
 }
 
 __device__ __forceinline__ bool fwd_open(const FwdPix& q) { return q.stop_pos < 0; }
 
 // One surviving list entry for one pixel: alpha (Eq. 3), the transmittance stop,
 // colour (Eq. 5) and the entropy term -w log2 w (Eq. 10).  pos1: the entry's list
-// position + 1.  The ray stops once per pixel, so its bookkeeping sits in a branch
-// the wavefront almost always skips; the test count is a wavefront sum of a lane
-// mask (scalar work).
+// position + 1.  Whether a lane is open, and the counts, are lane masks and their
+// sums (scalar work); the ray stops once per pixel, so its bookkeeping sits in a
+// branch the wavefront almost always skips.
 template <bool RENDER>
-__device__ __forceinline__ void fwd_step(FwdPix& q, FwdCount& wc, float4 g0, float4 g1, float b, float fpx, float fpy,
+__device__ __forceinline__ void fwd_step(FwdPix& q, FwdWave& wc, float4 g0, float4 g1, float b, float fpx, float fpy,
                                          int32_t pos1)
 {
     const float p = gauss_p2(g0.z, g0.w, g1.x, g0.x - fpx, g0.y - fpy);
     const float alpha = fminf(kAlphaMax, g1.y * __builtin_amdgcn_exp2f(p));
     const float Tn = q.T * (1.f - alpha);
-    const bool open = fwd_open(q);
-    const bool hit = open && alpha >= kAlphaMin;
-    const bool stop = hit && Tn < kTStop;                    // this entry would take T below 1e-4
-    const bool blend = hit && !stop;
-    wc.tested += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(open));
-    if (__builtin_expect(stop, 0)) q.stop_pos = pos1 - 1;
-    if (blend) {
+    // lane masks: open pixels the entry reaches; of those, the ones it would take below
+    // T = 1e-4 (they stop) and the rest (they blend)
+    const uint64_t hit = wc.open & __builtin_amdgcn_ballot_w64(alpha >= kAlphaMin);
+    const uint64_t low = __builtin_amdgcn_ballot_w64(Tn < kTStop);
+    const uint64_t stop = hit & low, blend = hit & ~low;
+    wc.tested += (uint32_t)__popcll(wc.open);
+    wc.blended += (uint32_t)__popcll(blend);
+    wc.open &= ~stop;
+    if (__builtin_expect(__builtin_amdgcn_inverse_ballot_w64(stop), 0)) q.stop_pos = pos1 - 1;
+    if (__builtin_amdgcn_inverse_ballot_w64(blend)) {
         const float w = alpha * q.T;
         q.Cr = fmaf(w, g1.z, q.Cr);
         q.Cg = fmaf(w, g1.w, q.Cg);
@@ -312,14 +319,13 @@ __device__ __forceinline__ void fwd_step(FwdPix& q, FwdCount& wc, float4 g0, flo
         if (!RENDER) q.H2 = fmaf(-w, __builtin_amdgcn_logf(w), q.H2);    // -w log2 w   (Eq. 10)
         q.T = Tn;
         q.last = pos1;
-        ++q.nbl;
     }
 }
 
 // Outputs of one pixel and the work counts of its 8x8 block.
 template <bool RENDER>
 __device__ __forceinline__ void fwd_store(const BlendFwdArgs& a, const BlockGeom& g, const FwdPix& q,
-                                          const FwdCount& wc, uint2 rg, uint32_t wb, uint32_t lane)
+                                          const FwdWave& wc, uint2 rg, uint32_t wb, uint32_t lane)
 {
     // background weight T_{N+1} (Eq. 9-10), then natural-log units
     const float H = RENDER ? 0.f : kLn2 * fmaf(-q.T, __builtin_amdgcn_logf(q.T), q.H2);
@@ -337,7 +343,7 @@ __device__ __forceinline__ void fwd_store(const BlendFwdArgs& a, const BlockGeom
     const int32_t n_eval = !g.inside ? 0 : (!fwd_open(q) ? q.stop_pos + 1 : (int32_t)(rg.y - rg.x));
     const uint32_t ne = (uint32_t)wave_sum_all_i(n_eval);
     const uint32_t nc = (uint32_t)wave_sum_all_i(q.last);
-    const uint32_t nb = (uint32_t)wave_sum_all_i((int)q.nbl);
+    const uint32_t nb = wc.blended;
     // alpha tests at list positions that survived the block cull that this kernel
     // made (until the ray stopped); the backward adds its own count (up to the last
     // contributor) in the next word
@@ -383,8 +389,8 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
     const float fpx = (float)g.px + 0.5f, fpy = (float)g.py + 0.5f;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     FwdPix q;
-    fwd_init(q, g.inside);
-    FwdCount wc = { 0u };
+    FwdWave wc;
+    fwd_init(q, wc, g.inside);
     // a batch's records are loaded into registers one batch ahead (in flight while the
     // previous batch blends), their record indices (two dependent loads) two batches
     // ahead, 64 entries a register
@@ -407,7 +413,7 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
         if (jh < (uint32_t)B && e2 < rg.y) pv[h] = a.emit_vg[a.pair_vals[e2]];
     }
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
-        if (__ballot(fwd_open(q)) == 0ull) break;
+        if (wc.open == 0ull) break;
         const uint32_t cnt = (rg.y - bs) < (uint32_t)B ? (rg.y - bs) : (uint32_t)B;
         // stage the batch, keeping (in list order) only Gaussians that can reach this block
         uint32_t m = 0;
@@ -465,7 +471,9 @@ __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
     // entry each, read 16-byte strides (no bank conflicts), and the blend loop reads all
     // four parts of entry j at one offset, 16 j
     __shared__ float4 s_rec[kFwdRecF4][B];
-    __shared__ int32_t s_idx[kWavesPerGroup][B];  // each wavefront's surviving batch entries (byte offsets), in list order
+    // each wavefront's surviving batch entries (byte offsets), in list order; read two at
+    // a time, so a row holds one more (never used) slot
+    __shared__ int2 s_idx2[kWavesPerGroup][B / 2 + 1];
     __shared__ uint32_t s_item;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, tid = threadIdx.x;
     const uint32_t n_items = a.n_blocks / kWavesPerGroup;      // tiles
@@ -486,8 +494,8 @@ __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
     const float fpx = (float)g.px + 0.5f, fpy = (float)g.py + 0.5f;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     FwdPix q;
-    fwd_init(q, g.inside);
-    FwdCount wc = { 0u };
+    FwdWave wc;
+    fwd_init(q, wc, g.inside);
     // each thread stages one entry of a batch: its record is loaded into registers one
     // batch ahead (in flight while the previous batch blends), its record index (two
     // dependent loads) two batches ahead
@@ -503,7 +511,7 @@ __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
     if (tid < (uint32_t)B && rg.x + B + tid < rg.y) pv = a.emit_vg[a.pair_vals[rg.x + B + tid]];
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
         // (also orders this batch's staging after every wavefront's reads of the last one)
-        if (!__syncthreads_or(fwd_open(q) ? 1 : 0)) break;      // every pixel of the tile has stopped
+        if (!__syncthreads_or(wc.open != 0ull ? 1 : 0)) break;  // every pixel of the tile has stopped
         const uint32_t cnt = (rg.y - bs) < (uint32_t)B ? (rg.y - bs) : (uint32_t)B;
         if (tid < cnt) {
             s_rec[0][tid] = n0;
@@ -520,23 +528,29 @@ __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
         }
         if (tid < (uint32_t)B && bs + 2 * B + tid < rg.y) pv = a.emit_vg[a.pair_vals[bs + 2 * B + tid]];
         uint32_t m = 0;
-        if (__ballot(fwd_open(q)) != 0ull) {                     // this block still has open pixels
+        if (wc.open != 0ull) {                                   // this block still has open pixels
             for (uint32_t j0 = 0; j0 < cnt; j0 += kWave) {
                 const uint32_t j = j0 + lane;
                 const bool keep = j < cnt && !culled(g, s_rec[0][j], s_rec[1][j].x, s_rec[2][j]);
                 const uint64_t bal = __ballot(keep);
-                if (keep) s_idx[wid][m + (uint32_t)__popcll(bal & lt_mask)] = (int32_t)(sizeof(float4) * j);
+                if (keep) {
+                    const uint32_t k = m + (uint32_t)__popcll(bal & lt_mask);
+                    reinterpret_cast<int32_t*>(&s_idx2[wid][0])[k] = (int32_t)(sizeof(float4) * j);
+                }
                 m += (uint32_t)__popcll(bal);
             }
         }
         wave_lds_sync();
         m = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);   // wavefront-uniform: a scalar loop
-        // the next entry's offset is read one step ahead (its LDS latency off the chain)
-        int32_t off = m > 0 ? s_idx[wid][0] : 0;
-        for (uint32_t k = 0; k < m; ++k) {
+        // two entries a step, their offsets read together
+        auto entry = [&](int32_t off) {
             const float4* r = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(&s_rec[0][0]) + off);
-            if (k + 1 < m) off = s_idx[wid][k + 1];
             fwd_step<RENDER>(q, wc, r[0], r[B], r[2 * B].x, fpx, fpy, __float_as_int(r[3 * B].x));
+        };
+        for (uint32_t k = 0; k < m; k += 2) {
+            const int2 off = s_idx2[wid][k / 2];                 // k + 1 <= B: inside the row
+            entry(off.x);
+            if (k + 1 < m) entry(off.y);
         }
     }
     fwd_store<RENDER>(a, g, q, wc, rg, wb, lane);
@@ -698,8 +712,10 @@ __global__ __launch_bounds__(256, (SHARED && B <= 64 && !PERSIST) ? 8 : 1) void 
     __shared__ float s_acc[kWavesPerGroup][B * kAccF];   // per-wavefront sums of each window entry
     // surviving window entries of each wavefront, as the offsets of their record
     // (float4 index) and of their accumulator row (float index)
-    __shared__ int32_t s_idx[kWavesPerGroup][B];
-    __shared__ int32_t s_aidx[kWavesPerGroup][B];
+    // surviving entries' record offsets and accumulator offsets, entry k at [.][k + 1]
+    // (the same row shape, so that one address serves both; the first slot is never used)
+    __shared__ int32_t s_idx[kWavesPerGroup][B + 1];
+    __shared__ int32_t s_aidx[kWavesPerGroup][B + 1];
     __shared__ int32_t s_max[kWavesPerGroup];
     __shared__ uint32_t s_item;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
@@ -825,8 +841,8 @@ __global__ __launch_bounds__(256, (SHARED && B <= 64 && !PERSIST) ? 8 : 1) void 
             const uint64_t bal = __ballot(keep);
             if (keep) {
                 const int32_t k = m + (int32_t)__popcll(bal & ((1ull << lane) - 1ull));
-                s_idx[wid][k] = RL::kBytes * j;
-                s_aidx[wid][k] = kAccF * j;
+                s_idx[wid][k + 1] = RL::kBytes * j;
+                s_aidx[wid][k + 1] = kAccF * j;
             }
             m += (int32_t)__popcll(bal);
         }
@@ -834,13 +850,10 @@ __global__ __launch_bounds__(256, (SHARED && B <= 64 && !PERSIST) ? 8 : 1) void 
         // window entries j < nrel lie in this pixel's list (compared as the byte offset
         // of the entry's record in s_rec)
         const int32_t nrel = RL::kBytes * (q.n - lo);
-        // walk them back to front; per Gaussian, the wavefront sums go to this wavefront's slot;
-        // the next entry's offset is read one step ahead
-        int32_t off = m > 0 ? s_idx[wid][m - 1] : 0;
-        for (int32_t kk = m - 1; kk >= 0; --kk) {
-            const int32_t j3 = off;
+        // walk them back to front, two entries a step (their offsets read together); per
+        // Gaussian, the wavefront sums go to this wavefront's slot
+        auto entry = [&](int32_t kk, int32_t j3) {
             const float4* r = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(rec_w) + j3);
-            if (kk > 0) off = s_idx[wid][kk - 1];
             const float4 g1 = r[RL::kPart];
             const BwdAlpha al = bwd_alpha(q, j3, nrel, r[0], g1);
             tested += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(j3 < nrel));
@@ -849,12 +862,19 @@ __global__ __launch_bounds__(256, (SHARED && B <= 64 && !PERSIST) ? 8 : 1) void 
                 bwd_grad(q, al, g1, r[2 * RL::kPart].x, o);
                 const float tot = wave_sum9<SHARED>(o, lane);
                 if (tcomp >= 0) {
-                    float* acc = &s_acc[wid][s_aidx[wid][kk]];
+                    float* acc = &s_acc[wid][s_aidx[wid][kk + 1]];
                     acc[tcomp] = tot;
                     acc[kG2] = 1.f;                          // (every total's lane writes the same flag)
                 }
             }
+        };
+        int32_t kk = m - 1;
+        for (; kk >= 1; kk -= 2) {
+            const int32_t oa = s_idx[wid][kk + 1], ob = s_idx[wid][kk];   // entries kk, kk - 1
+            entry(kk, oa);
+            entry(kk - 1, ob);
         }
+        if (kk == 0) entry(0, s_idx[wid][1]);
         if (SHARED) __syncthreads(); else wave_lds_sync();
         // store the rows of the window's blended entries (emission slots),
         // summing the flagged wavefront slots in a fixed order and clearing their flags

@@ -290,17 +290,24 @@ __device__ __forceinline__ void fwd_init(FwdPix& q, FwdWave& wc, bool inside)
 
 __device__ __forceinline__ bool fwd_open(const FwdPix& q) { return q.stop_pos < 0; }
 
-// One surviving list entry for one pixel: alpha (Eq. 3), the transmittance stop,
+// Alpha of one list entry at this lane's pixel (Eq. 3): g0 = (mean, A', B'),
+// g1 = (C', opacity, ...).  A pure function of the record and the pixel, so the
+// alphas of consecutive entries can be evaluated together.
+__device__ __forceinline__ float fwd_alpha(float4 g0, float4 g1, float fpx, float fpy)
+{
+    const float p = gauss_p2(g0.z, g0.w, g1.x, g0.x - fpx, g0.y - fpy);
+    return fminf(kAlphaMax, g1.y * __builtin_amdgcn_exp2f(p));
+}
+
+// One surviving list entry for one pixel, given its alpha: the transmittance stop,
 // colour (Eq. 5) and the entropy term -w log2 w (Eq. 10).  pos1: the entry's list
 // position + 1.  Whether a lane is open, and the counts, are lane masks and their
 // sums (scalar work); the ray stops once per pixel, so its bookkeeping sits in a
 // branch the wavefront almost always skips.
 template <bool RENDER>
-__device__ __forceinline__ void fwd_step(FwdPix& q, FwdWave& wc, float4 g0, float4 g1, float b, float fpx, float fpy,
-                                         int32_t pos1)
+__device__ __forceinline__ void fwd_apply(FwdPix& q, FwdWave& wc, float alpha, float cr, float cg, float cb,
+                                          int32_t pos1)
 {
-    const float p = gauss_p2(g0.z, g0.w, g1.x, g0.x - fpx, g0.y - fpy);
-    const float alpha = fminf(kAlphaMax, g1.y * __builtin_amdgcn_exp2f(p));
     const float Tn = q.T * (1.f - alpha);
     // lane masks: open pixels the entry reaches; of those, the ones it would take below
     // T = 1e-4 (they stop) and the rest (they blend)
@@ -313,13 +320,20 @@ __device__ __forceinline__ void fwd_step(FwdPix& q, FwdWave& wc, float4 g0, floa
     if (__builtin_expect(__builtin_amdgcn_inverse_ballot_w64(stop), 0)) q.stop_pos = pos1 - 1;
     if (__builtin_amdgcn_inverse_ballot_w64(blend)) {
         const float w = alpha * q.T;
-        q.Cr = fmaf(w, g1.z, q.Cr);
-        q.Cg = fmaf(w, g1.w, q.Cg);
-        q.Cb = fmaf(w, b, q.Cb);
+        q.Cr = fmaf(w, cr, q.Cr);
+        q.Cg = fmaf(w, cg, q.Cg);
+        q.Cb = fmaf(w, cb, q.Cb);
         if (!RENDER) q.H2 = fmaf(-w, __builtin_amdgcn_logf(w), q.H2);    // -w log2 w   (Eq. 10)
         q.T = Tn;
         q.last = pos1;
     }
+}
+
+template <bool RENDER>
+__device__ __forceinline__ void fwd_step(FwdPix& q, FwdWave& wc, float4 g0, float4 g1, float b, float fpx, float fpy,
+                                         int32_t pos1)
+{
+    fwd_apply<RENDER>(q, wc, fwd_alpha(g0, g1, fpx, fpy), g1.z, g1.w, b, pos1);
 }
 
 // Outputs of one pixel and the work counts of its 8x8 block.
@@ -540,17 +554,22 @@ __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
                 m += (uint32_t)__popcll(bal);
             }
         }
+        // the slot after the last survivor holds a valid offset (entry 0), so that a step's
+        // second entry can always be read
+        if (lane == 0) reinterpret_cast<int32_t*>(&s_idx2[wid][0])[m] = 0;
         wave_lds_sync();
         m = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);   // wavefront-uniform: a scalar loop
-        // two entries a step, their offsets read together
-        auto entry = [&](int32_t off) {
-            const float4* r = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(&s_rec[0][0]) + off);
-            fwd_step<RENDER>(q, wc, r[0], r[B], r[2 * B].x, fpx, fpy, __float_as_int(r[3 * B].x));
-        };
+        // two entries a step: their offsets read together, both alphas evaluated before
+        // either is applied (independent chains), then applied in list order
         for (uint32_t k = 0; k < m; k += 2) {
             const int2 off = s_idx2[wid][k / 2];                 // k + 1 <= B: inside the row
-            entry(off.x);
-            if (k + 1 < m) entry(off.y);
+            const float4* ra = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(&s_rec[0][0]) + off.x);
+            const float4* rb = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(&s_rec[0][0]) + off.y);
+            const float4 a1 = ra[B], b1 = rb[B];
+            const float aa = fwd_alpha(ra[0], a1, fpx, fpy);
+            const float ab = fwd_alpha(rb[0], b1, fpx, fpy);
+            fwd_apply<RENDER>(q, wc, aa, a1.z, a1.w, ra[2 * B].x, __float_as_int(ra[3 * B].x));
+            if (k + 1 < m) fwd_apply<RENDER>(q, wc, ab, b1.z, b1.w, rb[2 * B].x, __float_as_int(rb[3 * B].x));
         }
     }
     fwd_store<RENDER>(a, g, q, wc, rg, wb, lane);

@@ -8,9 +8,12 @@
 // of 4 wavefronts (its 4 blocks), an 8x8 tile is one wavefront.  The tile
 // shape sets the sort granularity; the wavefront sets the blend granularity.
 //
-// Forward: each wavefront stages its list in LDS in batches of B records
-// (its own LDS region: no workgroup barrier, and a wavefront whose 64 pixels
-// are all saturated leaves at the next batch boundary).
+// Forward, two forms.  Per block: each wavefront stages its list in LDS in
+// batches of B records (its own LDS region: no workgroup barrier, and a
+// wavefront whose 64 pixels have all stopped leaves at the next batch
+// boundary).  Shared (16x16 and 32x8 tiles, long lists): the 4 wavefronts of a
+// tile stage each batch once, one entry per thread, and the tile's batch loop
+// ends when none of its pixels is open.
 //
 // Culling: while staging, every wavefront drops the Gaussians that cannot
 // reach alpha >= 1/255 at any pixel centre of its 8x8 block: the exact maximum
@@ -460,9 +463,18 @@ __global__ __launch_bounds__(256) void blend_fwd_kernel(BlendFwdArgs a)
         }
         wave_lds_sync();
         m = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);   // wavefront-uniform: a scalar loop
-        for (uint32_t k = 0; k < m; ++k) {
-            const float2 bp = s_bp[wid][k];
-            fwd_step<RENDER>(q, wc, s_g0[wid][k], s_g1[wid][k], bp.x, fpx, fpy, __float_as_int(bp.y));
+        // two entries a step: both alphas evaluated before either is applied
+        for (uint32_t k = 0; k < m; k += 2) {
+            const uint32_t k1 = k + 1 < m ? k + 1 : k;           // an entry that can be read
+            const float4 a1 = s_g1[wid][k], b1 = s_g1[wid][k1];
+            const float aa = fwd_alpha(s_g0[wid][k], a1, fpx, fpy);
+            const float ab = fwd_alpha(s_g0[wid][k1], b1, fpx, fpy);
+            const float2 pa = s_bp[wid][k];
+            fwd_apply<RENDER>(q, wc, aa, a1.z, a1.w, pa.x, __float_as_int(pa.y));
+            if (k + 1 < m) {
+                const float2 pb = s_bp[wid][k1];
+                fwd_apply<RENDER>(q, wc, ab, b1.z, b1.w, pb.x, __float_as_int(pb.y));
+            }
         }
         wave_lds_sync();
     }

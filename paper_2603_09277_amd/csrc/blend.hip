@@ -497,8 +497,9 @@ __global__ __launch_bounds__(256) void blend_fwd_shared_kernel(BlendFwdArgs a)
     // entry each, read 16-byte strides (no bank conflicts), and the blend loop reads all
     // four parts of entry j at one offset, 16 j
     __shared__ float4 s_rec[kFwdRecF4][B];
-    // each wavefront's surviving batch entries (byte offsets), in list order; read two at
-    // a time, so a row holds one more (never used) slot
+    // each wavefront's surviving batch entries (byte offsets), in list order, and after
+    // the last of them a valid offset; read two at a time, so a row holds one pair more
+    // than a batch needs
     __shared__ int2 s_idx2[kWavesPerGroup][B / 2 + 1];
     __shared__ uint32_t s_item;
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, tid = threadIdx.x;
